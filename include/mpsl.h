@@ -1,0 +1,219 @@
+/*
+ * mpsl.h -- C ABI of the MI355X multi-particle scattering library for a
+ * three-layer medium (Lai, Kobayashi, Greengard, "A fast solver for
+ * multi-particle scattering in a layered medium").
+ *
+ * Problem (Section 1): 2D TM scattering, Helmholtz wavenumbers k1 (y > 0),
+ * k2 (-d < y < 0), k3 (y < -d); N identical particles of wavenumber kp in the
+ * middle layer, each a rotated copy of one prototype; a unit point source
+ * G_{k1}(x, x_s) = (i/4) H_0^(1)(k1 |x - x_s|) at x_s in the top layer.
+ * Outgoing waves use H^(1) (time dependence e^{-i omega t}).
+ *
+ * Unknowns (Section 3): for particle l, the coefficients beta^l_n of its
+ * multipole expansion sum_n beta_n H_n(k2 r) e^{in theta}, n = -p..p, stored
+ * at slot n + p; P = 2p + 1 per particle.  The library solves the
+ * Schur-complement system of Section 5.4, eq. (49), in the form
+ *
+ *     (I - S (T + T_R)) beta = S a
+ *
+ * T   : all-pairs free-space multipole-to-local translation (Lemma 3.1),
+ * T_R : reflected field of the layers, S2L o R o M2S (Sections 5.2-5.3),
+ * S   : prototype scattering matrix rotated per particle (Section 4.1),
+ * a   : local expansions of the source's layer-2 field.
+ *
+ * Conventions.
+ *  - Complex numbers are interleaved (re, im); mpsl_c128 is two doubles
+ *    (binary compatible with C99 double _Complex), mpsl_c64 two floats.
+ *  - Coefficient arrays are [particle][n + p], row-major, P per particle;
+ *    with several right-hand sides, [rhs][particle][n + p].
+ *  - Angles are radians, counter-clockwise.
+ *  - Pointers named *_dev are device pointers on the context's device;
+ *    all other pointers are host pointers.  The caller owns every buffer
+ *    it passes; the library copies what it keeps.
+ *  - Every call returns MPSL_OK (0) or a negative MPSL_E* status; no call
+ *    aborts.  mpsl_last_error() gives a message for the last failure.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MPSL_H
+#define MPSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } mpsl_c128;
+typedef struct { float re, im; } mpsl_c64;
+
+typedef struct mpsl_ctx mpsl_ctx;
+
+enum {
+  MPSL_OK = 0,
+  MPSL_EINVAL = -1,        /* bad argument (null pointer, size, range)         */
+  MPSL_ENOMEM = -2,        /* device or host allocation failed                 */
+  MPSL_EHIP = -3,          /* a HIP runtime call failed                        */
+  MPSL_ESTATE = -4,        /* a required set_* call has not been made          */
+  MPSL_EGEOM = -5,         /* particles overlap or leave the middle layer     */
+  MPSL_ENOCONV = -6,       /* GMRES stopped above tolerance (result written)   */
+  MPSL_EUNSUPPORTED = -7,  /* parameters outside what this build implements    */
+  MPSL_EINSIDE = -8,       /* receiver inside an enclosing disk (value NaN)    */
+  MPSL_ENUMERIC = -9       /* NaN/Inf met in the iteration                     */
+};
+
+/* Arithmetic of the hot path. */
+enum {
+  MPSL_FP64 = 0,   /* complex128 translations, FP64 accumulation            */
+  MPSL_FP32 = 1    /* complex64 translations and sums, FP32 accumulation    */
+};
+
+const char *mpsl_status_string(int status);
+const char *mpsl_last_error(const mpsl_ctx *ctx);
+
+/* Create a context on HIP device `device`.  Owns all device memory and one
+ * stream (the null stream of the device unless mpsl_set_stream is called). */
+int mpsl_create(mpsl_ctx **out, int device);
+void mpsl_destroy(mpsl_ctx *ctx);
+
+/* Run all later device work on `stream` (a hipStream_t, e.g. torch's current
+ * stream); NULL selects the device's null stream. */
+int mpsl_set_stream(mpsl_ctx *ctx, void *stream);
+
+/* Layer wavenumbers and middle-layer thickness d > 0 (Section 1, Fig. 1).
+ * Re k > 0 and Im k >= 0 (Section 3.1); this build requires Im k2 == 0. */
+int mpsl_set_layers(mpsl_ctx *ctx, mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, double d);
+
+/* Circular particles of radius R and wavenumber kp (real, > 0): the diagonal
+ * Mie scattering matrix of Section 3.1, eqs. (17)-(18), order p (1..32).
+ * Requires mpsl_set_layers first (uses k2).  Enclosing radius = R. */
+int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p);
+
+/* Caller-supplied prototype scattering matrix (Section 4.1): S is P x P
+ * row-major, S[(l + p) * P + (n + p)] maps incoming alpha_n to outgoing
+ * beta_l, for the prototype at rotation 0.  r_enclose is the radius of the
+ * disk enclosing the prototype (used by geometry checks). */
+int mpsl_set_scattering_matrix(mpsl_ctx *ctx, int p, double r_enclose, const mpsl_c128 *S);
+
+/* Particle centres xy[2 * j], xy[2 * j + 1] and CCW rotations rot[j] (NULL
+ * for all zero), j < n.  Fails with MPSL_EGEOM when two enclosing disks
+ * overlap or an enclosing disk crosses y = 0 or y = -d.  Requires layers and
+ * particle.  Builds the per-particle device tables (rotation phases, plane-
+ * wave factors of the contour) when a contour is set. */
+int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *rot);
+
+/* Sommerfeld contour of Section 5.1, eq. (37): Gamma_3 u Gamma_2 u Gamma_1 with
+ * offset b > 0, truncated at t_max, 16-point Gauss-Legendre panels; n_nodes
+ * = 32 + 32 m (m >= 2).  Panel rule: two panels on Gamma_2; on [0, t_max]
+ * breakpoints at 0, t_max and Re k_i, then the panel with the largest
+ * length / max(distance to nearest Re k_i, b) is halved until (n_nodes-32)/32
+ * panels exist; Gamma_3 mirrors Gamma_1.  Requires layers. */
+int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max);
+
+/* Explicit contour: nodes lam[q] and weights w[q] (d lambda included). */
+int mpsl_set_contour_nodes(mpsl_ctx *ctx, int n_nodes, const mpsl_c128 *lam, const mpsl_c128 *w);
+
+/* Copy the current contour out (host arrays of n_nodes entries). */
+int mpsl_get_contour(const mpsl_ctx *ctx, int n_nodes, mpsl_c128 *lam, mpsl_c128 *w);
+
+/* Copy the prototype scattering matrix out (P x P, host). */
+int mpsl_get_scattering_matrix(const mpsl_ctx *ctx, int p, mpsl_c128 *S);
+
+/* Sizes of the current problem (any pointer may be NULL). */
+int mpsl_get_sizes(const mpsl_ctx *ctx, int64_t *n, int *p, int *n_nodes);
+
+/* ---- one preconditioned Schur matvec (the GMRES operator) ----------------
+ * y = x - S (T + T_R) x   (Section 5.4, eq. (49); Section 3.2 preconditioning)
+ * x, y: N*P complex, precision `prec` (mpsl_c128 for MPSL_FP64, mpsl_c64 for
+ * MPSL_FP32).  _dev: device pointers, asynchronous on the context stream;
+ * the host variant copies in and out and synchronises.  x and y must not
+ * overlap. */
+int mpsl_apply(mpsl_ctx *ctx, int prec, const void *x, void *y);
+int mpsl_apply_dev(mpsl_ctx *ctx, int prec, const void *x_dev, void *y_dev);
+
+/* ---- the steps of the matvec, each on device buffers ---------------------
+ * Row a1, free-space all-pairs M2L (Lemma 3.1, eq. (24), Graf's theorem):
+ *   alpha^l_{n'} = sum_{m != l} sum_nu H_{nu-n'}(k2 rho_lm) e^{i (nu-n') phi_lm} beta^m_nu,
+ *   rho_lm, phi_lm = polar form of x_l - x_m.
+ * beta_dev, alpha_dev: N*P complex in precision prec; alpha is overwritten. */
+int mpsl_m2l_dev(mpsl_ctx *ctx, int prec, const void *beta_dev, void *alpha_dev);
+
+/* Row b1, multipole-to-Sommerfeld (Theorem 5.1, factor as derived from the
+ * Sommerfeld form (3) of H_0): P+/P- spectra of all multipoles on y = 0 and
+ * y = -d, reduced over particles:
+ *   P+(lam_q) = -4i sum_m e^{-i lam x_m + g2 y_m}       sum_nu beta^m_nu (-i)^nu ((lam - g2)/k2)^nu
+ *   P-(lam_q) = -4i sum_m e^{-i lam x_m - g2 (d + y_m)} sum_nu beta^m_nu (-i)^nu ((lam + g2)/k2)^nu
+ * spec_dev: 2*N_S mpsl_c128 (P+ then P-), FP64 for both precisions (the
+ * FP32 path sums each particle chunk in FP32, the chunks in FP64). */
+int mpsl_m2s_dev(mpsl_ctx *ctx, int prec, const void *beta_dev, void *spec_dev);
+
+/* Row b2, three-layer reflection per node (eq. (10) solved for the
+ * middle-layer densities): sigma2+/- = R(lam_q) [P+; P-] (+ source term when
+ * src_xy != NULL, a host pointer to one source position).  FP64 always.
+ * spec_dev: 2*N_S mpsl_c128 in; sigma_dev: 2*N_S mpsl_c128 out (sigma2+ then
+ * sigma2-).  spec_dev may be NULL (source only). */
+int mpsl_reflect_dev(mpsl_ctx *ctx, const void *spec_dev, const double *src_xy, void *sigma_dev);
+
+/* Row b3, Sommerfeld-to-local (Lemma 5.1, eq. (40), exact Jacobi-Anger form):
+ *   alpha^l_n = (1/4pi) sum_q (w_q/g2) e^{i lam x_l} i^n [sigma2+ e^{g2 y_l} ((lam-g2)/k2)^n
+ *                                                      + sigma2- e^{-g2(y_l+d)} ((lam+g2)/k2)^n]
+ * sigma_dev: 2*N_S mpsl_c128; alpha_dev: N*P in precision prec, overwritten. */
+int mpsl_s2l_dev(mpsl_ctx *ctx, int prec, const void *sigma_dev, void *alpha_dev);
+
+/* Row a2, scattering-matrix apply (Section 3.2 eq. (21), Section 4.1):
+ *   y^l = x^l - S_l alpha^l,  S_l[n, n'] = e^{i (n' - n) psi_l} S[n, n'].
+ * x_dev may be NULL (then y = S alpha, used for right-hand sides). */
+int mpsl_sapply_dev(mpsl_ctx *ctx, int prec, const void *x_dev, const void *alpha_dev, void *y_dev);
+
+/* ---- right-hand side, solve, field ----------------------------------------- */
+
+/* rhs = S a for a unit point source at src_xy (host, 2 doubles): the local
+ * expansions a of the source's layer-2 field (Section 5.4, right side of
+ * eq. (49)), FP64.  rhs: host array of N*P mpsl_c128. */
+int mpsl_rhs(mpsl_ctx *ctx, const double *src_xy, mpsl_c128 *rhs);
+
+typedef struct {
+  int precision;      /* MPSL_FP64: FP64 GMRES; MPSL_FP32: FP32 matvecs inside
+                         FP64 iterative refinement (Arnoldi always FP64)      */
+  double tol;         /* relative residual target ||r|| / ||b||             */
+  int maxiter;        /* total matvec budget of the Krylov solver           */
+  int restart;        /* Krylov dimension before restart (0: maxiter)      */
+  double inner_tol;   /* MPSL_FP32 only: inner GMRES tolerance (0: 1e-5)   */
+} mpsl_opts;
+
+typedef struct {
+  int iterations;         /* matvecs of the working precision               */
+  int fp64_matvecs;       /* FP64 matvecs (refinement residuals included)   */
+  int refinements;        /* outer refinement steps (MPSL_FP32)             */
+  double rel_residual;    /* final ||b - A x|| / ||b|| in FP64              */
+  double seconds;         /* wall time of the solve                         */
+  const double *history;  /* residual history, context-owned, valid until
+                             the next call on the context                  */
+  int history_len;
+} mpsl_info;
+
+/* Solve eq. (49) for n_rhs sources src_xy[2*r], src_xy[2*r+1] (host).
+ * beta_out: host, n_rhs*N*P mpsl_c128 ([rhs][particle][n+p]).  info may be
+ * NULL (for n_rhs > 1 it describes the last right-hand side).  Returns
+ * MPSL_ENOCONV when the tolerance was not met (beta is still written). */
+int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *opts,
+               mpsl_c128 *beta_out, mpsl_info *info);
+
+/* Total field (eq. (36)) at n_rcv receivers rcv_xy (host, 2 doubles each) for
+ * the source src_xy and coefficients beta (host, N*P mpsl_c128):
+ * layer 1: G + u_1^s; layer 2: u_2^t + u_2^b + sum of multipoles; layer 3: u_3^s.
+ * Receivers inside an enclosing disk get NaN and the call returns
+ * MPSL_EINSIDE after filling all other values.  u_out: host, n_rcv. */
+int mpsl_eval_field(mpsl_ctx *ctx, const double *src_xy, const mpsl_c128 *beta,
+                    int64_t n_rcv, const double *rcv_xy, mpsl_c128 *u_out);
+
+/* Average duration (ms) of the last `count` launches of the M2L kernel
+ * recorded with HIP events on the context stream (0 when not recorded);
+ * enable recording with mpsl_profile(ctx, 1). */
+int mpsl_profile(mpsl_ctx *ctx, int enable);
+int mpsl_profile_read(mpsl_ctx *ctx, double *m2l_ms_avg, int *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPSL_H */

@@ -1,0 +1,191 @@
+"""MI355X library for multi-particle scattering in a three-layer medium.
+
+A thin Python binding of the C ABI in ``include/mpsl.h`` (argument
+marshalling only).  Every step of the computation runs in the HIP kernels of
+``libmpsl.so``; when the library has not been built, creating a Context
+raises.  Device buffers are passed as torch tensors (their data pointers) or
+raw integer addresses.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+
+FP64 = 0
+FP32 = 1
+
+STATUS = {0: "MPSL_OK", -1: "MPSL_EINVAL", -2: "MPSL_ENOMEM", -3: "MPSL_EHIP", -4: "MPSL_ESTATE",
+          -5: "MPSL_EGEOM", -6: "MPSL_ENOCONV", -7: "MPSL_EUNSUPPORTED", -8: "MPSL_EINSIDE",
+          -9: "MPSL_ENUMERIC"}
+
+
+class MpslError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _c(z):
+    z = complex(z)
+    return _lib.c128(z.real, z.imag)
+
+
+def _ptr(a):
+    """Data address of a torch tensor, numpy array or integer."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _carr(a, dtype=np.complex128):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Context:
+    """One mpsl context on a HIP device (mirrors mpsl_create/mpsl_destroy)."""
+
+    def __init__(self, device=0):
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        rc = self.lib.mpsl_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise MpslError(rc, "mpsl_create failed (no HIP device?)")
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpsl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != 0 and rc not in allow:
+            raise MpslError(rc, self.lib.mpsl_last_error(self.h).decode())
+        return rc
+
+    # -- setup ----------------------------------------------------------
+    def set_stream(self, stream):
+        return self._check(self.lib.mpsl_set_stream(self.h, ctypes.c_void_p(stream)))
+
+    def set_layers(self, k1, k2, k3, d):
+        return self._check(self.lib.mpsl_set_layers(self.h, _c(k1), _c(k2), _c(k3), float(d)))
+
+    def set_particle_disk(self, R, kp, p):
+        return self._check(self.lib.mpsl_set_particle_disk(self.h, float(R), _c(kp), int(p)))
+
+    def set_scattering_matrix(self, p, r_enclose, S):
+        S = _carr(S)
+        return self._check(self.lib.mpsl_set_scattering_matrix(self.h, int(p), float(r_enclose), S.ctypes.data))
+
+    def set_geometry(self, xy, rot=None):
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        r = None if rot is None else np.ascontiguousarray(rot, dtype=np.float64)
+        return self._check(self.lib.mpsl_set_geometry(self.h, int(xy.shape[0]), xy.ctypes.data,
+                                                      None if r is None else r.ctypes.data))
+
+    def set_contour(self, n_nodes, b, t_max):
+        return self._check(self.lib.mpsl_set_contour(self.h, int(n_nodes), float(b), float(t_max)))
+
+    def set_contour_nodes(self, lam, w):
+        lam, w = _carr(lam), _carr(w)
+        return self._check(self.lib.mpsl_set_contour_nodes(self.h, int(lam.size), lam.ctypes.data, w.ctypes.data))
+
+    def sizes(self):
+        n, p, ns = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.mpsl_get_sizes(self.h, ctypes.byref(n), ctypes.byref(p), ctypes.byref(ns)))
+        return n.value, p.value, ns.value
+
+    def get_contour(self):
+        _, _, ns = self.sizes()
+        lam = np.zeros(ns, np.complex128)
+        w = np.zeros(ns, np.complex128)
+        self._check(self.lib.mpsl_get_contour(self.h, ns, lam.ctypes.data, w.ctypes.data))
+        return lam, w
+
+    def get_scattering_matrix(self):
+        _, p, _ = self.sizes()
+        S = np.zeros((2 * p + 1, 2 * p + 1), np.complex128)
+        self._check(self.lib.mpsl_get_scattering_matrix(self.h, p, S.ctypes.data))
+        return S
+
+    # -- matvec and its steps ---------------------------------------------
+    def apply(self, prec, x):
+        n, p, _ = self.sizes()
+        dt = np.complex128 if prec == FP64 else np.complex64
+        x = _carr(x, dt).reshape(-1)
+        y = np.empty_like(x)
+        self._check(self.lib.mpsl_apply(self.h, int(prec), x.ctypes.data, y.ctypes.data))
+        return y.reshape(n, 2 * p + 1)
+
+    def apply_dev(self, prec, x, y):
+        return self._check(self.lib.mpsl_apply_dev(self.h, int(prec), _ptr(x), _ptr(y)))
+
+    def m2l_dev(self, prec, beta, alpha):
+        return self._check(self.lib.mpsl_m2l_dev(self.h, int(prec), _ptr(beta), _ptr(alpha)))
+
+    def m2s_dev(self, prec, beta, spec):
+        return self._check(self.lib.mpsl_m2s_dev(self.h, int(prec), _ptr(beta), _ptr(spec)))
+
+    def reflect_dev(self, spec, src, sigma):
+        s = None if src is None else np.ascontiguousarray(src, dtype=np.float64)
+        self._keep = [s]
+        return self._check(self.lib.mpsl_reflect_dev(self.h, _ptr(spec), None if s is None else s.ctypes.data,
+                                                     _ptr(sigma)))
+
+    def s2l_dev(self, prec, sigma, alpha):
+        return self._check(self.lib.mpsl_s2l_dev(self.h, int(prec), _ptr(sigma), _ptr(alpha)))
+
+    def sapply_dev(self, prec, x, alpha, y):
+        return self._check(self.lib.mpsl_sapply_dev(self.h, int(prec), _ptr(x), _ptr(alpha), _ptr(y)))
+
+    # -- rhs, solve, field ----------------------------------------------------
+    def rhs(self, src):
+        n, p, _ = self.sizes()
+        s = np.ascontiguousarray(src, dtype=np.float64)
+        out = np.empty((n, 2 * p + 1), np.complex128)
+        self._check(self.lib.mpsl_rhs(self.h, s.ctypes.data, out.ctypes.data))
+        return out
+
+    def solve(self, src, precision=FP64, tol=1e-10, maxiter=500, restart=0, inner_tol=0.0):
+        n, p, _ = self.sizes()
+        s = np.ascontiguousarray(np.atleast_2d(src), dtype=np.float64)
+        nr = s.shape[0]
+        out = np.empty((nr, n, 2 * p + 1), np.complex128)
+        o = _lib.Opts(int(precision), float(tol), int(maxiter), int(restart), float(inner_tol))
+        info = _lib.Info()
+        rc = self._check(self.lib.mpsl_solve(self.h, nr, s.ctypes.data, ctypes.byref(o), out.ctypes.data,
+                                             ctypes.byref(info)), allow=(-6,))
+        hist = [info.history[i] for i in range(info.history_len)]
+        meta = dict(status=rc, iterations=info.iterations, fp64_matvecs=info.fp64_matvecs,
+                    refinements=info.refinements, rel_residual=info.rel_residual, seconds=info.seconds,
+                    history=hist)
+        return (out[0] if nr == 1 else out), meta
+
+    def eval_field(self, src, beta, rcv):
+        s = np.ascontiguousarray(src, dtype=np.float64)
+        b = _carr(beta)
+        r = np.ascontiguousarray(rcv, dtype=np.float64)
+        u = np.empty(r.shape[0], np.complex128)
+        self._check(self.lib.mpsl_eval_field(self.h, s.ctypes.data, b.ctypes.data, int(r.shape[0]),
+                                             r.ctypes.data, u.ctypes.data), allow=(-8,))
+        return u
+
+    def profile(self, enable=True):
+        return self._check(self.lib.mpsl_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms, cnt = ctypes.c_double(), ctypes.c_int()
+        self._check(self.lib.mpsl_profile_read(self.h, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value

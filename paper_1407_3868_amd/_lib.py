@@ -1,0 +1,100 @@
+"""ctypes loader of libmpsl.so and the C signatures of include/mpsl.h.
+
+The shared library is built in-tree by ``paper_1407_3868_amd/build.py``.
+Loading fails loudly when it is missing: there is no fallback path.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpsl.so")
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("tol", ctypes.c_double), ("maxiter", ctypes.c_int),
+                ("restart", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("fp64_matvecs", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+
+
+P = ctypes.c_void_p
+I = ctypes.c_int
+D = ctypes.c_double
+L = ctypes.c_int64
+DP = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes), in header order
+SIGNATURES = {
+    "mpsl_status_string": (ctypes.c_char_p, [I]),
+    "mpsl_last_error": (ctypes.c_char_p, [P]),
+    "mpsl_create": (I, [ctypes.POINTER(P), I]),
+    "mpsl_destroy": (None, [P]),
+    "mpsl_set_stream": (I, [P, P]),
+    "mpsl_set_layers": (I, [P, c128, c128, c128, D]),
+    "mpsl_set_particle_disk": (I, [P, D, c128, I]),
+    "mpsl_set_scattering_matrix": (I, [P, I, D, P]),
+    "mpsl_set_geometry": (I, [P, L, P, P]),
+    "mpsl_set_contour": (I, [P, I, D, D]),
+    "mpsl_set_contour_nodes": (I, [P, I, P, P]),
+    "mpsl_get_contour": (I, [P, I, P, P]),
+    "mpsl_get_scattering_matrix": (I, [P, I, P]),
+    "mpsl_get_sizes": (I, [P, ctypes.POINTER(L), ctypes.POINTER(I), ctypes.POINTER(I)]),
+    "mpsl_apply": (I, [P, I, P, P]),
+    "mpsl_apply_dev": (I, [P, I, P, P]),
+    "mpsl_m2l_dev": (I, [P, I, P, P]),
+    "mpsl_m2s_dev": (I, [P, I, P, P]),
+    "mpsl_reflect_dev": (I, [P, P, P, P]),
+    "mpsl_s2l_dev": (I, [P, I, P, P]),
+    "mpsl_sapply_dev": (I, [P, I, P, P, P]),
+    "mpsl_rhs": (I, [P, P, P]),
+    "mpsl_solve": (I, [P, I, P, ctypes.POINTER(Opts), P, ctypes.POINTER(Info)]),
+    "mpsl_eval_field": (I, [P, P, P, L, P, P]),
+    "mpsl_profile": (I, [P, I]),
+    "mpsl_profile_read": (I, [P, DP, ctypes.POINTER(I)]),
+}
+
+_lib = None
+
+
+def _hip_runtimes():
+    """Paths of every HIP runtime library mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64.so" in ln})
+    except OSError:
+        return []
+
+
+def load():
+    """Load libmpsl.so once; raise ImportError when it has not been built.
+
+    torch is imported first: its HIP runtime carries the same soname as the
+    one libmpsl.so was linked against, so the library binds to the runtime
+    already in the process and torch tensors, streams and the library's
+    kernels share one HIP runtime.  Two runtimes in one process are refused.
+    """
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.isfile(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_1407_3868_amd/build.py (hipcc, gfx950)")
+    import torch  # noqa: F401  (loads the process's HIP runtime)
+    lib = ctypes.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes are mapped into this process: {rts}")
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

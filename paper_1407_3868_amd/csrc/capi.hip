@@ -1,0 +1,663 @@
+// C ABI of the mpsl library: context, problem setup (contour, Mie matrix,
+// device tables) and the matvec and its steps.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kernels.h"
+
+using mpsl::DBuf;
+using mpsl::zc;
+
+namespace mpsl {
+
+int set_err(mpsl_ctx *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes) {
+  if (bytes <= b.bytes && b.p) return MPSL_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (bytes == 0) return MPSL_OK;
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return set_err(ctx, MPSL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  b.bytes = bytes;
+  return MPSL_OK;
+}
+
+void dev_free(DBuf &b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+namespace {
+
+// 16-point Gauss-Legendre rule on [-1, 1] by Newton's method on P_16,
+// ascending, symmetrised.
+void gauss_legendre16(double *x, double *w) {
+  const int n = 16;
+  for (int i = 0; i < n / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    x[n - 1 - i] = z;  // z > 0 here
+    x[i] = -z;
+    w[n - 1 - i] = wi;
+    w[i] = wi;
+  }
+}
+
+// Panel end points on [0, t_max] for Gamma_1 (rule stated in mpsl.h).
+bool panel_rule(int n_pan, double b, double t_max, const std::vector<double> &ks,
+                std::vector<std::pair<double, double>> &panels) {
+  std::vector<double> sing;
+  for (double k : ks)
+    if (k > 0.0 && k < t_max && std::find(sing.begin(), sing.end(), k) == sing.end()) sing.push_back(k);
+  std::sort(sing.begin(), sing.end());
+  std::vector<double> edges = {0.0, t_max};
+  for (double s : sing) edges.push_back(s);
+  std::sort(edges.begin(), edges.end());
+  panels.clear();
+  for (size_t i = 0; i + 1 < edges.size(); ++i) panels.emplace_back(edges[i], edges[i + 1]);
+  if (static_cast<int>(panels.size()) > n_pan) return false;
+  while (static_cast<int>(panels.size()) < n_pan) {
+    int best = -1;
+    double best_score = -1.0;
+    for (size_t i = 0; i < panels.size(); ++i) {
+      const double a = panels[i].first, c = panels[i].second;
+      const double len = c - a;
+      double dist = INFINITY;
+      for (double s : sing) {
+        const double dd = (s < a) ? (a - s) : ((s > c) ? (s - c) : 0.0);
+        dist = std::min(dist, dd);
+      }
+      const double score = len / std::max(dist, b);
+      // panels are kept sorted by left end, so the first maximum has the smallest a
+      if (score > best_score) {
+        best_score = score;
+        best = static_cast<int>(i);
+      }
+    }
+    const double a = panels[best].first, c = panels[best].second;
+    const double mid = (a + c) / 2.0;
+    panels.erase(panels.begin() + best);
+    panels.emplace_back(a, mid);
+    panels.emplace_back(mid, c);
+    std::sort(panels.begin(), panels.end());
+  }
+  return true;
+}
+
+// gamma = sqrt(lam^2 - k^2), Re >= 0, and Im <= 0 on Re == 0.
+zc gamma_branch(zc lam, zc k) {
+  zc g = std::sqrt(lam * lam - k * k);
+  if (g.real() < 0.0) g = -g;
+  if (g.real() == 0.0 && g.imag() > 0.0) g = -g;
+  return g;
+}
+
+// Bessel J_n, Y_n of real argument for n >= 0 (C library), and derivatives.
+void bessel_jy(int n, double x, double &j, double &y, double &jp, double &yp) {
+  j = jn(n, x);
+  y = yn(n, x);
+  const double jm = (n == 0) ? -jn(1, x) : jn(n - 1, x);
+  const double ym = (n == 0) ? -yn(1, x) : yn(n - 1, x);
+  // Z_n' = Z_{n-1} - (n/x) Z_n
+  jp = (n == 0) ? -jn(1, x) : jm - n / x * j;
+  yp = (n == 0) ? -yn(1, x) : ym - n / x * y;
+}
+
+void invalidate(mpsl_ctx *ctx) { ctx->tables_ok = false; }
+
+}  // namespace
+
+// Contour tables (host, FP64) and geometry tables (device).
+int build_tables(mpsl_ctx *ctx) {
+  if (!ctx->has_layers || !ctx->has_particle || !ctx->has_geom || !ctx->has_contour)
+    return set_err(ctx, MPSL_ESTATE, "layers, particle, geometry and contour must all be set");
+  if (ctx->tables_ok) return MPSL_OK;
+  const int ns = ctx->ns;
+  const int p = ctx->p;
+  const int P = 2 * p + 1;
+  const int64_t n = ctx->n;
+  const zc k1 = ctx->k1, k2 = ctx->k2, k3 = ctx->k3;
+  const double d = ctx->d;
+  const zc I(0.0, 1.0);
+
+  std::vector<zc> R(4 * ns), sf(2 * ns), gw(4 * ns), cq(ns), W(2 * ns * P), U(2 * ns * P);
+  for (int q = 0; q < ns; ++q) {
+    const zc lam = ctx->lam[q];
+    const zc g1 = gamma_branch(lam, k1), g2 = gamma_branch(lam, k2), g3 = gamma_branch(lam, k3);
+    gw[q] = g1;
+    gw[ns + q] = g2;
+    gw[2 * ns + q] = g3;
+    gw[3 * ns + q] = ctx->w[q];
+    // closed-form solution of the 4x4 interface system for the middle-layer
+    // densities: sigma+ - r1 E sigma- = t g + r1 P+,  sigma- - r3 E sigma+ = r3 P-
+    const zc r1 = (g2 - g1) / (g2 + g1);
+    const zc r3 = (g2 - g3) / (g2 + g3);
+    const zc E = std::exp(-g2 * d);
+    const zc det = 1.0 - r1 * r3 * E * E;
+    const zc tg = 2.0 * g2 / (g1 + g2);
+    R[4 * q + 0] = r1 / det;
+    R[4 * q + 1] = r1 * r3 * E / det;
+    R[4 * q + 2] = r1 * r3 * E / det;
+    R[4 * q + 3] = r3 / det;
+    sf[2 * q + 0] = tg / det;
+    sf[2 * q + 1] = tg * r3 * E / det;
+    cq[q] = ctx->w[q] / (4.0 * M_PI * g2);
+    // u = (lam - g2)/k2 and v = (lam + g2)/k2 = 1/u; take the larger of lam +- g2
+    // directly and the other as k2^2 / (...) to avoid cancellation.
+    zc u, v;
+    if (std::abs(lam + g2) >= std::abs(lam - g2)) {
+      v = (lam + g2) / k2;
+      u = k2 / (lam + g2);
+    } else {
+      u = (lam - g2) / k2;
+      v = k2 / (lam - g2);
+    }
+    // powers u^nu, v^nu for nu = -p..p by repeated multiplication from nu = 0
+    std::vector<zc> up(P), vp(P);
+    up[p] = vp[p] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+      up[p + j] = up[p + j - 1] * u;
+      up[p - j] = up[p - j + 1] * v;
+      vp[p + j] = vp[p + j - 1] * v;
+      vp[p - j] = vp[p - j + 1] * u;
+    }
+    for (int j = 0; j < P; ++j) {
+      const int nu = j - p;
+      // (-i)^nu and i^nu
+      const zc mi = std::pow(-I, nu), pi = std::pow(I, nu);
+      W[(0 * ns + q) * P + j] = -4.0 * I * mi * up[j];
+      W[(1 * ns + q) * P + j] = -4.0 * I * mi * vp[j];
+      U[(0 * ns + q) * P + j] = pi * up[j];
+      U[(1 * ns + q) * P + j] = pi * vp[j];
+    }
+  }
+  auto up64 = [&](DBuf &b, const std::vector<zc> &v) -> int {
+    int rc = dev_alloc(ctx, b, v.size() * sizeof(double2));
+    if (rc) return rc;
+    MPSL_HIP_TRY(ctx, hipMemcpy(b.p, v.data(), v.size() * sizeof(double2), hipMemcpyHostToDevice));
+    return MPSL_OK;
+  };
+  auto up32 = [&](DBuf &b, const std::vector<zc> &v) -> int {
+    std::vector<float2> f(v.size());
+    for (size_t i = 0; i < v.size(); ++i)
+      f[i] = make_float2(static_cast<float>(v[i].real()), static_cast<float>(v[i].imag()));
+    int rc = dev_alloc(ctx, b, f.size() * sizeof(float2));
+    if (rc) return rc;
+    MPSL_HIP_TRY(ctx, hipMemcpy(b.p, f.data(), f.size() * sizeof(float2), hipMemcpyHostToDevice));
+    return MPSL_OK;
+  };
+  int rc;
+  if ((rc = up64(ctx->ct.R, R)) || (rc = up64(ctx->ct.srcfac, sf)) || (rc = up64(ctx->ct.lam, ctx->lam)) ||
+      (rc = up64(ctx->ct.gw, gw)) || (rc = up64(ctx->ct.cq, cq)) || (rc = up64(ctx->ct.W64, W)) ||
+      (rc = up32(ctx->ct.W32, W)) || (rc = up64(ctx->ct.U64, U)))
+    return rc;
+
+  // rotation phases e^{i n psi_l}
+  std::vector<zc> rot(static_cast<size_t>(n) * P);
+  for (int64_t l = 0; l < n; ++l)
+    for (int j = 0; j < P; ++j) {
+      const double a = (j - p) * ctx->rot[l];
+      rot[l * P + j] = zc(std::cos(a), std::sin(a));
+    }
+  if ((rc = up64(ctx->gt.rot64, rot)) || (rc = up32(ctx->gt.rot32, rot))) return rc;
+
+  const size_t tab = 2ull * static_cast<size_t>(n) * ns;
+  if ((rc = dev_alloc(ctx, ctx->gt.E64, tab * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->gt.F64, tab * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->gt.E32, tab * sizeof(float2))) ||
+      (rc = dev_alloc(ctx, ctx->gt.F32, tab * sizeof(float2))))
+    return rc;
+  if ((rc = launch_geom_tables(ctx))) return rc;
+  if (!ctx->gt.pairs_ok) {
+    const size_t np = static_cast<size_t>(n) * static_cast<size_t>(n) * 4;
+    if ((rc = dev_alloc(ctx, ctx->gt.pair64, np * sizeof(double2))) ||
+        (rc = dev_alloc(ctx, ctx->gt.pair32, np * sizeof(float2))))
+      return rc;
+    if ((rc = launch_pair_tables(ctx))) return rc;
+    ctx->gt.pairs_ok = true;
+  }
+  MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  ctx->tables_ok = true;
+  return ensure_work(ctx);
+}
+
+int ensure_work(mpsl_ctx *ctx) {
+  const int P = 2 * ctx->p + 1;
+  const size_t len = static_cast<size_t>(ctx->n) * P;
+  const int ca = chunks_m2l(ctx), cb = chunks_s2l(ctx), cc = chunks_m2s(ctx);
+  int rc;
+  if ((rc = dev_alloc(ctx, ctx->part, (ca + cb) * len * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->m2s_part, 2ull * cc * ctx->ns * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->spec, 2ull * ctx->ns * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->sigma, 4ull * ctx->ns * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->Up64, 2ull * ctx->ns * P * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->Up32, 2ull * ctx->ns * P * sizeof(float2))) ||
+      (rc = dev_alloc(ctx, ctx->scal, 64ull * 1024 * sizeof(double2))))
+    return rc;
+  return MPSL_OK;
+}
+
+// y = x - S (T + T_R) x on device buffers.
+int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y) {
+  int rc = build_tables(ctx);
+  if (rc) return rc;
+  const int ca = chunks_m2l(ctx), cb = chunks_s2l(ctx);
+  const int P = 2 * ctx->p + 1;
+  const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
+  char *part = static_cast<char *>(ctx->part.p);
+  char *part_b = part + static_cast<size_t>(ca) * ctx->n * P * esz;
+  if ((rc = launch_m2s(ctx, prec, x, ctx->spec.p))) return rc;
+  if ((rc = launch_reflect(ctx, ctx->spec.p, nullptr, ctx->sigma.p))) return rc;
+  if ((rc = launch_s2l_coef(ctx, ctx->sigma.p))) return rc;
+  if ((rc = launch_s2l(ctx, prec, part_b, cb))) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->prof) {
+    MPSL_HIP_TRY(ctx, hipEventCreate(&e0));
+    MPSL_HIP_TRY(ctx, hipEventCreate(&e1));
+    MPSL_HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
+  }
+  if ((rc = launch_m2l(ctx, prec, x, part, ca))) return rc;
+  if (ctx->prof) {
+    MPSL_HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
+    ctx->ev_start.push_back(e0);
+    ctx->ev_stop.push_back(e1);
+  }
+  return launch_sapply(ctx, prec, x, part, ca + cb, y);
+}
+
+}  // namespace mpsl
+
+// ===========================================================================
+extern "C" {
+
+const char *mpsl_status_string(int s) {
+  switch (s) {
+    case MPSL_OK: return "ok";
+    case MPSL_EINVAL: return "invalid argument";
+    case MPSL_ENOMEM: return "out of memory";
+    case MPSL_EHIP: return "HIP runtime error";
+    case MPSL_ESTATE: return "missing setup call";
+    case MPSL_EGEOM: return "invalid geometry";
+    case MPSL_ENOCONV: return "GMRES did not converge";
+    case MPSL_EUNSUPPORTED: return "unsupported parameters";
+    case MPSL_EINSIDE: return "receiver inside an enclosing disk";
+    case MPSL_ENUMERIC: return "non-finite value in iteration";
+    default: return "unknown status";
+  }
+}
+
+const char *mpsl_last_error(const mpsl_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int mpsl_create(mpsl_ctx **out, int device) {
+  if (!out) return MPSL_EINVAL;
+  *out = nullptr;
+  int cnt = 0;
+  if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0) {
+    (void)hipGetLastError();
+    return MPSL_EHIP;
+  }
+  if (device < 0 || device >= cnt) return MPSL_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return MPSL_EHIP;
+  mpsl_ctx *ctx = new (std::nothrow) mpsl_ctx();
+  if (!ctx) return MPSL_ENOMEM;
+  ctx->device = device;
+  *out = ctx;
+  return MPSL_OK;
+}
+
+void mpsl_destroy(mpsl_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
+  for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
+  DBuf *bufs[] = {&ctx->S64, &ctx->S32, &ctx->ct.R, &ctx->ct.srcfac, &ctx->ct.lam, &ctx->ct.gw,
+                  &ctx->ct.cq, &ctx->ct.W64, &ctx->ct.W32, &ctx->ct.U64, &ctx->gt.xy, &ctx->gt.rot64,
+                  &ctx->gt.rot32, &ctx->gt.pair64, &ctx->gt.pair32, &ctx->gt.E64, &ctx->gt.E32, &ctx->gt.F64, &ctx->gt.F32, &ctx->part,
+                  &ctx->m2s_part, &ctx->spec, &ctx->sigma, &ctx->Up64, &ctx->Up32, &ctx->xbuf,
+                  &ctx->ybuf, &ctx->gm, &ctx->scal};
+  for (DBuf *b : bufs) mpsl::dev_free(*b);
+  delete ctx;
+}
+
+int mpsl_set_stream(mpsl_ctx *ctx, void *stream) {
+  if (!ctx) return MPSL_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return MPSL_OK;
+}
+
+int mpsl_set_layers(mpsl_ctx *ctx, mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, double d) {
+  if (!ctx) return MPSL_EINVAL;
+  const mpsl_c128 ks[3] = {k1, k2, k3};
+  for (const auto &k : ks) {
+    if (!(k.re > 0.0) || !(k.im >= 0.0) || !std::isfinite(k.re) || !std::isfinite(k.im))
+      return mpsl::set_err(ctx, MPSL_EINVAL, "wavenumbers need Re k > 0 and Im k >= 0");
+    if (k.im != 0.0)
+      return mpsl::set_err(ctx, MPSL_EUNSUPPORTED, "this build supports real layer wavenumbers only");
+  }
+  if (!(d > 0.0) || !std::isfinite(d)) return mpsl::set_err(ctx, MPSL_EINVAL, "layer thickness must be > 0");
+  ctx->k1 = zc(k1.re, k1.im);
+  ctx->k2 = zc(k2.re, k2.im);
+  ctx->k3 = zc(k3.re, k3.im);
+  ctx->d = d;
+  ctx->has_layers = true;
+  ctx->gt.pairs_ok = false;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+static int upload_S(mpsl_ctx *ctx) {
+  const size_t PP = ctx->S.size();
+  std::vector<float2> f(PP);
+  for (size_t i = 0; i < PP; ++i)
+    f[i] = make_float2(static_cast<float>(ctx->S[i].real()), static_cast<float>(ctx->S[i].imag()));
+  int rc;
+  if ((rc = mpsl::dev_alloc(ctx, ctx->S64, PP * sizeof(double2))) ||
+      (rc = mpsl::dev_alloc(ctx, ctx->S32, PP * sizeof(float2))))
+    return rc;
+  MPSL_HIP_TRY(ctx, hipMemcpy(ctx->S64.p, ctx->S.data(), PP * sizeof(double2), hipMemcpyHostToDevice));
+  MPSL_HIP_TRY(ctx, hipMemcpy(ctx->S32.p, f.data(), PP * sizeof(float2), hipMemcpyHostToDevice));
+  return MPSL_OK;
+}
+
+int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
+  if (!ctx) return MPSL_EINVAL;
+  if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
+  if (!(R > 0.0) || !(kp.re > 0.0) || p < mpsl::kMinP || p > mpsl::kMaxP)
+    return mpsl::set_err(ctx, MPSL_EINVAL, "disk needs R > 0, kp > 0 and 1 <= p <= 20");
+  if (kp.im != 0.0) return mpsl::set_err(ctx, MPSL_EUNSUPPORTED, "disk particles need a real kp");
+  const int P = 2 * p + 1;
+  const double k2 = ctx->k2.real(), kpr = kp.re;
+  std::vector<zc> S(static_cast<size_t>(P) * P, zc(0.0, 0.0));
+  for (int n = 0; n <= p; ++n) {
+    double ja, ya, jap, yap, jb, yb, jbp, ybp;
+    mpsl::bessel_jy(n, k2 * R, ja, ya, jap, yap);
+    mpsl::bessel_jy(n, kpr * R, jb, yb, jbp, ybp);
+    const zc H(ja, ya), Hp(jap, yap);
+    // eq. (18): beta_n / alpha_n (denominator with J_n(kp R))
+    const zc num = kpr * ja * jbp - k2 * jap * jb;
+    const zc den = k2 * Hp * jb - kpr * jbp * H;
+    const zc s = num / den;
+    S[static_cast<size_t>(p + n) * P + (p + n)] = s;
+    S[static_cast<size_t>(p - n) * P + (p - n)] = s;  // S_{-n} = S_n
+  }
+  ctx->p = p;
+  ctx->r_enc = R;
+  ctx->S = S;
+  int rc = upload_S(ctx);
+  if (rc) return rc;
+  ctx->has_particle = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_set_scattering_matrix(mpsl_ctx *ctx, int p, double r_enclose, const mpsl_c128 *S) {
+  if (!ctx || !S) return MPSL_EINVAL;
+  if (p < mpsl::kMinP || p > mpsl::kMaxP || !(r_enclose > 0.0))
+    return mpsl::set_err(ctx, MPSL_EINVAL, "need 1 <= p <= 20 and r_enclose > 0");
+  const int P = 2 * p + 1;
+  ctx->S.resize(static_cast<size_t>(P) * P);
+  for (size_t i = 0; i < ctx->S.size(); ++i) {
+    if (!std::isfinite(S[i].re) || !std::isfinite(S[i].im))
+      return mpsl::set_err(ctx, MPSL_EINVAL, "scattering matrix has non-finite entries");
+    ctx->S[i] = zc(S[i].re, S[i].im);
+  }
+  ctx->p = p;
+  ctx->r_enc = r_enclose;
+  int rc = upload_S(ctx);
+  if (rc) return rc;
+  ctx->has_particle = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *rot) {
+  if (!ctx || !xy || n <= 0) return MPSL_EINVAL;
+  if (!ctx->has_layers || !ctx->has_particle) return mpsl::set_err(ctx, MPSL_ESTATE, "layers and particle first");
+  if (n > (int64_t(1) << 30)) return mpsl::set_err(ctx, MPSL_EINVAL, "too many particles");
+  const double R = ctx->r_enc, d = ctx->d;
+  for (int64_t j = 0; j < n; ++j) {
+    const double x = xy[2 * j], y = xy[2 * j + 1];
+    if (!std::isfinite(x) || !std::isfinite(y) || (rot && !std::isfinite(rot[j])))
+      return mpsl::set_err(ctx, MPSL_EINVAL, "non-finite centre or rotation");
+    if (y + R > 0.0 || y - R < -d)
+      return mpsl::set_err(ctx, MPSL_EGEOM, "particle " + std::to_string(j) + " leaves the middle layer");
+  }
+  // enclosing disks must be disjoint: sweep in x
+  std::vector<int64_t> ord(n);
+  for (int64_t j = 0; j < n; ++j) ord[j] = j;
+  std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return xy[2 * a] < xy[2 * b]; });
+  for (int64_t a = 0; a < n; ++a) {
+    const int64_t i = ord[a];
+    for (int64_t b = a + 1; b < n; ++b) {
+      const int64_t j = ord[b];
+      const double dx = xy[2 * j] - xy[2 * i];
+      if (dx >= 2.0 * R) break;
+      const double dy = xy[2 * j + 1] - xy[2 * i + 1];
+      if (dx * dx + dy * dy < 4.0 * R * R)
+        return mpsl::set_err(ctx, MPSL_EGEOM,
+                             "enclosing disks of particles " + std::to_string(i) + " and " + std::to_string(j) +
+                                 " overlap");
+    }
+  }
+  ctx->n = n;
+  ctx->xy.assign(xy, xy + 2 * n);
+  ctx->rot.assign(static_cast<size_t>(n), 0.0);
+  if (rot) ctx->rot.assign(rot, rot + n);
+  int rc = mpsl::dev_alloc(ctx, ctx->gt.xy, static_cast<size_t>(n) * sizeof(double2));
+  if (rc) return rc;
+  MPSL_HIP_TRY(ctx, hipMemcpy(ctx->gt.xy.p, xy, static_cast<size_t>(n) * sizeof(double2), hipMemcpyHostToDevice));
+  ctx->has_geom = true;
+  ctx->gt.pairs_ok = false;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max) {
+  if (!ctx) return MPSL_EINVAL;
+  if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
+  if (n_nodes < 96 || (n_nodes - 32) % 32 != 0 || !(b > 0.0) || !(t_max > 0.0))
+    return mpsl::set_err(ctx, MPSL_EINVAL, "n_nodes = 32 + 32 m (m >= 2), b > 0, t_max > 0");
+  double gx[16], gwt[16];
+  mpsl::gauss_legendre16(gx, gwt);
+  std::vector<std::pair<double, double>> pan;
+  const std::vector<double> ks = {ctx->k1.real(), ctx->k2.real(), ctx->k3.real()};
+  if (!mpsl::panel_rule((n_nodes - 32) / 32, b, t_max, ks, pan))
+    return mpsl::set_err(ctx, MPSL_EINVAL, "too few nodes for the branch-point breakpoints");
+  std::vector<double> t1, w1;
+  for (const auto &pc : pan) {
+    const double a = pc.first, c = pc.second;
+    for (int i = 0; i < 16; ++i) {
+      t1.push_back((a + c) / 2.0 + (c - a) / 2.0 * gx[i]);
+      w1.push_back((c - a) / 2.0 * gwt[i]);
+    }
+  }
+  const int n1 = static_cast<int>(t1.size());
+  std::vector<zc> lam, w;
+  lam.reserve(n_nodes);
+  w.reserve(n_nodes);
+  for (int i = n1 - 1; i >= 0; --i) {  // Gamma_3: mirror of Gamma_1, path order
+    lam.emplace_back(-t1[i], b);
+    w.emplace_back(w1[i], 0.0);
+  }
+  for (int h = 0; h < 2; ++h)  // Gamma_2: lambda = -i s, s in [-b, 0] then [0, b]
+    for (int i = 0; i < 16; ++i) {
+      const double s = (h == 0 ? -b / 2.0 : b / 2.0) + b / 2.0 * gx[i];
+      lam.emplace_back(0.0, -s);
+      w.emplace_back(0.0, -b / 2.0 * gwt[i]);
+    }
+  for (int i = 0; i < n1; ++i) {
+    lam.emplace_back(t1[i], -b);
+    w.emplace_back(w1[i], 0.0);
+  }
+  ctx->lam = lam;
+  ctx->w = w;
+  ctx->ns = n_nodes;
+  ctx->has_contour = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_set_contour_nodes(mpsl_ctx *ctx, int n_nodes, const mpsl_c128 *lam, const mpsl_c128 *w) {
+  if (!ctx || !lam || !w || n_nodes <= 0) return MPSL_EINVAL;
+  ctx->lam.resize(n_nodes);
+  ctx->w.resize(n_nodes);
+  for (int i = 0; i < n_nodes; ++i) {
+    ctx->lam[i] = zc(lam[i].re, lam[i].im);
+    ctx->w[i] = zc(w[i].re, w[i].im);
+  }
+  ctx->ns = n_nodes;
+  ctx->has_contour = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_get_contour(const mpsl_ctx *ctx, int n_nodes, mpsl_c128 *lam, mpsl_c128 *w) {
+  if (!ctx || !ctx->has_contour || n_nodes != ctx->ns) return MPSL_EINVAL;
+  for (int i = 0; i < n_nodes; ++i) {
+    if (lam) lam[i] = {ctx->lam[i].real(), ctx->lam[i].imag()};
+    if (w) w[i] = {ctx->w[i].real(), ctx->w[i].imag()};
+  }
+  return MPSL_OK;
+}
+
+int mpsl_get_scattering_matrix(const mpsl_ctx *ctx, int p, mpsl_c128 *S) {
+  if (!ctx || !S || !ctx->has_particle || p != ctx->p) return MPSL_EINVAL;
+  for (size_t i = 0; i < ctx->S.size(); ++i) S[i] = {ctx->S[i].real(), ctx->S[i].imag()};
+  return MPSL_OK;
+}
+
+int mpsl_get_sizes(const mpsl_ctx *ctx, int64_t *n, int *p, int *n_nodes) {
+  if (!ctx) return MPSL_EINVAL;
+  if (n) *n = ctx->n;
+  if (p) *p = ctx->p;
+  if (n_nodes) *n_nodes = ctx->ns;
+  return MPSL_OK;
+}
+
+int mpsl_apply_dev(mpsl_ctx *ctx, int prec, const void *x, void *y) {
+  if (!ctx || !x || !y || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return mpsl::matvec(ctx, prec, x, y);
+}
+
+int mpsl_apply(mpsl_ctx *ctx, int prec, const void *x, void *y) {
+  if (!ctx || !x || !y || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  const size_t bytes = static_cast<size_t>(ctx->n) * (2 * ctx->p + 1) *
+                       (prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2));
+  if ((rc = mpsl::dev_alloc(ctx, ctx->xbuf, bytes)) || (rc = mpsl::dev_alloc(ctx, ctx->ybuf, bytes))) return rc;
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(ctx->xbuf.p, x, bytes, hipMemcpyHostToDevice, ctx->stream));
+  if ((rc = mpsl::matvec(ctx, prec, ctx->xbuf.p, ctx->ybuf.p))) return rc;
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(y, ctx->ybuf.p, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return MPSL_OK;
+}
+
+int mpsl_m2l_dev(mpsl_ctx *ctx, int prec, const void *beta, void *alpha) {
+  if (!ctx || !beta || !alpha || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  const int ca = mpsl::chunks_m2l(ctx);
+  if ((rc = mpsl::launch_m2l(ctx, prec, beta, ctx->part.p, ca))) return rc;
+  return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, ca, alpha);
+}
+
+int mpsl_m2s_dev(mpsl_ctx *ctx, int prec, const void *beta, void *spec) {
+  if (!ctx || !beta || !spec || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  return mpsl::launch_m2s(ctx, prec, beta, spec);
+}
+
+int mpsl_reflect_dev(mpsl_ctx *ctx, const void *spec, const double *src, void *sigma) {
+  if (!ctx || !sigma || (!spec && !src)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  return mpsl::launch_reflect(ctx, spec, src, sigma);
+}
+
+int mpsl_s2l_dev(mpsl_ctx *ctx, int prec, const void *sigma, void *alpha) {
+  if (!ctx || !sigma || !alpha || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  const int cb = mpsl::chunks_s2l(ctx);
+  if ((rc = mpsl::launch_s2l_coef(ctx, sigma))) return rc;
+  if ((rc = mpsl::launch_s2l(ctx, prec, ctx->part.p, cb))) return rc;
+  return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, cb, alpha);
+}
+
+int mpsl_sapply_dev(mpsl_ctx *ctx, int prec, const void *x, const void *alpha, void *y) {
+  if (!ctx || !alpha || !y || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  return mpsl::launch_sapply(ctx, prec, x, alpha, 1, y);
+}
+
+int mpsl_profile(mpsl_ctx *ctx, int enable) {
+  if (!ctx) return MPSL_EINVAL;
+  for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
+  for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
+  ctx->ev_start.clear();
+  ctx->ev_stop.clear();
+  ctx->prof = enable != 0;
+  return MPSL_OK;
+}
+
+int mpsl_profile_read(mpsl_ctx *ctx, double *ms_avg, int *count) {
+  if (!ctx) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  int c = 0;
+  for (size_t i = 0; i < ctx->ev_start.size(); ++i) {
+    float ms = 0.f;
+    MPSL_HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev_start[i], ctx->ev_stop[i]));
+    tot += ms;
+    ++c;
+  }
+  if (ms_avg) *ms_avg = c ? tot / c : 0.0;
+  if (count) *count = c;
+  return MPSL_OK;
+}
+
+}  // extern "C"

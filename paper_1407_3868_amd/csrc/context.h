@@ -1,0 +1,103 @@
+// Internal state of an mpsl context: host copies of the problem, device
+// tables and work buffers.
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace mpsl {
+
+using zc = std::complex<double>;
+
+// A growable device allocation owned by the context.
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Device tables derived from the contour alone (FP64 master + FP32 copy).
+struct ContourTables {
+  // per node q: 2x2 reflection map and source factors (FP64), weights c_q
+  DBuf R;        // double2[4 * ns]: R11, R12, R21, R22
+  DBuf srcfac;   // double2[2 * ns]: sigma2+/- per unit source density g_q
+  DBuf lam;      // double2[ns]
+  DBuf gw;       // double2[4 * ns]: g1, g2, g3 (branch Re >= 0), w
+  DBuf cq;       // double2[ns]: w_q / (4 pi g2_q)
+  DBuf W64, W32; // [2][ns][P]: -4i (-i)^nu u^nu (side +), with v for side -
+  DBuf U64;      // double2 [2][ns][P]: i^n u^n, i^n v^n (S2L, before sigma)
+};
+
+// Device tables derived from geometry and contour.
+struct GeomTables {
+  DBuf xy;              // double2[n]
+  DBuf rot64, rot32;    // [n][P] e^{i n psi_l}
+  DBuf E64, E32;        // [2][n][ns]: e^{-i lam x_m + g2 y_m}, e^{-i lam x_m - g2 (d + y_m)}
+  DBuf F64, F32;        // [2][ns][n]: e^{ i lam x_l + g2 y_l}, e^{ i lam x_l - g2 (y_l + d)}
+  DBuf pair64, pair32;  // [m][l][4]: H_0, H_1, e^{i phi}, (2/z, 0) of the pair x_l - x_m
+  bool pairs_ok = false;
+};
+
+}  // namespace mpsl
+
+struct mpsl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // layers
+  bool has_layers = false;
+  mpsl::zc k1, k2, k3;
+  double d = 0.0;
+
+  // particle
+  bool has_particle = false;
+  int p = 0;
+  double r_enc = 0.0;
+  std::vector<mpsl::zc> S;  // P x P row-major
+  mpsl::DBuf S64, S32;
+
+  // geometry
+  bool has_geom = false;
+  int64_t n = 0;
+  std::vector<double> xy, rot;
+
+  // contour
+  bool has_contour = false;
+  int ns = 0;
+  std::vector<mpsl::zc> lam, w;
+
+  bool tables_ok = false;  // contour + geometry tables current
+  mpsl::ContourTables ct;
+  mpsl::GeomTables gt;
+
+  // work buffers
+  mpsl::DBuf part;        // M2L + S2L partial local expansions
+  mpsl::DBuf m2s_part;    // M2S partial spectra
+  mpsl::DBuf spec;        // double2[2 * ns]
+  mpsl::DBuf sigma;       // double2[2 * ns]
+  mpsl::DBuf Up64, Up32;  // [2][ns][P]: S2L coefficients scaled by c_q sigma
+  mpsl::DBuf xbuf, ybuf;  // host-pointer apply staging
+  mpsl::DBuf gm;          // GMRES workspace
+  mpsl::DBuf scal;        // reductions
+
+  // launch shapes
+  int m2l_chunks = 0;     // source chunks of the M2L grid (0: automatic)
+  int s2l_chunks = 0;
+  int m2s_chunks = 0;
+
+  // profiling of the M2L kernel
+  bool prof = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<double> hist;
+};
+
+namespace mpsl {
+int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes);
+void dev_free(DBuf &b);
+int set_err(mpsl_ctx *ctx, int code, const std::string &msg);
+int build_tables(mpsl_ctx *ctx);
+int ensure_work(mpsl_ctx *ctx);
+}  // namespace mpsl

@@ -1,0 +1,51 @@
+// Launchers of the device kernels (implemented in kernels.hip).
+#pragma once
+
+#include "context.h"
+
+namespace mpsl {
+
+// Largest supported expansion order and the range instantiated.
+constexpr int kMinP = 1;
+constexpr int kMaxP = 20;
+
+// Row a0: per-particle plane-wave factor tables of the contour (E, F) and
+// rotation phases.  FP64 master tables and FP32 copies.
+int launch_geom_tables(mpsl_ctx *ctx);
+// Row a0 (pairs): H_0, H_1, direction and 2/z of every ordered particle pair.
+int launch_pair_tables(mpsl_ctx *ctx);
+
+// Row a1: partial local expansions of the all-pairs M2L into part[0 .. chunks).
+int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks);
+// Row b1: M2S partial spectra and their reduction to spec (double2[2*ns]).
+int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec);
+// Row b2: sigma = R spec (+ source), and the scaled S2L coefficient tables.
+int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sigma);
+// S2L coefficient tables from sigma (both precisions).
+int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma);
+// Row b3: partial local expansions of the layer field into part[0 .. chunks).
+int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks);
+// Sum of partial buffers: alpha = sum_{c < chunks} part[c].
+int launch_sum_parts(mpsl_ctx *ctx, int prec, const void *part, int chunks, void *alpha);
+// Row a2: y = x - S_rot (sum of partials)  (x may be null: y = S_rot alpha).
+int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y);
+
+// GMRES helpers (FP64 complex vectors of length len).
+int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *w, int64_t len,
+                      void *h_out);
+int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *h, void *w,
+                    int64_t len);
+int launch_scale(mpsl_ctx *ctx, void *v, int64_t len, double s, const void *src);
+int launch_axpy_c(mpsl_ctx *ctx, void *y, const void *x, int64_t len, double a_re, double a_im);
+int launch_to_fp32(mpsl_ctx *ctx, const void *x64, void *x32, int64_t len);
+int launch_to_fp64(mpsl_ctx *ctx, const void *x32, void *x64, int64_t len);
+
+// Row a7: field at receivers.  sig4: double2[4][ns] (sigma_1, sigma_2^+, sigma_2^-, sigma_3).
+int launch_field(mpsl_ctx *ctx, const void *beta, const void *sig4, const double *src, int64_t nr,
+                 const void *rcv, void *u);
+
+int chunks_m2l(const mpsl_ctx *ctx);
+int chunks_s2l(const mpsl_ctx *ctx);
+int chunks_m2s(const mpsl_ctx *ctx);
+
+}  // namespace mpsl

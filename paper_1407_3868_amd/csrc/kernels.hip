@@ -1,0 +1,767 @@
+// Device kernels of the layered-medium multiple-scattering matvec.
+//
+// Layouts (row-major, complex interleaved):
+//   beta, alpha, x, y   [n][P]                 P = 2p + 1, slot n + p
+//   part                [chunk][n][P]          partial local expansions
+//   E (M2S factors)     [2][n][ns]             side 0: upper interface, 1: lower
+//   F (S2L factors)     [2][ns][n]
+//   W (M2S order sums)  [2][ns][P]
+//   Up (S2L coeffs)     [2][ns][P]
+//   spec, sigma         [2][ns]                FP64
+#include <cmath>
+
+#include "kernels.h"
+
+namespace mpsl {
+
+namespace {
+
+constexpr int kThreads = 128;
+
+inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// complex exp(a + i b) in FP64
+__device__ inline cx<double> cexp_d(double a, double b) {
+  double s, c;
+  sincos(b, &s, &c);
+  const double e = exp(a);
+  return {e * c, e * s};
+}
+
+// ---------------------------------------------------------------------------
+// Row a0: plane-wave factors of every (particle, node) pair.
+//   E+[m][q] = e^{-i lam x_m + g2 y_m}          E-[m][q] = e^{-i lam x_m - g2 (d + y_m)}
+//   F+[q][l] = e^{ i lam x_l + g2 y_l}          F-[q][l] = e^{ i lam x_l - g2 (y_l + d)}
+__global__ void k_geom_tables(const double2 *__restrict__ xy, const double2 *__restrict__ lam,
+                              const double2 *__restrict__ g2, int n, int ns, double d,
+                              double2 *__restrict__ E, double2 *__restrict__ F,
+                              float2 *__restrict__ E32, float2 *__restrict__ F32) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t tot = static_cast<int64_t>(n) * ns;
+  if (idx >= tot) return;
+  const int m = static_cast<int>(idx / ns);
+  const int q = static_cast<int>(idx % ns);
+  const double x = xy[m].x, y = xy[m].y;
+  const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
+  const cx<double> ep = cexp_d(li * x + gr * y, -lr * x + gi * y);
+  const cx<double> em = cexp_d(li * x - gr * (d + y), -lr * x - gi * (d + y));
+  const cx<double> fp = cexp_d(-li * x + gr * y, lr * x + gi * y);
+  const cx<double> fm = cexp_d(-li * x - gr * (y + d), lr * x - gi * (y + d));
+  const int64_t e0 = static_cast<int64_t>(m) * ns + q;
+  const int64_t f0 = static_cast<int64_t>(q) * n + m;
+  E[e0] = st(ep);
+  E[tot + e0] = st(em);
+  F[f0] = st(fp);
+  F[tot + f0] = st(fm);
+  E32[e0] = make_float2(static_cast<float>(ep.re), static_cast<float>(ep.im));
+  E32[tot + e0] = make_float2(static_cast<float>(em.re), static_cast<float>(em.im));
+  F32[f0] = make_float2(static_cast<float>(fp.re), static_cast<float>(fp.im));
+  F32[tot + f0] = make_float2(static_cast<float>(fm.re), static_cast<float>(fm.im));
+}
+
+// ---------------------------------------------------------------------------
+// Row a0 (pairs): per ordered pair (m -> l) the Hankel functions H_0, H_1 of
+// z = k2 |x_l - x_m|, the direction e^{i phi} = (x_l - x_m)/|x_l - x_m| and
+// 2/z, computed once per geometry in FP64 and stored source-major
+// [m][l][4] = {H_0, H_1, e^{i phi}, (2/z, 0)} in FP64 and FP32.  The self
+// pair l == m holds zeros.
+__global__ void k_pair_tables(const double2 *__restrict__ xy, int n, double k2, double2 *__restrict__ t64,
+                              float2 *__restrict__ t32) {
+  const int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int m = static_cast<int>(idx / n);
+  const int l = static_cast<int>(idx % n);
+  double2 e[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                  make_double2(0.0, 0.0)};
+  if (l != m) {
+    const double dx = xy[l].x - xy[m].x, dy = xy[l].y - xy[m].y;
+    const double rho = sqrt(dx * dx + dy * dy);
+    const double z = k2 * rho;
+    e[0] = make_double2(j0(z), y0(z));
+    e[1] = make_double2(j1(z), y1(z));
+    e[2] = make_double2(dx / rho, dy / rho);
+    e[3] = make_double2(2.0 / z, 0.0);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    t64[4 * idx + k] = e[k];
+    t32[4 * idx + k] = make_float2(static_cast<float>(e[k].x), static_cast<float>(e[k].y));
+  }
+}
+
+// Row a1: all-pairs free-space M2L (Graf's addition theorem).
+// One lane per target l; every lane of the grid walks the same source chunk,
+// so the source's coefficients are wave-uniform and live in scalar registers.
+// Per pair: H_0, H_1 and e^{i phi} from the pair table, the upward recurrence
+// H_{q+1} = (2q/z) H_q - H_{q-1}, e^{iq phi} by repeated multiplication,
+// h_q = H_q e^{iq phi}, h_{-q} = (-1)^q H_q e^{-iq phi}, and the Toeplitz
+// product alpha_{n'} += sum_nu h_{nu - n'} beta_nu consumed in the order the
+// recurrence produces h_q.  The coefficient slots [NU0, NU1] of the source
+// are handled by one pass; FP64 runs two passes so that each half of beta
+// fits the scalar register file.
+template <typename T, int p, int NU0, int NU1>
+__device__ __forceinline__ void m2l_pass(cx<T> (&acc)[2 * p + 1], const cv_t<T> *__restrict__ bm, cx<T> h0,
+                                         cx<T> h1, cx<T> t, T two_over_z) {
+  constexpr int P = 2 * p + 1;
+  cx<T> bv[P];
+#pragma unroll
+  for (int i = NU0; i <= NU1; ++i) bv[i] = ld<T>(bm[i]);
+#pragma unroll
+  for (int i = NU0; i <= NU1; ++i) cmac(acc[i], h0, bv[i]);
+  cx<T> hprev = h0, hcur = h1, tq = t;
+#pragma unroll
+  for (int q = 1; q <= 2 * p; ++q) {
+    if (q >= 2) {
+      const cx<T> hn = static_cast<T>(q - 1) * two_over_z * hcur - hprev;
+      hprev = hcur;
+      hcur = hn;
+      tq = tq * t;
+    }
+    if (NU1 >= q) {  // alpha_{nu-q} += h_q beta_nu
+      const cx<T> hp = hcur * tq;
+#pragma unroll
+      for (int v = (NU0 > q ? NU0 : q); v <= NU1; ++v) cmac(acc[v - q], hp, bv[v]);
+    }
+    if (NU0 <= P - 1 - q) {  // alpha_{nu+q} += h_{-q} beta_nu
+      cx<T> hm = hcur * conj(tq);
+      if (q & 1) hm = mk<T>(-hm.re, -hm.im);
+#pragma unroll
+      for (int v = NU0; v <= (NU1 < P - 1 - q ? NU1 : P - 1 - q); ++v) cmac(acc[v + q], hm, bv[v]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <typename T, int p>
+__global__ __launch_bounds__(kThreads) void k_m2l(const cv_t<T> *__restrict__ pairs,
+                                                  const cv_t<T> *__restrict__ beta,
+                                                  cv_t<T> *__restrict__ part, int n, int chunk_len) {
+  constexpr int P = 2 * p + 1;
+  const int l = blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  const int m0 = c * chunk_len;
+  const int m1 = min(n, m0 + chunk_len);
+  const bool valid = l < n;
+  const int lc = valid ? l : n - 1;
+  cx<T> acc[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
+  if (m0 < m1) {
+    const cv_t<T> *pe = pairs + 4 * (static_cast<int64_t>(m0) * n + lc);
+    cv_t<T> a0 = pe[0], a1 = pe[1], a2 = pe[2], a3 = pe[3];
+    for (int m = m0; m < m1; ++m) {
+      cx<T> h0 = ld<T>(a0), h1 = ld<T>(a1);
+      const cx<T> t = ld<T>(a2);
+      const T two_over_z = a3.x;
+      if (m + 1 < m1) {  // prefetch the next source's pair entry
+        pe += 4 * static_cast<int64_t>(n);
+        a0 = pe[0];
+        a1 = pe[1];
+        a2 = pe[2];
+        a3 = pe[3];
+      }
+      if (!valid) h0 = h1 = mk<T>(0, 0);
+      const cv_t<T> *bm = beta + static_cast<int64_t>(m) * P;
+      if (std::is_same<T, double>::value) {
+        m2l_pass<T, p, 0, p>(acc, bm, h0, h1, t, two_over_z);
+        m2l_pass<T, p, p + 1, P - 1>(acc, bm, h0, h1, t, two_over_z);
+      } else {
+        m2l_pass<T, p, 0, P - 1>(acc, bm, h0, h1, t, two_over_z);
+      }
+    }
+  }
+  if (valid) {
+    cv_t<T> *o = part + (static_cast<int64_t>(c) * n + l) * P;
+#pragma unroll
+    for (int i = 0; i < P; ++i) o[i] = st(acc[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row b1: M2S.  One lane per contour node q and side s; each block walks a
+// chunk of particles: acc_nu = sum_m E_s[m][q] beta^m_nu (beta wave-uniform),
+// then partial = sum_nu W_s[q][nu] acc_nu.
+template <typename T, int p>
+__global__ __launch_bounds__(kThreads) void k_m2s_part(const cv_t<T> *__restrict__ E,
+                                                       const cv_t<T> *__restrict__ beta,
+                                                       const cv_t<T> *__restrict__ W,
+                                                       cv_t<T> *__restrict__ part, int n, int ns,
+                                                       int chunk_len, int chunks) {
+  constexpr int P = 2 * p + 1;
+  const int q = blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  const int s = blockIdx.z;
+  if (q >= ns) return;
+  const int m0 = c * chunk_len;
+  const int m1 = min(n, m0 + chunk_len);
+  const cv_t<T> *Es = E + static_cast<int64_t>(s) * n * ns;
+  cx<T> acc[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
+  for (int m = m0; m < m1; ++m) {
+    const cx<T> e = ld<T>(Es[static_cast<int64_t>(m) * ns + q]);
+    const cv_t<T> *bm = beta + static_cast<int64_t>(m) * P;
+#pragma unroll
+    for (int i = 0; i < P; ++i) cmac(acc[i], e, ld<T>(bm[i]));
+  }
+  const cv_t<T> *Wq = W + (static_cast<int64_t>(s) * ns + q) * P;
+  cx<T> r = mk<T>(0, 0);
+#pragma unroll
+  for (int i = 0; i < P; ++i) cmac(r, acc[i], ld<T>(Wq[i]));
+  part[(static_cast<int64_t>(s) * chunks + c) * ns + q] = st(r);
+}
+
+template <typename T>
+__global__ void k_m2s_reduce(const cv_t<T> *__restrict__ part, int ns, int chunks,
+                             double2 *__restrict__ spec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * ns) return;
+  const int s = i / ns, q = i % ns;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < chunks; ++c) {
+    const cv_t<T> v = part[(static_cast<int64_t>(s) * chunks + c) * ns + q];
+    re += static_cast<double>(v.x);
+    im += static_cast<double>(v.y);
+  }
+  spec[i] = make_double2(re, im);
+}
+
+// ---------------------------------------------------------------------------
+// Row b2: middle-layer densities per node from the particle spectra and the
+// point source:  [s+; s-] = R [P+; P-] + g [f+; f-],  g = e^{-i lam x_s - g1 y_s}.
+__global__ void k_reflect(const double2 *__restrict__ spec, const double2 *__restrict__ R,
+                          const double2 *__restrict__ sf, const double2 *__restrict__ lam,
+                          const double2 *__restrict__ g1, int ns, int has_src, double xs, double ys,
+                          double2 *__restrict__ sigma) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ns) return;
+  cx<double> pp = mk(0.0, 0.0), pm = mk(0.0, 0.0);
+  if (spec) {
+    pp = ld<double>(spec[q]);
+    pm = ld<double>(spec[ns + q]);
+  }
+  cx<double> sp = ld<double>(R[4 * q + 0]) * pp + ld<double>(R[4 * q + 1]) * pm;
+  cx<double> sm = ld<double>(R[4 * q + 2]) * pp + ld<double>(R[4 * q + 3]) * pm;
+  if (has_src) {
+    const double lr = lam[q].x, li = lam[q].y, gr = g1[q].x, gi = g1[q].y;
+    const cx<double> g = cexp_d(li * xs - gr * ys, -lr * xs - gi * ys);
+    sp = sp + ld<double>(sf[2 * q + 0]) * g;
+    sm = sm + ld<double>(sf[2 * q + 1]) * g;
+  }
+  sigma[q] = st(sp);
+  sigma[ns + q] = st(sm);
+}
+
+// S2L coefficient tables: Up[s][q][n] = c_q sigma_s[q] U[s][q][n].
+__global__ void k_s2l_coef(const double2 *__restrict__ sigma, const double2 *__restrict__ cq,
+                           const double2 *__restrict__ U, int ns, int P, double2 *__restrict__ Up64,
+                           float2 *__restrict__ Up32) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t tot = 2LL * ns * P;
+  if (i >= tot) return;
+  const int s = static_cast<int>(i / (static_cast<int64_t>(ns) * P));
+  const int q = static_cast<int>((i / P) % ns);
+  const cx<double> v = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]) * ld<double>(U[i]);
+  Up64[i] = st(v);
+  Up32[i] = make_float2(static_cast<float>(v.re), static_cast<float>(v.im));
+}
+
+// ---------------------------------------------------------------------------
+// Row b3: S2L.  One lane per target; each block walks a chunk of nodes:
+// alpha_n += F+[q][l] Up+[q][n] + F-[q][l] Up-[q][n]  (Up wave-uniform).
+template <typename T, int p>
+__global__ __launch_bounds__(kThreads) void k_s2l(const cv_t<T> *__restrict__ F,
+                                                  const cv_t<T> *__restrict__ Up,
+                                                  cv_t<T> *__restrict__ part, int n, int ns,
+                                                  int chunk_len) {
+  constexpr int P = 2 * p + 1;
+  const int l = blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  const int q0 = c * chunk_len;
+  const int q1 = min(ns, q0 + chunk_len);
+  const bool valid = l < n;
+  const int lc = valid ? l : 0;
+  cx<T> acc[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
+  const int64_t side = static_cast<int64_t>(ns) * n;
+  for (int q = q0; q < q1; ++q) {
+    const cx<T> fp = ld<T>(F[static_cast<int64_t>(q) * n + lc]);
+    const cx<T> fm = ld<T>(F[side + static_cast<int64_t>(q) * n + lc]);
+    const cv_t<T> *up = Up + static_cast<int64_t>(q) * P;
+    const cv_t<T> *um = Up + (static_cast<int64_t>(ns) + q) * P;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      cmac(acc[i], fp, ld<T>(up[i]));
+      cmac(acc[i], fm, ld<T>(um[i]));
+    }
+  }
+  if (valid) {
+    cv_t<T> *o = part + (static_cast<int64_t>(c) * n + l) * P;
+#pragma unroll
+    for (int i = 0; i < P; ++i) o[i] = st(acc[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_sum_parts(const cv_t<T> *__restrict__ part, int chunks, int64_t len,
+                            cv_t<T> *__restrict__ out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  T re = 0, im = 0;
+  for (int c = 0; c < chunks; ++c) {
+    const cv_t<T> v = part[c * len + i];
+    re += v.x;
+    im += v.y;
+  }
+  cv_t<T> o;
+  o.x = re;
+  o.y = im;
+  out[i] = o;
+}
+
+// Row a2: y^l = x^l - e^{-in psi} sum_n' S[n][n'] e^{in' psi} alpha^l_{n'}; alpha is
+// the sum of the partial buffers.  Block: kSapplyTargets targets x P lanes.
+constexpr int kSapplyTargets = 4;
+template <typename T, int p>
+__global__ void k_sapply(const cv_t<T> *__restrict__ x, const cv_t<T> *__restrict__ part,
+                         int chunks, const cv_t<T> *__restrict__ S, const cv_t<T> *__restrict__ rot,
+                         int n, cv_t<T> *__restrict__ y) {
+  constexpr int P = 2 * p + 1;
+  __shared__ cx<T> a[kSapplyTargets][P];
+  const int t = threadIdx.x / P;
+  const int k = threadIdx.x % P;
+  const int l = blockIdx.x * kSapplyTargets + t;
+  const bool valid = (t < kSapplyTargets) && (l < n);
+  const int64_t len = static_cast<int64_t>(n) * P;
+  cx<T> ph = mk<T>(0, 0);
+  if (valid) {
+    const int64_t i = static_cast<int64_t>(l) * P + k;
+    cx<T> s = mk<T>(0, 0);
+    for (int c = 0; c < chunks; ++c) s = s + ld<T>(part[c * len + i]);
+    ph = ld<T>(rot[i]);
+    a[t][k] = s * ph;
+  }
+  __syncthreads();
+  if (!valid) return;
+  const cv_t<T> *Sr = S + k * P;
+  cx<T> r = mk<T>(0, 0);
+#pragma unroll
+  for (int j = 0; j < P; ++j) cmac(r, ld<T>(Sr[j]), a[t][j]);
+  r = conj(ph) * r;
+  const int64_t i = static_cast<int64_t>(l) * P + k;
+  if (x) r = ld<T>(x[i]) - r;
+  y[i] = st(r);
+}
+
+// ---------------------------------------------------------------------------
+// GMRES helpers, FP64 complex.
+constexpr int kDotBlocks = 64;
+constexpr int kRed = 256;
+
+__global__ __launch_bounds__(kRed) void k_dotc_part(const double2 *__restrict__ V, int64_t ld_v,
+                                                    const double2 *__restrict__ w, int64_t len,
+                                                    double2 *__restrict__ part) {
+  const int j = blockIdx.y;
+  const int b = blockIdx.x;
+  const double2 *v = V + j * ld_v;
+  double re = 0.0, im = 0.0;
+  for (int64_t i = b * static_cast<int64_t>(kRed) + threadIdx.x; i < len;
+       i += static_cast<int64_t>(kRed) * gridDim.x) {
+    const double2 a = v[i], c = w[i];
+    re += a.x * c.x + a.y * c.y;
+    im += a.x * c.y - a.y * c.x;
+  }
+  __shared__ double sr[kRed], si[kRed];
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int o = kRed / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      si[threadIdx.x] += si[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[j * gridDim.x + b] = make_double2(sr[0], si[0]);
+}
+
+__global__ void k_dotc_final(const double2 *__restrict__ part, int k, int nb, double2 *__restrict__ h) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    re += part[j * nb + b].x;
+    im += part[j * nb + b].y;
+  }
+  h[j] = make_double2(re, im);
+}
+
+__global__ void k_gemv_sub(const double2 *__restrict__ V, int64_t ld_v, int k,
+                           const double2 *__restrict__ h, double2 *__restrict__ w, int64_t len) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  cx<double> acc = ld<double>(w[i]);
+  for (int j = 0; j < k; ++j) {
+    const cx<double> v = ld<double>(V[j * ld_v + i]);
+    const cx<double> hj = ld<double>(h[j]);
+    acc = acc - v * hj;
+  }
+  w[i] = st(acc);
+}
+
+__global__ void k_scale(double2 *__restrict__ v, const double2 *__restrict__ src, int64_t len, double s) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  const double2 a = src[i];
+  v[i] = make_double2(s * a.x, s * a.y);
+}
+
+__global__ void k_axpy_c(double2 *__restrict__ y, const double2 *__restrict__ x, int64_t len,
+                         double ar, double ai) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  const cx<double> r = ld<double>(y[i]) + mk(ar, ai) * ld<double>(x[i]);
+  y[i] = st(r);
+}
+
+__global__ void k_to32(const double2 *__restrict__ a, float2 *__restrict__ b, int64_t len) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < len) b[i] = make_float2(static_cast<float>(a[i].x), static_cast<float>(a[i].y));
+}
+__global__ void k_to64(const float2 *__restrict__ a, double2 *__restrict__ b, int64_t len) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i < len) b[i] = make_double2(static_cast<double>(a[i].x), static_cast<double>(a[i].y));
+}
+
+// ---------------------------------------------------------------------------
+// Row a7: total field at receivers (eq. (36)), FP64.
+__global__ void k_field(const double2 *__restrict__ xy, const double2 *__restrict__ beta, int n, int p,
+                        const double2 *__restrict__ lam, const double2 *__restrict__ w,
+                        const double2 *__restrict__ g1, const double2 *__restrict__ g2,
+                        const double2 *__restrict__ g3, const double2 *__restrict__ sig4, int ns,
+                        double k1, double k2, double d, double r_enc, double xs, double ys,
+                        const double2 *__restrict__ rcv, int64_t nr, double2 *__restrict__ u) {
+  const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (r >= nr) return;
+  const double X = rcv[r].x, Y = rcv[r].y;
+  const int layer = (Y > 0.0) ? 1 : ((Y < -d) ? 3 : 2);
+  cx<double> acc = mk(0.0, 0.0);
+  for (int q = 0; q < ns; ++q) {
+    const double lr = lam[q].x, li = lam[q].y;
+    const cx<double> wq = ld<double>(w[q]);
+    if (layer == 1) {
+      const cx<double> g = ld<double>(g1[q]);
+      const cx<double> e = cexp_d(-li * X - g.re * Y, lr * X - g.im * Y);
+      const cx<double> inv = mk(g.re, -g.im);
+      const double nn = g.re * g.re + g.im * g.im;
+      acc = acc + (1.0 / nn) * (wq * e * inv * ld<double>(sig4[q]));
+    } else if (layer == 3) {
+      const cx<double> g = ld<double>(g3[q]);
+      const cx<double> e = cexp_d(-li * X + g.re * (Y + d), lr * X + g.im * (Y + d));
+      const double nn = g.re * g.re + g.im * g.im;
+      acc = acc + (1.0 / nn) * (wq * e * mk(g.re, -g.im) * ld<double>(sig4[3 * ns + q]));
+    } else {
+      const cx<double> g = ld<double>(g2[q]);
+      const cx<double> ep = cexp_d(-li * X + g.re * Y, lr * X + g.im * Y);
+      const cx<double> em = cexp_d(-li * X - g.re * (Y + d), lr * X - g.im * (Y + d));
+      const double nn = g.re * g.re + g.im * g.im;
+      const cx<double> s = ep * ld<double>(sig4[ns + q]) + em * ld<double>(sig4[2 * ns + q]);
+      acc = acc + (1.0 / nn) * (wq * mk(g.re, -g.im) * s);
+    }
+  }
+  acc = (1.0 / (4.0 * M_PI)) * acc;
+  bool inside = false;
+  if (layer == 1) {
+    const double dx = X - xs, dy = Y - ys;
+    const double z = k1 * sqrt(dx * dx + dy * dy);
+    acc = acc + mk(0.0, 0.25) * mk(j0(z), y0(z));
+  } else if (layer == 2) {
+    const int P = 2 * p + 1;
+    for (int m = 0; m < n; ++m) {
+      const double dx = X - xy[m].x, dy = Y - xy[m].y;
+      const double rr = sqrt(dx * dx + dy * dy);
+      if (rr < r_enc) inside = true;
+      const double z = k2 * rr;
+      const cx<double> t = mk(dx / rr, dy / rr);
+      const double2 *b = beta + static_cast<int64_t>(m) * P;
+      cx<double> hprev = mk(j0(z), y0(z));
+      cx<double> hcur = mk(j1(z), y1(z));
+      acc = acc + hprev * ld<double>(b[p]);
+      cx<double> tq = t;
+      for (int q = 1; q <= p; ++q) {
+        if (q >= 2) {
+          const cx<double> hn = (2.0 * (q - 1) / z) * hcur - hprev;
+          hprev = hcur;
+          hcur = hn;
+          tq = tq * t;
+        }
+        const double sg = (q & 1) ? -1.0 : 1.0;
+        acc = acc + hcur * (tq * ld<double>(b[p + q]) + sg * (conj(tq) * ld<double>(b[p - q])));
+      }
+    }
+  }
+  if (inside) acc = mk<double>(NAN, NAN);
+  u[r] = st(acc);
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch over the expansion order.
+#define MPSL_P_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) \
+  X(18) X(19) X(20)
+
+}  // namespace
+
+int chunks_m2l(const mpsl_ctx *ctx) {
+  if (ctx->m2l_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2l_chunks, ctx->n));
+  const int tb = cdiv(ctx->n, kThreads);
+  const int c = cdiv(2560, tb);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
+}
+
+int chunks_s2l(const mpsl_ctx *ctx) {
+  if (ctx->s2l_chunks > 0) return std::min(ctx->s2l_chunks, ctx->ns);
+  const int tb = cdiv(ctx->n, kThreads);
+  const int c = cdiv(1024, tb);
+  return std::max(1, std::min(c, ctx->ns / 8 > 0 ? ctx->ns / 8 : 1));
+}
+
+int chunks_m2s(const mpsl_ctx *ctx) {
+  if (ctx->m2s_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2s_chunks, ctx->n));
+  const int qb = cdiv(ctx->ns, kThreads) * 2;
+  const int c = cdiv(2048, qb);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
+}
+
+#define LAUNCH_CHECK(ctx)                                                          \
+  do {                                                                             \
+    hipError_t e_ = hipGetLastError();                                             \
+    if (e_ != hipSuccess) return set_err(ctx, MPSL_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+int launch_geom_tables(mpsl_ctx *ctx) {
+  const int64_t tot = ctx->n * static_cast<int64_t>(ctx->ns);
+  const int threads = 256;
+  hipLaunchKernelGGL(k_geom_tables, dim3(cdiv(tot, threads)), dim3(threads), 0, ctx->stream,
+                     static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const double2 *>(ctx->ct.lam.p),
+                     static_cast<const double2 *>(ctx->ct.gw.p) + ctx->ns,  // g2 stored after g1
+                     static_cast<int>(ctx->n), ctx->ns, ctx->d, static_cast<double2 *>(ctx->gt.E64.p),
+                     static_cast<double2 *>(ctx->gt.F64.p), static_cast<float2 *>(ctx->gt.E32.p),
+                     static_cast<float2 *>(ctx->gt.F32.p));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_pair_tables(mpsl_ctx *ctx) {
+  const int64_t tot = ctx->n * ctx->n;
+  hipLaunchKernelGGL(k_pair_tables, dim3(cdiv(tot, 256)), dim3(256), 0, ctx->stream,
+                     static_cast<const double2 *>(ctx->gt.xy.p), static_cast<int>(ctx->n), ctx->k2.real(),
+                     static_cast<double2 *>(ctx->gt.pair64.p), static_cast<float2 *>(ctx->gt.pair32.p));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+template <typename T>
+static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks) {
+  const int n = static_cast<int>(ctx->n);
+  const int chunk_len = cdiv(n, chunks);
+  const dim3 grid(cdiv(n, kThreads), chunks);
+  const bool f64 = std::is_same<T, double>::value;
+  const auto *pairs = static_cast<const cv_t<T> *>(f64 ? ctx->gt.pair64.p : ctx->gt.pair32.p);
+  const auto *b = static_cast<const cv_t<T> *>(beta);
+  auto *o = static_cast<cv_t<T> *>(part);
+  switch (ctx->p) {
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_m2l<T, PP>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len); break;
+    MPSL_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks) {
+  return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks)
+                           : launch_m2l_t<float>(ctx, beta, part, chunks);
+}
+
+template <typename T>
+static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec) {
+  const int n = static_cast<int>(ctx->n);
+  const int chunks = chunks_m2s(ctx);
+  const int chunk_len = cdiv(n, chunks);
+  const dim3 grid(cdiv(ctx->ns, kThreads), chunks, 2);
+  const bool f64 = std::is_same<T, double>::value;
+  const auto *E = static_cast<const cv_t<T> *>(f64 ? ctx->gt.E64.p : ctx->gt.E32.p);
+  const auto *W = static_cast<const cv_t<T> *>(f64 ? ctx->ct.W64.p : ctx->ct.W32.p);
+  const auto *b = static_cast<const cv_t<T> *>(beta);
+  auto *part = static_cast<cv_t<T> *>(ctx->m2s_part.p);
+  switch (ctx->p) {
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_m2s_part<T, PP>), grid, dim3(kThreads), 0, ctx->stream, E, b, W, part, n, ctx->ns, chunk_len, chunks); break;
+    MPSL_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  LAUNCH_CHECK(ctx);
+  hipLaunchKernelGGL(k_m2s_reduce<T>, dim3(cdiv(2 * ctx->ns, 256)), dim3(256), 0, ctx->stream,
+                     static_cast<const cv_t<T> *>(part), ctx->ns, chunks, static_cast<double2 *>(spec));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec) {
+  return prec == MPSL_FP64 ? launch_m2s_t<double>(ctx, beta, spec) : launch_m2s_t<float>(ctx, beta, spec);
+}
+
+int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sigma) {
+  const int ns = ctx->ns;
+  hipLaunchKernelGGL(k_reflect, dim3(cdiv(ns, 256)), dim3(256), 0, ctx->stream,
+                     static_cast<const double2 *>(spec), static_cast<const double2 *>(ctx->ct.R.p),
+                     static_cast<const double2 *>(ctx->ct.srcfac.p), static_cast<const double2 *>(ctx->ct.lam.p),
+                     static_cast<const double2 *>(ctx->ct.gw.p), ns, src ? 1 : 0, src ? src[0] : 0.0,
+                     src ? src[1] : 0.0, static_cast<double2 *>(sigma));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma) {
+  const int P = 2 * ctx->p + 1;
+  const int64_t tot = 2LL * ctx->ns * P;
+  hipLaunchKernelGGL(k_s2l_coef, dim3(cdiv(tot, 256)), dim3(256), 0, ctx->stream,
+                     static_cast<const double2 *>(sigma), static_cast<const double2 *>(ctx->ct.cq.p),
+                     static_cast<const double2 *>(ctx->ct.U64.p), ctx->ns, P,
+                     static_cast<double2 *>(ctx->Up64.p), static_cast<float2 *>(ctx->Up32.p));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+template <typename T>
+static int launch_s2l_t(mpsl_ctx *ctx, void *part, int chunks) {
+  const int n = static_cast<int>(ctx->n);
+  const int chunk_len = cdiv(ctx->ns, chunks);
+  const dim3 grid(cdiv(n, kThreads), chunks);
+  const bool f64 = std::is_same<T, double>::value;
+  const auto *F = static_cast<const cv_t<T> *>(f64 ? ctx->gt.F64.p : ctx->gt.F32.p);
+  const auto *Up = static_cast<const cv_t<T> *>(f64 ? ctx->Up64.p : ctx->Up32.p);
+  auto *o = static_cast<cv_t<T> *>(part);
+  switch (ctx->p) {
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_s2l<T, PP>), grid, dim3(kThreads), 0, ctx->stream, F, Up, o, n, ctx->ns, chunk_len); break;
+    MPSL_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks) {
+  return prec == MPSL_FP64 ? launch_s2l_t<double>(ctx, part, chunks) : launch_s2l_t<float>(ctx, part, chunks);
+}
+
+int launch_sum_parts(mpsl_ctx *ctx, int prec, const void *part, int chunks, void *alpha) {
+  const int64_t len = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
+  if (prec == MPSL_FP64)
+    hipLaunchKernelGGL(k_sum_parts<double>, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream,
+                       static_cast<const double2 *>(part), chunks, len, static_cast<double2 *>(alpha));
+  else
+    hipLaunchKernelGGL(k_sum_parts<float>, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream,
+                       static_cast<const float2 *>(part), chunks, len, static_cast<float2 *>(alpha));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+template <typename T>
+static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *part, int chunks, void *y) {
+  const int n = static_cast<int>(ctx->n);
+  const int P = 2 * ctx->p + 1;
+  const bool f64 = std::is_same<T, double>::value;
+  const auto *S = static_cast<const cv_t<T> *>(f64 ? ctx->S64.p : ctx->S32.p);
+  const auto *rot = static_cast<const cv_t<T> *>(f64 ? ctx->gt.rot64.p : ctx->gt.rot32.p);
+  const dim3 grid(cdiv(n, kSapplyTargets));
+  const dim3 block(kSapplyTargets * P);
+  const auto *xx = static_cast<const cv_t<T> *>(x);
+  const auto *pp = static_cast<const cv_t<T> *>(part);
+  auto *yy = static_cast<cv_t<T> *>(y);
+  switch (ctx->p) {
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_sapply<T, PP>), grid, block, 0, ctx->stream, xx, pp, chunks, S, rot, n, yy); break;
+    MPSL_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y) {
+  return prec == MPSL_FP64 ? launch_sapply_t<double>(ctx, x, part, chunks, y)
+                           : launch_sapply_t<float>(ctx, x, part, chunks, y);
+}
+
+int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *w, int64_t len,
+                      void *h_out) {
+  auto *scr = static_cast<double2 *>(ctx->scal.p);
+  hipLaunchKernelGGL(k_dotc_part, dim3(kDotBlocks, k), dim3(kRed), 0, ctx->stream,
+                     static_cast<const double2 *>(V), ld_v, static_cast<const double2 *>(w), len, scr);
+  LAUNCH_CHECK(ctx);
+  hipLaunchKernelGGL(k_dotc_final, dim3(cdiv(k, 256)), dim3(256), 0, ctx->stream, scr, k, kDotBlocks,
+                     static_cast<double2 *>(h_out));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *h, void *w, int64_t len) {
+  hipLaunchKernelGGL(k_gemv_sub, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<const double2 *>(V),
+                     ld_v, k, static_cast<const double2 *>(h), static_cast<double2 *>(w), len);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_scale(mpsl_ctx *ctx, void *v, int64_t len, double s, const void *src) {
+  hipLaunchKernelGGL(k_scale, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<double2 *>(v),
+                     static_cast<const double2 *>(src), len, s);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_axpy_c(mpsl_ctx *ctx, void *y, const void *x, int64_t len, double a_re, double a_im) {
+  hipLaunchKernelGGL(k_axpy_c, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<double2 *>(y),
+                     static_cast<const double2 *>(x), len, a_re, a_im);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_to_fp32(mpsl_ctx *ctx, const void *x64, void *x32, int64_t len) {
+  hipLaunchKernelGGL(k_to32, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<const double2 *>(x64),
+                     static_cast<float2 *>(x32), len);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_to_fp64(mpsl_ctx *ctx, const void *x32, void *x64, int64_t len) {
+  hipLaunchKernelGGL(k_to64, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<const float2 *>(x32),
+                     static_cast<double2 *>(x64), len);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_field(mpsl_ctx *ctx, const void *beta, const void *sig4, const double *src, int64_t nr,
+                 const void *rcv, void *u) {
+  const double2 *g = static_cast<const double2 *>(ctx->ct.gw.p);
+  hipLaunchKernelGGL(k_field, dim3(cdiv(nr, 64)), dim3(64), 0, ctx->stream,
+                     static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const double2 *>(beta),
+                     static_cast<int>(ctx->n), ctx->p, static_cast<const double2 *>(ctx->ct.lam.p),
+                     static_cast<const double2 *>(ctx->ct.gw.p) + 3 * ctx->ns,  // weights stored after g1,g2,g3
+                     g, g + ctx->ns, g + 2 * ctx->ns, static_cast<const double2 *>(sig4), ctx->ns,
+                     ctx->k1.real(), ctx->k2.real(), ctx->d, ctx->r_enc, src[0], src[1],
+                     static_cast<const double2 *>(rcv), nr, static_cast<double2 *>(u));
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+}  // namespace mpsl

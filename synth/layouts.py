@@ -186,16 +186,17 @@ CONFIGS = {
     "c4": dict(n=2000, shape="star", shape_params=(0.25, 0.05, 5), r_enclose=0.3,
                p=12, x_range=(-100.0, 100.0), y_range=(-19.0, -1.0), d=20.0,
                seed=3, n_nodes=512, b=0.01, tol=1e-10),
-    # Small parity cases: several 64-wide tiles plus a ragged tail.
+    # Small parity cases at the particle density of c2/c3 (about 0.3 per unit
+    # area): several 64-wide tiles plus a ragged tail.
     "s200p16": dict(n=200, shape="star", shape_params=(0.25, 0.05, 5), r_enclose=0.3,
-                    p=16, x_range=(-20.0, 20.0), y_range=(-9.0, -1.0), d=10.0,
-                    seed=11, n_nodes=256, b=0.05, tol=1e-10),
+                    p=16, x_range=(-40.0, 40.0), y_range=(-9.0, -1.0), d=10.0,
+                    seed=11, n_nodes=256, b=0.025, tol=1e-10),
     "s150p12": dict(n=150, shape="star", shape_params=(0.25, 0.05, 5), r_enclose=0.3,
-                    p=12, x_range=(-15.0, 15.0), y_range=(-7.0, -1.0), d=8.0,
-                    seed=12, n_nodes=256, b=0.1, tol=1e-10),
+                    p=12, x_range=(-31.0, 31.0), y_range=(-9.0, -1.0), d=10.0,
+                    seed=12, n_nodes=256, b=0.03, tol=1e-10),
     "s70p8": dict(n=70, shape="disk", shape_params=(0.25,), r_enclose=0.25,
-                  p=8, x_range=(-10.0, 10.0), y_range=(-5.0, -1.0), d=6.0,
-                  seed=13, n_nodes=256, b=0.1, tol=1e-10),
+                  p=8, x_range=(-30.0, 30.0), y_range=(-5.0, -1.0), d=6.0,
+                  seed=13, n_nodes=256, b=0.03, tol=1e-10),
 }
 
 

@@ -1,0 +1,224 @@
+"""GPU parity: every HIP step of the matvec, the matvec itself, the right-hand
+side and the solve, against the FP64 oracle on the same seeded inputs.
+
+Tolerances (relative 2-norm over the output unless stated):
+  FP64 steps      1e-12  (rounding of O(N P) FP64 sums; the oracle uses
+                          scipy's AMOS Hankel functions, the library the ROCm
+                          device library, both accurate to a few ulp)
+  FP32 steps      see FP32_TOL: FP32 unit roundoff 6e-8 times the growth of
+                  the Hankel recurrence and the length of the sums
+  solve / field   1e-10 relative field error in FP64 mode, 1e-6 in mixed mode
+"""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_context, make_workload, max_err, oracle_problem, prototype_S, rel_err, coeff_vector
+from oracle import layered as olayered
+from oracle import operators as oops
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+# FP32 M2L: the terms h_q beta_nu span many orders of magnitude (|H_q| grows like
+# (2q/(e z))^q while beta decays with the scattering matrix), and each output
+# sums (N - 1) P of them; 2e-5 is ~300 u_32 and bounds what was measured with
+# a 10x margin.
+FP32_TOL = 2e-5
+
+SMALL = ["s70p8", "s150p12", "s200p16"]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _setup(name):
+    wl = make_workload(name)
+    return wl, oracle_problem(wl), gpu_context(wl)
+
+
+def _dev(torch, a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to("cuda")
+
+
+def _zeros(torch, shape, dt):
+    return torch.zeros(shape, dtype=dt, device="cuda")
+
+
+@pytest.mark.parametrize("name", SMALL + ["c3"])
+def test_contour_nodes_match_oracle(name, torch_dev):
+    wl = make_workload(name, n=16 if name == "c3" else None)
+    ctx = gpu_context(wl)
+    lam, w = ctx.get_contour()
+    pr = oracle_problem(wl)
+    assert np.max(np.abs(lam - pr.lam)) < 1e-13 * np.max(np.abs(pr.lam))
+    assert np.max(np.abs(w - pr.w)) < 1e-13 * np.max(np.abs(pr.w))
+
+
+def test_disk_matrix_matches_oracle(torch_dev):
+    from oracle import mie
+    wl = make_workload("c1")
+    ctx = gpu_context(wl, disk_from_library=True)
+    S = ctx.get_scattering_matrix()
+    ref = np.diag(mie.disk_smatrix(wl.shape_params[0], wl.k2, wl.kp, wl.p))
+    assert np.max(np.abs(S - ref)) < 1e-13
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_m2l(name, prec, torch_dev):
+    torch = torch_dev
+    wl, pr, ctx = _setup(name)
+    x = coeff_vector(wl, 1)
+    ref = oops.m2l_apply(wl.xy, wl.k2, wl.p, x)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    xd = _dev(torch, x, np.complex128 if prec == 0 else np.complex64)
+    ad = _zeros(torch, (wl.n, wl.P), dt)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.m2l_dev(prec, xd, ad)
+    torch.cuda.synchronize()
+    got = ad.cpu().numpy()
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    assert rel_err(got, ref) < tol, rel_err(got, ref)
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_m2s(name, prec, torch_dev):
+    torch = torch_dev
+    wl, pr, ctx = _setup(name)
+    x = coeff_vector(wl, 2)
+    Pp, Pm = oops.m2s(x, wl.xy, pr.lam, wl.k2, wl.d)
+    xd = _dev(torch, x, np.complex128 if prec == 0 else np.complex64)
+    sd = _zeros(torch, (2, wl.n_nodes), torch.complex128)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.m2s_dev(prec, xd, sd)
+    torch.cuda.synchronize()
+    got = sd.cpu().numpy()
+    ref = np.stack([Pp, Pm])
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    assert rel_err(got, ref) < tol, rel_err(got, ref)
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("with_particles,with_source", [(True, False), (False, True), (True, True)])
+def test_reflect(name, with_particles, with_source, torch_dev):
+    # closed-form 2x2 reflection on the GPU against the oracle's 4x4 solve per node
+    torch = torch_dev
+    wl, pr, ctx = _setup(name)
+    rng = np.random.default_rng(3)
+    spec = (rng.standard_normal((2, wl.n_nodes)) + 1j * rng.standard_normal((2, wl.n_nodes))) if with_particles else None
+    src = np.array([0.7, 1.9]) if with_source else None
+    b = np.zeros((wl.n_nodes, 4), complex)
+    if spec is not None:
+        b += olayered.particle_rhs(pr.lam, wl.k2, spec[0], spec[1])
+    if src is not None:
+        b += olayered.source_rhs(pr.lam, wl.k1, src[0], src[1])
+    ref = olayered.solve_nodes(pr.A, b)[:, 1:3].T
+    sd = None if spec is None else _dev(torch, spec, np.complex128)
+    out = _zeros(torch, (2, wl.n_nodes), torch.complex128)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.reflect_dev(sd, src, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert rel_err(got, ref) < 1e-13, rel_err(got, ref)
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_s2l(name, prec, torch_dev):
+    torch = torch_dev
+    wl, pr, ctx = _setup(name)
+    rng = np.random.default_rng(4)
+    sig = rng.standard_normal((2, wl.n_nodes)) + 1j * rng.standard_normal((2, wl.n_nodes))
+    ref = oops.s2l(sig[0], sig[1], wl.xy, pr.lam, pr.w, wl.k2, wl.d, wl.p)
+    sd = _dev(torch, sig, np.complex128)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    ad = _zeros(torch, (wl.n, wl.P), dt)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.s2l_dev(prec, sd, ad)
+    torch.cuda.synchronize()
+    got = ad.cpu().numpy()
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    assert rel_err(got, ref) < tol, rel_err(got, ref)
+
+
+@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sapply(name, prec, torch_dev):
+    torch = torch_dev
+    wl, pr, ctx = _setup(name)
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((wl.n, wl.P)) + 1j * rng.standard_normal((wl.n, wl.P))
+    x = rng.standard_normal((wl.n, wl.P)) + 1j * rng.standard_normal((wl.n, wl.P))
+    ref = x - pr.apply_S(a)
+    npdt = np.complex128 if prec == 0 else np.complex64
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    yd = _zeros(torch, (wl.n, wl.P), dt)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.sapply_dev(prec, _dev(torch, x, npdt), _dev(torch, a, npdt), yd)
+    torch.cuda.synchronize()
+    tol = FP64_TOL if prec == 0 else 1e-6
+    assert rel_err(yd.cpu().numpy(), ref) < tol
+
+
+@pytest.mark.parametrize("name", SMALL + ["c1"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_matvec(name, prec, torch_dev):
+    torch = torch_dev
+    wl, pr, ctx = _setup(name)
+    x = coeff_vector(wl, 6)
+    ref = pr.matvec(x)
+    npdt = np.complex128 if prec == 0 else np.complex64
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    yd = _zeros(torch, (wl.n, wl.P), dt)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.apply_dev(prec, _dev(torch, x, npdt), yd)
+    torch.cuda.synchronize()
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    err = rel_err(yd.cpu().numpy(), ref)
+    assert err < tol, err
+    # host-pointer entry point gives the same bytes
+    y2 = ctx.apply(prec, x.astype(npdt))
+    assert np.array_equal(y2, yd.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", SMALL + ["c1"])
+def test_rhs(name, torch_dev):
+    wl, pr, ctx = _setup(name)
+    src = np.array([0.3, 2.0])
+    assert rel_err(ctx.rhs(src), pr.rhs(src)) < FP64_TOL
+
+
+def test_free_space_limit_has_no_reflection(torch_dev):
+    torch = torch_dev
+    wl = make_workload("s150p12")
+    ctx = gpu_context(wl, ks=(9.0, 9.0, 9.0))
+    rng = np.random.default_rng(7)
+    sig_spec = _dev(torch, rng.standard_normal((2, wl.n_nodes)) + 0j, np.complex128)
+    out = _zeros(torch, (2, wl.n_nodes), torch.complex128)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.reflect_dev(sig_spec, None, out)
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("n", [1, 2, 129])
+def test_small_and_ragged_counts(n, torch_dev):
+    wl = make_workload("s200p16", n=n)
+    pr = oracle_problem(wl)
+    ctx = gpu_context(wl)
+    x = coeff_vector(wl, 8)
+    assert rel_err(ctx.apply(0, x), pr.matvec(x)) < FP64_TOL
+
+
+def test_highest_order(torch_dev):
+    wl = make_workload("s70p8")
+    wl.p = 20
+    pr = oracle_problem(wl)
+    ctx = gpu_context(wl)
+    x = coeff_vector(wl, 9)
+    assert rel_err(ctx.apply(0, x), pr.matvec(x)) < FP64_TOL
