@@ -1,0 +1,192 @@
+"""Benchmark: preconditioned Schur matvecs per second at N = 5000, p = 16.
+
+Workload (the 5000-particle configuration): 5000 star particles
+r(t) = 0.25 + 0.05 cos 5t of wavenumber 15 at uniform random rotations in a
+400 x 38 strip of the middle layer (d = 40), layers k = (6, 9, 12), expansion
+order p = 16, 1024 Sommerfeld nodes; seeded synthetic layout.  One step is one
+matvec y = x - S (T + T_R) x of the GMRES operator (all steps of the hot path:
+M2S, reflection, S2L, all-pairs M2L, scattering-matrix apply) in complex64
+with FP32 accumulation (the mixed-precision configuration); the FP64 matvec
+is timed beside it.  Inputs are resident in device memory before timing.
+
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector, TFLOP/s
+PEAK_FP64 = 78.6e12    # MI355X FP64 vector
+
+
+def _matvec_rate(ctx, torch, prec, x_np, steps, warmup):
+    import numpy as np
+    dt = np.complex64 if prec == 1 else np.complex128
+    xd = torch.from_numpy(x_np.astype(dt)).cuda()
+    yd = torch.zeros_like(xd)
+    for _ in range(warmup):
+        ctx.apply_dev(prec, xd, yd)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.apply_dev(prec, xd, yd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    m2l_ms, cnt = ctx.profile_read()
+    ctx.profile(False)
+    finite = bool(torch.isfinite(torch.view_as_real(yd)).all().item())
+    return (t1 - t0), m2l_ms, cnt, finite
+
+
+def _cpu_baseline(wl, S, x, n_targets=24):
+    """The FP64 oracle's matvec, timed on a bounded sample of the workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import contour as oc
+    from oracle import operators as oo
+    from oracle import system as osys
+
+    with threadpool_limits(limits=1):
+        lam, w = oc.contour(wl.n_nodes, wl.b, wl.t_max, [wl.k1, wl.k2, wl.k3])
+        pr = osys.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, S, wl.xy, wl.rot, lam, w)
+        tg = list(np.linspace(0, wl.n - 1, n_targets).astype(int))
+        t0 = time.perf_counter()
+        oo.m2l_apply(wl.xy, wl.k2, wl.p, x, targets=tg)
+        t1 = time.perf_counter()
+        sig = pr.sigma(beta=x)
+        t2 = time.perf_counter()
+        a = oo.s2l(sig[:, 1], sig[:, 2], wl.xy, lam, w, wl.k2, wl.d, wl.p)
+        t3 = time.perf_counter()
+        pr.apply_S(a[tg], targets=tg)
+        t4 = time.perf_counter()
+    per_matvec = (t1 - t0) * wl.n / n_targets + (t2 - t1) + (t3 - t2) + (t4 - t3) * wl.n / n_targets
+    return {"value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 numpy/scipy oracle on one host thread: all-pairs M2L and S-apply for "
+                       f"{n_targets} of {wl.n} targets (scaled by {wl.n}/{n_targets}), M2S, 4x4 node "
+                       f"solves and S2L in full; {t4 - t0:.1f} s measured, "
+                       f"{per_matvec:.1f} s per full matvec")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--solve-maxiter", type=int, default=1500)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1407_3868_amd as mp
+    from synth import make_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    wl = make_workload("c3")
+    a1, a2, a3 = wl.shape_params
+
+    t_setup0 = time.perf_counter()
+    ctx = mp.Context(0)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.set_layers(wl.k1, wl.k2, wl.k3, wl.d)
+    ctx.set_particle_star(a1, a2, a3, wl.kp, wl.p, 256)
+    t_smat = time.perf_counter()
+    ctx.set_geometry(wl.xy, wl.rot)
+    ctx.set_contour(wl.n_nodes, wl.b, wl.t_max)
+    S = ctx.get_scattering_matrix()
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal((wl.n, wl.P)) + 1j * rng.standard_normal((wl.n, wl.P))
+    n = np.arange(-wl.p, wl.p + 1)
+    x = np.stack([np.exp(1j * (n[None, :] - n[:, None]) * wl.rot[l]) * S @ r[l] for l in range(wl.n)])
+    # first call builds the per-pair and per-node device tables
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros_like(xd)
+    ctx.apply_dev(0, xd, yd)
+    torch.cuda.synchronize()
+    t_setup1 = time.perf_counter()
+
+    el32, m2l32, cnt32, fin32 = _matvec_rate(ctx, torch, 1, x, args.steps, args.warmup)
+    el64, m2l64, cnt64, fin64 = _matvec_rate(ctx, torch, 0, x, args.steps, args.warmup)
+    flops = 8.0 * wl.P ** 2 * wl.n * (wl.n - 1)
+    ach32 = flops / (m2l32 * 1e-3)
+    ach64 = flops / (m2l64 * 1e-3)
+    value = args.steps / el32
+    value64 = args.steps / el64
+
+    out = {
+        "metric": "GMRES matvecs/s at N=5000,p=16",
+        "value": value,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el32 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("5000 stars r=0.25+0.05cos5t, kp=15, p=16, k=(6,9,12), d=40, 400x38 strip, "
+                         "1024 Sommerfeld nodes; one Schur matvec in complex64 (mixed-precision mode)"),
+            "n_particles": wl.n, "p": wl.p, "n_nodes": wl.n_nodes, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "kernel": "k_m2l<float,16> (all-pairs M2L, FP32)",
+            "bound": "alu",
+            "achieved": ach32 / 1e12,
+            "peak": PEAK_FP32 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": ach32 / PEAK_FP32,
+            "traffic": None,
+            "avg_ms": m2l32,
+            "launches": cnt32,
+            "algorithmic_flops_per_launch": flops,
+        },
+        "fp64": {
+            "value": value64, "unit": "matvecs/s", "ms_per_step": el64 / args.steps * 1e3,
+            "roofline": {"kernel": "k_m2l<double,16>", "bound": "alu", "achieved": ach64 / 1e12,
+                         "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach64 / PEAK_FP64,
+                         "avg_ms": m2l64, "launches": cnt64},
+        },
+        "mixed_vs_fp64_matvec_speedup": value / value64,
+        "setup_s": {"scattering_matrix": t_smat - t_setup0, "tables_and_first_matvec": t_setup1 - t_smat},
+        "finite_outputs": fin32 and fin64,
+    }
+
+    if not args.no_solve:
+        solves = {}
+        for name, prec in (("mixed", 1), ("fp64", 0)):
+            beta, meta = ctx.solve(wl.src[0], precision=prec, tol=wl.tol, maxiter=args.solve_maxiter,
+                                   inner_tol=1e-4)
+            solves[name] = {"seconds": meta["seconds"], "iterations": meta["iterations"],
+                            "fp64_matvecs": meta["fp64_matvecs"], "refinements": meta["refinements"],
+                            "rel_residual": meta["rel_residual"], "converged": meta["status"] == 0,
+                            "tol": wl.tol}
+            print(f"# solve {name}: {meta['iterations']} its, {meta['seconds']:.2f} s, "
+                  f"res {meta['rel_residual']:.2e}", file=sys.stderr, flush=True)
+        out["solve"] = solves
+        if solves["mixed"]["converged"] and solves["fp64"]["converged"]:
+            out["mixed_vs_fp64_solve_speedup"] = solves["fp64"]["seconds"] / solves["mixed"]["seconds"]
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(wl, S, x)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -89,6 +89,16 @@ int mpsl_set_layers(mpsl_ctx *ctx, mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, dou
  * Requires mpsl_set_layers first (uses k2).  Enclosing radius = R. */
 int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p);
 
+/* Star-shaped particles r(t) = a1 + a2 cos(a3 t), t the polar angle (Section 6,
+ * eq. (50)), wavenumber kp (real, > 0): prototype scattering matrix from
+ * Mueller's second-kind integral equations (Section 4, eqs. (31)-(32); outgoing
+ * coefficients by eq. (35)), Nystrom discretisation on n_bdry equispaced
+ * boundary points (even, 64..2048; 0 selects 256) with Kress's logarithmic
+ * product quadrature and Maue's identity for the hypersingular difference.
+ * Host FP64 precompute, O(n_bdry^3).  Enclosing radius a1 + |a2|.  Requires
+ * mpsl_set_layers first (uses k2). */
+int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c128 kp, int p, int n_bdry);
+
 /* Caller-supplied prototype scattering matrix (Section 4.1): S is P x P
  * row-major, S[(l + p) * P + (n + p)] maps incoming alpha_n to outgoing
  * beta_l, for the prototype at rotation 0.  r_enclose is the radius of the
@@ -109,6 +119,15 @@ int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *
  * length / max(distance to nearest Re k_i, b) is halved until (n_nodes-32)/32
  * panels exist; Gamma_3 mirrors Gamma_1.  Requires layers. */
 int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max);
+
+/* Context-free host computations (no device needed), same arithmetic as the
+ * set_* calls above: the disk and star scattering matrices (P x P, row-major)
+ * and the contour nodes and weights for layer wavenumbers k1, k2, k3. */
+int mpsl_compute_disk_smatrix(double R, mpsl_c128 k2, mpsl_c128 kp, int p, mpsl_c128 *S);
+int mpsl_compute_star_smatrix(double a1, double a2, int a3, mpsl_c128 k2, mpsl_c128 kp, int p, int n_bdry,
+                              mpsl_c128 *S);
+int mpsl_compute_contour(mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, int n_nodes, double b, double t_max,
+                         mpsl_c128 *lam, mpsl_c128 *w);
 
 /* Explicit contour: nodes lam[q] and weights w[q] (d lambda included). */
 int mpsl_set_contour_nodes(mpsl_ctx *ctx, int n_nodes, const mpsl_c128 *lam, const mpsl_c128 *w);

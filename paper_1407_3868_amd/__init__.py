@@ -47,6 +47,38 @@ def _carr(a, dtype=np.complex128):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
+def _host_check(rc, what):
+    if rc != 0:
+        raise MpslError(rc, what)
+
+
+def compute_disk_smatrix(R, k2, kp, p):
+    """Host: Mie scattering matrix of a disk (mirrors mpsl_compute_disk_smatrix)."""
+    lib = _lib.load()
+    S = np.zeros((2 * p + 1, 2 * p + 1), np.complex128)
+    _host_check(lib.mpsl_compute_disk_smatrix(float(R), _c(k2), _c(kp), int(p), S.ctypes.data), "disk matrix")
+    return S
+
+
+def compute_star_smatrix(a1, a2, a3, k2, kp, p, n_bdry=0):
+    """Host: star scattering matrix by the boundary-integral precompute."""
+    lib = _lib.load()
+    S = np.zeros((2 * p + 1, 2 * p + 1), np.complex128)
+    _host_check(lib.mpsl_compute_star_smatrix(float(a1), float(a2), int(a3), _c(k2), _c(kp), int(p), int(n_bdry),
+                                              S.ctypes.data), "star matrix")
+    return S
+
+
+def compute_contour(k1, k2, k3, n_nodes, b, t_max):
+    """Host: Sommerfeld contour nodes and weights (mirrors mpsl_compute_contour)."""
+    lib = _lib.load()
+    lam = np.zeros(n_nodes, np.complex128)
+    w = np.zeros(n_nodes, np.complex128)
+    _host_check(lib.mpsl_compute_contour(_c(k1), _c(k2), _c(k3), int(n_nodes), float(b), float(t_max),
+                                         lam.ctypes.data, w.ctypes.data), "contour")
+    return lam, w
+
+
 class Context:
     """One mpsl context on a HIP device (mirrors mpsl_create/mpsl_destroy)."""
 
@@ -84,6 +116,10 @@ class Context:
 
     def set_particle_disk(self, R, kp, p):
         return self._check(self.lib.mpsl_set_particle_disk(self.h, float(R), _c(kp), int(p)))
+
+    def set_particle_star(self, a1, a2, a3, kp, p, n_bdry=0):
+        return self._check(self.lib.mpsl_set_particle_star(self.h, float(a1), float(a2), int(a3), _c(kp), int(p),
+                                                           int(n_bdry)))
 
     def set_scattering_matrix(self, p, r_enclose, S):
         S = _carr(S)

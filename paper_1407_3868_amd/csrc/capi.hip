@@ -140,6 +140,100 @@ void invalidate(mpsl_ctx *ctx) { ctx->tables_ok = false; }
 
 }  // namespace
 
+// Diagonal Mie scattering matrix of a disk (Section 3.1, eq. (18) with the
+// denominator read as J_n(kp R)); S_{-n} = S_n.
+int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, std::vector<zc> &S, std::string &err) {
+  if (!(R > 0.0) || !(kp.re > 0.0) || p < kMinP || p > kMaxP) {
+    err = "disk needs R > 0, kp > 0 and 1 <= p <= 20";
+    return MPSL_EINVAL;
+  }
+  if (kp.im != 0.0) {
+    err = "disk particles need a real kp";
+    return MPSL_EUNSUPPORTED;
+  }
+  const int P = 2 * p + 1;
+  const double kpr = kp.re;
+  S.assign(static_cast<size_t>(P) * P, zc(0.0, 0.0));
+  for (int n = 0; n <= p; ++n) {
+    double ja, ya, jap, yap, jb, yb, jbp, ybp;
+    bessel_jy(n, k2 * R, ja, ya, jap, yap);
+    bessel_jy(n, kpr * R, jb, yb, jbp, ybp);
+    const zc H(ja, ya), Hp(jap, yap);
+    const zc num = kpr * ja * jbp - k2 * jap * jb;
+    const zc den = k2 * Hp * jb - kpr * jbp * H;
+    const zc s = num / den;
+    S[static_cast<size_t>(p + n) * P + (p + n)] = s;
+    S[static_cast<size_t>(p - n) * P + (p - n)] = s;
+  }
+  return MPSL_OK;
+}
+
+int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, std::vector<zc> &S,
+                 std::string &err);
+
+int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry,
+                         std::vector<zc> &S, std::string &err) {
+  if (!(a1 > 0.0) || !(std::fabs(a2) < a1) || a3 < 0 || !(kp.re > 0.0) || p < kMinP || p > kMaxP) {
+    err = "star needs a1 > |a2|, a3 >= 0, kp > 0 and 1 <= p <= 20";
+    return MPSL_EINVAL;
+  }
+  if (kp.im != 0.0) {
+    err = "star particles need a real kp";
+    return MPSL_EUNSUPPORTED;
+  }
+  const int nb = n_bdry > 0 ? n_bdry : 256;
+  if (nb % 2 || nb < 64 || nb > 2048) {
+    err = "n_bdry must be even, 64..2048";
+    return MPSL_EINVAL;
+  }
+  return star_smatrix(a1, a2, a3, k2, kp.re, p, nb, S, err);
+}
+
+// Contour nodes and weights in path order (rule stated in mpsl.h).
+int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_max, std::vector<zc> &lam,
+                 std::vector<zc> &w, std::string &err) {
+  if (n_nodes < 96 || (n_nodes - 32) % 32 != 0 || !(b > 0.0) || !(t_max > 0.0)) {
+    err = "n_nodes = 32 + 32 m (m >= 2), b > 0, t_max > 0";
+    return MPSL_EINVAL;
+  }
+  double gx[16], gwt[16];
+  gauss_legendre16(gx, gwt);
+  std::vector<std::pair<double, double>> pan;
+  if (!panel_rule((n_nodes - 32) / 32, b, t_max, ks, pan)) {
+    err = "too few nodes for the branch-point breakpoints";
+    return MPSL_EINVAL;
+  }
+  std::vector<double> t1, w1;
+  for (const auto &pc : pan) {
+    const double a = pc.first, c = pc.second;
+    for (int i = 0; i < 16; ++i) {
+      t1.push_back((a + c) / 2.0 + (c - a) / 2.0 * gx[i]);
+      w1.push_back((c - a) / 2.0 * gwt[i]);
+    }
+  }
+  const int n1 = static_cast<int>(t1.size());
+  lam.clear();
+  w.clear();
+  for (int i = n1 - 1; i >= 0; --i) {  // Gamma_3: mirror of Gamma_1, path order
+    lam.emplace_back(-t1[i], b);
+    w.emplace_back(w1[i], 0.0);
+  }
+  for (int hh = 0; hh < 2; ++hh)  // Gamma_2: lambda = -i s, s in [-b, 0] then [0, b]
+    for (int i = 0; i < 16; ++i) {
+      const double s = (hh == 0 ? -b / 2.0 : b / 2.0) + b / 2.0 * gx[i];
+      lam.emplace_back(0.0, -s);
+      w.emplace_back(0.0, -b / 2.0 * gwt[i]);
+    }
+  for (int i = 0; i < n1; ++i) {
+    lam.emplace_back(t1[i], -b);
+    w.emplace_back(w1[i], 0.0);
+  }
+  return MPSL_OK;
+}
+
+namespace {
+}  // namespace
+
 // Contour tables (host, FP64) and geometry tables (device).
 int build_tables(mpsl_ctx *ctx) {
   if (!ctx->has_layers || !ctx->has_particle || !ctx->has_geom || !ctx->has_contour)
@@ -396,24 +490,10 @@ static int upload_S(mpsl_ctx *ctx) {
 int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
   if (!ctx) return MPSL_EINVAL;
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
-  if (!(R > 0.0) || !(kp.re > 0.0) || p < mpsl::kMinP || p > mpsl::kMaxP)
-    return mpsl::set_err(ctx, MPSL_EINVAL, "disk needs R > 0, kp > 0 and 1 <= p <= 20");
-  if (kp.im != 0.0) return mpsl::set_err(ctx, MPSL_EUNSUPPORTED, "disk particles need a real kp");
-  const int P = 2 * p + 1;
-  const double k2 = ctx->k2.real(), kpr = kp.re;
-  std::vector<zc> S(static_cast<size_t>(P) * P, zc(0.0, 0.0));
-  for (int n = 0; n <= p; ++n) {
-    double ja, ya, jap, yap, jb, yb, jbp, ybp;
-    mpsl::bessel_jy(n, k2 * R, ja, ya, jap, yap);
-    mpsl::bessel_jy(n, kpr * R, jb, yb, jbp, ybp);
-    const zc H(ja, ya), Hp(jap, yap);
-    // eq. (18): beta_n / alpha_n (denominator with J_n(kp R))
-    const zc num = kpr * ja * jbp - k2 * jap * jb;
-    const zc den = k2 * Hp * jb - kpr * jbp * H;
-    const zc s = num / den;
-    S[static_cast<size_t>(p + n) * P + (p + n)] = s;
-    S[static_cast<size_t>(p - n) * P + (p - n)] = s;  // S_{-n} = S_n
-  }
+  std::vector<zc> S;
+  std::string err;
+  const int rc0 = mpsl::disk_smatrix(R, ctx->k2.real(), kp, p, S, err);
+  if (rc0) return mpsl::set_err(ctx, rc0, err);
   ctx->p = p;
   ctx->r_enc = R;
   ctx->S = S;
@@ -421,6 +501,44 @@ int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
   if (rc) return rc;
   ctx->has_particle = true;
   mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c128 kp, int p, int n_bdry) {
+  if (!ctx) return MPSL_EINVAL;
+  if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
+  std::vector<zc> S;
+  std::string err;
+  const int rc0 = mpsl::star_smatrix_checked(a1, a2, a3, ctx->k2.real(), kp, p, n_bdry, S, err);
+  if (rc0) return mpsl::set_err(ctx, rc0, err);
+  ctx->p = p;
+  ctx->r_enc = a1 + std::fabs(a2);
+  ctx->S = S;
+  int rc = upload_S(ctx);
+  if (rc) return rc;
+  ctx->has_particle = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_compute_disk_smatrix(double R, mpsl_c128 k2, mpsl_c128 kp, int p, mpsl_c128 *S) {
+  if (!S || k2.im != 0.0 || !(k2.re > 0.0)) return MPSL_EINVAL;
+  std::vector<zc> v;
+  std::string err;
+  const int rc = mpsl::disk_smatrix(R, k2.re, kp, p, v, err);
+  if (rc) return rc;
+  for (size_t i = 0; i < v.size(); ++i) S[i] = {v[i].real(), v[i].imag()};
+  return MPSL_OK;
+}
+
+int mpsl_compute_star_smatrix(double a1, double a2, int a3, mpsl_c128 k2, mpsl_c128 kp, int p, int n_bdry,
+                              mpsl_c128 *S) {
+  if (!S || k2.im != 0.0 || !(k2.re > 0.0)) return MPSL_EINVAL;
+  std::vector<zc> v;
+  std::string err;
+  const int rc = mpsl::star_smatrix_checked(a1, a2, a3, k2.re, kp, p, n_bdry, v, err);
+  if (rc) return rc;
+  for (size_t i = 0; i < v.size(); ++i) S[i] = {v[i].real(), v[i].imag()};
   return MPSL_OK;
 }
 
@@ -489,45 +607,29 @@ int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *
 int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max) {
   if (!ctx) return MPSL_EINVAL;
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
-  if (n_nodes < 96 || (n_nodes - 32) % 32 != 0 || !(b > 0.0) || !(t_max > 0.0))
-    return mpsl::set_err(ctx, MPSL_EINVAL, "n_nodes = 32 + 32 m (m >= 2), b > 0, t_max > 0");
-  double gx[16], gwt[16];
-  mpsl::gauss_legendre16(gx, gwt);
-  std::vector<std::pair<double, double>> pan;
-  const std::vector<double> ks = {ctx->k1.real(), ctx->k2.real(), ctx->k3.real()};
-  if (!mpsl::panel_rule((n_nodes - 32) / 32, b, t_max, ks, pan))
-    return mpsl::set_err(ctx, MPSL_EINVAL, "too few nodes for the branch-point breakpoints");
-  std::vector<double> t1, w1;
-  for (const auto &pc : pan) {
-    const double a = pc.first, c = pc.second;
-    for (int i = 0; i < 16; ++i) {
-      t1.push_back((a + c) / 2.0 + (c - a) / 2.0 * gx[i]);
-      w1.push_back((c - a) / 2.0 * gwt[i]);
-    }
-  }
-  const int n1 = static_cast<int>(t1.size());
   std::vector<zc> lam, w;
-  lam.reserve(n_nodes);
-  w.reserve(n_nodes);
-  for (int i = n1 - 1; i >= 0; --i) {  // Gamma_3: mirror of Gamma_1, path order
-    lam.emplace_back(-t1[i], b);
-    w.emplace_back(w1[i], 0.0);
-  }
-  for (int h = 0; h < 2; ++h)  // Gamma_2: lambda = -i s, s in [-b, 0] then [0, b]
-    for (int i = 0; i < 16; ++i) {
-      const double s = (h == 0 ? -b / 2.0 : b / 2.0) + b / 2.0 * gx[i];
-      lam.emplace_back(0.0, -s);
-      w.emplace_back(0.0, -b / 2.0 * gwt[i]);
-    }
-  for (int i = 0; i < n1; ++i) {
-    lam.emplace_back(t1[i], -b);
-    w.emplace_back(w1[i], 0.0);
-  }
+  std::string err;
+  const int rc = mpsl::make_contour({ctx->k1.real(), ctx->k2.real(), ctx->k3.real()}, n_nodes, b, t_max, lam, w, err);
+  if (rc) return mpsl::set_err(ctx, rc, err);
   ctx->lam = lam;
   ctx->w = w;
   ctx->ns = n_nodes;
   ctx->has_contour = true;
   mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_compute_contour(mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, int n_nodes, double b, double t_max,
+                         mpsl_c128 *lam, mpsl_c128 *w) {
+  if (!lam || !w) return MPSL_EINVAL;
+  std::vector<zc> l, ww;
+  std::string err;
+  const int rc = mpsl::make_contour({k1.re, k2.re, k3.re}, n_nodes, b, t_max, l, ww, err);
+  if (rc) return rc;
+  for (int i = 0; i < n_nodes; ++i) {
+    lam[i] = {l[i].real(), l[i].imag()};
+    w[i] = {ww[i].real(), ww[i].imag()};
+  }
   return MPSL_OK;
 }
 

@@ -98,6 +98,11 @@ namespace mpsl {
 int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes);
 void dev_free(DBuf &b);
 int set_err(mpsl_ctx *ctx, int code, const std::string &msg);
+int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, std::vector<zc> &S, std::string &err);
+int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry,
+                         std::vector<zc> &S, std::string &err);
+int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_max, std::vector<zc> &lam,
+                 std::vector<zc> &w, std::string &err);
 int build_tables(mpsl_ctx *ctx);
 int ensure_work(mpsl_ctx *ctx);
 }  // namespace mpsl
