@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--solve-maxiter", type=int, default=1500)
+    ap.add_argument("--no-autotune", action="store_true", help="use the default M2L launch shape")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -96,6 +99,12 @@ def main():
     from synth import make_workload
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = make_workload("c3")
     a1, a2, a3 = wl.shape_params
 
@@ -118,6 +127,13 @@ def main():
     ctx.apply_dev(0, xd, yd)
     torch.cuda.synchronize()
     t_setup1 = time.perf_counter()
+    # launch-shape autotuning of the M2L kernel, per precision (before timing)
+    tuning = {}
+    for name, prec in (("fp32", 1), ("fp64", 0)):
+        if not args.no_autotune:
+            ctx.autotune(prec)
+        tuning[name] = ctx.get_tuning(prec)
+    t_tune = time.perf_counter()
 
     el32, m2l32, cnt32, fin32 = _matvec_rate(ctx, torch, 1, x, args.steps, args.warmup)
     el64, m2l64, cnt64, fin64 = _matvec_rate(ctx, torch, 0, x, args.steps, args.warmup)
@@ -164,7 +180,9 @@ def main():
                          "avg_ms": m2l64, "launches": cnt64},
         },
         "mixed_vs_fp64_matvec_speedup": value / value64,
-        "setup_s": {"scattering_matrix": t_smat - t_setup0, "tables_and_first_matvec": t_setup1 - t_smat},
+        "setup_s": {"scattering_matrix": t_smat - t_setup0, "tables_and_first_matvec": t_setup1 - t_smat,
+                    "autotune": t_tune - t_setup1},
+        "m2l_tuning": tuning,
         "finite_outputs": fin32 and fin64,
     }
 

@@ -226,6 +226,19 @@ int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *
 int mpsl_eval_field(mpsl_ctx *ctx, const double *src_xy, const mpsl_c128 *beta,
                     int64_t n_rcv, const double *rcv_xy, mpsl_c128 *u_out);
 
+/* Launch-shape tuning of the M2L kernel (row a1), per precision.  Variants:
+ * 0 = one lane per target holding all P accumulators; 1 = two lanes per target
+ * (output halves, the upper half through the mirror symmetry of the Toeplitz
+ * translation) for more waves per SIMD at twice the recurrence work.
+ * mpsl_autotune times both variants at 1/2, 1 and 2 times the default number
+ * of source chunks on the current problem (pseudo-random input, HIP events on
+ * the context stream) and keeps the fastest; mpsl_set_tuning forces a choice
+ * (chunks 0 = default).  Tuning is kept until changed; it never changes
+ * results beyond floating-point summation order. */
+int mpsl_autotune(mpsl_ctx *ctx, int prec);
+int mpsl_set_tuning(mpsl_ctx *ctx, int prec, int variant, int chunks);
+int mpsl_get_tuning(const mpsl_ctx *ctx, int prec, int *variant, int *chunks, double *m2l_ms);
+
 /* Average duration (ms) of the last `count` launches of the M2L kernel
  * recorded with HIP events on the context stream (0 when not recorded);
  * enable recording with mpsl_profile(ctx, 1). */

@@ -218,6 +218,17 @@ class Context:
                                              r.ctypes.data, u.ctypes.data), allow=(-8,))
         return u
 
+    def autotune(self, prec):
+        return self._check(self.lib.mpsl_autotune(self.h, int(prec)))
+
+    def set_tuning(self, prec, variant, chunks=0):
+        return self._check(self.lib.mpsl_set_tuning(self.h, int(prec), int(variant), int(chunks)))
+
+    def get_tuning(self, prec):
+        v, c, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(self.lib.mpsl_get_tuning(self.h, int(prec), ctypes.byref(v), ctypes.byref(c), ctypes.byref(ms)))
+        return dict(variant=v.value, chunks=c.value, m2l_ms=ms.value)
+
     def profile(self, enable=True):
         return self._check(self.lib.mpsl_profile(self.h, 1 if enable else 0))
 

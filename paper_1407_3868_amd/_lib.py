@@ -62,6 +62,9 @@ SIGNATURES = {
     "mpsl_rhs": (I, [P, P, P]),
     "mpsl_solve": (I, [P, I, P, ctypes.POINTER(Opts), P, ctypes.POINTER(Info)]),
     "mpsl_eval_field": (I, [P, P, P, L, P, P]),
+    "mpsl_autotune": (I, [P, I]),
+    "mpsl_set_tuning": (I, [P, I, I, I]),
+    "mpsl_get_tuning": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), DP]),
     "mpsl_profile": (I, [P, I]),
     "mpsl_profile_read": (I, [P, DP, ctypes.POINTER(I)]),
 }

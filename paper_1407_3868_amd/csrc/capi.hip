@@ -351,7 +351,8 @@ int build_tables(mpsl_ctx *ctx) {
 int ensure_work(mpsl_ctx *ctx) {
   const int P = 2 * ctx->p + 1;
   const size_t len = static_cast<size_t>(ctx->n) * P;
-  const int ca = chunks_m2l(ctx), cb = chunks_s2l(ctx), cc = chunks_m2s(ctx);
+  const int ca = std::max(chunks_m2l(ctx, MPSL_FP64), chunks_m2l(ctx, MPSL_FP32));
+  const int cb = chunks_s2l(ctx), cc = chunks_m2s(ctx);
   int rc;
   if ((rc = dev_alloc(ctx, ctx->part, (ca + cb) * len * sizeof(double2))) ||
       (rc = dev_alloc(ctx, ctx->m2s_part, 2ull * cc * ctx->ns * sizeof(double2))) ||
@@ -368,11 +369,13 @@ int ensure_work(mpsl_ctx *ctx) {
 int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y) {
   int rc = build_tables(ctx);
   if (rc) return rc;
-  const int ca = chunks_m2l(ctx), cb = chunks_s2l(ctx);
+  const int ca = chunks_m2l(ctx, prec), cb = chunks_s2l(ctx);
+  const int sa = m2l_slots(ctx, prec);
   const int P = 2 * ctx->p + 1;
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
+  if ((rc = dev_alloc(ctx, ctx->part, static_cast<size_t>(sa + cb) * ctx->n * P * esz))) return rc;
   char *part = static_cast<char *>(ctx->part.p);
-  char *part_b = part + static_cast<size_t>(ca) * ctx->n * P * esz;
+  char *part_b = part + static_cast<size_t>(sa) * ctx->n * P * esz;
   if ((rc = launch_m2s(ctx, prec, x, ctx->spec.p))) return rc;
   if ((rc = launch_reflect(ctx, ctx->spec.p, nullptr, ctx->sigma.p))) return rc;
   if ((rc = launch_s2l_coef(ctx, ctx->sigma.p))) return rc;
@@ -389,7 +392,7 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y) {
     ctx->ev_start.push_back(e0);
     ctx->ev_stop.push_back(e1);
   }
-  return launch_sapply(ctx, prec, x, part, ca + cb, y);
+  return launch_sapply(ctx, prec, x, part, sa + cb, y);
 }
 
 }  // namespace mpsl
@@ -696,9 +699,11 @@ int mpsl_m2l_dev(mpsl_ctx *ctx, int prec, const void *beta, void *alpha) {
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
-  const int ca = mpsl::chunks_m2l(ctx);
+  const int ca = mpsl::chunks_m2l(ctx, prec);
+  const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
+  if ((rc = mpsl::dev_alloc(ctx, ctx->part, static_cast<size_t>(ca) * ctx->n * (2 * ctx->p + 1) * esz))) return rc;
   if ((rc = mpsl::launch_m2l(ctx, prec, beta, ctx->part.p, ca))) return rc;
-  return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, ca, alpha);
+  return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, mpsl::m2l_slots(ctx, prec), alpha);
 }
 
 int mpsl_m2s_dev(mpsl_ctx *ctx, int prec, const void *beta, void *spec) {
@@ -760,6 +765,75 @@ int mpsl_profile_read(mpsl_ctx *ctx, double *ms_avg, int *count) {
   if (ms_avg) *ms_avg = c ? tot / c : 0.0;
   if (count) *count = c;
   return MPSL_OK;
+}
+
+int mpsl_set_tuning(mpsl_ctx *ctx, int prec, int variant, int chunks) {
+  if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32) || (variant != mpsl::kM2LWhole && variant != mpsl::kM2LHalves) ||
+      chunks < 0)
+    return MPSL_EINVAL;
+  auto &t = ctx->tune[prec == MPSL_FP64 ? 0 : 1];
+  t.variant = variant;
+  t.chunks = chunks;
+  t.ms = 0.0;
+  return MPSL_OK;
+}
+
+int mpsl_get_tuning(const mpsl_ctx *ctx, int prec, int *variant, int *chunks, double *ms) {
+  if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  const auto &t = ctx->tune[prec == MPSL_FP64 ? 0 : 1];
+  if (variant) *variant = t.variant;
+  if (chunks) *chunks = mpsl::chunks_m2l(ctx, prec);
+  if (ms) *ms = t.ms;
+  return MPSL_OK;
+}
+
+int mpsl_autotune(mpsl_ctx *ctx, int prec) {
+  if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  auto &t = ctx->tune[prec == MPSL_FP64 ? 0 : 1];
+  t.chunks = 0;
+  const int base = mpsl::chunks_m2l(ctx, prec);
+  const int P = 2 * ctx->p + 1;
+  const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
+  const size_t len = static_cast<size_t>(ctx->n) * P;
+  if ((rc = mpsl::dev_alloc(ctx, ctx->xbuf, len * esz))) return rc;
+  if ((rc = mpsl::launch_fill_hash(ctx, prec, ctx->xbuf.p, static_cast<int64_t>(len), 12345u))) return rc;
+  const int cands[3] = {std::max(1, base / 2), base, static_cast<int>(std::min<int64_t>(2LL * base, ctx->n))};
+  hipEvent_t e0, e1;
+  MPSL_HIP_TRY(ctx, hipEventCreate(&e0));
+  MPSL_HIP_TRY(ctx, hipEventCreate(&e1));
+  double best = 1e300;
+  int bv = mpsl::kM2LWhole, bc = base;
+  for (int variant = mpsl::kM2LWhole; variant <= mpsl::kM2LHalves; ++variant)
+    for (int c : cands) {
+      if ((rc = mpsl::dev_alloc(ctx, ctx->part, static_cast<size_t>(c) * len * esz))) break;
+      if ((rc = mpsl::launch_m2l(ctx, prec, ctx->xbuf.p, ctx->part.p, c, variant))) break;  // warm-up
+      if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = MPSL_EHIP; break; }
+      const int reps = 3;
+      for (int r = 0; r < reps && !rc; ++r) rc = mpsl::launch_m2l(ctx, prec, ctx->xbuf.p, ctx->part.p, c, variant);
+      if (rc) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = MPSL_EHIP;
+        break;
+      }
+      const double avg = ms / reps;
+      if (avg < best) {
+        best = avg;
+        bv = variant;
+        bc = c;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return mpsl::set_err(ctx, rc, "autotune failed: " + ctx->err);
+  t.variant = bv;
+  t.chunks = bc;
+  t.ms = best;
+  return mpsl::ensure_work(ctx);
 }
 
 }  // extern "C"

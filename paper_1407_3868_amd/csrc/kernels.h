@@ -15,8 +15,11 @@ int launch_geom_tables(mpsl_ctx *ctx);
 // Row a0 (pairs): H_0, H_1, direction and 2/z of every ordered particle pair.
 int launch_pair_tables(mpsl_ctx *ctx);
 
-// Row a1: partial local expansions of the all-pairs M2L into part[0 .. chunks).
-int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks);
+// Row a1: partial local expansions of the all-pairs M2L into
+// part[0 .. chunks).  variant: kM2LWhole, kM2LHalves, or -1 for the tuned one.
+constexpr int kM2LWhole = 0;
+constexpr int kM2LHalves = 1;
+int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant = -1);
 // Row b1: M2S partial spectra and their reduction to spec (double2[2*ns]).
 int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec);
 // Row b2: sigma = R spec (+ source), and the scaled S2L coefficient tables.
@@ -39,12 +42,17 @@ int launch_scale(mpsl_ctx *ctx, void *v, int64_t len, double s, const void *src)
 int launch_axpy_c(mpsl_ctx *ctx, void *y, const void *x, int64_t len, double a_re, double a_im);
 int launch_to_fp32(mpsl_ctx *ctx, const void *x64, void *x32, int64_t len);
 int launch_to_fp64(mpsl_ctx *ctx, const void *x32, void *x64, int64_t len);
+// Deterministic pseudo-random complex vector (n_complex entries) in precision prec.
+int launch_fill_hash(mpsl_ctx *ctx, int prec, void *v, int64_t n_complex, uint32_t seed);
 
 // Row a7: field at receivers.  sig4: double2[4][ns] (sigma_1, sigma_2^+, sigma_2^-, sigma_3).
 int launch_field(mpsl_ctx *ctx, const void *beta, const void *sig4, const double *src, int64_t nr,
                  const void *rcv, void *u);
 
-int chunks_m2l(const mpsl_ctx *ctx);
+// Source chunks of the M2L grid for precision prec (tuned, set, or automatic).
+int chunks_m2l(const mpsl_ctx *ctx, int prec);
+// Partial buffers written by one M2L launch.
+inline int m2l_slots(const mpsl_ctx *ctx, int prec) { return chunks_m2l(ctx, prec); }
 int chunks_s2l(const mpsl_ctx *ctx);
 int chunks_m2s(const mpsl_ctx *ctx);
 

@@ -96,62 +96,72 @@ __global__ void k_pair_tables(const double2 *__restrict__ xy, int n, double k2, 
 // H_{q+1} = (2q/z) H_q - H_{q-1}, e^{iq phi} by repeated multiplication,
 // h_q = H_q e^{iq phi}, h_{-q} = (-1)^q H_q e^{-iq phi}, and the Toeplitz
 // product alpha_{n'} += sum_nu h_{nu - n'} beta_nu consumed in the order the
-// recurrence produces h_q.  The coefficient slots [NU0, NU1] of the source
-// are handled by one pass; FP64 runs two passes so that each half of beta
-// fits the scalar register file.
-template <typename T, int p, int NU0, int NU1>
-__device__ __forceinline__ void m2l_pass(cx<T> (&acc)[2 * p + 1], const cv_t<T> *__restrict__ bm, cx<T> h0,
-                                         cx<T> h1, cx<T> t, T two_over_z) {
-  constexpr int P = 2 * p + 1;
-  cx<T> bv[P];
+// recurrence produces h_q.
+//
+// m2l_block adds the contribution of source slots [V0, V1] to output slots
+// [O0, O1].  FP32 does everything in one call (33 accumulators, 66 scalar
+// registers of beta at p = 16).  FP64 splits the outputs over two lanes and
+// the source coefficients over two calls: 17 accumulators and at most 68
+// scalar registers of beta, at the cost of re-running the recurrence.
+template <typename T, int p, int O0, int O1, int V0, int V1, bool MIRROR>
+__device__ __forceinline__ void m2l_block(cx<T> (&acc)[O1 - O0 + 1], const cv_t<T> *__restrict__ bm, cx<T> h0,
+                                          cx<T> h1, cx<T> t, T two_over_z) {
+  constexpr int QA = V1 - O0, QB = O1 - V0;
+  constexpr int QMAX = (QA > QB ? QA : QB) < 2 * p ? (QA > QB ? QA : QB) : 2 * p;
+  cx<T> bv[V1 - V0 + 1];
 #pragma unroll
-  for (int i = NU0; i <= NU1; ++i) bv[i] = ld<T>(bm[i]);
+  for (int v = V0; v <= V1; ++v) bv[v - V0] = ld<T>(bm[MIRROR ? 2 * p - v : v]);
 #pragma unroll
-  for (int i = NU0; i <= NU1; ++i) cmac(acc[i], h0, bv[i]);
+  for (int v = (V0 > O0 ? V0 : O0); v <= (V1 < O1 ? V1 : O1); ++v) cmac(acc[v - O0], h0, bv[v - V0]);
   cx<T> hprev = h0, hcur = h1, tq = t;
 #pragma unroll
-  for (int q = 1; q <= 2 * p; ++q) {
+  for (int q = 1; q <= QMAX; ++q) {
     if (q >= 2) {
       const cx<T> hn = static_cast<T>(q - 1) * two_over_z * hcur - hprev;
       hprev = hcur;
       hcur = hn;
       tq = tq * t;
     }
-    if (NU1 >= q) {  // alpha_{nu-q} += h_q beta_nu
+    // alpha_{v-q} += h_q beta_v for v - q in [O0, O1]
+    if ((V1 < O1 + q ? V1 : O1 + q) >= (V0 > O0 + q ? V0 : O0 + q)) {
       const cx<T> hp = hcur * tq;
 #pragma unroll
-      for (int v = (NU0 > q ? NU0 : q); v <= NU1; ++v) cmac(acc[v - q], hp, bv[v]);
+      for (int v = (V0 > O0 + q ? V0 : O0 + q); v <= (V1 < O1 + q ? V1 : O1 + q); ++v)
+        cmac(acc[v - q - O0], hp, bv[v - V0]);
     }
-    if (NU0 <= P - 1 - q) {  // alpha_{nu+q} += h_{-q} beta_nu
+    // alpha_{v+q} += h_{-q} beta_v for v + q in [O0, O1]
+    if ((V1 < O1 - q ? V1 : O1 - q) >= (V0 > O0 - q ? V0 : O0 - q)) {
       cx<T> hm = hcur * conj(tq);
       if (q & 1) hm = mk<T>(-hm.re, -hm.im);
 #pragma unroll
-      for (int v = NU0; v <= (NU1 < P - 1 - q ? NU1 : P - 1 - q); ++v) cmac(acc[v + q], hm, bv[v]);
+      for (int v = (V0 > O0 - q ? V0 : O0 - q); v <= (V1 < O1 - q ? V1 : O1 - q); ++v)
+        cmac(acc[v + q - O0], hm, bv[v - V0]);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-template <typename T, int p>
-__global__ __launch_bounds__(kThreads) void k_m2l(const cv_t<T> *__restrict__ pairs,
-                                                  const cv_t<T> *__restrict__ beta,
-                                                  cv_t<T> *__restrict__ part, int n, int chunk_len) {
+// Mirror identity: with reversed indices (alpha~_k = alpha_{-k},
+// beta~_nu = beta_{-nu}) the translation keeps its Toeplitz form with
+// h~_q = h_{-q} = H_q e^{iq(pi - phi)}, i.e. e^{i phi} -> -conj(e^{i phi}).
+// MIRROR = true computes output slots 2p - [O0, O1] that way.
+template <typename T, int p, int O0, int O1, int SPLIT, bool MIRROR>
+__device__ __forceinline__ void m2l_body(const cv_t<T> *__restrict__ pairs, const cv_t<T> *__restrict__ beta,
+                                         cv_t<T> *__restrict__ part, int n, int m0, int m1, int l) {
   constexpr int P = 2 * p + 1;
-  const int l = blockIdx.x * kThreads + threadIdx.x;
-  const int c = blockIdx.y;
-  const int m0 = c * chunk_len;
-  const int m1 = min(n, m0 + chunk_len);
+  constexpr int NO = O1 - O0 + 1;
   const bool valid = l < n;
   const int lc = valid ? l : n - 1;
-  cx<T> acc[P];
+  cx<T> acc[NO];
 #pragma unroll
-  for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
+  for (int i = 0; i < NO; ++i) acc[i] = mk<T>(0, 0);
   if (m0 < m1) {
     const cv_t<T> *pe = pairs + 4 * (static_cast<int64_t>(m0) * n + lc);
     cv_t<T> a0 = pe[0], a1 = pe[1], a2 = pe[2], a3 = pe[3];
     for (int m = m0; m < m1; ++m) {
       cx<T> h0 = ld<T>(a0), h1 = ld<T>(a1);
-      const cx<T> t = ld<T>(a2);
+      cx<T> t = ld<T>(a2);
+      if (MIRROR) t.re = -t.re;
       const T two_over_z = a3.x;
       if (m + 1 < m1) {  // prefetch the next source's pair entry
         pe += 4 * static_cast<int64_t>(n);
@@ -162,19 +172,45 @@ __global__ __launch_bounds__(kThreads) void k_m2l(const cv_t<T> *__restrict__ pa
       }
       if (!valid) h0 = h1 = mk<T>(0, 0);
       const cv_t<T> *bm = beta + static_cast<int64_t>(m) * P;
-      if (std::is_same<T, double>::value) {
-        m2l_pass<T, p, 0, p>(acc, bm, h0, h1, t, two_over_z);
-        m2l_pass<T, p, p + 1, P - 1>(acc, bm, h0, h1, t, two_over_z);
+      if (SPLIT) {  // source coefficients in two halves, one scalar-register set each
+        m2l_block<T, p, O0, O1, 0, p, MIRROR>(acc, bm, h0, h1, t, two_over_z);
+        __builtin_amdgcn_sched_barrier(0);
+        m2l_block<T, p, O0, O1, p + 1, P - 1, MIRROR>(acc, bm, h0, h1, t, two_over_z);
+        __builtin_amdgcn_sched_barrier(0);
       } else {
-        m2l_pass<T, p, 0, P - 1>(acc, bm, h0, h1, t, two_over_z);
+        m2l_block<T, p, O0, O1, 0, P - 1, MIRROR>(acc, bm, h0, h1, t, two_over_z);
       }
     }
   }
   if (valid) {
-    cv_t<T> *o = part + (static_cast<int64_t>(c) * n + l) * P;
 #pragma unroll
-    for (int i = 0; i < P; ++i) o[i] = st(acc[i]);
+    for (int i = 0; i < NO; ++i) part[static_cast<int64_t>(l) * P + (MIRROR ? 2 * p - O0 - i : O0 + i)] = st(acc[i]);
   }
+}
+
+// grid: (target blocks, source chunks); part[chunk][n][P].  Two variants:
+//  whole  (HALF = -1): one lane holds all P accumulators of its target;
+//  halves (HALF = 0, 1, two launches): output slots [0, p] and, through the
+//         mirror identity, [p+1, 2p], at most p+1 accumulators per lane and
+//         more waves per SIMD, for twice the recurrence work.  The two halves
+//         are separate kernels: in one kernel the compiler merges the bodies
+//         and doubles the live registers.
+// FP64 always takes the source coefficients in two scalar-register halves.
+// The launcher runs the variant the autotuner picked (default: whole).
+template <typename T, int p, int HALF>
+__global__ __launch_bounds__(kThreads) void k_m2l(const cv_t<T> *__restrict__ pairs,
+                                                  const cv_t<T> *__restrict__ beta,
+                                                  cv_t<T> *__restrict__ part, int n, int chunk_len) {
+  constexpr int P = 2 * p + 1;
+  const int l = blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  const int m0 = c * chunk_len;
+  const int m1 = min(n, m0 + chunk_len);
+  cv_t<T> *o = part + static_cast<int64_t>(c) * n * P;
+  constexpr int SPLIT = std::is_same<T, double>::value ? 1 : 0;
+  if (HALF == 0) m2l_body<T, p, 0, p, SPLIT, false>(pairs, beta, o, n, m0, m1, l);
+  else if (HALF == 1) m2l_body<T, p, 0, p - 1, SPLIT, true>(pairs, beta, o, n, m0, m1, l);
+  else m2l_body<T, p, 0, P - 1, SPLIT, false>(pairs, beta, o, n, m0, m1, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,6 +462,31 @@ __global__ void k_axpy_c(double2 *__restrict__ y, const double2 *__restrict__ x,
   y[i] = st(r);
 }
 
+// Deterministic pseudo-random fill in [-1, 1) (tuning input with realistic
+// operand switching; zero operands run faster and mislead the tuner).
+__global__ void k_fill_hash(double *__restrict__ v, int64_t len, uint32_t seed) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  uint32_t h = static_cast<uint32_t>(i) * 2654435761u ^ seed;
+  h ^= h >> 16;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  h *= 3266489917u;
+  h ^= h >> 16;
+  v[i] = static_cast<double>(h) * (2.0 / 4294967296.0) - 1.0;
+}
+__global__ void k_fill_hash32(float *__restrict__ v, int64_t len, uint32_t seed) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  uint32_t h = static_cast<uint32_t>(i) * 2654435761u ^ seed;
+  h ^= h >> 16;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  h *= 3266489917u;
+  h ^= h >> 16;
+  v[i] = static_cast<float>(static_cast<double>(h) * (2.0 / 4294967296.0) - 1.0);
+}
+
 __global__ void k_to32(const double2 *__restrict__ a, float2 *__restrict__ b, int64_t len) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i < len) b[i] = make_float2(static_cast<float>(a[i].x), static_cast<float>(a[i].y));
@@ -514,7 +575,9 @@ __global__ void k_field(const double2 *__restrict__ xy, const double2 *__restric
 
 }  // namespace
 
-int chunks_m2l(const mpsl_ctx *ctx) {
+int chunks_m2l(const mpsl_ctx *ctx, int prec) {
+  const int tuned = ctx->tune[prec == MPSL_FP64 ? 0 : 1].chunks;
+  if (tuned > 0) return static_cast<int>(std::min<int64_t>(tuned, ctx->n));
   if (ctx->m2l_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2l_chunks, ctx->n));
   const int tb = cdiv(ctx->n, kThreads);
   const int c = cdiv(2560, tb);
@@ -564,17 +627,24 @@ int launch_pair_tables(mpsl_ctx *ctx) {
 }
 
 template <typename T>
-static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks) {
+static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks, int variant) {
   const int n = static_cast<int>(ctx->n);
   const int chunk_len = cdiv(n, chunks);
-  const dim3 grid(cdiv(n, kThreads), chunks);
   const bool f64 = std::is_same<T, double>::value;
+  const dim3 grid(cdiv(n, kThreads), chunks);
   const auto *pairs = static_cast<const cv_t<T> *>(f64 ? ctx->gt.pair64.p : ctx->gt.pair32.p);
   const auto *b = static_cast<const cv_t<T> *>(beta);
   auto *o = static_cast<cv_t<T> *>(part);
   switch (ctx->p) {
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_m2l<T, PP>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len); break;
+#define X(PP)                                                                                                     \
+  case PP:                                                                                                        \
+    if (variant == kM2LHalves) {                                                                                  \
+      hipLaunchKernelGGL((k_m2l<T, PP, 0>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len);   \
+      hipLaunchKernelGGL((k_m2l<T, PP, 1>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len);   \
+    } else {                                                                                                      \
+      hipLaunchKernelGGL((k_m2l<T, PP, -1>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len);  \
+    }                                                                                                             \
+    break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
@@ -583,9 +653,10 @@ static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks)
   return MPSL_OK;
 }
 
-int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks) {
-  return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks)
-                           : launch_m2l_t<float>(ctx, beta, part, chunks);
+int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant) {
+  if (variant < 0) variant = ctx->tune[prec == MPSL_FP64 ? 0 : 1].variant;
+  return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks, variant)
+                           : launch_m2l_t<float>(ctx, beta, part, chunks, variant);
 }
 
 template <typename T>
@@ -739,6 +810,16 @@ int launch_axpy_c(mpsl_ctx *ctx, void *y, const void *x, int64_t len, double a_r
 int launch_to_fp32(mpsl_ctx *ctx, const void *x64, void *x32, int64_t len) {
   hipLaunchKernelGGL(k_to32, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<const double2 *>(x64),
                      static_cast<float2 *>(x32), len);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_fill_hash(mpsl_ctx *ctx, int prec, void *v, int64_t n_complex, uint32_t seed) {
+  const int64_t len = 2 * n_complex;
+  if (prec == MPSL_FP64)
+    hipLaunchKernelGGL(k_fill_hash, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<double *>(v), len, seed);
+  else
+    hipLaunchKernelGGL(k_fill_hash32, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<float *>(v), len, seed);
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }

@@ -222,3 +222,41 @@ def test_highest_order(torch_dev):
     ctx = gpu_context(wl)
     x = coeff_vector(wl, 9)
     assert rel_err(ctx.apply(0, x), pr.matvec(x)) < FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["s70p8", "s150p12", "s200p16"])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("variant,chunks", [(0, 3), (1, 0), (1, 7)])
+def test_m2l_variants(name, prec, variant, chunks, torch_dev):
+    # both launch shapes (whole / output halves through the mirror identity) and
+    # several source-chunk counts give the oracle's translation
+    torch = torch_dev
+    wl, pr, ctx = _setup(name)
+    ctx.set_tuning(prec, variant, chunks)
+    x = coeff_vector(wl, 12)
+    ref = oops.m2l_apply(wl.xy, wl.k2, wl.p, x)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    xd = _dev(torch, x, np.complex128 if prec == 0 else np.complex64)
+    ad = _zeros(torch, (wl.n, wl.P), dt)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.m2l_dev(prec, xd, ad)
+    torch.cuda.synchronize()
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    assert rel_err(ad.cpu().numpy(), ref) < tol
+    y = ctx.apply(prec, x.astype(np.complex128 if prec == 0 else np.complex64))
+    assert rel_err(y, pr.matvec(x)) < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_autotune_keeps_results(prec, torch_dev):
+    wl, pr, ctx = _setup("s200p16")
+    x = coeff_vector(wl, 13)
+    npdt = np.complex128 if prec == 0 else np.complex64
+    before = ctx.apply(prec, x.astype(npdt))
+    ctx.autotune(prec)
+    t = ctx.get_tuning(prec)
+    assert t["variant"] in (0, 1) and t["chunks"] >= 1 and t["m2l_ms"] > 0
+    after = ctx.apply(prec, x.astype(npdt))
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    assert rel_err(after, pr.matvec(x)) < tol
+    assert rel_err(after, before) < tol
