@@ -76,6 +76,103 @@ def _cpu_baseline(wl, S, x, n_targets=24):
                        f"{per_matvec:.1f} s per full matvec")}
 
 
+def _batch_workload(args, torch, mp):
+    """64 sources over one 2000-star p = 12 geometry, and 32 perturbed configurations."""
+    import numpy as np
+
+    from synth import make_workload, perturbed_layout, rejection_layout
+
+    wl = make_workload("c4", n_rhs=64, src_seed=4)
+    a1, a2, a3 = wl.shape_params
+    S = mp.compute_star_smatrix(a1, a2, a3, wl.k2, wl.kp, wl.p, 256)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def context(xy, rot, d, b):
+        c = mp.Context(0)
+        c.set_stream(stream)
+        c.set_layers(wl.k1, wl.k2, wl.k3, d)
+        c.set_scattering_matrix(wl.p, wl.r_enclose, S)
+        c.set_geometry(xy, rot)
+        c.set_contour(wl.n_nodes, b, wl.t_max)
+        return c
+
+    out = {"workload": "64 point sources over 2000 stars (p=12, 512 nodes); 32 perturbed configurations, "
+                       "N log-uniform in [500, 4000]"}
+    ctx = context(wl.xy, wl.rot, wl.d, wl.b)
+    R = wl.src.shape[0]
+    X = np.stack([ctx.rhs(s) for s in wl.src])
+    res = {}
+    for name, prec in (("fp32", 1), ("fp64", 0)):
+        ctx.autotune(prec)
+        npdt = np.complex64 if prec == 1 else np.complex128
+        xd = torch.from_numpy(X.astype(npdt)).cuda()
+        yd = torch.zeros_like(xd)
+        for _ in range(args.warmup):
+            ctx.apply_batch_dev(prec, R, xd, yd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.apply_batch_dev(prec, R, xd, yd)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / args.steps
+        x1, y1 = xd[0].contiguous(), yd[0].clone()
+        for _ in range(args.warmup):
+            ctx.apply_dev(prec, x1, y1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for r in range(R):
+                ctx.apply_dev(prec, xd[r], yd[r])
+        torch.cuda.synchronize()
+        t_loop = (time.perf_counter() - t0) / args.steps
+        flops = 8.0 * wl.P ** 2 * wl.n * (wl.n - 1) * R
+        res[name] = {"rhs_matvecs_per_s": R / t_batch, "ms_per_batch": t_batch * 1e3,
+                     "ms_per_64_single_matvecs": t_loop * 1e3, "batched_vs_loop": t_loop / t_batch,
+                     "m2l_tflops_equivalent": flops / t_batch / 1e12}
+    out["multi_rhs"] = res
+
+    rng = np.random.default_rng(5)
+    ns = np.round(np.exp(rng.uniform(np.log(500), np.log(4000), 32))).astype(int)
+    ctxs, xs, ys, pairs = [], [], [], 0
+    for i, n in enumerate(ns):
+        width = n / (0.3 * 18.0)
+        xy, rot = rejection_layout(int(n), (-width / 2, width / 2), (-19.0, -1.0), 0.75, 100 + i)
+        xy, rot = perturbed_layout(xy, rot, 0.05, 200 + i, 0.75, y_range=(-19.6, -0.4))
+        c = context(xy, rot, 20.0, min(0.2, 2.0 / width))
+        ctxs.append(c)
+        pairs += int(n) * (int(n) - 1)
+    cfg = {}
+    for name, prec in (("fp32", 1), ("fp64", 0)):
+        npdt = np.complex64 if prec == 1 else np.complex128
+        xs = [torch.from_numpy(np.stack([c.rhs(np.array([0.0, 2.0]))]).astype(npdt)).cuda() for c in ctxs]
+        ys = [torch.zeros_like(x) for x in xs]
+        t0 = time.perf_counter()
+        batch = mp.Batch([(c, prec, 1, x, y) for c, x, y in zip(ctxs, xs, ys)])
+        t_cap = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            batch.launch(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.launch(stream)
+        torch.cuda.synchronize()
+        t_graph = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for c, x, y in zip(ctxs, xs, ys):
+                c.apply_dev(prec, x, y)
+        torch.cuda.synchronize()
+        t_eager = (time.perf_counter() - t0) / args.steps
+        batch.close()
+        cfg[name] = {"config_matvecs_per_s": len(ctxs) / t_graph, "ms_per_graph": t_graph * 1e3,
+                     "ms_eager_sequence": t_eager * 1e3, "graph_vs_eager": t_eager / t_graph,
+                     "capture_s": t_cap,
+                     "m2l_tflops_equivalent": 8.0 * wl.P ** 2 * pairs / t_graph / 1e12}
+    out["multi_config"] = cfg
+    out["configs_n"] = [int(n) for n in ns]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--solve-maxiter", type=int, default=1500)
     ap.add_argument("--no-autotune", action="store_true", help="use the default M2L launch shape")
+    ap.add_argument("--workload", choices=["c3", "batch"], default="c3",
+                    help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -99,6 +198,9 @@ def main():
     from synth import make_workload
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.workload == "batch":
+        print(json.dumps(_batch_workload(args, torch, mp)), flush=True)
+        return
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -150,6 +150,27 @@ int mpsl_get_sizes(const mpsl_ctx *ctx, int64_t *n, int *p, int *n_nodes);
 int mpsl_apply(mpsl_ctx *ctx, int prec, const void *x, void *y);
 int mpsl_apply_dev(mpsl_ctx *ctx, int prec, const void *x_dev, void *y_dev);
 
+/* Batched matvec: nrhs right-hand sides X, Y laid out [nrhs][N][P] (device,
+ * precision prec), one launch per step for all of them. */
+int mpsl_apply_batch_dev(mpsl_ctx *ctx, int prec, int nrhs, const void *x_dev, void *y_dev);
+
+/* Multi-configuration batch: item i is one (possibly batched) matvec of
+ * context ctxs[i] in precision precs[i] with nrhs[i] right-hand sides (nrhs may
+ * be NULL: one each) on device buffers x[i] -> y[i].  mpsl_batch_create runs
+ * every item once (building tables and work buffers), then captures all of
+ * them into one HIP graph with one parallel branch per item; mpsl_batch_launch
+ * replays the whole batch with a single graph launch on `stream` (a
+ * hipStream_t, NULL for the null stream), reading the current contents of the
+ * x buffers.  The contexts and buffers must stay alive and unchanged in size
+ * while the batch exists; a context must not appear twice in one batch (its
+ * work buffers are shared).  Results are bitwise those of mpsl_apply_batch_dev
+ * on each item. */
+typedef struct mpsl_batch mpsl_batch;
+int mpsl_batch_create(mpsl_batch **out, int n_items, mpsl_ctx *const *ctxs, const int *precs, const int *nrhs,
+                      const void *const *x, void *const *y);
+int mpsl_batch_launch(mpsl_batch *batch, void *stream);
+void mpsl_batch_destroy(mpsl_batch *batch);
+
 /* ---- the steps of the matvec, each on device buffers ---------------------
  * Row a1, free-space all-pairs M2L (Lemma 3.1, eq. (24), Graf's theorem):
  *   alpha^l_{n'} = sum_{m != l} sum_nu H_{nu-n'}(k2 rho_lm) e^{i (nu-n') phi_lm} beta^m_nu,

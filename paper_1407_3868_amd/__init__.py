@@ -79,6 +79,42 @@ def compute_contour(k1, k2, k3, n_nodes, b, t_max):
     return lam, w
 
 
+class Batch:
+    """A captured multi-configuration batch of matvecs (mpsl_batch_*)."""
+
+    def __init__(self, items):
+        """items: list of (context, prec, nrhs, x_dev, y_dev)."""
+        self.lib = _lib.load()
+        n = len(items)
+        self._items = items  # keep contexts and buffers alive
+        ctxs = (ctypes.c_void_p * n)(*[it[0].h.value for it in items])
+        precs = (ctypes.c_int * n)(*[int(it[1]) for it in items])
+        nrhs = (ctypes.c_int * n)(*[int(it[2]) for it in items])
+        xs = (ctypes.c_void_p * n)(*[_ptr(it[3]) for it in items])
+        ys = (ctypes.c_void_p * n)(*[_ptr(it[4]) for it in items])
+        h = ctypes.c_void_p()
+        rc = self.lib.mpsl_batch_create(ctypes.byref(h), n, ctxs, precs, nrhs, xs, ys)
+        if rc != 0:
+            raise MpslError(rc, "mpsl_batch_create failed: " + items[0][0].lib.mpsl_last_error(items[0][0].h).decode())
+        self.h = h
+
+    def launch(self, stream=None):
+        rc = self.lib.mpsl_batch_launch(self.h, ctypes.c_void_p(stream) if stream else None)
+        if rc != 0:
+            raise MpslError(rc, "mpsl_batch_launch failed")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpsl_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """One mpsl context on a HIP device (mirrors mpsl_create/mpsl_destroy)."""
 
@@ -167,6 +203,9 @@ class Context:
 
     def apply_dev(self, prec, x, y):
         return self._check(self.lib.mpsl_apply_dev(self.h, int(prec), _ptr(x), _ptr(y)))
+
+    def apply_batch_dev(self, prec, nrhs, x, y):
+        return self._check(self.lib.mpsl_apply_batch_dev(self.h, int(prec), int(nrhs), _ptr(x), _ptr(y)))
 
     def m2l_dev(self, prec, beta, alpha):
         return self._check(self.lib.mpsl_m2l_dev(self.h, int(prec), _ptr(beta), _ptr(alpha)))

@@ -54,6 +54,11 @@ SIGNATURES = {
     "mpsl_get_sizes": (I, [P, ctypes.POINTER(L), ctypes.POINTER(I), ctypes.POINTER(I)]),
     "mpsl_apply": (I, [P, I, P, P]),
     "mpsl_apply_dev": (I, [P, I, P, P]),
+    "mpsl_apply_batch_dev": (I, [P, I, I, P, P]),
+    "mpsl_batch_create": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P), ctypes.POINTER(I), ctypes.POINTER(I),
+                              ctypes.POINTER(P), ctypes.POINTER(P)]),
+    "mpsl_batch_launch": (I, [P, P]),
+    "mpsl_batch_destroy": (None, [P]),
     "mpsl_m2l_dev": (I, [P, I, P, P]),
     "mpsl_m2s_dev": (I, [P, I, P, P]),
     "mpsl_reflect_dev": (I, [P, P, P, P]),

@@ -365,35 +365,49 @@ int ensure_work(mpsl_ctx *ctx) {
   return MPSL_OK;
 }
 
-// y = x - S (T + T_R) x on device buffers.
-int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y) {
+// Y = X - S (T + T_R) X for nrhs right-hand sides ([nrhs][n][P]) on device
+// buffers.  Work buffers grow on demand (never during graph capture: callers
+// that capture run one call first).
+int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
   int rc = build_tables(ctx);
   if (rc) return rc;
-  const int ca = chunks_m2l(ctx, prec), cb = chunks_s2l(ctx);
-  const int sa = m2l_slots(ctx, prec);
+  if (nrhs < 1) return set_err(ctx, MPSL_EINVAL, "nrhs must be >= 1");
+  // the right-hand-side dimension already multiplies the grid: fewer chunks
+  const int ca = std::max(1, chunks_m2l(ctx, prec) / nrhs), cb = chunks_s2l(ctx, nrhs);
+  const int cc = chunks_m2s(ctx, nrhs);
   const int P = 2 * ctx->p + 1;
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
-  if ((rc = dev_alloc(ctx, ctx->part, static_cast<size_t>(sa + cb) * ctx->n * P * esz))) return rc;
+  const int64_t len = ctx->n * static_cast<int64_t>(P);
+  const int64_t pstride = static_cast<int64_t>(ca + cb) * len;
+  if ((rc = dev_alloc(ctx, ctx->part, static_cast<size_t>(pstride) * nrhs * esz)) ||
+      (rc = dev_alloc(ctx, ctx->m2s_part, 2ull * nrhs * cc * ctx->ns * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->spec, 2ull * nrhs * ctx->ns * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->sigma, std::max(4ull, 2ull * nrhs) * ctx->ns * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->Up64, 2ull * nrhs * ctx->ns * P * sizeof(double2))) ||
+      (rc = dev_alloc(ctx, ctx->Up32, 2ull * nrhs * ctx->ns * P * sizeof(float2))))
+    return rc;
   char *part = static_cast<char *>(ctx->part.p);
-  char *part_b = part + static_cast<size_t>(sa) * ctx->n * P * esz;
-  if ((rc = launch_m2s(ctx, prec, x, ctx->spec.p))) return rc;
-  if ((rc = launch_reflect(ctx, ctx->spec.p, nullptr, ctx->sigma.p))) return rc;
-  if ((rc = launch_s2l_coef(ctx, ctx->sigma.p))) return rc;
-  if ((rc = launch_s2l(ctx, prec, part_b, cb))) return rc;
+  char *part_b = part + static_cast<size_t>(ca) * len * esz;
+  if ((rc = launch_m2s(ctx, prec, x, ctx->spec.p, nrhs))) return rc;
+  if ((rc = launch_reflect(ctx, ctx->spec.p, nullptr, ctx->sigma.p, nrhs))) return rc;
+  if ((rc = launch_s2l_coef(ctx, ctx->sigma.p, nrhs))) return rc;
+  if ((rc = launch_s2l(ctx, prec, part_b, cb, nrhs, pstride))) return rc;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->prof) {
     MPSL_HIP_TRY(ctx, hipEventCreate(&e0));
     MPSL_HIP_TRY(ctx, hipEventCreate(&e1));
     MPSL_HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
   }
-  if ((rc = launch_m2l(ctx, prec, x, part, ca))) return rc;
+  if ((rc = launch_m2l(ctx, prec, x, part, ca, -1, nrhs, pstride))) return rc;
   if (ctx->prof) {
     MPSL_HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     ctx->ev_start.push_back(e0);
     ctx->ev_stop.push_back(e1);
   }
-  return launch_sapply(ctx, prec, x, part, sa + cb, y);
+  return launch_sapply(ctx, prec, x, part, ca + cb, y, nrhs, pstride);
 }
+
+int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y) { return matvec(ctx, prec, x, y, 1); }
 
 }  // namespace mpsl
 
@@ -677,6 +691,12 @@ int mpsl_apply_dev(mpsl_ctx *ctx, int prec, const void *x, void *y) {
   if (!ctx || !x || !y || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   return mpsl::matvec(ctx, prec, x, y);
+}
+
+int mpsl_apply_batch_dev(mpsl_ctx *ctx, int prec, int nrhs, const void *x, void *y) {
+  if (!ctx || !x || !y || nrhs < 1 || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  return mpsl::matvec(ctx, prec, x, y, nrhs);
 }
 
 int mpsl_apply(mpsl_ctx *ctx, int prec, const void *x, void *y) {

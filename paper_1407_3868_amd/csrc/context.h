@@ -110,4 +110,6 @@ int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_
                  std::vector<zc> &w, std::string &err);
 int build_tables(mpsl_ctx *ctx);
 int ensure_work(mpsl_ctx *ctx);
+int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs);
+int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y);
 }  // namespace mpsl

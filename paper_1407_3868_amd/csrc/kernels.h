@@ -19,19 +19,24 @@ int launch_pair_tables(mpsl_ctx *ctx);
 // part[0 .. chunks).  variant: kM2LWhole, kM2LHalves, or -1 for the tuned one.
 constexpr int kM2LWhole = 0;
 constexpr int kM2LHalves = 1;
-int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant = -1);
+// nrhs right-hand sides: beta [nrhs][n][P]; part of rhs r at part + r * pstride.
+int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant = -1,
+               int nrhs = 1, int64_t pstride = 0);
 // Row b1: M2S partial spectra and their reduction to spec (double2[2*ns]).
-int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec);
+// spec: double2[nrhs][2][ns].
+int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec, int nrhs = 1);
 // Row b2: sigma = R spec (+ source), and the scaled S2L coefficient tables.
-int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sigma);
+// spec, sigma: double2[nrhs][2][ns] (spec may be null; src the same for every rhs).
+int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sigma, int nrhs = 1);
 // S2L coefficient tables from sigma (both precisions).
-int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma);
+int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma, int nrhs = 1);
 // Row b3: partial local expansions of the layer field into part[0 .. chunks).
-int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks);
+int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs = 1, int64_t pstride = 0);
 // Sum of partial buffers: alpha = sum_{c < chunks} part[c].
 int launch_sum_parts(mpsl_ctx *ctx, int prec, const void *part, int chunks, void *alpha);
 // Row a2: y = x - S_rot (sum of partials)  (x may be null: y = S_rot alpha).
-int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y);
+int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y, int nrhs = 1,
+                  int64_t pstride = 0);
 
 // GMRES helpers (FP64 complex vectors of length len).
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *w, int64_t len,
@@ -53,7 +58,7 @@ int launch_field(mpsl_ctx *ctx, const void *beta, const void *sig4, const double
 int chunks_m2l(const mpsl_ctx *ctx, int prec);
 // Partial buffers written by one M2L launch.
 inline int m2l_slots(const mpsl_ctx *ctx, int prec) { return chunks_m2l(ctx, prec); }
-int chunks_s2l(const mpsl_ctx *ctx);
-int chunks_m2s(const mpsl_ctx *ctx);
+int chunks_s2l(const mpsl_ctx *ctx, int nrhs = 1);
+int chunks_m2s(const mpsl_ctx *ctx, int nrhs = 1);
 
 }  // namespace mpsl

@@ -200,10 +200,13 @@ __device__ __forceinline__ void m2l_body(const cv_t<T> *__restrict__ pairs, cons
 template <typename T, int p, int HALF>
 __global__ __launch_bounds__(kThreads) void k_m2l(const cv_t<T> *__restrict__ pairs,
                                                   const cv_t<T> *__restrict__ beta,
-                                                  cv_t<T> *__restrict__ part, int n, int chunk_len) {
+                                                  cv_t<T> *__restrict__ part, int n, int chunk_len,
+                                                  int64_t bstride, int64_t pstride) {
   constexpr int P = 2 * p + 1;
   const int l = blockIdx.x * kThreads + threadIdx.x;
   const int c = blockIdx.y;
+  beta += blockIdx.z * bstride;  // right-hand side
+  part += blockIdx.z * pstride;
   const int m0 = c * chunk_len;
   const int m1 = min(n, m0 + chunk_len);
   cv_t<T> *o = part + static_cast<int64_t>(c) * n * P;
@@ -226,7 +229,9 @@ __global__ __launch_bounds__(kThreads) void k_m2s_part(const cv_t<T> *__restrict
   constexpr int P = 2 * p + 1;
   const int q = blockIdx.x * kThreads + threadIdx.x;
   const int c = blockIdx.y;
-  const int s = blockIdx.z;
+  const int s = blockIdx.z & 1;  // side
+  const int r = blockIdx.z >> 1; // right-hand side
+  beta += static_cast<int64_t>(r) * n * P;
   if (q >= ns) return;
   const int m0 = c * chunk_len;
   const int m1 = min(n, m0 + chunk_len);
@@ -241,21 +246,21 @@ __global__ __launch_bounds__(kThreads) void k_m2s_part(const cv_t<T> *__restrict
     for (int i = 0; i < P; ++i) cmac(acc[i], e, ld<T>(bm[i]));
   }
   const cv_t<T> *Wq = W + (static_cast<int64_t>(s) * ns + q) * P;
-  cx<T> r = mk<T>(0, 0);
+  cx<T> acc_r = mk<T>(0, 0);
 #pragma unroll
-  for (int i = 0; i < P; ++i) cmac(r, acc[i], ld<T>(Wq[i]));
-  part[(static_cast<int64_t>(s) * chunks + c) * ns + q] = st(r);
+  for (int i = 0; i < P; ++i) cmac(acc_r, acc[i], ld<T>(Wq[i]));
+  part[((2 * static_cast<int64_t>(r) + s) * chunks + c) * ns + q] = st(acc_r);
 }
 
 template <typename T>
-__global__ void k_m2s_reduce(const cv_t<T> *__restrict__ part, int ns, int chunks,
+__global__ void k_m2s_reduce(const cv_t<T> *__restrict__ part, int ns, int chunks, int nrhs,
                              double2 *__restrict__ spec) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * ns) return;
-  const int s = i / ns, q = i % ns;
+  if (i >= 2 * ns * nrhs) return;
+  const int rs = i / ns, q = i % ns;  // rs = 2 * rhs + side
   double re = 0.0, im = 0.0;
   for (int c = 0; c < chunks; ++c) {
-    const cv_t<T> v = part[(static_cast<int64_t>(s) * chunks + c) * ns + q];
+    const cv_t<T> v = part[(static_cast<int64_t>(rs) * chunks + c) * ns + q];
     re += static_cast<double>(v.x);
     im += static_cast<double>(v.y);
   }
@@ -271,6 +276,8 @@ __global__ void k_reflect(const double2 *__restrict__ spec, const double2 *__res
                           double2 *__restrict__ sigma) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ns) return;
+  sigma += 2 * static_cast<int64_t>(ns) * blockIdx.y;  // right-hand side
+  if (spec) spec += 2 * static_cast<int64_t>(ns) * blockIdx.y;
   cx<double> pp = mk(0.0, 0.0), pm = mk(0.0, 0.0);
   if (spec) {
     pp = ld<double>(spec[q]);
@@ -290,14 +297,15 @@ __global__ void k_reflect(const double2 *__restrict__ spec, const double2 *__res
 
 // S2L coefficient tables: Up[s][q][n] = c_q sigma_s[q] U[s][q][n].
 __global__ void k_s2l_coef(const double2 *__restrict__ sigma, const double2 *__restrict__ cq,
-                           const double2 *__restrict__ U, int ns, int P, double2 *__restrict__ Up64,
+                           const double2 *__restrict__ U, int ns, int P, int nrhs, double2 *__restrict__ Up64,
                            float2 *__restrict__ Up32) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  const int64_t tot = 2LL * ns * P;
-  if (i >= tot) return;
-  const int s = static_cast<int>(i / (static_cast<int64_t>(ns) * P));
-  const int q = static_cast<int>((i / P) % ns);
-  const cx<double> v = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]) * ld<double>(U[i]);
+  const int64_t per = 2LL * ns * P;
+  if (i >= per * nrhs) return;
+  const int64_t r = i / per, k = i % per;
+  const int s = static_cast<int>(k / (static_cast<int64_t>(ns) * P));
+  const int q = static_cast<int>((k / P) % ns);
+  const cx<double> v = ld<double>(cq[q]) * ld<double>(sigma[(2 * r + s) * ns + q]) * ld<double>(U[k]);
   Up64[i] = st(v);
   Up32[i] = make_float2(static_cast<float>(v.re), static_cast<float>(v.im));
 }
@@ -309,10 +317,12 @@ template <typename T, int p>
 __global__ __launch_bounds__(kThreads) void k_s2l(const cv_t<T> *__restrict__ F,
                                                   const cv_t<T> *__restrict__ Up,
                                                   cv_t<T> *__restrict__ part, int n, int ns,
-                                                  int chunk_len) {
+                                                  int chunk_len, int64_t pstride) {
   constexpr int P = 2 * p + 1;
   const int l = blockIdx.x * kThreads + threadIdx.x;
   const int c = blockIdx.y;
+  Up += 2 * static_cast<int64_t>(ns) * P * blockIdx.z;  // right-hand side
+  part += blockIdx.z * pstride;
   const int q0 = c * chunk_len;
   const int q1 = min(ns, q0 + chunk_len);
   const bool valid = l < n;
@@ -363,8 +373,14 @@ constexpr int kSapplyTargets = 4;
 template <typename T, int p>
 __global__ void k_sapply(const cv_t<T> *__restrict__ x, const cv_t<T> *__restrict__ part,
                          int chunks, const cv_t<T> *__restrict__ S, const cv_t<T> *__restrict__ rot,
-                         int n, cv_t<T> *__restrict__ y) {
+                         int n, cv_t<T> *__restrict__ y, int64_t pstride) {
   constexpr int P = 2 * p + 1;
+  {  // right-hand side
+    const int64_t off = static_cast<int64_t>(blockIdx.y) * n * P;
+    if (x) x += off;
+    y += off;
+    part += blockIdx.y * pstride;
+  }
   __shared__ cx<T> a[kSapplyTargets][P];
   const int t = threadIdx.x / P;
   const int k = threadIdx.x % P;
@@ -584,16 +600,16 @@ int chunks_m2l(const mpsl_ctx *ctx, int prec) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
 }
 
-int chunks_s2l(const mpsl_ctx *ctx) {
+int chunks_s2l(const mpsl_ctx *ctx, int nrhs) {
   if (ctx->s2l_chunks > 0) return std::min(ctx->s2l_chunks, ctx->ns);
-  const int tb = cdiv(ctx->n, kThreads);
+  const int tb = cdiv(ctx->n, kThreads) * nrhs;
   const int c = cdiv(1024, tb);
   return std::max(1, std::min(c, ctx->ns / 8 > 0 ? ctx->ns / 8 : 1));
 }
 
-int chunks_m2s(const mpsl_ctx *ctx) {
+int chunks_m2s(const mpsl_ctx *ctx, int nrhs) {
   if (ctx->m2s_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2s_chunks, ctx->n));
-  const int qb = cdiv(ctx->ns, kThreads) * 2;
+  const int qb = cdiv(ctx->ns, kThreads) * 2 * nrhs;
   const int c = cdiv(2048, qb);
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
 }
@@ -627,23 +643,28 @@ int launch_pair_tables(mpsl_ctx *ctx) {
 }
 
 template <typename T>
-static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks, int variant) {
+static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks, int variant, int nrhs,
+                        int64_t pstride) {
   const int n = static_cast<int>(ctx->n);
   const int chunk_len = cdiv(n, chunks);
   const bool f64 = std::is_same<T, double>::value;
-  const dim3 grid(cdiv(n, kThreads), chunks);
+  const dim3 grid(cdiv(n, kThreads), chunks, nrhs);
   const auto *pairs = static_cast<const cv_t<T> *>(f64 ? ctx->gt.pair64.p : ctx->gt.pair32.p);
   const auto *b = static_cast<const cv_t<T> *>(beta);
   auto *o = static_cast<cv_t<T> *>(part);
+  const int64_t bs = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
   switch (ctx->p) {
-#define X(PP)                                                                                                     \
-  case PP:                                                                                                        \
-    if (variant == kM2LHalves) {                                                                                  \
-      hipLaunchKernelGGL((k_m2l<T, PP, 0>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len);   \
-      hipLaunchKernelGGL((k_m2l<T, PP, 1>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len);   \
-    } else {                                                                                                      \
-      hipLaunchKernelGGL((k_m2l<T, PP, -1>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len);  \
-    }                                                                                                             \
+#define X(PP)                                                                                               \
+  case PP:                                                                                                  \
+    if (variant == kM2LHalves) {                                                                            \
+      hipLaunchKernelGGL((k_m2l<T, PP, 0>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len, \
+                         bs, pstride);                                                                      \
+      hipLaunchKernelGGL((k_m2l<T, PP, 1>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n, chunk_len, \
+                         bs, pstride);                                                                      \
+    } else {                                                                                                \
+      hipLaunchKernelGGL((k_m2l<T, PP, -1>), grid, dim3(kThreads), 0, ctx->stream, pairs, b, o, n,           \
+                         chunk_len, bs, pstride);                                                           \
+    }                                                                                                       \
     break;
     MPSL_P_CASES(X)
 #undef X
@@ -653,18 +674,19 @@ static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks,
   return MPSL_OK;
 }
 
-int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant) {
+int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant, int nrhs,
+               int64_t pstride) {
   if (variant < 0) variant = ctx->tune[prec == MPSL_FP64 ? 0 : 1].variant;
-  return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks, variant)
-                           : launch_m2l_t<float>(ctx, beta, part, chunks, variant);
+  return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks, variant, nrhs, pstride)
+                           : launch_m2l_t<float>(ctx, beta, part, chunks, variant, nrhs, pstride);
 }
 
 template <typename T>
-static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec) {
+static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
   const int n = static_cast<int>(ctx->n);
-  const int chunks = chunks_m2s(ctx);
+  const int chunks = chunks_m2s(ctx, nrhs);
   const int chunk_len = cdiv(n, chunks);
-  const dim3 grid(cdiv(ctx->ns, kThreads), chunks, 2);
+  const dim3 grid(cdiv(ctx->ns, kThreads), chunks, 2 * nrhs);
   const bool f64 = std::is_same<T, double>::value;
   const auto *E = static_cast<const cv_t<T> *>(f64 ? ctx->gt.E64.p : ctx->gt.E32.p);
   const auto *W = static_cast<const cv_t<T> *>(f64 ? ctx->ct.W64.p : ctx->ct.W32.p);
@@ -678,19 +700,20 @@ static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec) {
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
   }
   LAUNCH_CHECK(ctx);
-  hipLaunchKernelGGL(k_m2s_reduce<T>, dim3(cdiv(2 * ctx->ns, 256)), dim3(256), 0, ctx->stream,
-                     static_cast<const cv_t<T> *>(part), ctx->ns, chunks, static_cast<double2 *>(spec));
+  hipLaunchKernelGGL(k_m2s_reduce<T>, dim3(cdiv(2 * ctx->ns * nrhs, 256)), dim3(256), 0, ctx->stream,
+                     static_cast<const cv_t<T> *>(part), ctx->ns, chunks, nrhs, static_cast<double2 *>(spec));
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }
 
-int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec) {
-  return prec == MPSL_FP64 ? launch_m2s_t<double>(ctx, beta, spec) : launch_m2s_t<float>(ctx, beta, spec);
+int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec, int nrhs) {
+  return prec == MPSL_FP64 ? launch_m2s_t<double>(ctx, beta, spec, nrhs)
+                           : launch_m2s_t<float>(ctx, beta, spec, nrhs);
 }
 
-int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sigma) {
+int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sigma, int nrhs) {
   const int ns = ctx->ns;
-  hipLaunchKernelGGL(k_reflect, dim3(cdiv(ns, 256)), dim3(256), 0, ctx->stream,
+  hipLaunchKernelGGL(k_reflect, dim3(cdiv(ns, 256), nrhs), dim3(256), 0, ctx->stream,
                      static_cast<const double2 *>(spec), static_cast<const double2 *>(ctx->ct.R.p),
                      static_cast<const double2 *>(ctx->ct.srcfac.p), static_cast<const double2 *>(ctx->ct.lam.p),
                      static_cast<const double2 *>(ctx->ct.gw.p), ns, src ? 1 : 0, src ? src[0] : 0.0,
@@ -699,29 +722,29 @@ int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sig
   return MPSL_OK;
 }
 
-int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma) {
+int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma, int nrhs) {
   const int P = 2 * ctx->p + 1;
-  const int64_t tot = 2LL * ctx->ns * P;
+  const int64_t tot = 2LL * ctx->ns * P * nrhs;
   hipLaunchKernelGGL(k_s2l_coef, dim3(cdiv(tot, 256)), dim3(256), 0, ctx->stream,
                      static_cast<const double2 *>(sigma), static_cast<const double2 *>(ctx->ct.cq.p),
-                     static_cast<const double2 *>(ctx->ct.U64.p), ctx->ns, P,
+                     static_cast<const double2 *>(ctx->ct.U64.p), ctx->ns, P, nrhs,
                      static_cast<double2 *>(ctx->Up64.p), static_cast<float2 *>(ctx->Up32.p));
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }
 
 template <typename T>
-static int launch_s2l_t(mpsl_ctx *ctx, void *part, int chunks) {
+static int launch_s2l_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstride) {
   const int n = static_cast<int>(ctx->n);
   const int chunk_len = cdiv(ctx->ns, chunks);
-  const dim3 grid(cdiv(n, kThreads), chunks);
+  const dim3 grid(cdiv(n, kThreads), chunks, nrhs);
   const bool f64 = std::is_same<T, double>::value;
   const auto *F = static_cast<const cv_t<T> *>(f64 ? ctx->gt.F64.p : ctx->gt.F32.p);
   const auto *Up = static_cast<const cv_t<T> *>(f64 ? ctx->Up64.p : ctx->Up32.p);
   auto *o = static_cast<cv_t<T> *>(part);
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_s2l<T, PP>), grid, dim3(kThreads), 0, ctx->stream, F, Up, o, n, ctx->ns, chunk_len); break;
+  case PP: hipLaunchKernelGGL((k_s2l<T, PP>), grid, dim3(kThreads), 0, ctx->stream, F, Up, o, n, ctx->ns, chunk_len, pstride); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
@@ -730,8 +753,9 @@ static int launch_s2l_t(mpsl_ctx *ctx, void *part, int chunks) {
   return MPSL_OK;
 }
 
-int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks) {
-  return prec == MPSL_FP64 ? launch_s2l_t<double>(ctx, part, chunks) : launch_s2l_t<float>(ctx, part, chunks);
+int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs, int64_t pstride) {
+  return prec == MPSL_FP64 ? launch_s2l_t<double>(ctx, part, chunks, nrhs, pstride)
+                           : launch_s2l_t<float>(ctx, part, chunks, nrhs, pstride);
 }
 
 int launch_sum_parts(mpsl_ctx *ctx, int prec, const void *part, int chunks, void *alpha) {
@@ -747,20 +771,21 @@ int launch_sum_parts(mpsl_ctx *ctx, int prec, const void *part, int chunks, void
 }
 
 template <typename T>
-static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *part, int chunks, void *y) {
+static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *part, int chunks, void *y, int nrhs,
+                           int64_t pstride) {
   const int n = static_cast<int>(ctx->n);
   const int P = 2 * ctx->p + 1;
   const bool f64 = std::is_same<T, double>::value;
   const auto *S = static_cast<const cv_t<T> *>(f64 ? ctx->S64.p : ctx->S32.p);
   const auto *rot = static_cast<const cv_t<T> *>(f64 ? ctx->gt.rot64.p : ctx->gt.rot32.p);
-  const dim3 grid(cdiv(n, kSapplyTargets));
+  const dim3 grid(cdiv(n, kSapplyTargets), nrhs);
   const dim3 block(kSapplyTargets * P);
   const auto *xx = static_cast<const cv_t<T> *>(x);
   const auto *pp = static_cast<const cv_t<T> *>(part);
   auto *yy = static_cast<cv_t<T> *>(y);
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_sapply<T, PP>), grid, block, 0, ctx->stream, xx, pp, chunks, S, rot, n, yy); break;
+  case PP: hipLaunchKernelGGL((k_sapply<T, PP>), grid, block, 0, ctx->stream, xx, pp, chunks, S, rot, n, yy, pstride); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
@@ -769,9 +794,10 @@ static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *part, int c
   return MPSL_OK;
 }
 
-int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y) {
-  return prec == MPSL_FP64 ? launch_sapply_t<double>(ctx, x, part, chunks, y)
-                           : launch_sapply_t<float>(ctx, x, part, chunks, y);
+int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y, int nrhs,
+                  int64_t pstride) {
+  return prec == MPSL_FP64 ? launch_sapply_t<double>(ctx, x, part, chunks, y, nrhs, pstride)
+                           : launch_sapply_t<float>(ctx, x, part, chunks, y, nrhs, pstride);
 }
 
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *w, int64_t len,

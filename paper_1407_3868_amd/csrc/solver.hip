@@ -10,7 +10,6 @@ using mpsl::DBuf;
 using mpsl::zc;
 
 namespace mpsl {
-int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y);
 
 namespace {
 
