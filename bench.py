@@ -173,6 +173,60 @@ def _batch_workload(args, torch, mp):
     return out
 
 
+def _serve_workload(args, torch, mp):
+    """A Poisson stream of design-loop requests through the continuous-batching server."""
+    import numpy as np
+
+    from synth import rejection_layout
+
+    rng = np.random.default_rng(6)
+    nreq = args.requests
+
+    def make(i):
+        n = int(round(np.exp(rng.uniform(np.log(200), np.log(2000)))))
+        p = int(rng.choice([8, 12]))
+        star = bool(rng.integers(0, 2))
+        k2 = float(rng.uniform(6.0, 12.0))
+        d = float(rng.uniform(8.0, 30.0))
+        h = d - 2.0
+        width = n / (0.3 * h)
+        xy, rot = rejection_layout(n, (-width / 2, width / 2), (-d + 1.0, -1.0), 0.75, 1000 + i)
+        return dict(k=(6.0, k2, 12.0), d=d, particle=1 if star else 0,
+                    shape=(0.25, 0.05, 5) if star else (0.25,), kp=15.0, p=p, xy=xy, rot=rot, n_nodes=512,
+                    b=min(0.2, 2.0 / width), t_max=32.0, src=(0.0, 2.0), tol=1e-8, maxiter=400, n_bdry=128)
+
+    reqs = [make(i) for i in range(nreq)]
+    out = {"workload": (f"{nreq} requests: N log-uniform [200, 2000], p in {{8, 12}}, star or disk, k2 ~ U[6, 12], "
+                        "d ~ U[8, 30], 512 nodes, tol 1e-8, at most 400 iterations; Poisson arrivals at "
+                        "0.8 / (mean isolated service time)")}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        # isolated service time on a calibration sample
+        srv = mp.Server(0, hbm_budget=200 << 30, max_active=1)
+        cal = [srv.wait(srv.submit(**dict(r, precision=prec))) for r in reqs[:6]]
+        srv.close()
+        mean_service = float(np.mean([c["t_finish"] - c["t_submit"] for c in cal]))
+        qps = 0.8 / mean_service
+        gaps = np.random.default_rng(7).exponential(1.0 / qps, nreq)
+        srv = mp.Server(0, hbm_budget=200 << 30, max_active=16)
+        t0 = time.perf_counter()
+        tickets = []
+        for r, g in zip(reqs, gaps):
+            time.sleep(float(g))
+            tickets.append(srv.submit(**dict(r, precision=prec)))
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = np.array([r["t_finish"] - r["t_submit"] for r in res]) * 1e3
+        conv = sum(1 for r in res if r["status"] == 0)
+        out[name] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                     "mean_ms": float(lat.mean()), "throughput_req_s": nreq / wall, "qps_offered": qps,
+                     "mean_isolated_service_ms": mean_service * 1e3, "converged": conv, "requests": nreq,
+                     "iterations_mean": float(np.mean([r["iterations"] for r in res]))}
+        print(f"# serve {name}: p50 {out[name]['p50_ms']:.1f} ms, p99 {out[name]['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,8 +236,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--solve-maxiter", type=int, default=1500)
     ap.add_argument("--no-autotune", action="store_true", help="use the default M2L launch shape")
-    ap.add_argument("--workload", choices=["c3", "batch"], default="c3",
-                    help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching")
+    ap.add_argument("--workload", choices=["c3", "batch", "serve"], default="c3",
+                    help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching; "
+                         "serve: Poisson request stream through the server")
+    ap.add_argument("--requests", type=int, default=80, help="serve: number of requests")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -200,6 +256,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     if args.workload == "batch":
         print(json.dumps(_batch_workload(args, torch, mp)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(_serve_workload(args, torch, mp)), flush=True)
         return
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")

@@ -59,7 +59,8 @@ enum {
   MPSL_ENOCONV = -6,       /* GMRES stopped above tolerance (result written)   */
   MPSL_EUNSUPPORTED = -7,  /* parameters outside what this build implements    */
   MPSL_EINSIDE = -8,       /* receiver inside an enclosing disk (value NaN)    */
-  MPSL_ENUMERIC = -9       /* NaN/Inf met in the iteration                     */
+  MPSL_ENUMERIC = -9,      /* NaN/Inf met in the iteration                     */
+  MPSL_PENDING = 1         /* server: the request has not finished yet          */
 };
 
 /* Arithmetic of the hot path. */
@@ -265,6 +266,68 @@ int mpsl_get_tuning(const mpsl_ctx *ctx, int prec, int *variant, int *chunks, do
  * enable recording with mpsl_profile(ctx, 1). */
 int mpsl_profile(mpsl_ctx *ctx, int enable);
 int mpsl_profile_read(mpsl_ctx *ctx, double *m2l_ms_avg, int *count);
+
+/* ---- serving: continuous batching of design-loop solves ------------------- */
+
+enum { MPSL_PARTICLE_DISK = 0, MPSL_PARTICLE_STAR = 1, MPSL_PARTICLE_MATRIX = 2 };
+
+/* One self-contained solve request (the library copies every array). */
+typedef struct {
+  mpsl_c128 k1, k2, k3;    /* layer wavenumbers (see mpsl_set_layers)          */
+  double d;                /* middle-layer thickness                           */
+  int particle;            /* MPSL_PARTICLE_*                                  */
+  double shape[3];         /* disk: R; star: a1, a2, a3                        */
+  mpsl_c128 kp;            /* particle wavenumber (disk, star)                 */
+  int p;                   /* expansion order                                  */
+  int n_bdry;              /* star boundary points (0: 256)                    */
+  const mpsl_c128 *S;      /* MPSL_PARTICLE_MATRIX: P x P prototype matrix     */
+  double r_enclose;        /* MPSL_PARTICLE_MATRIX: enclosing radius           */
+  int64_t n;               /* particles                                        */
+  const double *xy;        /* 2n centres                                       */
+  const double *rot;       /* n rotations or NULL                              */
+  int n_nodes;             /* Sommerfeld nodes (see mpsl_set_contour)          */
+  double b, t_max;         /* contour offset and truncation                    */
+  double src[2];           /* point source in layer 1                          */
+  mpsl_opts opts;          /* precision, tol, maxiter, restart, inner_tol      */
+} mpsl_request;
+
+typedef struct {
+  int status;                 /* MPSL_OK, MPSL_ENOCONV or the request's error   */
+  int64_t n;
+  int p;
+  const mpsl_c128 *beta;      /* n*P coefficients, owned by the server until
+                                 mpsl_server_release (NULL on error)          */
+  int iterations, fp64_matvecs, refinements;
+  double rel_residual;
+  double t_submit, t_admit, t_start, t_finish;  /* seconds on the server clock:
+                                 queued, admitted (memory reserved), prepared,
+                                 finished                                      */
+  size_t hbm_bytes;           /* device memory reserved for the request        */
+} mpsl_result;
+
+typedef struct mpsl_server mpsl_server;
+
+/* A server on `device` that keeps at most max_active requests and at most
+ * hbm_budget bytes (estimated per request from N, p, N_S and the Krylov
+ * dimension) admitted at once.  Admission is in arrival order.  Each admitted
+ * request gets its own context and stream; the worker advances all prepared
+ * requests by one solver step per tick, so their device work overlaps.
+ * Results are identical whatever else is in flight (own buffers, fixed launch
+ * shapes, deterministic reductions). */
+int mpsl_server_create(mpsl_server **out, int device, size_t hbm_budget, int max_active);
+/* Queue a request; returns at once with a ticket.  MPSL_ENOMEM when the request
+ * alone exceeds the budget. */
+int mpsl_server_submit(mpsl_server *s, const mpsl_request *req, uint64_t *ticket);
+/* MPSL_OK and the result when finished, MPSL_PENDING otherwise. */
+int mpsl_server_poll(mpsl_server *s, uint64_t ticket, mpsl_result *res);
+/* Block until finished (timeout_s < 0: no limit); MPSL_PENDING on timeout. */
+int mpsl_server_wait(mpsl_server *s, uint64_t ticket, double timeout_s, mpsl_result *res);
+/* Free a finished request's result. */
+int mpsl_server_release(mpsl_server *s, uint64_t ticket);
+int mpsl_server_stats(mpsl_server *s, int *queued, int *active, uint64_t *completed, size_t *bytes_in_use);
+/* Cancel requests not yet admitted (status MPSL_ESTATE), finish the admitted
+ * ones, stop the threads and free everything. */
+void mpsl_server_destroy(mpsl_server *s);
 
 #ifdef __cplusplus
 }

@@ -275,3 +275,97 @@ class Context:
         ms, cnt = ctypes.c_double(), ctypes.c_int()
         self._check(self.lib.mpsl_profile_read(self.h, ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+
+PARTICLE_DISK, PARTICLE_STAR, PARTICLE_MATRIX = 0, 1, 2
+
+
+class Server:
+    """Continuous-batching solve server (mpsl_server_*)."""
+
+    def __init__(self, device=0, hbm_budget=64 << 30, max_active=8):
+        self.lib = _lib.load()
+        h = ctypes.c_void_p()
+        rc = self.lib.mpsl_server_create(ctypes.byref(h), int(device), int(hbm_budget), int(max_active))
+        if rc != 0:
+            raise MpslError(rc, "mpsl_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def submit(self, k, d, particle, shape, kp, p, xy, rot, n_nodes, b, t_max, src, precision=FP64, tol=1e-10,
+               maxiter=500, restart=0, inner_tol=0.0, S=None, r_enclose=0.0, n_bdry=0):
+        """Queue one request; returns its ticket (arrays are copied by the library)."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        rot = None if rot is None else np.ascontiguousarray(rot, dtype=np.float64)
+        Sa = None if S is None else _carr(S)
+        r = _lib.Request()
+        r.k1, r.k2, r.k3 = _c(k[0]), _c(k[1]), _c(k[2])
+        r.d = float(d)
+        r.particle = int(particle)
+        for i, v in enumerate(list(shape) + [0.0] * (3 - len(shape))):
+            r.shape[i] = float(v)
+        r.kp = _c(kp)
+        r.p = int(p)
+        r.n_bdry = int(n_bdry)
+        r.S = None if Sa is None else Sa.ctypes.data
+        r.r_enclose = float(r_enclose)
+        r.n = int(xy.shape[0])
+        r.xy = xy.ctypes.data
+        r.rot = None if rot is None else rot.ctypes.data
+        r.n_nodes, r.b, r.t_max = int(n_nodes), float(b), float(t_max)
+        r.src[0], r.src[1] = float(src[0]), float(src[1])
+        r.opts = _lib.Opts(int(precision), float(tol), int(maxiter), int(restart), float(inner_tol))
+        t = ctypes.c_uint64()
+        rc = self.lib.mpsl_server_submit(self.h, ctypes.byref(r), ctypes.byref(t))
+        if rc != 0:
+            raise MpslError(rc, "mpsl_server_submit failed")
+        return t.value
+
+    @staticmethod
+    def _result(res):
+        out = dict(status=res.status, iterations=res.iterations, fp64_matvecs=res.fp64_matvecs,
+                   refinements=res.refinements, rel_residual=res.rel_residual, t_submit=res.t_submit,
+                   t_admit=res.t_admit, t_start=res.t_start, t_finish=res.t_finish, hbm_bytes=res.hbm_bytes)
+        if res.beta:
+            P = 2 * res.p + 1
+            arr = np.ctypeslib.as_array(ctypes.cast(res.beta, ctypes.POINTER(ctypes.c_double)),
+                                        shape=(res.n * P * 2,))
+            out["beta"] = arr.view(np.complex128).reshape(res.n, P).copy()
+        return out
+
+    def poll(self, ticket):
+        res = _lib.Result()
+        rc = self.lib.mpsl_server_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(res))
+        if rc == 1:
+            return None
+        if rc != 0:
+            raise MpslError(rc, "mpsl_server_poll failed")
+        return self._result(res)
+
+    def wait(self, ticket, timeout=-1.0, release=True):
+        res = _lib.Result()
+        rc = self.lib.mpsl_server_wait(self.h, ctypes.c_uint64(ticket), float(timeout), ctypes.byref(res))
+        if rc == 1:
+            return None
+        if rc != 0:
+            raise MpslError(rc, "mpsl_server_wait failed")
+        out = self._result(res)
+        if release:
+            self.lib.mpsl_server_release(self.h, ctypes.c_uint64(ticket))
+        return out
+
+    def stats(self):
+        q, a, c, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64(), ctypes.c_size_t()
+        self.lib.mpsl_server_stats(self.h, ctypes.byref(q), ctypes.byref(a), ctypes.byref(c), ctypes.byref(b))
+        return dict(queued=q.value, active=a.value, completed=c.value, bytes_in_use=b.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpsl_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

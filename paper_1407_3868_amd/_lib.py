@@ -110,3 +110,32 @@ def load():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("k1", c128), ("k2", c128), ("k3", c128), ("d", ctypes.c_double), ("particle", ctypes.c_int),
+                ("shape", ctypes.c_double * 3), ("kp", c128), ("p", ctypes.c_int), ("n_bdry", ctypes.c_int),
+                ("S", ctypes.c_void_p), ("r_enclose", ctypes.c_double), ("n", ctypes.c_int64),
+                ("xy", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("n_nodes", ctypes.c_int),
+                ("b", ctypes.c_double), ("t_max", ctypes.c_double), ("src", ctypes.c_double * 2),
+                ("opts", Opts)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n", ctypes.c_int64), ("p", ctypes.c_int),
+                ("beta", ctypes.POINTER(c128)), ("iterations", ctypes.c_int), ("fp64_matvecs", ctypes.c_int),
+                ("refinements", ctypes.c_int), ("rel_residual", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_finish", ctypes.c_double),
+                ("hbm_bytes", ctypes.c_size_t)]
+
+
+SIGNATURES.update({
+    "mpsl_server_create": (I, [ctypes.POINTER(P), I, ctypes.c_size_t, I]),
+    "mpsl_server_submit": (I, [P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "mpsl_server_poll": (I, [P, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "mpsl_server_wait": (I, [P, ctypes.c_uint64, D, ctypes.POINTER(Result)]),
+    "mpsl_server_release": (I, [P, ctypes.c_uint64]),
+    "mpsl_server_stats": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint64),
+                              ctypes.POINTER(ctypes.c_size_t)]),
+    "mpsl_server_destroy": (None, [P]),
+})

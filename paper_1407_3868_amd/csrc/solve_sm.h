@@ -1,0 +1,64 @@
+// Resumable solver for eq. (49): restarted GMRES (Arnoldi by classical
+// Gram-Schmidt applied twice, FP64; Givens rotations on the host) inside an
+// FP64 residual loop.  In FP64 mode the inner matvecs are FP64 and the loop
+// is plain restarted GMRES with a final true-residual check; in FP32 mode the
+// inner matvecs are complex64 (iterative refinement: x += d, r = b - A x in
+// FP64 after every inner solve).
+//
+// Each step is split into launch() (asynchronous work on the context stream)
+// and complete() (waits for that stream, then host bookkeeping), so a caller
+// can keep the steps of many solves in flight on their own streams.
+#pragma once
+
+#include <vector>
+
+#include "kernels.h"
+
+namespace mpsl {
+
+// Right-hand side S a of eq. (49) for one point source into dev (FP64, n*P).
+int rhs_device(mpsl_ctx *ctx, const double *src, void *dev);
+
+class SolveSM {
+ public:
+  enum Status { kRunning = 0, kConverged = 1, kExhausted = 2 };
+
+  ~SolveSM();
+  // Prepare for a solve of A x = b; b_dev (FP64, n*P) is copied.
+  int init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev);
+  int launch();
+  int complete();
+  int status() const { return status_; }
+  const double2 *x() const { return xs_; }
+  int iterations() const { return inner_mv_; }
+  int fp64_matvecs() const { return fp64_mv_; }
+  int refinements() const { return refin_; }
+  double rel_residual() const { return rel_res_; }
+  const std::vector<double> &history() const { return hist_; }
+
+ private:
+  int begin_inner();
+  int finish_cycle();
+
+  enum Phase { kInner, kResidual };
+  mpsl_ctx *ctx_ = nullptr;
+  mpsl_opts o_{};
+  int64_t len_ = 0;
+  int m_ = 0;
+  int phase_ = kInner;
+  int status_ = kRunning;
+  // device (inside ctx->gm)
+  double2 *V_ = nullptr, *w_ = nullptr, *r_ = nullptr, *xs_ = nullptr, *b_ = nullptr, *d_ = nullptr;
+  double2 *h_ = nullptr, *h2_ = nullptr, *nrm_ = nullptr;
+  float2 *x32_ = nullptr, *y32_ = nullptr;
+  // pinned host staging
+  double2 *hh_ = nullptr;  // 2 (m + 2) + 1 entries: h, h2, norm
+  // host Hessenberg state
+  std::vector<zc> H_, cs_, sn_, gv_;
+  int j_ = 0;
+  double bn_ = 0.0, rn_ = 0.0, inner_abs_ = 0.0, rel_res_ = 1.0;
+  int inner_mv_ = 0, fp64_mv_ = 0, refin_ = 0;
+  std::vector<double> hist_;
+};
+
+}  // namespace mpsl

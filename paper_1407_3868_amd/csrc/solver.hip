@@ -4,19 +4,15 @@
 #include <cmath>
 #include <vector>
 
-#include "kernels.h"
+#include "solve_sm.h"
 
 using mpsl::DBuf;
 using mpsl::zc;
 
 namespace mpsl {
 
-namespace {
-
-int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
-
 // rhs = S a for one source, into dev (double2[n*P]).
-int rhs_dev(mpsl_ctx *ctx, const double *src, void *dev) {
+int rhs_device(mpsl_ctx *ctx, const double *src, void *dev) {
   int rc = build_tables(ctx);
   if (rc) return rc;
   const int cb = chunks_s2l(ctx);
@@ -26,33 +22,25 @@ int rhs_dev(mpsl_ctx *ctx, const double *src, void *dev) {
   return launch_sapply(ctx, MPSL_FP64, nullptr, ctx->part.p, cb, dev);
 }
 
-// ||v||_2 of a device vector (FP64 complex), synchronous.
-int norm2(mpsl_ctx *ctx, const void *v, int64_t len, double &out, void *hbuf) {
-  int rc = launch_dotc_multi(ctx, v, 0, 1, v, len, hbuf);
-  if (rc) return rc;
-  double2 h;
-  MPSL_HIP_TRY(ctx, hipMemcpyAsync(&h, hbuf, sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
-  MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  out = std::sqrt(std::max(h.x, 0.0));
-  return MPSL_OK;
+namespace {
+
+
+}  // namespace
+
+SolveSM::~SolveSM() {
+  if (hh_) (void)hipHostFree(hh_);
 }
 
-struct Gm {
-  double2 *V = nullptr;     // (m+1) x len
-  double2 *w = nullptr;     // len
-  double2 *h = nullptr;     // (m+1)
-  double2 *h2 = nullptr;    // (m+1)
-  float2 *x32 = nullptr;    // len
-  float2 *y32 = nullptr;    // len
-  double2 *r = nullptr;     // len (residual)
-  double2 *xs = nullptr;    // len (solution)
-  double2 *b = nullptr;     // len (rhs)
-  double2 *d = nullptr;     // len (correction)
-};
-
-int gm_alloc(mpsl_ctx *ctx, int m, int64_t len, Gm &g) {
+int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
+  ctx_ = ctx;
+  o_ = o;
+  if (o_.inner_tol <= 0.0) o_.inner_tol = 1e-5;
+  len_ = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
+  m_ = (o.restart > 0 && o.restart < o.maxiter) ? o.restart : o.maxiter;
+  m_ = std::min(m_, 1000);  // Arnoldi dot products are reduced in a 64K-entry scratch
   const size_t c = sizeof(double2);
-  const size_t bytes = (static_cast<size_t>(m + 1) + 5) * len * c + 2 * (m + 2) * c + 2 * len * sizeof(float2) + 4096;
+  const size_t bytes = (static_cast<size_t>(m_ + 1) + 5) * len_ * c + 3 * static_cast<size_t>(m_ + 2) * c +
+                       2 * len_ * sizeof(float2) + 8192;
   int rc = dev_alloc(ctx, ctx->gm, bytes);
   if (rc) return rc;
   char *p = static_cast<char *>(ctx->gm.p);
@@ -61,126 +49,171 @@ int gm_alloc(mpsl_ctx *ctx, int m, int64_t len, Gm &g) {
     p += (nb + 255) / 256 * 256;
     return q;
   };
-  g.V = reinterpret_cast<double2 *>(take((m + 1) * len * c));
-  g.w = reinterpret_cast<double2 *>(take(len * c));
-  g.r = reinterpret_cast<double2 *>(take(len * c));
-  g.xs = reinterpret_cast<double2 *>(take(len * c));
-  g.b = reinterpret_cast<double2 *>(take(len * c));
-  g.d = reinterpret_cast<double2 *>(take(len * c));
-  g.h = reinterpret_cast<double2 *>(take((m + 2) * c));
-  g.h2 = reinterpret_cast<double2 *>(take((m + 2) * c));
-  g.x32 = reinterpret_cast<float2 *>(take(len * sizeof(float2)));
-  g.y32 = reinterpret_cast<float2 *>(take(len * sizeof(float2)));
-  return MPSL_OK;
-}
-
-// w = A v in precision prec (v, w FP64 device vectors).
-int op(mpsl_ctx *ctx, int prec, const double2 *v, double2 *w, Gm &g, int64_t len) {
-  if (prec == MPSL_FP64) return matvec(ctx, MPSL_FP64, v, w);
-  int rc;
-  if ((rc = launch_to_fp32(ctx, v, g.x32, len))) return rc;
-  if ((rc = matvec(ctx, MPSL_FP32, g.x32, g.y32))) return rc;
-  return launch_to_fp64(ctx, g.y32, w, len);
-}
-
-// Restarted GMRES on A x = rhs with x0 = 0 (x written to xout).  Arnoldi by
-// classical Gram-Schmidt applied twice, FP64; Givens rotations on the host.
-// Stops when the estimated relative residual is below tol or after maxit
-// matvecs.  Returns the number of matvecs through *its.
-int gmres(mpsl_ctx *ctx, int prec, const double2 *rhs, double2 *xout, int64_t len, double tol, int maxit,
-          int m, Gm &g, int *its, std::vector<double> &hist) {
-  int rc;
-  MPSL_HIP_TRY(ctx, hipMemsetAsync(xout, 0, len * sizeof(double2), ctx->stream));
-  double bn;
-  if ((rc = norm2(ctx, rhs, len, bn, g.h))) return rc;
-  *its = 0;
-  if (bn == 0.0) return MPSL_OK;
-  int total = 0;
-  bool first = true;
-  while (total < maxit) {
-    // r = rhs - A x
-    double beta0;
-    if (first) {
-      if ((rc = launch_scale(ctx, g.V, len, 1.0, rhs))) return rc;
-      beta0 = bn;
-    } else {
-      if ((rc = op(ctx, prec, xout, g.w, g, len))) return rc;
-      ++total;
-      if ((rc = launch_scale(ctx, g.V, len, 1.0, rhs))) return rc;
-      if ((rc = launch_axpy_c(ctx, g.V, g.w, len, -1.0, 0.0))) return rc;
-      if ((rc = norm2(ctx, g.V, len, beta0, g.h))) return rc;
-    }
-    first = false;
-    if (!std::isfinite(beta0)) return set_err(ctx, MPSL_ENUMERIC, "non-finite residual");
-    if (beta0 / bn < tol) break;
-    if ((rc = launch_scale(ctx, g.V, len, 1.0 / beta0, g.V))) return rc;
-    std::vector<zc> H(static_cast<size_t>(m + 1) * m, zc(0, 0)), cs(m), sn(m), gv(m + 1, zc(0, 0));
-    gv[0] = beta0;
-    int j = 0;
-    double res = beta0 / bn;
-    for (; j < m && total < maxit; ++j) {
-      double2 *vj = g.V + j * len;
-      double2 *vn = g.V + (j + 1) * len;
-      if ((rc = op(ctx, prec, vj, vn, g, len))) return rc;
-      ++total;
-      // two passes of classical Gram-Schmidt
-      std::vector<double2> hh(j + 1), hh2(j + 1);
-      if ((rc = launch_dotc_multi(ctx, g.V, len, j + 1, vn, len, g.h))) return rc;
-      if ((rc = launch_gemv_sub(ctx, g.V, len, j + 1, g.h, vn, len))) return rc;
-      if ((rc = launch_dotc_multi(ctx, g.V, len, j + 1, vn, len, g.h2))) return rc;
-      if ((rc = launch_gemv_sub(ctx, g.V, len, j + 1, g.h2, vn, len))) return rc;
-      MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh.data(), g.h, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
-      MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh2.data(), g.h2, (j + 1) * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
-      double hn;
-      if ((rc = norm2(ctx, vn, len, hn, g.h))) return rc;
-      for (int i = 0; i <= j; ++i) H[i * m + j] = zc(hh[i].x + hh2[i].x, hh[i].y + hh2[i].y);
-      H[(j + 1) * m + j] = hn;
-      if (!std::isfinite(hn)) return set_err(ctx, MPSL_ENUMERIC, "non-finite Arnoldi norm");
-      if (hn > 0.0 && (rc = launch_scale(ctx, vn, len, 1.0 / hn, vn))) return rc;
-      // apply previous rotations, then a new one
-      for (int i = 0; i < j; ++i) {
-        const zc a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[i * m + j] = std::conj(cs[i]) * a + std::conj(sn[i]) * b;
-        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-      }
-      const zc a = H[j * m + j], b = H[(j + 1) * m + j];
-      const double den = std::sqrt(std::norm(a) + std::norm(b));
-      if (den == 0.0) {
-        cs[j] = 1.0;
-        sn[j] = 0.0;
-      } else {
-        cs[j] = a / den;
-        sn[j] = b / den;
-      }
-      H[j * m + j] = std::conj(cs[j]) * a + std::conj(sn[j]) * b;
-      H[(j + 1) * m + j] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = std::conj(cs[j]) * gv[j];
-      res = std::abs(gv[j + 1]) / bn;
-      hist.push_back(res);
-      if (res < tol || hn == 0.0) {
-        ++j;
-        break;
-      }
-    }
-    // back substitution, x += V y
-    std::vector<zc> y(j);
-    for (int i = j - 1; i >= 0; --i) {
-      zc s = gv[i];
-      for (int k = i + 1; k < j; ++k) s -= H[i * m + k] * y[k];
-      y[i] = s / H[i * m + i];
-    }
-    std::vector<double2> yd(j);
-    for (int i = 0; i < j; ++i) yd[i] = make_double2(-y[i].real(), -y[i].imag());
-    MPSL_HIP_TRY(ctx, hipMemcpyAsync(g.h, yd.data(), j * sizeof(double2), hipMemcpyHostToDevice, ctx->stream));
-    if ((rc = launch_gemv_sub(ctx, g.V, len, j, g.h, xout, len))) return rc;  // x -= V (-y)
-    MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (res < tol) break;
+  V_ = reinterpret_cast<double2 *>(take((m_ + 1) * len_ * c));
+  w_ = reinterpret_cast<double2 *>(take(len_ * c));
+  r_ = reinterpret_cast<double2 *>(take(len_ * c));
+  xs_ = reinterpret_cast<double2 *>(take(len_ * c));
+  b_ = reinterpret_cast<double2 *>(take(len_ * c));
+  d_ = reinterpret_cast<double2 *>(take(len_ * c));
+  h_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
+  h2_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
+  nrm_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
+  x32_ = reinterpret_cast<float2 *>(take(len_ * sizeof(float2)));
+  y32_ = reinterpret_cast<float2 *>(take(len_ * sizeof(float2)));
+  if (hh_) (void)hipHostFree(hh_);
+  hh_ = nullptr;
+  // pinned staging: h (m+2), h2 (m+2), norm (1), y (m+1)
+  if (hipHostMalloc(reinterpret_cast<void **>(&hh_), (3 * static_cast<size_t>(m_ + 2) + 1) * c) != hipSuccess) {
+    hh_ = nullptr;
+    return set_err(ctx, MPSL_ENOMEM, "pinned host allocation failed");
   }
-  *its = total;
+  status_ = kRunning;
+  inner_mv_ = fp64_mv_ = refin_ = 0;
+  hist_.clear();
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(b_, b_dev, len_ * c, hipMemcpyDeviceToDevice, ctx->stream));
+  MPSL_HIP_TRY(ctx, hipMemsetAsync(xs_, 0, len_ * c, ctx->stream));
+  if ((rc = launch_scale(ctx, r_, len_, 1.0, b_))) return rc;
+  if ((rc = launch_dotc_multi(ctx, b_, 0, 1, b_, len_, nrm_))) return rc;
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + 2 * (m_ + 2), nrm_, c, hipMemcpyDeviceToHost, ctx->stream));
+  MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  bn_ = std::sqrt(std::max(hh_[2 * (m_ + 2)].x, 0.0));
+  if (!std::isfinite(bn_)) return set_err(ctx, MPSL_ENUMERIC, "non-finite right-hand side");
+  if (bn_ == 0.0) {
+    status_ = kConverged;
+    rel_res_ = 0.0;
+    return MPSL_OK;
+  }
+  rn_ = bn_;
+  rel_res_ = 1.0;
+  hist_.push_back(1.0);
+  return begin_inner();
+}
+
+int SolveSM::begin_inner() {
+  inner_abs_ = (o_.precision == MPSL_FP64) ? o_.tol * bn_ : std::max(o_.inner_tol * rn_, 0.5 * o_.tol * bn_);
+  int rc = launch_scale(ctx_, V_, len_, 1.0 / rn_, r_);
+  if (rc) return rc;
+  H_.assign(static_cast<size_t>(m_ + 1) * m_, zc(0.0, 0.0));
+  cs_.assign(m_, zc(0.0, 0.0));
+  sn_.assign(m_, zc(0.0, 0.0));
+  gv_.assign(m_ + 1, zc(0.0, 0.0));
+  gv_[0] = rn_;
+  j_ = 0;
+  phase_ = kInner;
   return MPSL_OK;
 }
 
+int SolveSM::launch() {
+  if (status_ != kRunning) return MPSL_OK;
+  mpsl_ctx *ctx = ctx_;
+  const size_t c = sizeof(double2);
+  int rc;
+  if (phase_ == kInner) {
+    double2 *vj = V_ + j_ * len_;
+    double2 *vn = V_ + (j_ + 1) * len_;
+    if (o_.precision == MPSL_FP64) {
+      if ((rc = matvec(ctx, MPSL_FP64, vj, vn))) return rc;
+    } else {
+      if ((rc = launch_to_fp32(ctx, vj, x32_, len_)) || (rc = matvec(ctx, MPSL_FP32, x32_, y32_)) ||
+          (rc = launch_to_fp64(ctx, y32_, vn, len_)))
+        return rc;
+    }
+    // two passes of classical Gram-Schmidt, then the norm
+    if ((rc = launch_dotc_multi(ctx, V_, len_, j_ + 1, vn, len_, h_)) ||
+        (rc = launch_gemv_sub(ctx, V_, len_, j_ + 1, h_, vn, len_)) ||
+        (rc = launch_dotc_multi(ctx, V_, len_, j_ + 1, vn, len_, h2_)) ||
+        (rc = launch_gemv_sub(ctx, V_, len_, j_ + 1, h2_, vn, len_)) ||
+        (rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_)))
+      return rc;
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_, h_, (j_ + 1) * c, hipMemcpyDeviceToHost, ctx->stream));
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + (m_ + 2), h2_, (j_ + 1) * c, hipMemcpyDeviceToHost, ctx->stream));
+  } else {
+    if ((rc = matvec(ctx, MPSL_FP64, xs_, w_)) || (rc = launch_scale(ctx, r_, len_, 1.0, b_)) ||
+        (rc = launch_axpy_c(ctx, r_, w_, len_, -1.0, 0.0)) ||
+        (rc = launch_dotc_multi(ctx, r_, 0, 1, r_, len_, nrm_)))
+      return rc;
+  }
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + 2 * (m_ + 2), nrm_, c, hipMemcpyDeviceToHost, ctx->stream));
+  return MPSL_OK;
+}
+
+int SolveSM::complete() {
+  if (status_ != kRunning) return MPSL_OK;
+  mpsl_ctx *ctx = ctx_;
+  MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  const double nn = std::sqrt(std::max(hh_[2 * (m_ + 2)].x, 0.0));
+  int rc;
+  if (phase_ == kInner) {
+    ++inner_mv_;
+    if (o_.precision == MPSL_FP64) ++fp64_mv_;
+    const int j = j_, m = m_;
+    if (!std::isfinite(nn)) return set_err(ctx, MPSL_ENUMERIC, "non-finite Arnoldi norm");
+    for (int i = 0; i <= j; ++i)
+      H_[i * m + j] = zc(hh_[i].x + hh_[m + 2 + i].x, hh_[i].y + hh_[m + 2 + i].y);
+    H_[(j + 1) * m + j] = nn;
+    if (nn > 0.0 && (rc = launch_scale(ctx, V_ + (j + 1) * len_, len_, 1.0 / nn, V_ + (j + 1) * len_))) return rc;
+    for (int i = 0; i < j; ++i) {  // previous rotations, then a new one
+      const zc a = H_[i * m + j], b = H_[(i + 1) * m + j];
+      H_[i * m + j] = std::conj(cs_[i]) * a + std::conj(sn_[i]) * b;
+      H_[(i + 1) * m + j] = -sn_[i] * a + cs_[i] * b;
+    }
+    const zc a = H_[j * m + j], b = H_[(j + 1) * m + j];
+    const double den = std::sqrt(std::norm(a) + std::norm(b));
+    if (den == 0.0) {
+      cs_[j] = 1.0;
+      sn_[j] = 0.0;
+    } else {
+      cs_[j] = a / den;
+      sn_[j] = b / den;
+    }
+    H_[j * m + j] = std::conj(cs_[j]) * a + std::conj(sn_[j]) * b;
+    H_[(j + 1) * m + j] = 0.0;
+    gv_[j + 1] = -sn_[j] * gv_[j];
+    gv_[j] = std::conj(cs_[j]) * gv_[j];
+    const double res = std::abs(gv_[j + 1]);
+    hist_.push_back(res / bn_);
+    j_ = j + 1;
+    if (res < inner_abs_ || j_ == m_ || nn == 0.0 || inner_mv_ >= o_.maxiter) return finish_cycle();
+    return MPSL_OK;
+  }
+  // residual phase
+  ++fp64_mv_;
+  if (!std::isfinite(nn)) return set_err(ctx, MPSL_ENUMERIC, "non-finite residual");
+  rn_ = nn;
+  rel_res_ = rn_ / bn_;
+  if (rel_res_ < o_.tol) {
+    status_ = kConverged;
+    return MPSL_OK;
+  }
+  if (inner_mv_ >= o_.maxiter || refin_ >= 100) {
+    status_ = kExhausted;
+    return MPSL_OK;
+  }
+  return begin_inner();
+}
+
+int SolveSM::finish_cycle() {
+  mpsl_ctx *ctx = ctx_;
+  const int j = j_, m = m_;
+  std::vector<zc> y(j);
+  for (int i = j - 1; i >= 0; --i) {
+    zc s = gv_[i];
+    for (int k = i + 1; k < j; ++k) s -= H_[i * m + k] * y[k];
+    y[i] = s / H_[i * m + i];
+  }
+  double2 *hy = hh_ + 2 * (m_ + 2) + 1;  // pinned, separate from the D2H staging
+  for (int i = 0; i < j; ++i) hy[i] = make_double2(-y[i].real(), -y[i].imag());
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(h_, hy, j * sizeof(double2), hipMemcpyHostToDevice, ctx->stream));
+  MPSL_HIP_TRY(ctx, hipMemsetAsync(d_, 0, len_ * sizeof(double2), ctx->stream));
+  int rc;
+  if ((rc = launch_gemv_sub(ctx, V_, len_, j, h_, d_, len_))) return rc;  // d = V y
+  if ((rc = launch_axpy_c(ctx, xs_, d_, len_, 1.0, 0.0))) return rc;
+  ++refin_;
+  phase_ = kResidual;
+  return MPSL_OK;
+}
+
+namespace {
 }  // namespace
 }  // namespace mpsl
 
@@ -194,7 +227,7 @@ int mpsl_rhs(mpsl_ctx *ctx, const double *src, mpsl_c128 *rhs) {
   if (!(src[1] > 0.0)) return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top layer (y > 0)");
   const size_t bytes = static_cast<size_t>(ctx->n) * (2 * ctx->p + 1) * sizeof(double2);
   if ((rc = mpsl::dev_alloc(ctx, ctx->ybuf, bytes))) return rc;
-  if ((rc = mpsl::rhs_dev(ctx, src, ctx->ybuf.p))) return rc;
+  if ((rc = mpsl::rhs_device(ctx, src, ctx->ybuf.p))) return rc;
   MPSL_HIP_TRY(ctx, hipMemcpyAsync(rhs, ctx->ybuf.p, bytes, hipMemcpyDeviceToHost, ctx->stream));
   MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   return MPSL_OK;
@@ -210,74 +243,34 @@ int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *
   if (opts) o = *opts;
   if (o.precision != MPSL_FP64 && o.precision != MPSL_FP32) return MPSL_EINVAL;
   if (!(o.tol > 0.0) || o.maxiter <= 0) return mpsl::set_err(ctx, MPSL_EINVAL, "tol > 0 and maxiter > 0");
-  const int m = (o.restart > 0 && o.restart < o.maxiter) ? o.restart : o.maxiter;
   const int64_t len = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
-  mpsl::Gm g;
-  if ((rc = mpsl::gm_alloc(ctx, m, len, g))) return rc;
   int status = MPSL_OK;
   for (int r = 0; r < n_rhs; ++r) {
     const double *src = src_xy + 2 * r;
     if (!(src[1] > 0.0)) return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top layer (y > 0)");
     const auto t0 = std::chrono::steady_clock::now();
-    ctx->hist.clear();
-    if ((rc = mpsl::rhs_dev(ctx, src, g.b))) return rc;
-    double bn;
-    if ((rc = mpsl::norm2(ctx, g.b, len, bn, g.h))) return rc;
-    int iters = 0, fp64mv = 0, refin = 0;
-    double relres = 0.0;
-    if (o.precision == MPSL_FP64) {
-      int its = 0;
-      if ((rc = mpsl::gmres(ctx, MPSL_FP64, g.b, g.xs, len, o.tol, o.maxiter, m, g, &its, ctx->hist))) return rc;
-      iters = its;
-      fp64mv = its;
-    } else {
-      // FP64 iterative refinement around an FP32-matvec GMRES
-      const double itol = o.inner_tol > 0.0 ? o.inner_tol : 1e-5;
-      MPSL_HIP_TRY(ctx, hipMemsetAsync(g.xs, 0, len * sizeof(double2), ctx->stream));
-      if ((rc = mpsl::launch_scale(ctx, g.r, len, 1.0, g.b))) return rc;
-      int budget = o.maxiter;
-      for (;;) {
-        double rn;
-        if ((rc = mpsl::norm2(ctx, g.r, len, rn, g.h))) return rc;
-        if (!std::isfinite(rn)) return mpsl::set_err(ctx, MPSL_ENUMERIC, "non-finite refinement residual");
-        ctx->hist.push_back(rn / bn);
-        if (rn / bn < o.tol || budget <= 0 || refin >= 50) break;
-        int its = 0;
-        std::vector<double> inner;
-        if ((rc = mpsl::gmres(ctx, MPSL_FP32, g.r, g.d, len, itol, budget, m, g, &its, inner))) return rc;
-        budget -= its;
-        iters += its;
-        ++refin;
-        if ((rc = mpsl::launch_axpy_c(ctx, g.xs, g.d, len, 1.0, 0.0))) return rc;
-        // r = b - A64 x
-        if ((rc = mpsl::matvec(ctx, MPSL_FP64, g.xs, g.w))) return rc;
-        ++fp64mv;
-        if ((rc = mpsl::launch_scale(ctx, g.r, len, 1.0, g.b))) return rc;
-        if ((rc = mpsl::launch_axpy_c(ctx, g.r, g.w, len, -1.0, 0.0))) return rc;
-      }
+    if ((rc = mpsl::dev_alloc(ctx, ctx->ybuf, len * sizeof(double2)))) return rc;
+    if ((rc = mpsl::rhs_device(ctx, src, ctx->ybuf.p))) return rc;
+    mpsl::SolveSM sm;
+    if ((rc = sm.init(ctx, o, ctx->ybuf.p))) return rc;
+    while (sm.status() == mpsl::SolveSM::kRunning) {
+      if ((rc = sm.launch()) || (rc = sm.complete())) return rc;
     }
-    // true FP64 residual
-    if ((rc = mpsl::matvec(ctx, MPSL_FP64, g.xs, g.w))) return rc;
-    ++fp64mv;
-    if ((rc = mpsl::launch_scale(ctx, g.r, len, 1.0, g.b))) return rc;
-    if ((rc = mpsl::launch_axpy_c(ctx, g.r, g.w, len, -1.0, 0.0))) return rc;
-    double rn;
-    if ((rc = mpsl::norm2(ctx, g.r, len, rn, g.h))) return rc;
-    relres = bn > 0 ? rn / bn : 0.0;
-    MPSL_HIP_TRY(ctx, hipMemcpyAsync(beta_out + r * len, g.xs, len * sizeof(double2), hipMemcpyDeviceToHost,
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(beta_out + r * len, sm.x(), len * sizeof(double2), hipMemcpyDeviceToHost,
                                      ctx->stream));
     MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const auto t1 = std::chrono::steady_clock::now();
+    ctx->hist = sm.history();
     if (info) {
-      info->iterations = iters;
-      info->fp64_matvecs = fp64mv;
-      info->refinements = refin;
-      info->rel_residual = relres;
+      info->iterations = sm.iterations();
+      info->fp64_matvecs = sm.fp64_matvecs();
+      info->refinements = sm.refinements();
+      info->rel_residual = sm.rel_residual();
       info->seconds = std::chrono::duration<double>(t1 - t0).count();
       info->history = ctx->hist.data();
       info->history_len = static_cast<int>(ctx->hist.size());
     }
-    if (!(relres < o.tol * 10.0)) status = MPSL_ENOCONV;
+    if (sm.status() != mpsl::SolveSM::kConverged) status = MPSL_ENOCONV;
   }
   return status;
 }
