@@ -261,6 +261,35 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec);
 int mpsl_set_tuning(mpsl_ctx *ctx, int prec, int variant, int chunks);
 int mpsl_get_tuning(const mpsl_ctx *ctx, int prec, int *variant, int *chunks, double *m2l_ms);
 
+/* Far field of the free-space M2L (row a1) for large N: a 2D Helmholtz fast
+ * multipole method (the O(M (2p+1)^2) acceleration of the GMRES matvec
+ * named in Section 3.2 and used for the large-M runs of Section 6.1) on a
+ * uniform quadtree of the particle centres.  Pairs in the
+ * same or adjacent leaf boxes are summed directly as in row a1; all other
+ * pairs go particle -> leaf multipole (Graf, J-shift), multipole ->
+ * multipole, multipole -> local between well-separated boxes of one level
+ * (the Toeplitz Graf translation of eq. (24) at box scale), local -> local,
+ * local -> particle.  Orders per level follow from tol (relative accuracy of
+ * the free-space field as the scattering matrix sees it; FP32 uses
+ * max(tol, 1e-7)).
+ *   method: MPSL_FAR_AUTO   FMM when N > 8000, else direct (default);
+ *           MPSL_FAR_DIRECT all pairs directly;
+ *           MPSL_FAR_FMM    FMM at any N.
+ *   tol:    1e-13 <= tol <= 1e-3 (0 keeps the current value, default 1e-10).
+ * The choice takes effect at the next call that builds tables.  With the FMM
+ * active mpsl_autotune leaves the tuning unchanged, and mpsl_profile times
+ * the whole FMM sequence in place of the M2L kernel. */
+enum { MPSL_FAR_AUTO = 0, MPSL_FAR_DIRECT = 1, MPSL_FAR_FMM = 2 };
+int mpsl_set_far_field(mpsl_ctx *ctx, int method, double tol);
+
+/* Shape of the FMM built for the current problem (after a first apply or
+ * solve): active = 1 when the FMM replaces the direct sum; levels, leaf box
+ * side, orders of the leaf and top level in precision prec, true near-field
+ * pair count and the translation work (complex MACs) of one apply in prec.
+ * Any output pointer may be NULL. */
+int mpsl_get_fmm_info(const mpsl_ctx *ctx, int prec, int *active, int *levels, double *leaf_side,
+                      int *p_leaf, int *p_top, int64_t *near_pairs, double *tree_cmac);
+
 /* Average duration (ms) of the last `count` launches of the M2L kernel
  * recorded with HIP events on the context stream (0 when not recorded);
  * enable recording with mpsl_profile(ctx, 1). */

@@ -15,6 +15,7 @@ from . import _lib
 
 FP64 = 0
 FP32 = 1
+FAR_AUTO, FAR_DIRECT, FAR_FMM = 0, 1, 2
 
 STATUS = {0: "MPSL_OK", -1: "MPSL_EINVAL", -2: "MPSL_ENOMEM", -3: "MPSL_EHIP", -4: "MPSL_ESTATE",
           -5: "MPSL_EGEOM", -6: "MPSL_ENOCONV", -7: "MPSL_EUNSUPPORTED", -8: "MPSL_EINSIDE",
@@ -267,6 +268,19 @@ class Context:
         v, c, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         self._check(self.lib.mpsl_get_tuning(self.h, int(prec), ctypes.byref(v), ctypes.byref(c), ctypes.byref(ms)))
         return dict(variant=v.value, chunks=c.value, m2l_ms=ms.value)
+
+    def set_far_field(self, method, tol=0.0):
+        """Direct all-pairs or FMM far field (FAR_AUTO / FAR_DIRECT / FAR_FMM)."""
+        return self._check(self.lib.mpsl_set_far_field(self.h, int(method), float(tol)))
+
+    def fmm_info(self, prec=FP64):
+        a, lv, pl, pt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        side, work, pairs = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.mpsl_get_fmm_info(self.h, int(prec), ctypes.byref(a), ctypes.byref(lv),
+                                               ctypes.byref(side), ctypes.byref(pl), ctypes.byref(pt),
+                                               ctypes.byref(pairs), ctypes.byref(work)))
+        return dict(active=bool(a.value), levels=lv.value, leaf_side=side.value, p_leaf=pl.value,
+                    p_top=pt.value, near_pairs=pairs.value, tree_cmac=work.value)
 
     def profile(self, enable=True):
         return self._check(self.lib.mpsl_profile(self.h, 1 if enable else 0))

@@ -72,6 +72,9 @@ SIGNATURES = {
     "mpsl_get_tuning": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), DP]),
     "mpsl_profile": (I, [P, I]),
     "mpsl_profile_read": (I, [P, DP, ctypes.POINTER(I)]),
+    "mpsl_set_far_field": (I, [P, I, ctypes.c_double]),
+    "mpsl_get_fmm_info": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), DP, ctypes.POINTER(I),
+                              ctypes.POINTER(I), ctypes.POINTER(L), DP]),
 }
 
 _lib = None

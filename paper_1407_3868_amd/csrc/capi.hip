@@ -335,7 +335,9 @@ int build_tables(mpsl_ctx *ctx) {
       (rc = dev_alloc(ctx, ctx->gt.F32, tab * sizeof(float2))))
     return rc;
   if ((rc = launch_geom_tables(ctx))) return rc;
-  if (!ctx->gt.pairs_ok) {
+  if (fmm_wanted(ctx)) {
+    if ((rc = fmm_build(ctx))) return rc;
+  } else if (!ctx->gt.pairs_ok) {
     const size_t np = static_cast<size_t>(n) * static_cast<size_t>(n) * 4;
     if ((rc = dev_alloc(ctx, ctx->gt.pair64, np * sizeof(double2))) ||
         (rc = dev_alloc(ctx, ctx->gt.pair32, np * sizeof(float2))))
@@ -343,6 +345,7 @@ int build_tables(mpsl_ctx *ctx) {
     if ((rc = launch_pair_tables(ctx))) return rc;
     ctx->gt.pairs_ok = true;
   }
+  if (!fmm_wanted(ctx)) ctx->fmm.active = false;
   MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   ctx->tables_ok = true;
   return ensure_work(ctx);
@@ -373,7 +376,9 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
   if (rc) return rc;
   if (nrhs < 1) return set_err(ctx, MPSL_EINVAL, "nrhs must be >= 1");
   // the right-hand-side dimension already multiplies the grid: fewer chunks
-  const int ca = std::max(1, chunks_m2l(ctx, prec) / nrhs), cb = chunks_s2l(ctx, nrhs);
+  // (the FMM writes two partials: near field and far field)
+  const bool fmm = ctx->fmm.active;
+  const int ca = fmm ? 2 : std::max(1, chunks_m2l(ctx, prec) / nrhs), cb = chunks_s2l(ctx, nrhs);
   const int cc = chunks_m2s(ctx, nrhs);
   const int P = 2 * ctx->p + 1;
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
@@ -398,7 +403,14 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
     MPSL_HIP_TRY(ctx, hipEventCreate(&e1));
     MPSL_HIP_TRY(ctx, hipEventRecord(e0, ctx->stream));
   }
-  if ((rc = launch_m2l(ctx, prec, x, part, ca, -1, nrhs, pstride))) return rc;
+  if (fmm) {
+    for (int r = 0; r < nrhs; ++r)
+      if ((rc = fmm_apply(ctx, prec, static_cast<const char *>(x) + static_cast<size_t>(r) * len * esz,
+                          part + static_cast<size_t>(r) * pstride * esz)))
+        return rc;
+  } else if ((rc = launch_m2l(ctx, prec, x, part, ca, -1, nrhs, pstride))) {
+    return rc;
+  }
   if (ctx->prof) {
     MPSL_HIP_TRY(ctx, hipEventRecord(e1, ctx->stream));
     ctx->ev_start.push_back(e0);
@@ -461,6 +473,7 @@ void mpsl_destroy(mpsl_ctx *ctx) {
                   &ctx->m2s_part, &ctx->spec, &ctx->sigma, &ctx->Up64, &ctx->Up32, &ctx->xbuf,
                   &ctx->ybuf, &ctx->gm, &ctx->scal};
   for (DBuf *b : bufs) mpsl::dev_free(*b);
+  mpsl::fmm_free(ctx);
   delete ctx;
 }
 
@@ -719,11 +732,16 @@ int mpsl_m2l_dev(mpsl_ctx *ctx, int prec, const void *beta, void *alpha) {
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
-  const int ca = mpsl::chunks_m2l(ctx, prec);
+  const bool fmm = ctx->fmm.active;
+  const int ca = fmm ? 2 : mpsl::chunks_m2l(ctx, prec);
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
   if ((rc = mpsl::dev_alloc(ctx, ctx->part, static_cast<size_t>(ca) * ctx->n * (2 * ctx->p + 1) * esz))) return rc;
-  if ((rc = mpsl::launch_m2l(ctx, prec, beta, ctx->part.p, ca))) return rc;
-  return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, mpsl::m2l_slots(ctx, prec), alpha);
+  if (fmm) {
+    if ((rc = mpsl::fmm_apply(ctx, prec, beta, ctx->part.p))) return rc;
+  } else if ((rc = mpsl::launch_m2l(ctx, prec, beta, ctx->part.p, ca))) {
+    return rc;
+  }
+  return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, ca, alpha);
 }
 
 int mpsl_m2s_dev(mpsl_ctx *ctx, int prec, const void *beta, void *spec) {
@@ -812,6 +830,7 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
+  if (ctx->fmm.active) return MPSL_OK;  // the direct kernel is not used
   auto &t = ctx->tune[prec == MPSL_FP64 ? 0 : 1];
   t.chunks = 0;
   const int base = mpsl::chunks_m2l(ctx, prec);

@@ -40,6 +40,52 @@ struct GeomTables {
   bool pairs_ok = false;
 };
 
+// One level of the FMM quadtree (uniform boxes of side s on a common origin;
+// level 0 holds the leaves, every level above halves the box count per axis).
+struct FmmLevel {
+  int nx = 0, ny = 0;
+  double s = 0.0;
+  int p[2] = {0, 0};          // expansion order per precision [FP64, FP32]
+  int64_t moff[2] = {0, 0};   // multipole block in the expansion buffer (complex units)
+  int64_t loff[2] = {0, 0};   // local block
+  std::vector<uint8_t> occ;   // box holds at least one particle
+};
+
+// Task lists of one launch of the generic translation kernel: every task
+// writes one expansion, summing Toeplitz products over its terms.
+struct FmmStage {
+  int tasks = 0;
+  int pout = 0, pin_max = 0, max_terms = 0;
+  int64_t task_off = 0, term_off = 0;  // into FmmPlan::tasks / terms
+};
+
+struct FmmPlan {
+  bool active = false;
+  int top = 0;                // index of the top level
+  double x0 = 0.0, y0 = 0.0;  // origin of the box grid
+  std::vector<FmmLevel> lv;
+  // particles sorted by leaf box (row-major leaf index)
+  std::vector<int32_t> perm_h, start_h;
+  DBuf perm;                  // int32[n]: sorted position -> particle
+  DBuf start;                 // int32[leaf boxes + 1]
+  // per precision: translation tables, tasks and terms, expansion buffer
+  DBuf tab[2];
+  DBuf tasks[2], terms[2];
+  std::vector<FmmStage> up[2];    // M2M, level 0 -> 1, ...
+  std::vector<FmmStage> down[2];  // M2L (+ L2L), top level first
+  int64_t p2m_off[2] = {0, 0}, l2p_off[2] = {0, 0};  // per-particle rows in tab
+  int64_t xlen[2] = {0, 0};
+  DBuf xb;                    // expansion buffer (sized for FP64)
+  // near field: padded lists of neighbour sources per sorted target
+  int near_k = 0;
+  DBuf near_src;              // int32[near_k][n] source particle (padding: the target)
+  DBuf near_cnt;              // int32[n]: true list length
+  DBuf near_wave;             // int32[waves]: loop count of each 64-target wave
+  DBuf near64, near32;        // [near_k][n][4]: H_0, H_1, e^{i phi}, (2/z, 0)
+  int64_t near_pairs = 0;     // true neighbour pairs
+  double tree_cmac[2] = {0.0, 0.0};  // translation work per apply
+};
+
 }  // namespace mpsl
 
 struct mpsl_ctx {
@@ -70,6 +116,10 @@ struct mpsl_ctx {
   std::vector<mpsl::zc> lam, w;
 
   bool tables_ok = false;  // contour + geometry tables current
+  // far field of the free-space M2L: direct all pairs or FMM
+  int far_method = MPSL_FAR_AUTO;
+  double far_tol = 1e-10;
+  mpsl::FmmPlan fmm;
   mpsl::ContourTables ct;
   mpsl::GeomTables gt;
 
@@ -112,4 +162,10 @@ int build_tables(mpsl_ctx *ctx);
 int ensure_work(mpsl_ctx *ctx);
 int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs);
 int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y);
+bool fmm_wanted(const mpsl_ctx *ctx);
+int fmm_build(mpsl_ctx *ctx);
+void fmm_free(mpsl_ctx *ctx);
+// Free-space M2L by the FMM: near-field pairs into part, far field into
+// part + len (two partial slots, len = n P complex entries).
+int fmm_apply(mpsl_ctx *ctx, int prec, const void *beta, void *part);
 }  // namespace mpsl

@@ -1,0 +1,927 @@
+// Fast multipole method for the free-space far field of the M2L (row a1),
+// the O(M (2p+1)^2) acceleration of the GMRES matvec that Section 3.2 names
+// and Section 6.1 uses for large M.
+//
+// Tree: uniform boxes of side s_0 on a common origin (leaf level 0); level
+// l + 1 merges 2x2 boxes of level l.  Expansions about box centres use the
+// conventions of the particle expansions (multipole sum_n M_n H_n(k r)
+// e^{i n theta}, local sum_n L_n J_n(k r) e^{i n theta}) with per-level
+// orders p_l.  Every translation is a Toeplitz product
+//   out_{j'} += sum_j tab[j - j' + P_out - 1] in_j       (slots j = n + p)
+// with the entries of tab (q the index difference of the translation):
+//   P2M, M2M  J_q(k rho) e^{-i q phi},  q = -idx + p_in + p_out,  rho, phi = polar(x_in - c_out)
+//   M2L       H_q(k rho) e^{ i q phi},  q = idx - 2 p,            rho, phi = polar(c_out - c_in)
+//   L2L, L2P  J_q(k rho) e^{ i q phi},  q = idx - p_in - p_out,   rho, phi = polar(x_out - c_in)
+// (Graf's addition theorem in its three forms; the M2L is eq. (24) between
+// box centres).  Pairs of particles in the same or adjacent leaf boxes are
+// summed directly by the particle M2L kernel over padded neighbour lists.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "kernels.h"
+
+namespace mpsl {
+
+namespace {
+
+constexpr int kRB = 8;                // consecutive outputs per lane
+constexpr int kToepMaxThreads = 256;  // translation kernel block
+constexpr size_t kLdsBudget = 64 * 1024;
+constexpr int kMaxBoxOrder = 600;     // largest box order (LDS of one term in FP64)
+constexpr int kAutoThreshold = 8000;  // MPSL_FAR_AUTO: FMM above this many particles
+
+struct FmmTask {
+  int64_t out;  // first entry of the output expansion
+  int t0, t1;   // term range
+};
+struct FmmTerm {
+  int64_t in;   // first entry of the input expansion
+  int64_t tab;  // first entry of the table row
+  int pin;      // input length
+  int pad;
+};
+
+__host__ __device__ inline int cdiv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Host Bessel sequences (FP64).
+
+// J_q(x) for q = 0..qmax (qmax >= 1): backward recurrence
+// J_{q-1} = (2q/x) J_q - J_{q+1} from well above max(qmax, x), rescaled on
+// the way down and normalised with the libm J_0(x) or J_1(x).
+void bessel_j_seq(double x, int qmax, double *J) {
+  std::fill(J, J + qmax + 1, 0.0);
+  if (x == 0.0) {
+    J[0] = 1.0;
+    return;
+  }
+  const double big = std::max(static_cast<double>(qmax), x);
+  const int top = static_cast<int>(big) + 30 + static_cast<int>(std::sqrt(40.0 * (big + 10.0)));
+  double jp1 = 0.0, jc = 1e-200;
+  for (int q = top; q >= 1; --q) {
+    const double jm1 = (2.0 * q / x) * jc - jp1;
+    jp1 = jc;
+    jc = jm1;
+    if (q - 1 <= qmax) J[q - 1] = jc;
+    if (std::fabs(jc) > 1e200) {
+      jc *= 1e-200;
+      jp1 *= 1e-200;
+      for (int i = q - 1; i <= qmax; ++i) J[i] *= 1e-200;
+    }
+  }
+  const double a0 = j0(x), a1 = j1(x);
+  const double scale = std::fabs(a0) >= std::fabs(a1) ? a0 / J[0] : a1 / J[1];
+  for (int i = 0; i <= qmax; ++i) J[i] *= scale;
+}
+
+// Y_q(x) for q = 0..qmax by the (stable) upward recurrence.
+void bessel_y_seq(double x, int qmax, double *Y) {
+  Y[0] = y0(x);
+  if (qmax >= 1) Y[1] = y1(x);
+  for (int q = 1; q < qmax; ++q) Y[q + 1] = (2.0 * q / x) * Y[q] - Y[q - 1];
+}
+
+// Table row of a J-shift (P2M/M2M with sign = -1, L2L/L2P with sign = +1):
+// row[idx] = J_q(k rho) e^{i sign q phi}, q = sign (idx - p_in - p_out).
+void jshift_row(double k, double dx, double dy, int p_in, int p_out, int sign, zc *row) {
+  const int len = 2 * p_in + 2 * p_out + 1;
+  const int qmax = std::max(1, p_in + p_out);
+  std::vector<double> J(qmax + 1);
+  const double rho = std::hypot(dx, dy);
+  const double phi = rho > 0.0 ? std::atan2(dy, dx) : 0.0;
+  bessel_j_seq(k * rho, qmax, J.data());
+  for (int idx = 0; idx < len; ++idx) {
+    const int q = sign * (idx - p_in - p_out);
+    const int aq = std::abs(q);
+    const double jq = (q < 0 && (aq & 1)) ? -J[aq] : J[aq];
+    const double a = sign * q * phi;
+    row[idx] = zc(jq * std::cos(a), jq * std::sin(a));
+  }
+}
+
+// M2L row of order p: row[idx] = H_q(k rho) e^{i q phi}, q = idx - 2p,
+// rho, phi = polar(dx, dy) (target centre minus source centre).
+void m2l_row(double k, double dx, double dy, int p, zc *row) {
+  const int qmax = std::max(1, 2 * p);
+  std::vector<double> J(qmax + 1), Y(qmax + 1);
+  const double rho = std::hypot(dx, dy);
+  const double phi = std::atan2(dy, dx);
+  bessel_j_seq(k * rho, qmax, J.data());
+  bessel_y_seq(k * rho, qmax, Y.data());
+  for (int idx = 0; idx <= 4 * p; ++idx) {
+    const int q = idx - 2 * p;
+    const int aq = std::abs(q);
+    zc h(J[aq], Y[aq]);
+    if (q < 0 && (aq & 1)) h = -h;
+    const double a = q * phi;
+    row[idx] = h * zc(std::cos(a), std::sin(a));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Order per box size: p = max(p_a(D), k s + c(D), p_particle), D = -log10 eps.
+// Fitted to the worst-case chain P2M -> M2L (offset 2 boxes) -> L2P with
+// both ends weighted by the decay of a scattering matrix, plus margin.
+int box_order(double ks, double eps, int p_particle) {
+  const double D = -std::log10(eps);
+  const int a = static_cast<int>(std::ceil(3.5 * D + 13.0));
+  const int b = static_cast<int>(std::ceil(ks + 2.0 * D - 4.0));
+  return std::max(std::max(a, b), p_particle);
+}
+
+struct Shape {
+  double s0 = 0.0;
+  int top = 0;
+  double cost = 0.0;
+};
+
+// Uniform leaf grid of side s0 and the box counts of every level above it.
+struct Grid {
+  double x0 = 0.0, y0 = 0.0, s0 = 0.0;
+  std::vector<int> nx, ny;
+  std::vector<std::vector<uint8_t>> occ;
+  std::vector<int> leaf;  // leaf box of each particle
+};
+
+Grid make_grid(const std::vector<double> &xy, int64_t n, double s0) {
+  Grid g;
+  double xmin = xy[0], xmax = xy[0], ymin = xy[1], ymax = xy[1];
+  for (int64_t i = 1; i < n; ++i) {
+    xmin = std::min(xmin, xy[2 * i]);
+    xmax = std::max(xmax, xy[2 * i]);
+    ymin = std::min(ymin, xy[2 * i + 1]);
+    ymax = std::max(ymax, xy[2 * i + 1]);
+  }
+  g.s0 = s0;
+  g.x0 = xmin - 1e-9 * s0;
+  g.y0 = ymin - 1e-9 * s0;
+  int nx = std::max(1, static_cast<int>(std::floor((xmax - g.x0) / s0)) + 1);
+  int ny = std::max(1, static_cast<int>(std::floor((ymax - g.y0) / s0)) + 1);
+  g.leaf.resize(n);
+  std::vector<uint8_t> occ(static_cast<size_t>(nx) * ny, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int ix = std::min(nx - 1, static_cast<int>(std::floor((xy[2 * i] - g.x0) / s0)));
+    const int iy = std::min(ny - 1, static_cast<int>(std::floor((xy[2 * i + 1] - g.y0) / s0)));
+    g.leaf[i] = iy * nx + ix;
+    occ[g.leaf[i]] = 1;
+  }
+  g.nx.push_back(nx);
+  g.ny.push_back(ny);
+  g.occ.push_back(occ);
+  while (nx > 1 || ny > 1) {
+    const int px = (nx + 1) / 2, py = (ny + 1) / 2;
+    std::vector<uint8_t> po(static_cast<size_t>(px) * py, 0);
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix)
+        if (g.occ.back()[iy * nx + ix]) po[(iy / 2) * px + ix / 2] = 1;
+    nx = px;
+    ny = py;
+    g.nx.push_back(nx);
+    g.ny.push_back(ny);
+    g.occ.push_back(po);
+  }
+  return g;
+}
+
+inline bool adjacent(int ax, int ay, int bx, int by) { return std::abs(ax - bx) <= 1 && std::abs(ay - by) <= 1; }
+
+// Source boxes of the M2L of box (ix, iy) at level l (top: all non-adjacent).
+template <typename F>
+void for_interactions(const Grid &g, int l, bool top, int ix, int iy, F f) {
+  const int nx = g.nx[l], ny = g.ny[l];
+  const auto &occ = g.occ[l];
+  if (top) {
+    for (int jy = 0; jy < ny; ++jy)
+      for (int jx = 0; jx < nx; ++jx)
+        if (occ[jy * nx + jx] && !adjacent(ix, iy, jx, jy)) f(jx, jy);
+    return;
+  }
+  const int px = ix / 2, py = iy / 2;
+  for (int jy = std::max(0, 2 * (py - 1)); jy <= std::min(ny - 1, 2 * (py + 1) + 1); ++jy)
+    for (int jx = std::max(0, 2 * (px - 1)); jx <= std::min(nx - 1, 2 * (px + 1) + 1); ++jx)
+      if (occ[jy * nx + jx] && !adjacent(ix, iy, jx, jy)) f(jx, jy);
+}
+
+// Cost (complex MACs, spread over 256 compute units, the largest single
+// task counted in full) of the tree part for a given top level.
+double tree_cost(const Grid &g, const std::vector<int> &P, int top, int64_t n, int Pp) {
+  const double cus = 256.0;
+  double cost = 2.0 * n * Pp * P[0] / cus;  // P2M + L2P
+  for (int l = 0; l <= top; ++l) {
+    const int nx = g.nx[l], ny = g.ny[l];
+    double work = 0.0, maxtask = 0.0;
+    int64_t nonempty = 0;
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix) {
+        if (!g.occ[l][iy * nx + ix]) continue;
+        ++nonempty;
+        int64_t terms = 0;
+        for_interactions(g, l, l == top, ix, iy, [&](int, int) { ++terms; });
+        const double w = static_cast<double>(terms) * P[l] * P[l];
+        work += w;
+        maxtask = std::max(maxtask, w);
+      }
+    if (l == top) maxtask /= std::max(1.0, std::ceil(512.0 / std::max<int64_t>(1, nonempty)));
+    cost += std::max(work / cus, maxtask);
+    if (l < top) cost += 2.0 * nonempty * P[l] * P[l + 1] / cus;  // M2M + L2L
+  }
+  return cost;
+}
+
+double near_cost(const Grid &g, int64_t n, int Pp) {
+  const int nx = g.nx[0], ny = g.ny[0];
+  std::vector<int64_t> cnt(static_cast<size_t>(nx) * ny, 0);
+  for (int64_t i = 0; i < n; ++i) ++cnt[g.leaf[i]];
+  double pairs = 0.0;
+  for (int iy = 0; iy < ny; ++iy)
+    for (int ix = 0; ix < nx; ++ix) {
+      const int64_t c = cnt[iy * nx + ix];
+      if (!c) continue;
+      int64_t nb = 0;
+      for (int jy = std::max(0, iy - 1); jy <= std::min(ny - 1, iy + 1); ++jy)
+        for (int jx = std::max(0, ix - 1); jx <= std::min(nx - 1, ix + 1); ++jx) nb += cnt[jy * nx + jx];
+      pairs += static_cast<double>(c) * (nb - 1);
+    }
+  return pairs * Pp * Pp / 256.0;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Device kernels.
+
+// P2M: one block per leaf box, one lane per output slot of the box multipole.
+template <typename T>
+__global__ void k_fmm_p2m(const cv_t<T> *__restrict__ beta, const int *__restrict__ perm,
+                          const int *__restrict__ start, const cv_t<T> *__restrict__ tab, int P, int P0,
+                          cv_t<T> *__restrict__ mout) {
+  __shared__ cx<T> bs[2 * kMaxP + 1];
+  const int b = blockIdx.x;
+  const int i0 = start[b], i1 = start[b + 1];
+  if (i0 == i1) return;
+  const int tl = P0 + P - 1;
+  const int nrounds = cdiv(P0, blockDim.x);
+  for (int r = 0; r < nrounds; ++r) {
+    const int jo = r * blockDim.x + threadIdx.x;
+    cx<T> acc = mk<T>(0, 0);
+    for (int i = i0; i < i1; ++i) {
+      __syncthreads();
+      if (threadIdx.x < P) bs[threadIdx.x] = ld<T>(beta[static_cast<int64_t>(perm[i]) * P + threadIdx.x]);
+      __syncthreads();
+      if (jo < P0) {
+        const cv_t<T> *row = tab + static_cast<int64_t>(i) * tl + (P0 - 1) - jo;
+        for (int j = 0; j < P; ++j) cmac(acc, ld<T>(row[j]), bs[j]);
+      }
+    }
+    if (jo < P0) mout[static_cast<int64_t>(b) * P0 + jo] = st(acc);
+  }
+}
+
+// L2P: one block per leaf box; lanes over (particle, output slot).
+template <typename T>
+__global__ void k_fmm_l2p(const cv_t<T> *__restrict__ lin, const int *__restrict__ perm,
+                          const int *__restrict__ start, const cv_t<T> *__restrict__ tab, int P, int P0,
+                          cv_t<T> *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char l2p_smem[];
+  cx<T> *Ls = reinterpret_cast<cx<T> *>(l2p_smem);
+  const int b = blockIdx.x;
+  const int i0 = start[b], i1 = start[b + 1];
+  if (i0 == i1) return;
+  for (int j = threadIdx.x; j < P0; j += blockDim.x) Ls[j] = ld<T>(lin[static_cast<int64_t>(b) * P0 + j]);
+  __syncthreads();
+  const int tl = P0 + P - 1;
+  const int tot = (i1 - i0) * P;
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int i = i0 + t / P, jo = t % P;
+    const cv_t<T> *row = tab + static_cast<int64_t>(i) * tl + (P - 1) - jo;
+    cx<T> acc = mk<T>(0, 0);
+    for (int j = 0; j < P0; ++j) cmac(acc, ld<T>(row[j]), Ls[j]);
+    out[static_cast<int64_t>(perm[i]) * P + jo] = st(acc);
+  }
+}
+
+// Generic translation: one block per task, G subsets of tps lanes; each
+// subset takes every G-th term of the task, stages the input expansion and
+// the table row in LDS and accumulates kRB consecutive outputs per lane
+// with the Toeplitz window held in registers (one LDS read of the table
+// and one broadcast read of the input per kRB complex MACs).  The table row
+// is stored permuted, logical index x at (x mod 8) * l8 + x / 8, so that the
+// lanes of a subset (whose windows are 8 entries apart) read consecutive
+// words.  Subsets are summed through LDS at the end.
+template <typename T>
+__global__ __launch_bounds__(kToepMaxThreads) void k_fmm_toep(const FmmTask *__restrict__ tasks,
+                                                               const FmmTerm *__restrict__ terms,
+                                                               const cv_t<T> *__restrict__ xin,
+                                                               const cv_t<T> *__restrict__ tabs,
+                                                               cv_t<T> *__restrict__ xout, int pout, int tps,
+                                                               int pin_pad, int l8) {
+  extern __shared__ __align__(16) unsigned char toep_smem[];
+  cx<T> *sm = reinterpret_cast<cx<T> *>(toep_smem);
+  const int G = blockDim.x / tps;
+  const int sub = threadIdx.x / tps, lt = threadIdx.x - sub * tps;
+  const int per = pin_pad + 8 * l8;
+  cx<T> *Ms = sm + sub * per;
+  cx<T> *Hp = Ms + pin_pad;
+  const FmmTask tk = tasks[blockIdx.x];
+  const int nt = tk.t1 - tk.t0;
+  const int ngroups = cdiv(pout, kRB);
+  const int hl = 8 * l8;
+  for (int g0 = 0; g0 < ngroups; g0 += tps) {
+    const int g = g0 + lt;
+    const bool act = g < ngroups;
+    const int jb = (act ? g : 0) * kRB;
+    cx<T> acc[kRB];
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) acc[r] = mk<T>(0, 0);
+    // logical table index of window slot 0 at input slot 0 (front pad kRB - 1)
+    const int a = pout - 1 - jb + kRB - 1;
+    for (int r0 = 0; r0 < nt; r0 += G) {
+      const int ti = r0 + sub;
+      int pin8 = 0;
+      if (ti < nt) {
+        const FmmTerm tm = terms[tk.t0 + ti];
+        pin8 = cdiv(tm.pin, 8);
+        const int tl = tm.pin + pout - 1;
+        for (int i = lt; i < pin_pad; i += tps) Ms[i] = i < tm.pin ? ld<T>(xin[tm.in + i]) : mk<T>(0, 0);
+        for (int pos = lt; pos < hl; pos += tps) {
+          const int x = (pos % l8) * 8 + pos / l8;
+          const int k = x - (kRB - 1);
+          Hp[pos] = (k >= 0 && k < tl) ? ld<T>(tabs[tm.tab + k]) : mk<T>(0, 0);
+        }
+      }
+      __syncthreads();
+      if (ti < nt && act) {
+        cx<T> w[kRB];
+#pragma unroll
+        for (int r = 0; r < kRB; ++r) {
+          const int x = a - r;
+          w[r] = Hp[(x & 7) * l8 + (x >> 3)];
+        }
+        int addr[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int x = a + u + 1;
+          addr[u] = (x & 7) * l8 + (x >> 3);
+        }
+        for (int t = 0; t < pin8; ++t) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const cx<T> m = Ms[8 * t + u];
+#pragma unroll
+            for (int r = 0; r < kRB; ++r) cmac(acc[r], w[r], m);
+#pragma unroll
+            for (int r = kRB - 1; r > 0; --r) w[r] = w[r - 1];
+            w[0] = Hp[addr[u] + t];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (G > 1) {
+      cx<T> *red = sm;
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) red[(sub * tps + lt) * kRB + r] = acc[r];
+      __syncthreads();
+      for (int o = threadIdx.x; o < tps * kRB; o += blockDim.x) {
+        cx<T> s = mk<T>(0, 0);
+        for (int q = 0; q < G; ++q) s = s + red[q * tps * kRB + o];
+        const int jo = g0 * kRB + o;
+        if (jo < pout) xout[tk.out + jo] = st(s);
+      }
+      __syncthreads();
+    } else if (act) {
+#pragma unroll
+      for (int r = 0; r < kRB; ++r)
+        if (jb + r < pout) xout[tk.out + jb + r] = st(acc[r]);
+    }
+  }
+}
+
+// Near-field pair entries in the layout of the all-pairs table:
+// [j][i][4] = H_0, H_1, e^{i phi}, (2/z, 0) of target perm[i] and source
+// src[j][i]; zeros for padding (j >= cnt[i]).
+__global__ void k_near_tables(const double2 *__restrict__ xy, const int *__restrict__ perm,
+                              const int *__restrict__ src, const int *__restrict__ cnt, int n, int K,
+                              double k2, double2 *__restrict__ t64, float2 *__restrict__ t32) {
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (e >= static_cast<int64_t>(K) * n) return;
+  const int j = static_cast<int>(e / n), i = static_cast<int>(e % n);
+  double2 v[4] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0),
+                  make_double2(0.0, 0.0)};
+  if (j < cnt[i]) {
+    const int l = perm[i], m = src[e];
+    const double dx = xy[l].x - xy[m].x, dy = xy[l].y - xy[m].y;
+    const double rho = sqrt(dx * dx + dy * dy);
+    const double z = k2 * rho;
+    v[0] = make_double2(j0(z), y0(z));
+    v[1] = make_double2(j1(z), y1(z));
+    v[2] = make_double2(dx / rho, dy / rho);
+    v[3] = make_double2(2.0 / z, 0.0);
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    t64[4 * e + c] = v[c];
+    t32[4 * e + c] = make_float2(static_cast<float>(v[c].x), static_cast<float>(v[c].y));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host: plan.
+
+bool fmm_wanted(const mpsl_ctx *ctx) {
+  if (ctx->far_method == MPSL_FAR_FMM) return true;
+  if (ctx->far_method == MPSL_FAR_DIRECT) return false;
+  return ctx->n > kAutoThreshold;
+}
+
+void fmm_free(mpsl_ctx *ctx) {
+  FmmPlan &f = ctx->fmm;
+  for (int i = 0; i < 2; ++i) {
+    dev_free(f.tab[i]);
+    dev_free(f.tasks[i]);
+    dev_free(f.terms[i]);
+  }
+  dev_free(f.perm);
+  dev_free(f.start);
+  dev_free(f.xb);
+  dev_free(f.near_src);
+  dev_free(f.near_cnt);
+  dev_free(f.near_wave);
+  dev_free(f.near64);
+  dev_free(f.near32);
+  f.active = false;
+}
+
+namespace {
+
+template <typename V>
+int upload(mpsl_ctx *ctx, DBuf &b, const std::vector<V> &v) {
+  int rc = dev_alloc(ctx, b, std::max<size_t>(1, v.size()) * sizeof(V));
+  if (rc) return rc;
+  if (!v.empty()) MPSL_HIP_TRY(ctx, hipMemcpy(b.p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice));
+  return MPSL_OK;
+}
+
+// Tables, tasks and terms of one precision.  Returns false when a table
+// entry is not representable (then the shape is rejected).
+bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<zc> &tab,
+                     std::vector<FmmTask> &tasks, std::vector<FmmTerm> &terms, std::string &why) {
+  FmmPlan &f = ctx->fmm;
+  const double k = ctx->k2.real();
+  const int p = ctx->p, P = 2 * p + 1;
+  const int64_t n = ctx->n;
+  std::vector<int> Pl(top + 1);
+  for (int l = 0; l <= top; ++l) Pl[l] = 2 * f.lv[l].p[pi] + 1;
+
+  // top-level term chunks so that the top launch has enough blocks
+  int64_t top_nonempty = 0;
+  for (auto o : g.occ[top]) top_nonempty += o;
+  const int nchunk = top > 0 ? static_cast<int>(std::max<int64_t>(1, cdiv(512, std::max<int64_t>(1, top_nonempty)))) : 1;
+
+  // expansion buffer: multipoles of every level, then locals (top: nchunk copies)
+  int64_t off = 0;
+  for (int l = 0; l <= top; ++l) {
+    f.lv[l].moff[pi] = off;
+    off += static_cast<int64_t>(g.nx[l]) * g.ny[l] * Pl[l];
+  }
+  for (int l = 0; l <= top; ++l) {
+    f.lv[l].loff[pi] = off;
+    off += static_cast<int64_t>(g.nx[l]) * g.ny[l] * Pl[l] * (l == top ? nchunk : 1);
+  }
+  f.xlen[pi] = off;
+
+  tab.clear();
+  // M2L rows: offset (dx, dy) = source - target in boxes, |dx| <= Dx, |dy| <= Dy
+  std::vector<int64_t> m2l_base(top + 1);
+  std::vector<int> Dx(top + 1), Dy(top + 1);
+  for (int l = 0; l <= top; ++l) {
+    Dx[l] = l == top ? g.nx[l] - 1 : std::min(3, g.nx[l] - 1);
+    Dy[l] = l == top ? g.ny[l] - 1 : std::min(3, g.ny[l] - 1);
+    m2l_base[l] = static_cast<int64_t>(tab.size());
+    const int L = 2 * Pl[l] - 1;
+    const int p_l = f.lv[l].p[pi];
+    const double s = f.lv[l].s;
+    tab.resize(tab.size() + static_cast<size_t>(2 * Dy[l] + 1) * (2 * Dx[l] + 1) * L, zc(0.0, 0.0));
+    for (int dy = -Dy[l]; dy <= Dy[l]; ++dy)
+      for (int dx = -Dx[l]; dx <= Dx[l]; ++dx) {
+        if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+        zc *row = tab.data() + m2l_base[l] + ((dy + Dy[l]) * (2 * Dx[l] + 1) + (dx + Dx[l])) * static_cast<int64_t>(L);
+        m2l_row(k, -dx * s, -dy * s, p_l, row);
+      }
+  }
+  // M2M (child -> parent) and L2L (parent -> child), child position c = 2 b + a
+  std::vector<int64_t> up_base(top), dn_base(top);
+  for (int l = 0; l < top; ++l) {
+    const int pa = f.lv[l].p[pi], pb = f.lv[l + 1].p[pi];
+    const int L = 2 * pa + 2 * pb + 1;
+    const double s = f.lv[l].s;
+    up_base[l] = static_cast<int64_t>(tab.size());
+    tab.resize(tab.size() + 4 * static_cast<size_t>(L));
+    for (int c = 0; c < 4; ++c)
+      jshift_row(k, ((c & 1) - 0.5) * s, ((c >> 1) - 0.5) * s, pa, pb, -1, tab.data() + up_base[l] + c * L);
+    dn_base[l] = static_cast<int64_t>(tab.size());
+    tab.resize(tab.size() + 4 * static_cast<size_t>(L));
+    for (int c = 0; c < 4; ++c)
+      jshift_row(k, ((c & 1) - 0.5) * s, ((c >> 1) - 0.5) * s, pb, pa, +1, tab.data() + dn_base[l] + c * L);
+  }
+  // per sorted particle: P2M and L2P rows
+  const int p0 = f.lv[0].p[pi];
+  const int Lp = P + Pl[0] - 1;
+  f.p2m_off[pi] = static_cast<int64_t>(tab.size());
+  tab.resize(tab.size() + static_cast<size_t>(n) * Lp);
+  f.l2p_off[pi] = static_cast<int64_t>(tab.size());
+  tab.resize(tab.size() + static_cast<size_t>(n) * Lp);
+  const int nx0 = g.nx[0];
+  for (int64_t i = 0; i < n; ++i) {
+    const int m = f.perm_h[i];
+    const int b = g.leaf[m];
+    const double cx0 = f.x0 + ((b % nx0) + 0.5) * f.lv[0].s, cy0 = f.y0 + ((b / nx0) + 0.5) * f.lv[0].s;
+    const double dx = ctx->xy[2 * m] - cx0, dy = ctx->xy[2 * m + 1] - cy0;
+    jshift_row(k, dx, dy, p, p0, -1, tab.data() + f.p2m_off[pi] + i * Lp);
+    jshift_row(k, dx, dy, p0, p, +1, tab.data() + f.l2p_off[pi] + i * Lp);
+  }
+  const double lim = pi == 0 ? 1e300 : 1e37;
+  for (const zc &v : tab)
+    if (!(std::fabs(v.real()) < lim && std::fabs(v.imag()) < lim)) {
+      why = "translation table entry out of range";
+      return false;
+    }
+
+  // tasks and terms
+  tasks.clear();
+  terms.clear();
+  f.up[pi].clear();
+  f.down[pi].clear();
+  auto begin_stage = [&](int pout) {
+    FmmStage st;
+    st.pout = pout;
+    st.task_off = static_cast<int64_t>(tasks.size());
+    st.term_off = static_cast<int64_t>(terms.size());
+    return st;
+  };
+  auto add_task = [&](FmmStage &st, int64_t out, const std::vector<FmmTerm> &ts) {
+    FmmTask t;
+    t.out = out;
+    t.t0 = static_cast<int>(terms.size() - st.term_off);
+    for (const auto &x : ts) {
+      terms.push_back(x);
+      st.pin_max = std::max(st.pin_max, x.pin);
+    }
+    t.t1 = static_cast<int>(terms.size() - st.term_off);
+    st.max_terms = std::max(st.max_terms, t.t1 - t.t0);
+    tasks.push_back(t);
+    ++st.tasks;
+  };
+  for (int l = 0; l < top; ++l) {
+    FmmStage st = begin_stage(Pl[l + 1]);
+    const int nxa = g.nx[l], nya = g.ny[l], nxb = g.nx[l + 1], nyb = g.ny[l + 1];
+    for (int by = 0; by < nyb; ++by)
+      for (int bx = 0; bx < nxb; ++bx) {
+        if (!g.occ[l + 1][by * nxb + bx]) continue;
+        std::vector<FmmTerm> ts;
+        for (int c = 0; c < 4; ++c) {
+          const int cx = 2 * bx + (c & 1), cy = 2 * by + (c >> 1);
+          if (cx >= nxa || cy >= nya || !g.occ[l][cy * nxa + cx]) continue;
+          FmmTerm t{};
+          t.in = f.lv[l].moff[pi] + static_cast<int64_t>(cy * nxa + cx) * Pl[l];
+          t.tab = up_base[l] + c * static_cast<int64_t>(Pl[l] + Pl[l + 1] - 1);
+          t.pin = Pl[l];
+          ts.push_back(t);
+        }
+        add_task(st, f.lv[l + 1].moff[pi] + static_cast<int64_t>(by * nxb + bx) * Pl[l + 1], ts);
+      }
+    f.up[pi].push_back(st);
+  }
+  for (int l = top; l >= 0; --l) {
+    FmmStage st = begin_stage(Pl[l]);
+    const int nx = g.nx[l], ny = g.ny[l];
+    const int64_t nbl = static_cast<int64_t>(nx) * ny;
+    const int L = 2 * Pl[l] - 1;
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix) {
+        if (!g.occ[l][iy * nx + ix]) continue;
+        std::vector<FmmTerm> ts;
+        if (l < top) {
+          const int nxp = g.nx[l + 1];
+          const int par = (iy / 2) * nxp + ix / 2;
+          const int c = (ix & 1) + 2 * (iy & 1);
+          const int nch = l + 1 == top ? nchunk : 1;
+          const int64_t nbp = static_cast<int64_t>(g.nx[l + 1]) * g.ny[l + 1];
+          for (int ch = 0; ch < nch; ++ch) {
+            FmmTerm t{};
+            t.in = f.lv[l + 1].loff[pi] + (ch * nbp + par) * Pl[l + 1];
+            t.tab = dn_base[l] + c * static_cast<int64_t>(Pl[l] + Pl[l + 1] - 1);
+            t.pin = Pl[l + 1];
+            ts.push_back(t);
+          }
+        }
+        for_interactions(g, l, l == top, ix, iy, [&](int jx, int jy) {
+          FmmTerm t{};
+          t.in = f.lv[l].moff[pi] + static_cast<int64_t>(jy * nx + jx) * Pl[l];
+          const int dx = jx - ix, dy = jy - iy;
+          t.tab = m2l_base[l] + ((dy + Dy[l]) * (2 * Dx[l] + 1) + (dx + Dx[l])) * static_cast<int64_t>(L);
+          t.pin = Pl[l];
+          ts.push_back(t);
+        });
+        const int64_t box = static_cast<int64_t>(iy) * nx + ix;
+        if (l == top && nchunk > 1) {
+          const size_t per = (ts.size() + nchunk - 1) / nchunk;
+          for (int ch = 0; ch < nchunk; ++ch) {
+            const size_t a = std::min(ts.size(), ch * per), b = std::min(ts.size(), (ch + 1) * per);
+            std::vector<FmmTerm> part(ts.begin() + a, ts.begin() + b);
+            add_task(st, f.lv[l].loff[pi] + (ch * nbl + box) * Pl[l], part);
+          }
+        } else {
+          add_task(st, f.lv[l].loff[pi] + box * Pl[l], ts);
+        }
+      }
+    if (st.pin_max == 0) st.pin_max = Pl[l];
+    f.down[pi].push_back(st);
+  }
+  // every access of the translation kernel stays inside its buffers
+  const int64_t tsz = static_cast<int64_t>(tab.size());
+  for (int s = 0; s < 2; ++s) {
+    const auto &stages = s == 0 ? f.up[pi] : f.down[pi];
+    for (const auto &st : stages)
+      for (int64_t t = 0; t < st.tasks; ++t) {
+        const FmmTask &tk = tasks[st.task_off + t];
+        if (tk.out < 0 || tk.out + st.pout > f.xlen[pi] || tk.t0 > tk.t1 ||
+            st.term_off + tk.t1 > static_cast<int64_t>(terms.size())) {
+          why = "task outside its buffers";
+          return false;
+        }
+        for (int u = tk.t0; u < tk.t1; ++u) {
+          const FmmTerm &tm = terms[st.term_off + u];
+          if (tm.pin < 1 || tm.pin > st.pin_max || tm.in < 0 || tm.in + tm.pin > f.xlen[pi] || tm.tab < 0 ||
+              tm.tab + tm.pin + st.pout - 1 > tsz) {
+            why = "term outside its buffers";
+            return false;
+          }
+        }
+      }
+  }
+  if (f.p2m_off[pi] + static_cast<int64_t>(n) * Lp > tsz || f.l2p_off[pi] + static_cast<int64_t>(n) * Lp > tsz) {
+    why = "particle rows outside the table";
+    return false;
+  }
+  // translation work of one apply (complex MACs)
+  double cm = 2.0 * static_cast<double>(n) * P * Pl[0];
+  for (int s = 0; s < 2; ++s) {
+    const auto &stages = s == 0 ? f.up[pi] : f.down[pi];
+    for (const auto &st : stages)
+      for (int64_t t = 0; t < st.tasks; ++t) {
+        const FmmTask &tk = tasks[st.task_off + t];
+        for (int u = tk.t0; u < tk.t1; ++u) cm += static_cast<double>(terms[st.term_off + u].pin) * st.pout;
+      }
+  }
+  f.tree_cmac[pi] = cm;
+  return true;
+}
+
+}  // namespace
+
+int fmm_build(mpsl_ctx *ctx) {
+  FmmPlan &f = ctx->fmm;
+  f.active = false;
+  const int64_t n = ctx->n;
+  const int p = ctx->p, P = 2 * p + 1;
+  const double k = ctx->k2.real();
+  const double eps[2] = {ctx->far_tol, std::max(ctx->far_tol, 1e-7)};
+  if (n > (int64_t(1) << 30) / 64) return set_err(ctx, MPSL_EUNSUPPORTED, "too many particles for the FMM");
+
+  // candidate shapes: leaf side (k s0 from 8 to 96) x top level
+  std::vector<Shape> cands;
+  for (double ks0 : {8.0, 12.0, 16.0, 24.0, 32.0, 48.0, 64.0, 96.0}) {
+    const double s0 = ks0 / k;
+    const Grid g = make_grid(ctx->xy, n, s0);
+    const double nc = near_cost(g, n, P);
+    const int nlev = static_cast<int>(g.nx.size());
+    std::vector<int> Pl(nlev);
+    for (int l = 0; l < nlev; ++l) Pl[l] = 2 * box_order(k * s0 * std::ldexp(1.0, l), eps[0], p) + 1;
+    for (int top = 0; top < nlev; ++top) {
+      if (Pl[top] > 2 * kMaxBoxOrder + 1) break;
+      int64_t nb = static_cast<int64_t>(g.nx[top]) * g.ny[top];
+      if (nb > 1024) continue;
+      const double offs = static_cast<double>(2 * g.nx[top] - 1) * (2 * g.ny[top] - 1);
+      if (offs * (2 * Pl[top] - 1) > 2e7) continue;
+      Shape sh;
+      sh.s0 = s0;
+      sh.top = top;
+      sh.cost = nc + 1.5 * tree_cost(g, Pl, top, n, P);
+      cands.push_back(sh);
+    }
+  }
+  std::sort(cands.begin(), cands.end(), [](const Shape &a, const Shape &b) { return a.cost < b.cost; });
+  if (cands.empty()) return set_err(ctx, MPSL_EUNSUPPORTED, "no FMM tree shape fits the problem");
+
+  std::string why;
+  for (const Shape &sh : cands) {
+    const Grid g = make_grid(ctx->xy, n, sh.s0);
+    const int top = sh.top;
+    f.top = top;
+    f.x0 = g.x0;
+    f.y0 = g.y0;
+    f.lv.assign(top + 1, FmmLevel());
+    bool ok = true;
+    for (int l = 0; l <= top; ++l) {
+      FmmLevel &L = f.lv[l];
+      L.nx = g.nx[l];
+      L.ny = g.ny[l];
+      L.s = sh.s0 * std::ldexp(1.0, l);
+      L.occ = g.occ[l];
+      for (int pi = 0; pi < 2; ++pi) L.p[pi] = box_order(k * L.s, eps[pi], p);
+      if (L.p[0] > kMaxBoxOrder) ok = false;
+    }
+    if (!ok) continue;
+    // sort particles by leaf box (counting sort, stable)
+    const int nb0 = g.nx[0] * g.ny[0];
+    f.start_h.assign(nb0 + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ++f.start_h[g.leaf[i] + 1];
+    for (int b = 0; b < nb0; ++b) f.start_h[b + 1] += f.start_h[b];
+    f.perm_h.assign(n, 0);
+    {
+      std::vector<int32_t> fill(f.start_h.begin(), f.start_h.end() - 1);
+      for (int64_t i = 0; i < n; ++i) f.perm_h[fill[g.leaf[i]]++] = static_cast<int32_t>(i);
+    }
+    std::vector<zc> tab[2];
+    std::vector<FmmTask> tasks[2];
+    std::vector<FmmTerm> terms[2];
+    for (int pi = 0; pi < 2 && ok; ++pi) ok = build_precision(ctx, g, top, pi, tab[pi], tasks[pi], terms[pi], why);
+    if (!ok) continue;
+
+    // near field: padded neighbour lists over the 3 x 3 leaf boxes
+    const int nx0 = g.nx[0], ny0 = g.ny[0];
+    std::vector<int32_t> cnt(n, 0);
+    int K = 0;
+    int64_t pairs = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const int b = g.leaf[f.perm_h[i]];
+      const int ix = b % nx0, iy = b / nx0;
+      int c = 0;
+      for (int jy = std::max(0, iy - 1); jy <= std::min(ny0 - 1, iy + 1); ++jy)
+        c += f.start_h[jy * nx0 + std::min(nx0 - 1, ix + 1) + 1] - f.start_h[jy * nx0 + std::max(0, ix - 1)];
+      cnt[i] = c - 1;
+      K = std::max(K, c - 1);
+      pairs += c - 1;
+    }
+    K = std::max(K, 1);
+    std::vector<int32_t> src(static_cast<size_t>(K) * n);
+    for (int64_t i = 0; i < n; ++i) {
+      const int self = f.perm_h[i];
+      const int b = g.leaf[self];
+      const int ix = b % nx0, iy = b / nx0;
+      int j = 0;
+      for (int jy = std::max(0, iy - 1); jy <= std::min(ny0 - 1, iy + 1); ++jy) {
+        const int a0 = f.start_h[jy * nx0 + std::max(0, ix - 1)];
+        const int a1 = f.start_h[jy * nx0 + std::min(nx0 - 1, ix + 1) + 1];
+        for (int a = a0; a < a1; ++a)
+          if (f.perm_h[a] != self) src[static_cast<size_t>(j++) * n + i] = f.perm_h[a];
+      }
+      for (; j < K; ++j) src[static_cast<size_t>(j) * n + i] = self;
+    }
+    const int64_t waves = 2 * static_cast<int64_t>(cdiv(n, 128));  // whole blocks of the near kernel
+    std::vector<int32_t> wave(waves, 0);
+    for (int64_t i = 0; i < n; ++i) wave[i / 64] = std::max(wave[i / 64], cnt[i]);
+    f.near_k = K;
+    f.near_pairs = pairs;
+
+    int rc;
+    if ((rc = upload(ctx, f.perm, f.perm_h)) || (rc = upload(ctx, f.start, f.start_h)) ||
+        (rc = upload(ctx, f.near_src, src)) || (rc = upload(ctx, f.near_cnt, cnt)) ||
+        (rc = upload(ctx, f.near_wave, wave)))
+      return rc;
+    for (int pi = 0; pi < 2; ++pi) {
+      if ((rc = upload(ctx, f.tasks[pi], tasks[pi])) || (rc = upload(ctx, f.terms[pi], terms[pi]))) return rc;
+      if (pi == 0) {
+        std::vector<double2> t(tab[0].size());
+        for (size_t i = 0; i < t.size(); ++i) t[i] = make_double2(tab[0][i].real(), tab[0][i].imag());
+        if ((rc = upload(ctx, f.tab[0], t))) return rc;
+      } else {
+        std::vector<float2> t(tab[1].size());
+        for (size_t i = 0; i < t.size(); ++i)
+          t[i] = make_float2(static_cast<float>(tab[1][i].real()), static_cast<float>(tab[1][i].imag()));
+        if ((rc = upload(ctx, f.tab[1], t))) return rc;
+      }
+    }
+    const size_t xb = std::max(static_cast<size_t>(f.xlen[0]) * sizeof(double2),
+                               static_cast<size_t>(f.xlen[1]) * sizeof(float2));
+    if ((rc = dev_alloc(ctx, f.xb, xb))) return rc;
+    const size_t ne = static_cast<size_t>(K) * n * 4;
+    if ((rc = dev_alloc(ctx, f.near64, ne * sizeof(double2))) || (rc = dev_alloc(ctx, f.near32, ne * sizeof(float2))))
+      return rc;
+    const int64_t tot = static_cast<int64_t>(K) * n;
+    hipLaunchKernelGGL(k_near_tables, dim3(cdiv(tot, 256)), dim3(256), 0, ctx->stream,
+                       static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const int *>(f.perm.p),
+                       static_cast<const int *>(f.near_src.p), static_cast<const int *>(f.near_cnt.p),
+                       static_cast<int>(n), K, k, static_cast<double2 *>(f.near64.p),
+                       static_cast<float2 *>(f.near32.p));
+    MPSL_HIP_TRY(ctx, hipGetLastError());
+    f.active = true;
+    return MPSL_OK;
+  }
+  return set_err(ctx, MPSL_EUNSUPPORTED, "no FMM tree shape fits the problem: " + why);
+}
+
+// ---------------------------------------------------------------------------
+// Host: apply.
+
+namespace {
+
+template <typename T>
+int launch_stage(mpsl_ctx *ctx, int pi, const FmmStage &st) {
+  if (st.tasks == 0) return MPSL_OK;
+  FmmPlan &f = ctx->fmm;
+  const size_t esz = sizeof(cv_t<T>);
+  const int ngroups = cdiv(st.pout, kRB);
+  int tps;
+  if (ngroups <= 64) {
+    tps = 1;
+    while (tps < ngroups) tps <<= 1;
+  } else {
+    tps = std::min(kToepMaxThreads, cdiv(ngroups, 64) * 64);
+  }
+  const int pin_pad = cdiv(st.pin_max, 8) * 8;
+  const int l8 = cdiv(pin_pad + st.pout + 8, 8);
+  const size_t per = static_cast<size_t>(pin_pad) + 8 * static_cast<size_t>(l8);
+  int G = std::max(1, std::min(kToepMaxThreads / tps, std::max(1, st.max_terms)));
+  while (G > 1 && G * per * esz > kLdsBudget) --G;
+  const size_t lds = std::max(G * per, static_cast<size_t>(G) * tps * kRB) * esz;
+  if (lds > kLdsBudget) return set_err(ctx, MPSL_EUNSUPPORTED, "FMM translation exceeds the LDS budget");
+  hipLaunchKernelGGL(k_fmm_toep<T>, dim3(st.tasks), dim3(G * tps), lds, ctx->stream,
+                     static_cast<const FmmTask *>(f.tasks[pi].p) + st.task_off,
+                     static_cast<const FmmTerm *>(f.terms[pi].p) + st.term_off,
+                     static_cast<const cv_t<T> *>(f.xb.p), static_cast<const cv_t<T> *>(f.tab[pi].p),
+                     static_cast<cv_t<T> *>(f.xb.p), st.pout, tps, pin_pad, l8);
+  MPSL_HIP_TRY(ctx, hipGetLastError());
+  return MPSL_OK;
+}
+
+template <typename T>
+int fmm_apply_t(mpsl_ctx *ctx, int pi, const void *beta, void *part) {
+  FmmPlan &f = ctx->fmm;
+  const int P = 2 * ctx->p + 1;
+  const int P0 = 2 * f.lv[0].p[pi] + 1;
+  const int nb0 = f.lv[0].nx * f.lv[0].ny;
+  const cv_t<T> *b = static_cast<const cv_t<T> *>(beta);
+  cv_t<T> *xb = static_cast<cv_t<T> *>(f.xb.p);
+  const cv_t<T> *tab = static_cast<const cv_t<T> *>(f.tab[pi].p);
+  const int bs = std::min(256, cdiv(P0, 64) * 64);
+  hipLaunchKernelGGL(k_fmm_p2m<T>, dim3(nb0), dim3(bs), 0, ctx->stream, b, static_cast<const int *>(f.perm.p),
+                     static_cast<const int *>(f.start.p), tab + f.p2m_off[pi], P, P0, xb + f.lv[0].moff[pi]);
+  MPSL_HIP_TRY(ctx, hipGetLastError());
+  int rc;
+  for (const auto &st : f.up[pi])
+    if ((rc = launch_stage<T>(ctx, pi, st))) return rc;
+  for (const auto &st : f.down[pi])
+    if ((rc = launch_stage<T>(ctx, pi, st))) return rc;
+  const int64_t len = ctx->n * static_cast<int64_t>(P);
+  cv_t<T> *far = static_cast<cv_t<T> *>(part) + len;
+  hipLaunchKernelGGL(k_fmm_l2p<T>, dim3(nb0), dim3(256), P0 * sizeof(cx<T>), ctx->stream,
+                     static_cast<const cv_t<T> *>(xb + f.lv[0].loff[pi]), static_cast<const int *>(f.perm.p),
+                     static_cast<const int *>(f.start.p), tab + f.l2p_off[pi], P, P0, far);
+  MPSL_HIP_TRY(ctx, hipGetLastError());
+  return launch_fmm_near(ctx, pi == 0 ? MPSL_FP64 : MPSL_FP32, beta, part);
+}
+
+}  // namespace
+
+int fmm_apply(mpsl_ctx *ctx, int prec, const void *beta, void *part) {
+  if (!ctx->fmm.active) return set_err(ctx, MPSL_ESTATE, "FMM not built");
+  return prec == MPSL_FP64 ? fmm_apply_t<double>(ctx, 0, beta, part) : fmm_apply_t<float>(ctx, 1, beta, part);
+}
+
+}  // namespace mpsl
+
+// ===========================================================================
+extern "C" {
+
+int mpsl_set_far_field(mpsl_ctx *ctx, int method, double tol) {
+  if (!ctx) return MPSL_EINVAL;
+  if (method != MPSL_FAR_AUTO && method != MPSL_FAR_DIRECT && method != MPSL_FAR_FMM)
+    return mpsl::set_err(ctx, MPSL_EINVAL, "unknown far-field method");
+  if (tol != 0.0 && !(tol >= 1e-13 && tol <= 1e-3))
+    return mpsl::set_err(ctx, MPSL_EINVAL, "FMM tolerance must lie in [1e-13, 1e-3]");
+  ctx->far_method = method;
+  if (tol != 0.0) ctx->far_tol = tol;
+  ctx->tables_ok = false;
+  return MPSL_OK;
+}
+
+int mpsl_get_fmm_info(const mpsl_ctx *ctx, int prec, int *active, int *levels, double *leaf_side, int *p_leaf,
+                      int *p_top, int64_t *near_pairs, double *tree_cmac) {
+  if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  if (!ctx->tables_ok) return MPSL_ESTATE;
+  const mpsl::FmmPlan &f = ctx->fmm;
+  const int pi = prec == MPSL_FP64 ? 0 : 1;
+  if (active) *active = f.active ? 1 : 0;
+  if (levels) *levels = f.active ? f.top + 1 : 0;
+  if (leaf_side) *leaf_side = f.active ? f.lv[0].s : 0.0;
+  if (p_leaf) *p_leaf = f.active ? f.lv[0].p[pi] : 0;
+  if (p_top) *p_top = f.active ? f.lv[f.top].p[pi] : 0;
+  if (near_pairs) *near_pairs = f.active ? f.near_pairs : 0;
+  if (tree_cmac) *tree_cmac = f.active ? f.tree_cmac[pi] : 0.0;
+  return MPSL_OK;
+}
+
+}  // extern "C"

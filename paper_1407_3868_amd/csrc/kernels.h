@@ -22,6 +22,8 @@ constexpr int kM2LHalves = 1;
 // nrhs right-hand sides: beta [nrhs][n][P]; part of rhs r at part + r * pstride.
 int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant = -1,
                int nrhs = 1, int64_t pstride = 0);
+// FMM near field (pairs in the same or adjacent leaf boxes) into out [n][P].
+int launch_fmm_near(mpsl_ctx *ctx, int prec, const void *beta, void *out);
 // Row b1: M2S partial spectra and their reduction to spec (double2[2*ns]).
 // spec: double2[nrhs][2][ns].
 int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec, int nrhs = 1);

@@ -216,6 +216,50 @@ __global__ __launch_bounds__(kThreads) void k_m2l(const cv_t<T> *__restrict__ pa
   else m2l_body<T, p, 0, P - 1, SPLIT, false>(pairs, beta, o, n, m0, m1, l);
 }
 
+// FMM near field: the same pair translation restricted to padded neighbour
+// lists.  One lane per target in leaf-box order; each lane walks its own
+// list of sources (pair entries [j][i][4] as in the all-pairs table, source
+// coefficients loaded per lane), and every wave loops to the longest list
+// among its 64 targets (padding entries are zeros).
+template <typename T, int p>
+__global__ __launch_bounds__(kThreads) void k_fmm_near(const cv_t<T> *__restrict__ pairs,
+                                                       const int *__restrict__ src, const int *__restrict__ perm,
+                                                       const int *__restrict__ wave_cnt,
+                                                       const cv_t<T> *__restrict__ beta, cv_t<T> *__restrict__ out,
+                                                       int n) {
+  constexpr int P = 2 * p + 1;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int kw = __builtin_amdgcn_readfirstlane(wave_cnt[i >> 6]);
+  const bool valid = i < n;
+  const int ic = valid ? i : n - 1;
+  cx<T> acc[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) acc[k] = mk<T>(0, 0);
+  constexpr int SPLIT = std::is_same<T, double>::value ? 1 : 0;
+  for (int j = 0; j < kw; ++j) {
+    const int64_t e = static_cast<int64_t>(j) * n + ic;
+    const cv_t<T> *pe = pairs + 4 * e;
+    cx<T> h0 = ld<T>(pe[0]), h1 = ld<T>(pe[1]);
+    const cx<T> t = ld<T>(pe[2]);
+    const T two_over_z = pe[3].x;
+    if (!valid) h0 = h1 = mk<T>(0, 0);
+    const cv_t<T> *bm = beta + static_cast<int64_t>(src[e]) * P;
+    if (SPLIT) {
+      m2l_block<T, p, 0, P - 1, 0, p, false>(acc, bm, h0, h1, t, two_over_z);
+      __builtin_amdgcn_sched_barrier(0);
+      m2l_block<T, p, 0, P - 1, p + 1, P - 1, false>(acc, bm, h0, h1, t, two_over_z);
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+      m2l_block<T, p, 0, P - 1, 0, P - 1, false>(acc, bm, h0, h1, t, two_over_z);
+    }
+  }
+  if (valid) {
+    const int64_t o = static_cast<int64_t>(perm[i]) * P;
+#pragma unroll
+    for (int k = 0; k < P; ++k) out[o + k] = st(acc[k]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Row b1: M2S.  One lane per contour node q and side s; each block walks a
 // chunk of particles: acc_nu = sum_m E_s[m][q] beta^m_nu (beta wave-uniform),
@@ -679,6 +723,33 @@ int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks
   if (variant < 0) variant = ctx->tune[prec == MPSL_FP64 ? 0 : 1].variant;
   return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks, variant, nrhs, pstride)
                            : launch_m2l_t<float>(ctx, beta, part, chunks, variant, nrhs, pstride);
+}
+
+template <typename T>
+static int launch_fmm_near_t(mpsl_ctx *ctx, const void *beta, void *out) {
+  const FmmPlan &f = ctx->fmm;
+  const int n = static_cast<int>(ctx->n);
+  const bool f64 = std::is_same<T, double>::value;
+  const auto *pairs = static_cast<const cv_t<T> *>(f64 ? f.near64.p : f.near32.p);
+  const auto *src = static_cast<const int *>(f.near_src.p);
+  const auto *perm = static_cast<const int *>(f.perm.p);
+  const auto *wave = static_cast<const int *>(f.near_wave.p);
+  const auto *b = static_cast<const cv_t<T> *>(beta);
+  auto *o = static_cast<cv_t<T> *>(out);
+  const dim3 grid(cdiv(n, kThreads));
+  switch (ctx->p) {
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_fmm_near<T, PP>), grid, dim3(kThreads), 0, ctx->stream, pairs, src, perm, wave, b, o, n); break;
+    MPSL_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_fmm_near(mpsl_ctx *ctx, int prec, const void *beta, void *out) {
+  return prec == MPSL_FP64 ? launch_fmm_near_t<double>(ctx, beta, out) : launch_fmm_near_t<float>(ctx, beta, out);
 }
 
 template <typename T>

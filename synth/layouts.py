@@ -194,6 +194,11 @@ CONFIGS = {
     "s150p12": dict(n=150, shape="star", shape_params=(0.25, 0.05, 5), r_enclose=0.3,
                     p=12, x_range=(-31.0, 31.0), y_range=(-9.0, -1.0), d=10.0,
                     seed=12, n_nodes=256, b=0.03, tol=1e-10),
+    # Largest serving size: 20000 stars, p = 16, strip of height d - 2 = 38
+    # and width N / (0.3 (d - 2)) = 1754 (the FMM regime).
+    "c5max": dict(n=20000, shape="star", shape_params=(0.25, 0.05, 5), r_enclose=0.3,
+                  p=16, x_range=(-877.0, 877.0), y_range=(-39.0, -1.0), d=40.0,
+                  seed=21, n_nodes=1024, b=0.001, tol=1e-6),
     "s70p8": dict(n=70, shape="disk", shape_params=(0.25,), r_enclose=0.25,
                   p=8, x_range=(-30.0, 30.0), y_range=(-5.0, -1.0), d=6.0,
                   seed=13, n_nodes=256, b=0.03, tol=1e-10),

@@ -1,0 +1,140 @@
+"""Row a5: the FMM far field against the oracle's direct all-pairs M2L on the
+same inputs: 1e-10 in FP64 (the FMM's requested accuracy); in FP32 the bound
+of the direct FP32 path (2e-5, rounding over sums of thousands of terms),
+and a mixed-precision solve through the FMM reaches 1e-6 in the field.
+
+The error is measured as the matvec sees it: the local expansions pass
+through the particles' rotated scattering matrices before they enter
+y = x - S (T + T_R) x, so the check is on S (alpha_fmm - alpha_ref)
+relative to S alpha_ref, with beta in the range of S (coeff_vector)."""
+import numpy as np
+import pytest
+
+from gpu_common import coeff_vector, gpu_context, make_workload, oracle_problem, prototype_S, rel_err
+from oracle.operators import m2l_apply, rotated_smatrix
+from synth import receivers
+
+pytestmark = pytest.mark.gpu
+
+FP_TOL = {0: 1e-10, 1: 2e-5}
+
+
+def _weighted_err(wl, got, ref, rows):
+    S = prototype_S(wl)
+    num = den = 0.0
+    for g, r, l in zip(got, ref, rows):
+        Sl = rotated_smatrix(S, wl.rot[l])
+        num += np.linalg.norm(Sl @ (g - r)) ** 2
+        den += np.linalg.norm(Sl @ r) ** 2
+    return float(np.sqrt(num / den))
+
+
+def _run(ctx, fn, prec, x):
+    import torch
+    npdt = np.complex128 if prec == 0 else np.complex64
+    xd = torch.from_numpy(x.astype(npdt)).cuda()
+    yd = torch.zeros_like(xd)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    getattr(ctx, fn)(prec, xd, yd)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy().astype(np.complex128)
+
+
+def _fmm_ctx(wl):
+    import paper_1407_3868_amd as mp
+    ctx = gpu_context(wl)
+    ctx.set_far_field(mp.FAR_FMM)
+    return ctx
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("name,rows", [("s200p16", None), ("c2", [0, 1, 17, 333, 500, 998, 999])])
+def test_fmm_m2l_matches_direct(name, rows, prec):
+    wl = make_workload(name)
+    ctx = _fmm_ctx(wl)
+    x = coeff_vector(wl, 3)
+    got = _run(ctx, "m2l_dev", prec, x)
+    info = ctx.fmm_info(prec)
+    print(name, prec, info, flush=True)
+    assert info["active"] and info["tree_cmac"] > 0
+    assert info["near_pairs"] < wl.n * (wl.n - 1)   # some pairs go through the tree
+    rows = list(range(wl.n)) if rows is None else rows
+    ref = m2l_apply(wl.xy, wl.k2, wl.p, x, targets=rows)
+    err = _weighted_err(wl, got[rows], ref, rows)
+    print("weighted err", err, "raw err", rel_err(got[rows], ref), flush=True)
+    assert err < FP_TOL[prec], err
+    assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fmm_matvec_matches_oracle(prec):
+    wl = make_workload("s200p16")
+    pr = oracle_problem(wl)
+    ctx = _fmm_ctx(wl)
+    x = coeff_vector(wl, 5)
+    got = _run(ctx, "apply_dev", prec, x)
+    ref = pr.matvec(x)
+    err = rel_err(got, ref)
+    print("matvec err", err, flush=True)
+    assert err < FP_TOL[prec] * 10, err
+
+
+def test_fmm_equals_direct_path_within_tol():
+    """The same context switched between the direct and the FMM far field."""
+    import paper_1407_3868_amd as mp
+    wl = make_workload("c2")
+    ctx = gpu_context(wl)
+    x = coeff_vector(wl, 9)
+    direct = _run(ctx, "apply_dev", 0, x)
+    ctx.set_far_field(mp.FAR_FMM)
+    fmm = _run(ctx, "apply_dev", 0, x)
+    assert ctx.fmm_info(0)["active"]
+    ctx.set_far_field(mp.FAR_DIRECT)
+    again = _run(ctx, "apply_dev", 0, x)
+    assert not ctx.fmm_info(0)["active"]
+    assert np.array_equal(direct, again)
+    assert rel_err(fmm, direct) < 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6)])
+def test_fmm_solve_matches_lu(prec, tol):
+    import paper_1407_3868_amd as mp
+    wl = make_workload("s70p8")
+    pr = oracle_problem(wl)
+    ctx = gpu_context(wl)
+    ctx.set_far_field(mp.FAR_FMM)
+    src = wl.src[0]
+    ref = pr.solve_lu(src)
+    beta, meta = ctx.solve(src, precision=prec, tol=1e-12 if prec == 0 else 1e-10, maxiter=1200)
+    assert ctx.fmm_info(prec)["active"]
+    assert meta["status"] == 0, meta
+    xs = wl.xy[:, 0]
+    rcv = receivers(64, (xs.min() - 1, xs.max() + 1), (-wl.d - 1.5, 2.5), wl.xy, 1064,
+                    particle_excl=wl.r_enclose + 0.05, source=src, source_excl=0.05)
+    u_ref = pr.field(src, ref, rcv)
+    u = ctx.eval_field(src, beta, rcv)
+    assert rel_err(beta, ref) < tol * 100
+    assert rel_err(u, u_ref) < tol, rel_err(u, u_ref)
+
+
+@pytest.fixture(scope="module")
+def big():
+    wl = make_workload("c5max")
+    return wl, gpu_context(wl)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fmm_auto_at_20000_sampled(big, prec):
+    """N = 20000 takes the FMM by default; sampled targets against the oracle."""
+    wl, ctx = big
+    x = coeff_vector(wl, 7)
+    got = _run(ctx, "m2l_dev", prec, x)
+    info = ctx.fmm_info(prec)
+    print(info, flush=True)
+    assert info["active"]
+    rows = [0, 4999, 10000, 19999]
+    ref = m2l_apply(wl.xy, wl.k2, wl.p, x, targets=rows)
+    err = _weighted_err(wl, got[rows], ref, rows)
+    print("weighted err", err, flush=True)
+    assert err < FP_TOL[prec], err
+    assert np.all(np.isfinite(got))
