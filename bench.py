@@ -227,6 +227,61 @@ def _serve_workload(args, torch, mp):
     return out
 
 
+def _fmm_workload(args, torch, mp):
+    """20000 stars, p = 16: the FMM far field (the default above 8000
+    particles) against the direct all-pairs M2L on the same context."""
+    import numpy as np
+
+    from synth import make_workload
+
+    wl = make_workload("c5max")
+    a1, a2, a3 = wl.shape_params
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = mp.Context(0)
+    ctx.set_stream(stream)
+    ctx.set_layers(wl.k1, wl.k2, wl.k3, wl.d)
+    ctx.set_particle_star(a1, a2, a3, wl.kp, wl.p, 256)
+    ctx.set_geometry(wl.xy, wl.rot)
+    ctx.set_contour(wl.n_nodes, wl.b, wl.t_max)
+    S = ctx.get_scattering_matrix()
+    rng = np.random.default_rng(1)
+    r = rng.standard_normal((wl.n, wl.P)) + 1j * rng.standard_normal((wl.n, wl.P))
+    n = np.arange(-wl.p, wl.p + 1)
+    x = np.stack([np.exp(1j * (n[None, :] - n[:, None]) * wl.rot[l]) * S @ r[l] for l in range(wl.n)])
+    out = {"metric": "GMRES matvecs/s", "unit": "matvec/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "config": {"workload": "20000 stars, p=16, 1024 contour nodes, strip 1754 x 38, "
+                                                      "FMM far field (MPSL_FAR_AUTO)"}}
+    res = {}
+    y_ref = {}
+    for mode, method in (("fmm", mp.FAR_AUTO), ("direct", mp.FAR_DIRECT)):
+        ctx.set_far_field(method)
+        t0 = time.perf_counter()
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.zeros_like(xd)
+        ctx.apply_dev(0, xd, yd)   # builds the tables of this far-field method
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        y_ref[mode] = yd.cpu().numpy()
+        steps = args.steps if mode == "fmm" else max(2, args.steps // 10)
+        for name, prec in (("fp32", 1), ("fp64", 0)):
+            dt, far_ms, cnt, finite = _matvec_rate(ctx, torch, prec, x, steps, 1)
+            res.setdefault(mode, {})[name] = {"matvecs_per_s": steps / dt, "ms_per_matvec": dt / steps * 1e3,
+                                              "far_field_ms": far_ms, "finite": finite, "steps": steps}
+            if mode == "fmm":
+                res[mode][name]["info"] = ctx.fmm_info(prec)
+        res[mode]["setup_s"] = setup
+    err = float(np.linalg.norm(y_ref["fmm"] - y_ref["direct"]) / np.linalg.norm(y_ref["direct"]))
+    out["fmm"] = res["fmm"]
+    out["direct"] = res["direct"]
+    out["fmm_vs_direct_fp64_matvec_rel_err"] = err
+    for name in ("fp32", "fp64"):
+        out["fmm"][name]["speedup_vs_direct"] = (res["direct"][name]["ms_per_matvec"] /
+                                                 res["fmm"][name]["ms_per_matvec"])
+    out["value"] = res["fmm"]["fp32"]["matvecs_per_s"]
+    out["dtype"] = "f32 (f64 tables)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,9 +291,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
     ap.add_argument("--solve-maxiter", type=int, default=1500)
     ap.add_argument("--no-autotune", action="store_true", help="use the default M2L launch shape")
-    ap.add_argument("--workload", choices=["c3", "batch", "serve"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "batch", "serve", "fmm"], default="c3",
                     help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching; "
-                         "serve: Poisson request stream through the server")
+                         "serve: Poisson request stream through the server; fmm: 20000 particles, FMM vs direct")
     ap.add_argument("--requests", type=int, default=80, help="serve: number of requests")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
@@ -259,6 +314,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(_serve_workload(args, torch, mp)), flush=True)
+        return
+    if args.workload == "fmm":
+        print(json.dumps(_fmm_workload(args, torch, mp)), flush=True)
         return
     if args.copy_mib > 0:
         src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device="cuda")

@@ -376,9 +376,9 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
   if (rc) return rc;
   if (nrhs < 1) return set_err(ctx, MPSL_EINVAL, "nrhs must be >= 1");
   // the right-hand-side dimension already multiplies the grid: fewer chunks
-  // (the FMM writes two partials: near field and far field)
+  // (the FMM writes its own partials: near-field chunks and far field)
   const bool fmm = ctx->fmm.active;
-  const int ca = fmm ? 2 : std::max(1, chunks_m2l(ctx, prec) / nrhs), cb = chunks_s2l(ctx, nrhs);
+  const int ca = fmm ? fmm_slots(ctx) : std::max(1, chunks_m2l(ctx, prec) / nrhs), cb = chunks_s2l(ctx, nrhs);
   const int cc = chunks_m2s(ctx, nrhs);
   const int P = 2 * ctx->p + 1;
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
@@ -733,7 +733,7 @@ int mpsl_m2l_dev(mpsl_ctx *ctx, int prec, const void *beta, void *alpha) {
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
   const bool fmm = ctx->fmm.active;
-  const int ca = fmm ? 2 : mpsl::chunks_m2l(ctx, prec);
+  const int ca = fmm ? mpsl::fmm_slots(ctx) : mpsl::chunks_m2l(ctx, prec);
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
   if ((rc = mpsl::dev_alloc(ctx, ctx->part, static_cast<size_t>(ca) * ctx->n * (2 * ctx->p + 1) * esz))) return rc;
   if (fmm) {

@@ -51,12 +51,16 @@ struct FmmLevel {
   std::vector<uint8_t> occ;   // box holds at least one particle
 };
 
-// Task lists of one launch of the generic translation kernel: every task
-// writes one expansion, summing Toeplitz products over its terms.
+// One launch of the translation kernel: groups of boxes, each writing one
+// expansion per box as a sum of Toeplitz products over the group's terms.
 struct FmmStage {
-  int tasks = 0;
-  int pout = 0, pin_max = 0, max_terms = 0;
-  int64_t task_off = 0, term_off = 0;  // into FmmPlan::tasks / terms
+  int tasks = 0;                       // groups launched (one block per output tile)
+  int pout = 0;                        // output expansion length
+  int tps = 0, G = 0, l8 = 0;          // lanes per box, boxes per group, table tile / 8
+  int tiles = 1;                       // output tiles of kRB * tps slots
+  int64_t task_off = 0;                // first group in FmmPlan::groups
+  int nchunk = 1;                      // partial-local chunks summed after the launch
+  int64_t sum_off = 0, sum_len = 0;    // chunk 0 and the length of one chunk
 };
 
 struct FmmPlan {
@@ -70,7 +74,7 @@ struct FmmPlan {
   DBuf start;                 // int32[leaf boxes + 1]
   // per precision: translation tables, tasks and terms, expansion buffer
   DBuf tab[2];
-  DBuf tasks[2], terms[2];
+  DBuf groups[2], terms[2], ins[2], outs[2];
   std::vector<FmmStage> up[2];    // M2M, level 0 -> 1, ...
   std::vector<FmmStage> down[2];  // M2L (+ L2L), top level first
   int64_t p2m_off[2] = {0, 0}, l2p_off[2] = {0, 0};  // per-particle rows in tab
@@ -78,6 +82,7 @@ struct FmmPlan {
   DBuf xb;                    // expansion buffer (sized for FP64)
   // near field: padded lists of neighbour sources per sorted target
   int near_k = 0;
+  int near_chunks = 1;        // partial slots of the near field
   DBuf near_src;              // int32[near_k][n] source particle (padding: the target)
   DBuf near_cnt;              // int32[n]: true list length
   DBuf near_wave;             // int32[waves]: loop count of each 64-target wave
@@ -165,7 +170,9 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y);
 bool fmm_wanted(const mpsl_ctx *ctx);
 int fmm_build(mpsl_ctx *ctx);
 void fmm_free(mpsl_ctx *ctx);
-// Free-space M2L by the FMM: near-field pairs into part, far field into
-// part + len (two partial slots, len = n P complex entries).
+// Free-space M2L by the FMM into fmm_slots() partial slots of len = n P
+// complex entries: the near field split over near_chunks slots, then the far
+// field.
 int fmm_apply(mpsl_ctx *ctx, int prec, const void *beta, void *part);
+inline int fmm_slots(const mpsl_ctx *ctx) { return ctx->fmm.near_chunks + 1; }
 }  // namespace mpsl

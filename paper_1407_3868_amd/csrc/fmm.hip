@@ -31,14 +31,19 @@ constexpr size_t kLdsBudget = 64 * 1024;
 constexpr int kMaxBoxOrder = 600;     // largest box order (LDS of one term in FP64)
 constexpr int kAutoThreshold = 8000;  // MPSL_FAR_AUTO: FMM above this many particles
 
-struct FmmTask {
-  int64_t out;  // first entry of the output expansion
-  int t0, t1;   // term range
+constexpr int kTileJ = 64;             // input tile of the translation kernel
+constexpr int kMaxGroup = 32;          // boxes per group
+
+struct FmmGroup {
+  int64_t outs;  // first of the group's output offsets (one per box)
+  int nbox;      // boxes in the group
+  int t0, t1;    // term range
+  int pad;
 };
-struct FmmTerm {
-  int64_t in;   // first entry of the input expansion
-  int64_t tab;  // first entry of the table row
-  int pin;      // input length
+struct FmmGTerm {
+  int64_t tab;   // first entry of the table row
+  int64_t ins;   // first of the per-box input offsets (G of them, -1: absent)
+  int pin;       // input length
   int pad;
 };
 
@@ -222,7 +227,7 @@ double tree_cost(const Grid &g, const std::vector<int> &P, int top, int64_t n, i
         work += w;
         maxtask = std::max(maxtask, w);
       }
-    if (l == top) maxtask /= std::max(1.0, std::ceil(512.0 / std::max<int64_t>(1, nonempty)));
+    maxtask /= std::min(16.0, std::max(1.0, std::ceil(1024.0 / std::max<int64_t>(1, nonempty))));
     cost += std::max(work / cus, maxtask);
     if (l < top) cost += 2.0 * nonempty * P[l] * P[l + 1] / cus;  // M2M + L2L
   }
@@ -301,101 +306,105 @@ __global__ void k_fmm_l2p(const cv_t<T> *__restrict__ lin, const int *__restrict
   }
 }
 
-// Generic translation: one block per task, G subsets of tps lanes; each
-// subset takes every G-th term of the task, stages the input expansion and
-// the table row in LDS and accumulates kRB consecutive outputs per lane
-// with the Toeplitz window held in registers (one LDS read of the table
-// and one broadcast read of the input per kRB complex MACs).  The table row
-// is stored permuted, logical index x at (x mod 8) * l8 + x / 8, so that the
-// lanes of a subset (whose windows are 8 entries apart) read consecutive
-// words.  Subsets are summed through LDS at the end.
+// Translation of a group of boxes (one block per group task).  The G boxes
+// of a group share every table row of the task's terms (boxes of one
+// parity class see the same offsets and the same child position), so each
+// term's table is staged once per input tile in LDS while every subset of
+// tps lanes stages its own box's input tile and keeps kRB consecutive
+// outputs per lane in registers across all terms, with the Toeplitz window
+// in registers (one LDS read of the table and one broadcast read of the
+// input per kRB complex MACs).  The table tile is stored permuted, logical
+// index x at (x mod 8) * l8 + x / 8, so that lanes whose windows lie 8
+// entries apart read consecutive words.  A box whose input is absent in a
+// term (ins < 0) skips it.
 template <typename T>
-__global__ __launch_bounds__(kToepMaxThreads) void k_fmm_toep(const FmmTask *__restrict__ tasks,
-                                                               const FmmTerm *__restrict__ terms,
-                                                               const cv_t<T> *__restrict__ xin,
-                                                               const cv_t<T> *__restrict__ tabs,
-                                                               cv_t<T> *__restrict__ xout, int pout, int tps,
-                                                               int pin_pad, int l8) {
-  extern __shared__ __align__(16) unsigned char toep_smem[];
-  cx<T> *sm = reinterpret_cast<cx<T> *>(toep_smem);
-  const int G = blockDim.x / tps;
-  const int sub = threadIdx.x / tps, lt = threadIdx.x - sub * tps;
-  const int per = pin_pad + 8 * l8;
-  cx<T> *Ms = sm + sub * per;
-  cx<T> *Hp = Ms + pin_pad;
-  const FmmTask tk = tasks[blockIdx.x];
-  const int nt = tk.t1 - tk.t0;
-  const int ngroups = cdiv(pout, kRB);
+__global__ __launch_bounds__(kToepMaxThreads) void k_fmm_group(const FmmGroup *__restrict__ groups,
+                                                                const FmmGTerm *__restrict__ terms,
+                                                                const int64_t *__restrict__ ins,
+                                                                const int64_t *__restrict__ outs,
+                                                                const cv_t<T> *__restrict__ xin,
+                                                                const cv_t<T> *__restrict__ tabs,
+                                                                cv_t<T> *__restrict__ xout, int pout, int tps, int G,
+                                                                int l8) {
+  extern __shared__ __align__(16) unsigned char grp_smem[];
+  cx<T> *Hp = reinterpret_cast<cx<T> *>(grp_smem);
   const int hl = 8 * l8;
-  for (int g0 = 0; g0 < ngroups; g0 += tps) {
-    const int g = g0 + lt;
-    const bool act = g < ngroups;
-    const int jb = (act ? g : 0) * kRB;
+  const int sub = threadIdx.x / tps, lt = threadIdx.x - sub * tps;
+  cx<T> *Ms = Hp + hl + sub * kTileJ;
+  const FmmGroup gr = groups[blockIdx.x];
+  const bool box_ok = sub < gr.nbox;
+  const int ngroups = cdiv(pout, kRB);
+  // output tile of this block: slots [o0, o0 + TO)
+  const int TO = kRB * tps, o0 = blockIdx.y * TO;
+  {
+    const int g = blockIdx.y * tps + lt;
+    const bool act = box_ok && g < ngroups;
+    const int jb = (g < ngroups ? g : blockIdx.y * tps) * kRB;
     cx<T> acc[kRB];
 #pragma unroll
     for (int r = 0; r < kRB; ++r) acc[r] = mk<T>(0, 0);
-    // logical table index of window slot 0 at input slot 0 (front pad kRB - 1)
-    const int a = pout - 1 - jb + kRB - 1;
-    for (int r0 = 0; r0 < nt; r0 += G) {
-      const int ti = r0 + sub;
-      int pin8 = 0;
-      if (ti < nt) {
-        const FmmTerm tm = terms[tk.t0 + ti];
-        pin8 = cdiv(tm.pin, 8);
-        const int tl = tm.pin + pout - 1;
-        for (int i = lt; i < pin_pad; i += tps) Ms[i] = i < tm.pin ? ld<T>(xin[tm.in + i]) : mk<T>(0, 0);
-        for (int pos = lt; pos < hl; pos += tps) {
-          const int x = (pos % l8) * 8 + pos / l8;
-          const int k = x - (kRB - 1);
+    // The table tile of input tile j0 holds rows k = j0 + pout - o0 - TO + x'
+    // at local x' (so that x' = j - j' + o0 + TO - 1 - j0); the window of
+    // slot r starts at local a - r.
+    const int a = o0 + TO - 1 - jb;
+    for (int t = gr.t0; t < gr.t1; ++t) {
+      const FmmGTerm tm = terms[t];
+      const int64_t in = box_ok ? ins[tm.ins + sub] : -1;
+      const int tl = tm.pin + pout - 1;
+      for (int j0 = 0; j0 < tm.pin; j0 += kTileJ) {
+        __syncthreads();
+        for (int pos = threadIdx.x; pos < hl; pos += blockDim.x) {
+          const int k = j0 + pout - o0 - TO + (pos % l8) * 8 + pos / l8;
           Hp[pos] = (k >= 0 && k < tl) ? ld<T>(tabs[tm.tab + k]) : mk<T>(0, 0);
         }
-      }
-      __syncthreads();
-      if (ti < nt && act) {
-        cx<T> w[kRB];
+        for (int i = lt; i < kTileJ; i += tps)
+          Ms[i] = (in >= 0 && j0 + i < tm.pin) ? ld<T>(xin[in + j0 + i]) : mk<T>(0, 0);
+        __syncthreads();
+        if (act && in >= 0) {
+          cx<T> w[kRB];
 #pragma unroll
-        for (int r = 0; r < kRB; ++r) {
-          const int x = a - r;
-          w[r] = Hp[(x & 7) * l8 + (x >> 3)];
-        }
-        int addr[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int x = a + u + 1;
-          addr[u] = (x & 7) * l8 + (x >> 3);
-        }
-        for (int t = 0; t < pin8; ++t) {
+          for (int r = 0; r < kRB; ++r) {
+            const int x = a - r;
+            w[r] = Hp[(x & 7) * l8 + (x >> 3)];
+          }
+          int addr[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const cx<T> m = Ms[8 * t + u];
+            const int x = a + u + 1;
+            addr[u] = (x & 7) * l8 + (x >> 3);
+          }
+          const int steps = cdiv(min(kTileJ, tm.pin - j0), 8);
+          for (int s8 = 0; s8 < steps; ++s8) {
 #pragma unroll
-            for (int r = 0; r < kRB; ++r) cmac(acc[r], w[r], m);
+            for (int u = 0; u < 8; ++u) {
+              const cx<T> m = Ms[8 * s8 + u];
 #pragma unroll
-            for (int r = kRB - 1; r > 0; --r) w[r] = w[r - 1];
-            w[0] = Hp[addr[u] + t];
+              for (int r = 0; r < kRB; ++r) cmac(acc[r], w[r], m);
+#pragma unroll
+              for (int r = kRB - 1; r > 0; --r) w[r] = w[r - 1];
+              w[0] = Hp[addr[u] + s8];
+            }
           }
         }
       }
-      __syncthreads();
     }
-    if (G > 1) {
-      cx<T> *red = sm;
-#pragma unroll
-      for (int r = 0; r < kRB; ++r) red[(sub * tps + lt) * kRB + r] = acc[r];
-      __syncthreads();
-      for (int o = threadIdx.x; o < tps * kRB; o += blockDim.x) {
-        cx<T> s = mk<T>(0, 0);
-        for (int q = 0; q < G; ++q) s = s + red[q * tps * kRB + o];
-        const int jo = g0 * kRB + o;
-        if (jo < pout) xout[tk.out + jo] = st(s);
-      }
-      __syncthreads();
-    } else if (act) {
+    if (act) {
+      const int64_t o = outs[gr.outs + sub];
 #pragma unroll
       for (int r = 0; r < kRB; ++r)
-        if (jb + r < pout) xout[tk.out + jb + r] = st(acc[r]);
+        if (jb + r < pout) xout[o + jb + r] = st(acc[r]);
     }
   }
+}
+
+// Partial locals of a chunked level: x[i] = sum_c x[c len + i], in order.
+template <typename T>
+__global__ void k_fmm_chunk_sum(cv_t<T> *__restrict__ x, int64_t len, int nchunk) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  cx<T> s = ld<T>(x[i]);
+  for (int c = 1; c < nchunk; ++c) s = s + ld<T>(x[c * len + i]);
+  x[i] = st(s);
 }
 
 // Near-field pair entries in the layout of the all-pairs table:
@@ -439,8 +448,10 @@ void fmm_free(mpsl_ctx *ctx) {
   FmmPlan &f = ctx->fmm;
   for (int i = 0; i < 2; ++i) {
     dev_free(f.tab[i]);
-    dev_free(f.tasks[i]);
+    dev_free(f.groups[i]);
     dev_free(f.terms[i]);
+    dev_free(f.ins[i]);
+    dev_free(f.outs[i]);
   }
   dev_free(f.perm);
   dev_free(f.start);
@@ -466,7 +477,8 @@ int upload(mpsl_ctx *ctx, DBuf &b, const std::vector<V> &v) {
 // Tables, tasks and terms of one precision.  Returns false when a table
 // entry is not representable (then the shape is rejected).
 bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<zc> &tab,
-                     std::vector<FmmTask> &tasks, std::vector<FmmTerm> &terms, std::string &why) {
+                     std::vector<FmmGroup> &groups, std::vector<FmmGTerm> &terms, std::vector<int64_t> &ins,
+                     std::vector<int64_t> &outs, std::string &why) {
   FmmPlan &f = ctx->fmm;
   const double k = ctx->k2.real();
   const int p = ctx->p, P = 2 * p + 1;
@@ -474,20 +486,50 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
   std::vector<int> Pl(top + 1);
   for (int l = 0; l <= top; ++l) Pl[l] = 2 * f.lv[l].p[pi] + 1;
 
-  // top-level term chunks so that the top launch has enough blocks
-  int64_t top_nonempty = 0;
-  for (auto o : g.occ[top]) top_nonempty += o;
-  const int nchunk = top > 0 ? static_cast<int>(std::max<int64_t>(1, cdiv(512, std::max<int64_t>(1, top_nonempty)))) : 1;
+  // launch shape of every stage: lanes per box (tps <= 64, kRB outputs
+  // each), output tiles, boxes per group and term chunks (partial
+  // expansions summed afterwards in a fixed order), chosen so that every
+  // launch has enough blocks to fill the chip
+  auto plan = [&](int pout, const std::vector<int64_t> &cls, int nterms) {
+    FmmStage s;
+    const int ng = cdiv(pout, kRB);
+    s.pout = pout;
+    s.tps = std::min(64, ng);
+    s.tiles = cdiv(ng, s.tps);
+    s.G = std::max(1, std::min(kMaxGroup, kToepMaxThreads / s.tps));
+    auto blocks = [&](int G) {
+      int64_t b = 0;
+      for (auto c : cls) b += cdiv(c, G);
+      return b * s.tiles;
+    };
+    // fewer boxes per group only while a block keeps two full waves
+    while (s.G > 1 && (s.G / 2) * s.tps >= 128 && blocks(s.G) < 1024) s.G /= 2;
+    s.nchunk = std::min(std::min(16, std::max(1, nterms)), std::max(1, cdiv(1024, std::max<int64_t>(1, blocks(s.G)))));
+    s.l8 = cdiv(kRB * s.tps + kTileJ + 8, 8);
+    return s;
+  };
+  std::vector<FmmStage> shp_up(top + 1), shp_dn(top + 1);
+  for (int l = 0; l <= top; ++l) {
+    std::vector<int64_t> cls(4, 0);
+    int64_t nonempty = 0;
+    for (int b = 0; b < g.nx[l] * g.ny[l]; ++b)
+      if (g.occ[l][b]) {
+        ++cls[l < top ? ((b % g.nx[l]) & 1) + 2 * ((b / g.nx[l]) & 1) : 0];
+        ++nonempty;
+      }
+    shp_dn[l] = plan(Pl[l], cls, l < top ? 28 : static_cast<int>(nonempty));
+    if (l > 0) shp_up[l] = plan(Pl[l], {nonempty}, 4);
+  }
 
-  // expansion buffer: multipoles of every level, then locals (top: nchunk copies)
+  // expansion buffer: multipoles of every level, then locals (chunk copies)
   int64_t off = 0;
   for (int l = 0; l <= top; ++l) {
     f.lv[l].moff[pi] = off;
-    off += static_cast<int64_t>(g.nx[l]) * g.ny[l] * Pl[l];
+    off += static_cast<int64_t>(g.nx[l]) * g.ny[l] * Pl[l] * (l > 0 ? shp_up[l].nchunk : 1);
   }
   for (int l = 0; l <= top; ++l) {
     f.lv[l].loff[pi] = off;
-    off += static_cast<int64_t>(g.nx[l]) * g.ny[l] * Pl[l] * (l == top ? nchunk : 1);
+    off += static_cast<int64_t>(g.nx[l]) * g.ny[l] * Pl[l] * shp_dn[l].nchunk;
   }
   f.xlen[pi] = off;
 
@@ -548,132 +590,172 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
       return false;
     }
 
-  // tasks and terms
-  tasks.clear();
+  // groups and terms
+  groups.clear();
   terms.clear();
+  ins.clear();
+  outs.clear();
   f.up[pi].clear();
   f.down[pi].clear();
-  auto begin_stage = [&](int pout) {
-    FmmStage st;
-    st.pout = pout;
-    st.task_off = static_cast<int64_t>(tasks.size());
-    st.term_off = static_cast<int64_t>(terms.size());
-    return st;
+  auto shape = [&](FmmStage &st, const FmmStage &from) {
+    st = from;
+    st.tasks = 0;
+    st.task_off = static_cast<int64_t>(groups.size());
   };
-  auto add_task = [&](FmmStage &st, int64_t out, const std::vector<FmmTerm> &ts) {
-    FmmTask t;
-    t.out = out;
-    t.t0 = static_cast<int>(terms.size() - st.term_off);
-    for (const auto &x : ts) {
-      terms.push_back(x);
-      st.pin_max = std::max(st.pin_max, x.pin);
-    }
-    t.t1 = static_cast<int>(terms.size() - st.term_off);
-    st.max_terms = std::max(st.max_terms, t.t1 - t.t0);
-    tasks.push_back(t);
+  // one term: table row, input length, per-box inputs (G entries)
+  auto add_term = [&](int64_t tab_row, int pin, const std::vector<int64_t> &in) {
+    FmmGTerm t{};
+    t.tab = tab_row;
+    t.ins = static_cast<int64_t>(ins.size());
+    t.pin = pin;
+    ins.insert(ins.end(), in.begin(), in.end());
+    terms.push_back(t);
+  };
+  auto add_group = [&](FmmStage &st, const std::vector<int64_t> &out_rows, int t0, int t1) {
+    FmmGroup gr{};
+    gr.outs = static_cast<int64_t>(outs.size());
+    gr.nbox = static_cast<int>(out_rows.size());
+    gr.t0 = t0;
+    gr.t1 = t1;
+    outs.insert(outs.end(), out_rows.begin(), out_rows.end());
+    groups.push_back(gr);
     ++st.tasks;
   };
+  // M2M, level l -> l + 1: groups of parents; terms are the four child positions
   for (int l = 0; l < top; ++l) {
-    FmmStage st = begin_stage(Pl[l + 1]);
+    FmmStage st;
+    shape(st, shp_up[l + 1]);
     const int nxa = g.nx[l], nya = g.ny[l], nxb = g.nx[l + 1], nyb = g.ny[l + 1];
-    for (int by = 0; by < nyb; ++by)
-      for (int bx = 0; bx < nxb; ++bx) {
-        if (!g.occ[l + 1][by * nxb + bx]) continue;
-        std::vector<FmmTerm> ts;
-        for (int c = 0; c < 4; ++c) {
-          const int cx = 2 * bx + (c & 1), cy = 2 * by + (c >> 1);
+    const int64_t nbb = static_cast<int64_t>(nxb) * nyb;
+    std::vector<int> par;
+    for (int b = 0; b < nxb * nyb; ++b)
+      if (g.occ[l + 1][b]) par.push_back(b);
+    for (size_t g0 = 0; g0 < par.size(); g0 += st.G) {
+      const size_t g1 = std::min(par.size(), g0 + st.G);
+      const int t0 = static_cast<int>(terms.size());
+      for (int c = 0; c < 4; ++c) {
+        std::vector<int64_t> in(st.G, -1);
+        bool any = false;
+        for (size_t i = g0; i < g1; ++i) {
+          const int cx = 2 * (par[i] % nxb) + (c & 1), cy = 2 * (par[i] / nxb) + (c >> 1);
           if (cx >= nxa || cy >= nya || !g.occ[l][cy * nxa + cx]) continue;
-          FmmTerm t{};
-          t.in = f.lv[l].moff[pi] + static_cast<int64_t>(cy * nxa + cx) * Pl[l];
-          t.tab = up_base[l] + c * static_cast<int64_t>(Pl[l] + Pl[l + 1] - 1);
-          t.pin = Pl[l];
-          ts.push_back(t);
+          in[i - g0] = f.lv[l].moff[pi] + static_cast<int64_t>(cy * nxa + cx) * Pl[l];
+          any = true;
         }
-        add_task(st, f.lv[l + 1].moff[pi] + static_cast<int64_t>(by * nxb + bx) * Pl[l + 1], ts);
+        if (any) add_term(up_base[l] + c * static_cast<int64_t>(Pl[l] + Pl[l + 1] - 1), Pl[l], in);
       }
+      const int t1 = static_cast<int>(terms.size());
+      const int per = cdiv(t1 - t0, st.nchunk);
+      for (int ch = 0; ch < st.nchunk; ++ch) {
+        std::vector<int64_t> rows;
+        for (size_t i = g0; i < g1; ++i) rows.push_back(f.lv[l + 1].moff[pi] + (ch * nbb + par[i]) * Pl[l + 1]);
+        add_group(st, rows, std::min(t1, t0 + ch * per), std::min(t1, t0 + (ch + 1) * per));
+      }
+    }
+    st.sum_off = f.lv[l + 1].moff[pi];
+    st.sum_len = nbb * Pl[l + 1];
     f.up[pi].push_back(st);
   }
+  // M2L (+ L2L from the parent), top level first: groups of boxes of one
+  // parity class (top level: one class); terms are the offsets of the union
+  // of the group's interaction lists
   for (int l = top; l >= 0; --l) {
-    FmmStage st = begin_stage(Pl[l]);
+    FmmStage st;
+    shape(st, shp_dn[l]);
     const int nx = g.nx[l], ny = g.ny[l];
     const int64_t nbl = static_cast<int64_t>(nx) * ny;
     const int L = 2 * Pl[l] - 1;
-    for (int iy = 0; iy < ny; ++iy)
-      for (int ix = 0; ix < nx; ++ix) {
-        if (!g.occ[l][iy * nx + ix]) continue;
-        std::vector<FmmTerm> ts;
+    const int ncls = l < top ? 4 : 1;
+    std::vector<std::vector<int>> cls(ncls);
+    for (int b = 0; b < nx * ny; ++b)
+      if (g.occ[l][b]) cls[l < top ? ((b % nx) & 1) + 2 * ((b / nx) & 1) : 0].push_back(b);
+    for (int c = 0; c < ncls; ++c) {
+      const auto &bx = cls[c];
+      for (size_t g0 = 0; g0 < bx.size(); g0 += st.G) {
+        const size_t g1 = std::min(bx.size(), g0 + st.G);
+        const int t0 = static_cast<int>(terms.size());
         if (l < top) {
-          const int nxp = g.nx[l + 1];
-          const int par = (iy / 2) * nxp + ix / 2;
-          const int c = (ix & 1) + 2 * (iy & 1);
-          const int nch = l + 1 == top ? nchunk : 1;
-          const int64_t nbp = static_cast<int64_t>(g.nx[l + 1]) * g.ny[l + 1];
-          for (int ch = 0; ch < nch; ++ch) {
-            FmmTerm t{};
-            t.in = f.lv[l + 1].loff[pi] + (ch * nbp + par) * Pl[l + 1];
-            t.tab = dn_base[l] + c * static_cast<int64_t>(Pl[l] + Pl[l + 1] - 1);
-            t.pin = Pl[l + 1];
-            ts.push_back(t);
+          std::vector<int64_t> in(st.G, -1);
+          for (size_t i = g0; i < g1; ++i) {
+            const int ix = bx[i] % nx, iy = bx[i] / nx;
+            in[i - g0] = f.lv[l + 1].loff[pi] + static_cast<int64_t>((iy / 2) * g.nx[l + 1] + ix / 2) * Pl[l + 1];
           }
+          add_term(dn_base[l] + c * static_cast<int64_t>(Pl[l] + Pl[l + 1] - 1), Pl[l + 1], in);
         }
-        for_interactions(g, l, l == top, ix, iy, [&](int jx, int jy) {
-          FmmTerm t{};
-          t.in = f.lv[l].moff[pi] + static_cast<int64_t>(jy * nx + jx) * Pl[l];
-          const int dx = jx - ix, dy = jy - iy;
-          t.tab = m2l_base[l] + ((dy + Dy[l]) * (2 * Dx[l] + 1) + (dx + Dx[l])) * static_cast<int64_t>(L);
-          t.pin = Pl[l];
-          ts.push_back(t);
-        });
-        const int64_t box = static_cast<int64_t>(iy) * nx + ix;
-        if (l == top && nchunk > 1) {
-          const size_t per = (ts.size() + nchunk - 1) / nchunk;
-          for (int ch = 0; ch < nchunk; ++ch) {
-            const size_t a = std::min(ts.size(), ch * per), b = std::min(ts.size(), (ch + 1) * per);
-            std::vector<FmmTerm> part(ts.begin() + a, ts.begin() + b);
-            add_task(st, f.lv[l].loff[pi] + (ch * nbl + box) * Pl[l], part);
+        for (int dy = -Dy[l]; dy <= Dy[l]; ++dy)
+          for (int dx = -Dx[l]; dx <= Dx[l]; ++dx) {
+            if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+            std::vector<int64_t> in(st.G, -1);
+            bool any = false;
+            for (size_t i = g0; i < g1; ++i) {
+              const int ix = bx[i] % nx, iy = bx[i] / nx;
+              const int jx = ix + dx, jy = iy + dy;
+              if (jx < 0 || jx >= nx || jy < 0 || jy >= ny || !g.occ[l][jy * nx + jx]) continue;
+              if (l < top && (std::abs(jx / 2 - ix / 2) > 1 || std::abs(jy / 2 - iy / 2) > 1)) continue;
+              in[i - g0] = f.lv[l].moff[pi] + static_cast<int64_t>(jy * nx + jx) * Pl[l];
+              any = true;
+            }
+            if (any)
+              add_term(m2l_base[l] + ((dy + Dy[l]) * (2 * Dx[l] + 1) + (dx + Dx[l])) * static_cast<int64_t>(L), Pl[l],
+                       in);
           }
-        } else {
-          add_task(st, f.lv[l].loff[pi] + box * Pl[l], ts);
+        const int t1 = static_cast<int>(terms.size());
+        const int per = cdiv(t1 - t0, st.nchunk);
+        for (int ch = 0; ch < st.nchunk; ++ch) {
+          std::vector<int64_t> rows;
+          for (size_t i = g0; i < g1; ++i) rows.push_back(f.lv[l].loff[pi] + (ch * nbl + bx[i]) * Pl[l]);
+          add_group(st, rows, std::min(t1, t0 + ch * per), std::min(t1, t0 + (ch + 1) * per));
         }
       }
-    if (st.pin_max == 0) st.pin_max = Pl[l];
+    }
+    st.sum_off = f.lv[l].loff[pi];
+    st.sum_len = nbl * Pl[l];
     f.down[pi].push_back(st);
   }
   // every access of the translation kernel stays inside its buffers
   const int64_t tsz = static_cast<int64_t>(tab.size());
+  double cm = 2.0 * static_cast<double>(n) * P * Pl[0];  // P2M + L2P
   for (int s = 0; s < 2; ++s) {
     const auto &stages = s == 0 ? f.up[pi] : f.down[pi];
-    for (const auto &st : stages)
-      for (int64_t t = 0; t < st.tasks; ++t) {
-        const FmmTask &tk = tasks[st.task_off + t];
-        if (tk.out < 0 || tk.out + st.pout > f.xlen[pi] || tk.t0 > tk.t1 ||
-            st.term_off + tk.t1 > static_cast<int64_t>(terms.size())) {
-          why = "task outside its buffers";
+    for (const auto &st : stages) {
+      if (st.nchunk > 1 && (st.sum_off < 0 || st.sum_off + st.nchunk * st.sum_len > f.xlen[pi])) {
+        why = "chunked locals outside the expansion buffer";
+        return false;
+      }
+      for (int64_t gi = 0; gi < st.tasks; ++gi) {
+        const FmmGroup &gr = groups[st.task_off + gi];
+        if (gr.nbox < 1 || gr.nbox > st.G || gr.t0 > gr.t1 || gr.t1 > static_cast<int>(terms.size()) ||
+            gr.outs + gr.nbox > static_cast<int64_t>(outs.size())) {
+          why = "group outside its lists";
           return false;
         }
-        for (int u = tk.t0; u < tk.t1; ++u) {
-          const FmmTerm &tm = terms[st.term_off + u];
-          if (tm.pin < 1 || tm.pin > st.pin_max || tm.in < 0 || tm.in + tm.pin > f.xlen[pi] || tm.tab < 0 ||
-              tm.tab + tm.pin + st.pout - 1 > tsz) {
+        for (int i = 0; i < gr.nbox; ++i)
+          if (outs[gr.outs + i] < 0 || outs[gr.outs + i] + st.pout > f.xlen[pi]) {
+            why = "group output outside the expansion buffer";
+            return false;
+          }
+        for (int t = gr.t0; t < gr.t1; ++t) {
+          const FmmGTerm &tm = terms[t];
+          if (tm.pin < 1 || tm.tab < 0 || tm.tab + tm.pin + st.pout - 1 > tsz || tm.ins < 0 ||
+              tm.ins + st.G > static_cast<int64_t>(ins.size())) {
             why = "term outside its buffers";
             return false;
           }
+          for (int i = 0; i < st.G; ++i) {
+            const int64_t v = ins[tm.ins + i];
+            if (v >= 0 && v + tm.pin > f.xlen[pi]) {
+              why = "term input outside the expansion buffer";
+              return false;
+            }
+            if (v >= 0 && i < gr.nbox) cm += static_cast<double>(tm.pin) * st.pout;
+          }
         }
       }
+    }
   }
   if (f.p2m_off[pi] + static_cast<int64_t>(n) * Lp > tsz || f.l2p_off[pi] + static_cast<int64_t>(n) * Lp > tsz) {
     why = "particle rows outside the table";
     return false;
-  }
-  // translation work of one apply (complex MACs)
-  double cm = 2.0 * static_cast<double>(n) * P * Pl[0];
-  for (int s = 0; s < 2; ++s) {
-    const auto &stages = s == 0 ? f.up[pi] : f.down[pi];
-    for (const auto &st : stages)
-      for (int64_t t = 0; t < st.tasks; ++t) {
-        const FmmTask &tk = tasks[st.task_off + t];
-        for (int u = tk.t0; u < tk.t1; ++u) cm += static_cast<double>(terms[st.term_off + u].pin) * st.pout;
-      }
   }
   f.tree_cmac[pi] = cm;
   return true;
@@ -745,9 +827,11 @@ int fmm_build(mpsl_ctx *ctx) {
       for (int64_t i = 0; i < n; ++i) f.perm_h[fill[g.leaf[i]]++] = static_cast<int32_t>(i);
     }
     std::vector<zc> tab[2];
-    std::vector<FmmTask> tasks[2];
-    std::vector<FmmTerm> terms[2];
-    for (int pi = 0; pi < 2 && ok; ++pi) ok = build_precision(ctx, g, top, pi, tab[pi], tasks[pi], terms[pi], why);
+    std::vector<FmmGroup> groups[2];
+    std::vector<FmmGTerm> terms[2];
+    std::vector<int64_t> ins[2], outs[2];
+    for (int pi = 0; pi < 2 && ok; ++pi)
+      ok = build_precision(ctx, g, top, pi, tab[pi], groups[pi], terms[pi], ins[pi], outs[pi], why);
     if (!ok) continue;
 
     // near field: padded neighbour lists over the 3 x 3 leaf boxes
@@ -785,6 +869,9 @@ int fmm_build(mpsl_ctx *ctx) {
     for (int64_t i = 0; i < n; ++i) wave[i / 64] = std::max(wave[i / 64], cnt[i]);
     f.near_k = K;
     f.near_pairs = pairs;
+    // split the neighbour lists over several partial slots when one lane
+    // per target leaves the chip short of waves
+    f.near_chunks = std::max(1, std::min({8, K, cdiv(2048, cdiv(n, 128))}));
 
     int rc;
     if ((rc = upload(ctx, f.perm, f.perm_h)) || (rc = upload(ctx, f.start, f.start_h)) ||
@@ -792,7 +879,9 @@ int fmm_build(mpsl_ctx *ctx) {
         (rc = upload(ctx, f.near_wave, wave)))
       return rc;
     for (int pi = 0; pi < 2; ++pi) {
-      if ((rc = upload(ctx, f.tasks[pi], tasks[pi])) || (rc = upload(ctx, f.terms[pi], terms[pi]))) return rc;
+      if ((rc = upload(ctx, f.groups[pi], groups[pi])) || (rc = upload(ctx, f.terms[pi], terms[pi])) ||
+          (rc = upload(ctx, f.ins[pi], ins[pi])) || (rc = upload(ctx, f.outs[pi], outs[pi])))
+        return rc;
       if (pi == 0) {
         std::vector<double2> t(tab[0].size());
         for (size_t i = 0; i < t.size(); ++i) t[i] = make_double2(tab[0][i].real(), tab[0][i].imag());
@@ -832,28 +921,20 @@ template <typename T>
 int launch_stage(mpsl_ctx *ctx, int pi, const FmmStage &st) {
   if (st.tasks == 0) return MPSL_OK;
   FmmPlan &f = ctx->fmm;
-  const size_t esz = sizeof(cv_t<T>);
-  const int ngroups = cdiv(st.pout, kRB);
-  int tps;
-  if (ngroups <= 64) {
-    tps = 1;
-    while (tps < ngroups) tps <<= 1;
-  } else {
-    tps = std::min(kToepMaxThreads, cdiv(ngroups, 64) * 64);
-  }
-  const int pin_pad = cdiv(st.pin_max, 8) * 8;
-  const int l8 = cdiv(pin_pad + st.pout + 8, 8);
-  const size_t per = static_cast<size_t>(pin_pad) + 8 * static_cast<size_t>(l8);
-  int G = std::max(1, std::min(kToepMaxThreads / tps, std::max(1, st.max_terms)));
-  while (G > 1 && G * per * esz > kLdsBudget) --G;
-  const size_t lds = std::max(G * per, static_cast<size_t>(G) * tps * kRB) * esz;
+  const size_t lds = (8 * static_cast<size_t>(st.l8) + static_cast<size_t>(st.G) * kTileJ) * sizeof(cx<T>);
   if (lds > kLdsBudget) return set_err(ctx, MPSL_EUNSUPPORTED, "FMM translation exceeds the LDS budget");
-  hipLaunchKernelGGL(k_fmm_toep<T>, dim3(st.tasks), dim3(G * tps), lds, ctx->stream,
-                     static_cast<const FmmTask *>(f.tasks[pi].p) + st.task_off,
-                     static_cast<const FmmTerm *>(f.terms[pi].p) + st.term_off,
-                     static_cast<const cv_t<T> *>(f.xb.p), static_cast<const cv_t<T> *>(f.tab[pi].p),
-                     static_cast<cv_t<T> *>(f.xb.p), st.pout, tps, pin_pad, l8);
+  hipLaunchKernelGGL(k_fmm_group<T>, dim3(st.tasks, st.tiles), dim3(st.G * st.tps), lds, ctx->stream,
+                     static_cast<const FmmGroup *>(f.groups[pi].p) + st.task_off,
+                     static_cast<const FmmGTerm *>(f.terms[pi].p), static_cast<const int64_t *>(f.ins[pi].p),
+                     static_cast<const int64_t *>(f.outs[pi].p), static_cast<const cv_t<T> *>(f.xb.p),
+                     static_cast<const cv_t<T> *>(f.tab[pi].p), static_cast<cv_t<T> *>(f.xb.p), st.pout, st.tps,
+                     st.G, st.l8);
   MPSL_HIP_TRY(ctx, hipGetLastError());
+  if (st.nchunk > 1) {
+    hipLaunchKernelGGL(k_fmm_chunk_sum<T>, dim3(cdiv(st.sum_len, 256)), dim3(256), 0, ctx->stream,
+                       static_cast<cv_t<T> *>(f.xb.p) + st.sum_off, st.sum_len, st.nchunk);
+    MPSL_HIP_TRY(ctx, hipGetLastError());
+  }
   return MPSL_OK;
 }
 
@@ -876,7 +957,7 @@ int fmm_apply_t(mpsl_ctx *ctx, int pi, const void *beta, void *part) {
   for (const auto &st : f.down[pi])
     if ((rc = launch_stage<T>(ctx, pi, st))) return rc;
   const int64_t len = ctx->n * static_cast<int64_t>(P);
-  cv_t<T> *far = static_cast<cv_t<T> *>(part) + len;
+  cv_t<T> *far = static_cast<cv_t<T> *>(part) + f.near_chunks * len;
   hipLaunchKernelGGL(k_fmm_l2p<T>, dim3(nb0), dim3(256), P0 * sizeof(cx<T>), ctx->stream,
                      static_cast<const cv_t<T> *>(xb + f.lv[0].loff[pi]), static_cast<const int *>(f.perm.p),
                      static_cast<const int *>(f.start.p), tab + f.l2p_off[pi], P, P0, far);

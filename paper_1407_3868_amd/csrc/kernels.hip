@@ -226,17 +226,20 @@ __global__ __launch_bounds__(kThreads) void k_fmm_near(const cv_t<T> *__restrict
                                                        const int *__restrict__ src, const int *__restrict__ perm,
                                                        const int *__restrict__ wave_cnt,
                                                        const cv_t<T> *__restrict__ beta, cv_t<T> *__restrict__ out,
-                                                       int n) {
+                                                       int n, int kc) {
   constexpr int P = 2 * p + 1;
   const int i = blockIdx.x * kThreads + threadIdx.x;
+  // list entries [j_lo, j_hi) of this chunk into partial slot blockIdx.y
   const int kw = __builtin_amdgcn_readfirstlane(wave_cnt[i >> 6]);
+  const int j_lo = blockIdx.y * kc, j_hi = min(kw, j_lo + kc);
+  out += static_cast<int64_t>(blockIdx.y) * n * P;
   const bool valid = i < n;
   const int ic = valid ? i : n - 1;
   cx<T> acc[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) acc[k] = mk<T>(0, 0);
   constexpr int SPLIT = std::is_same<T, double>::value ? 1 : 0;
-  for (int j = 0; j < kw; ++j) {
+  for (int j = j_lo; j < j_hi; ++j) {
     const int64_t e = static_cast<int64_t>(j) * n + ic;
     const cv_t<T> *pe = pairs + 4 * e;
     cx<T> h0 = ld<T>(pe[0]), h1 = ld<T>(pe[1]);
@@ -736,10 +739,11 @@ static int launch_fmm_near_t(mpsl_ctx *ctx, const void *beta, void *out) {
   const auto *wave = static_cast<const int *>(f.near_wave.p);
   const auto *b = static_cast<const cv_t<T> *>(beta);
   auto *o = static_cast<cv_t<T> *>(out);
-  const dim3 grid(cdiv(n, kThreads));
+  const int kc = cdiv(f.near_k, f.near_chunks);
+  const dim3 grid(cdiv(n, kThreads), f.near_chunks);
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_fmm_near<T, PP>), grid, dim3(kThreads), 0, ctx->stream, pairs, src, perm, wave, b, o, n); break;
+  case PP: hipLaunchKernelGGL((k_fmm_near<T, PP>), grid, dim3(kThreads), 0, ctx->stream, pairs, src, perm, wave, b, o, n, kc); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
