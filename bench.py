@@ -13,8 +13,10 @@ Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,6 +25,33 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3e12   # MI355X FP32 vector, TFLOP/s
 PEAK_FP64 = 78.6e12    # MI355X FP64 vector
+
+
+M2L_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "m2l_5000stars_p16_hbm_traffic.md")
+
+
+def m2l_source_sha256():
+    """Hash of the source of the all-pairs M2L kernel (its device functions and launch)."""
+    with open(os.path.join(ROOT, "paper_1407_3868_amd", "csrc", "kernels.hip")) as fh:
+        src = fh.read()
+    a = src.index("// Row a1: all-pairs free-space M2L")
+    b = src.index("// FMM near field:")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def _m2l_traffic():
+    """Scaled HBM bytes per launch of k_m2l<float,16> at this workload from the committed
+    rocprofv3 counter summary; None when the kernel source has changed since."""
+    try:
+        with open(M2L_TRAFFIC_SUMMARY) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"m2l_traffic_bytes_fp32: (\d+)", text)
+    h = re.search(r"m2l_source_sha256: ([0-9a-f]+)", text)
+    if not m or not h or h.group(1) != m2l_source_sha256():
+        return None
+    return int(m.group(1))
 
 
 def _matvec_rate(ctx, torch, prec, x_np, steps, warmup):
@@ -387,7 +416,7 @@ def main():
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": ach32 / PEAK_FP32,
-            "traffic": None,
+            "traffic": _m2l_traffic(),
             "avg_ms": m2l32,
             "launches": cnt32,
             "algorithmic_flops_per_launch": flops,
