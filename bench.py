@@ -212,22 +212,22 @@ def _serve_workload(args, torch, mp):
     nreq = args.requests
 
     def make(i):
-        n = int(round(np.exp(rng.uniform(np.log(200), np.log(2000)))))
-        p = int(rng.choice([8, 12]))
+        n = int(round(np.exp(rng.uniform(np.log(200), np.log(20000)))))
+        p = int(rng.choice([8, 12, 16]))
         star = bool(rng.integers(0, 2))
         k2 = float(rng.uniform(6.0, 12.0))
-        d = float(rng.uniform(8.0, 30.0))
+        d = float(rng.uniform(8.0, 60.0))
         h = d - 2.0
         width = n / (0.3 * h)
         xy, rot = rejection_layout(n, (-width / 2, width / 2), (-d + 1.0, -1.0), 0.75, 1000 + i)
         return dict(k=(6.0, k2, 12.0), d=d, particle=1 if star else 0,
-                    shape=(0.25, 0.05, 5) if star else (0.25,), kp=15.0, p=p, xy=xy, rot=rot, n_nodes=512,
+                    shape=(0.25, 0.05, 5) if star else (0.25,), kp=15.0, p=p, xy=xy, rot=rot, n_nodes=1024,
                     b=min(0.2, 2.0 / width), t_max=32.0, src=(0.0, 2.0), tol=1e-8, maxiter=400, n_bdry=128)
 
     reqs = [make(i) for i in range(nreq)]
-    out = {"workload": (f"{nreq} requests: N log-uniform [200, 2000], p in {{8, 12}}, star or disk, k2 ~ U[6, 12], "
-                        "d ~ U[8, 30], 512 nodes, tol 1e-8, at most 400 iterations; Poisson arrivals at "
-                        "0.8 / (mean isolated service time)")}
+    out = {"workload": (f"{nreq} requests: N log-uniform [200, 20000] (FMM far field above 8000), "
+                        "p in {8, 12, 16}, star or disk, k2 ~ U[6, 12], d ~ U[8, 60], 1024 nodes, tol 1e-8, "
+                        "at most 400 iterations; Poisson arrivals at 0.8 / (mean isolated service time)")}
     for name, prec in (("fp64", 0), ("mixed", 1)):
         # isolated service time on a calibration sample
         srv = mp.Server(0, hbm_budget=200 << 30, max_active=1)
@@ -323,7 +323,7 @@ def main():
     ap.add_argument("--workload", choices=["c3", "batch", "serve", "fmm"], default="c3",
                     help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching; "
                          "serve: Poisson request stream through the server; fmm: 20000 particles, FMM vs direct")
-    ap.add_argument("--requests", type=int, default=80, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()

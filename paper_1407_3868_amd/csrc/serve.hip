@@ -52,7 +52,9 @@ size_t estimate_bytes(const mpsl_request &r) {
                                                                                                        : maxit));
   const size_t tb = (n + 127) / 128;
   const size_t ca = std::min(n, (2560 + tb - 1) / tb), cb = std::max<size_t>(1, std::min(ns / 8, (1024 + tb - 1) / tb));
-  size_t b = 96 * n * n;                       // pair tables, FP64 + FP32
+  // far field: all-pairs tables, or the FMM (default above 8000 particles)
+  // with its neighbour lists, per-particle shift rows and box expansions
+  size_t b = n > 8000 ? 32768 * n + (64 << 20) : 96 * n * n;
   b += 2 * 2 * n * ns * 24;                    // plane-wave factors E, F, both precisions
   b += n * P * 24 + ns * P * 128;              // rotation phases, per-node tables
   b += (2 * ca + cb) * n * P * 16;             // partial local expansions (tuning headroom)
