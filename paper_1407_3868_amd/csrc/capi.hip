@@ -416,7 +416,8 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
     ctx->ev_start.push_back(e0);
     ctx->ev_stop.push_back(e1);
   }
-  return launch_sapply(ctx, prec, x, part, ca + cb, y, nrhs, pstride);
+  if ((rc = launch_fold_parts(ctx, prec, part, ca + cb, nrhs, pstride))) return rc;
+  return launch_sapply(ctx, prec, x, part, y, nrhs, pstride);
 }
 
 int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y) { return matvec(ctx, prec, x, y, 1); }
@@ -776,7 +777,7 @@ int mpsl_sapply_dev(mpsl_ctx *ctx, int prec, const void *x, const void *alpha, v
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
-  return mpsl::launch_sapply(ctx, prec, x, alpha, 1, y);
+  return mpsl::launch_sapply(ctx, prec, x, alpha, y);
 }
 
 int mpsl_profile(mpsl_ctx *ctx, int enable) {

@@ -36,9 +36,13 @@ int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma, int nrhs = 1);
 int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs = 1, int64_t pstride = 0);
 // Sum of partial buffers: alpha = sum_{c < chunks} part[c].
 int launch_sum_parts(mpsl_ctx *ctx, int prec, const void *part, int chunks, void *alpha);
-// Row a2: y = x - S_rot (sum of partials)  (x may be null: y = S_rot alpha).
-int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y, int nrhs = 1,
-                  int64_t pstride = 0);
+// Partial buffers of each right-hand side summed in place into slot 0
+// (part + r * pstride holds chunks slots of n P entries).
+int launch_fold_parts(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs = 1, int64_t pstride = 0);
+// Row a2 (MFMA): y = x - S_rot alpha  (x may be null: y = S_rot alpha);
+// alpha of right-hand side r at alpha + r * astride.
+int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *alpha, void *y, int nrhs = 1,
+                  int64_t astride = 0);
 
 // GMRES helpers (FP64 complex vectors of length len).
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *w, int64_t len,

@@ -414,44 +414,118 @@ __global__ void k_sum_parts(const cv_t<T> *__restrict__ part, int chunks, int64_
   out[i] = o;
 }
 
-// Row a2: y^l = x^l - e^{-in psi} sum_n' S[n][n'] e^{in' psi} alpha^l_{n'}; alpha is
-// the sum of the partial buffers.  Block: kSapplyTargets targets x P lanes.
-constexpr int kSapplyTargets = 4;
+// In-place sum of the partial buffers of each right-hand side into slot 0:
+// part[r][0][i] = sum_c part[r][c][i]  (one lane per entry, fixed order).
+template <typename T>
+__global__ void k_fold_parts(cv_t<T> *__restrict__ part, int chunks, int64_t len, int64_t pstride) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  part += blockIdx.y * pstride;
+  T re = 0, im = 0;
+  for (int c = 0; c < chunks; ++c) {
+    const cv_t<T> v = part[c * len + i];
+    re += v.x;
+    im += v.y;
+  }
+  cv_t<T> o;
+  o.x = re;
+  o.y = im;
+  part[i] = o;
+}
+
+// Row a2 on the matrix cores: y^l = x^l - e^{-in psi_l} sum_n' S[n][n'] e^{in' psi_l} alpha^l_{n'},
+// alpha one buffer per right-hand side (partials folded first).  One block
+// per tile of 16 particles: all lanes rotate the tile's expansions (a
+// contiguous range of 16 P entries) into LDS as B[K = n'][N = particle];
+// wave w < MT then
+// multiplies row tile w of the shared S (A[M = n][K = n'], zero-padded to
+// 16 MT x KP) by B with 16x16x4 MFMA, the complex product as four real
+// chains (re += Sr Br - Si Bi, im += Sr Bi + Si Br); the result goes back
+// through LDS for coalesced stores.
+//   MFMA 16x16x4 operand layout (both precisions): lane i supplies
+//   A[i % 16][i / 16] and B[i / 16][i % 16].  Result register j of lane i is
+//   D[4 (i / 16) + j][i % 16] for f32 and D[i / 16 + 4 j][i % 16] for f64
+//   (measured on gfx950 with one-hot operands).
+constexpr int kSapplyThreads = 256;
+template <typename T> struct mfma4;
+template <> struct mfma4<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
+template <> struct mfma4<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
+};
+
 template <typename T, int p>
-__global__ void k_sapply(const cv_t<T> *__restrict__ x, const cv_t<T> *__restrict__ part,
-                         int chunks, const cv_t<T> *__restrict__ S, const cv_t<T> *__restrict__ rot,
-                         int n, cv_t<T> *__restrict__ y, int64_t pstride) {
+__global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__restrict__ x,
+                                                           const cv_t<T> *__restrict__ alpha,
+                                                           const cv_t<T> *__restrict__ S,
+                                                           const cv_t<T> *__restrict__ rot, int n,
+                                                           cv_t<T> *__restrict__ y, int64_t astride) {
   constexpr int P = 2 * p + 1;
+  constexpr int MT = (P + 15) / 16;   // row tiles of S
+  constexpr int KP = (P + 3) / 4 * 4; // K padded to the MFMA depth
+  static_assert(MT <= kSapplyThreads / 64, "one wave per row tile");
   {  // right-hand side
     const int64_t off = static_cast<int64_t>(blockIdx.y) * n * P;
     if (x) x += off;
     y += off;
-    part += blockIdx.y * pstride;
+    alpha += blockIdx.y * astride;
   }
-  __shared__ cx<T> a[kSapplyTargets][P];
-  const int t = threadIdx.x / P;
-  const int k = threadIdx.x % P;
-  const int l = blockIdx.x * kSapplyTargets + t;
-  const bool valid = (t < kSapplyTargets) && (l < n);
-  const int64_t len = static_cast<int64_t>(n) * P;
-  cx<T> ph = mk<T>(0, 0);
-  if (valid) {
-    const int64_t i = static_cast<int64_t>(l) * P + k;
-    cx<T> s = mk<T>(0, 0);
-    for (int c = 0; c < chunks; ++c) s = s + ld<T>(part[c * len + i]);
-    ph = ld<T>(rot[i]);
-    a[t][k] = s * ph;
+  __shared__ T Sre[MT * 16][KP], Sim[MT * 16][KP];
+  __shared__ T Bre[KP][16], Bim[KP][16];
+  __shared__ cx<T> Yt[16 * P];
+  const int tid = threadIdx.x;
+  const int l0 = blockIdx.x * 16;
+  for (int i = tid; i < MT * 16 * KP; i += kSapplyThreads) {
+    const int r = i / KP, c = i % KP;
+    const cx<T> v = (r < P && c < P) ? ld<T>(S[r * P + c]) : mk<T>(0, 0);
+    Sre[r][c] = v.re;
+    Sim[r][c] = v.im;
+  }
+  for (int i = tid; i < KP * 16; i += kSapplyThreads) {
+    Bre[i / 16][i % 16] = 0;
+    Bim[i / 16][i % 16] = 0;
   }
   __syncthreads();
-  if (!valid) return;
-  const cv_t<T> *Sr = S + k * P;
-  cx<T> r = mk<T>(0, 0);
+  const int cnt = min(16, n - l0) * P;  // entries of the tile
+  const int64_t base = static_cast<int64_t>(l0) * P;
+  for (int i = tid; i < cnt; i += kSapplyThreads) {
+    const cx<T> s = ld<T>(alpha[base + i]) * ld<T>(rot[base + i]);
+    Bre[i % P][i / P] = s.re;
+    Bim[i % P][i / P] = s.im;
+  }
+  __syncthreads();
+  const int w = tid >> 6, lane = tid & 63;
+  if (w < MT) {
+    typename mfma4<T>::v4 are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+    const int row = w * 16 + (lane & 15);
+    const int col = lane & 15;
 #pragma unroll
-  for (int j = 0; j < P; ++j) cmac(r, ld<T>(Sr[j]), a[t][j]);
-  r = conj(ph) * r;
-  const int64_t i = static_cast<int64_t>(l) * P + k;
-  if (x) r = ld<T>(x[i]) - r;
-  y[i] = st(r);
+    for (int k0 = 0; k0 < KP; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      const T sr = Sre[row][k], si = Sim[row][k];
+      const T br = Bre[k][col], bi = Bim[k][col];
+      are = mfma4<T>::mac(sr, br, are);
+      are = mfma4<T>::mac(-si, bi, are);
+      aim = mfma4<T>::mac(sr, bi, aim);
+      aim = mfma4<T>::mac(si, br, aim);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int nn = w * 16 + mfma4<T>::row(lane, j);
+      if (nn < P) Yt[col * P + nn] = mk<T>(are[j], aim[j]);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < cnt; i += kSapplyThreads) {
+    cx<T> r = conj(ld<T>(rot[base + i])) * Yt[i];
+    if (x) r = ld<T>(x[base + i]) - r;
+    y[base + i] = st(r);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -846,21 +920,19 @@ int launch_sum_parts(mpsl_ctx *ctx, int prec, const void *part, int chunks, void
 }
 
 template <typename T>
-static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *part, int chunks, void *y, int nrhs,
-                           int64_t pstride) {
+static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *alpha, void *y, int nrhs, int64_t astride) {
   const int n = static_cast<int>(ctx->n);
-  const int P = 2 * ctx->p + 1;
   const bool f64 = std::is_same<T, double>::value;
   const auto *S = static_cast<const cv_t<T> *>(f64 ? ctx->S64.p : ctx->S32.p);
   const auto *rot = static_cast<const cv_t<T> *>(f64 ? ctx->gt.rot64.p : ctx->gt.rot32.p);
-  const dim3 grid(cdiv(n, kSapplyTargets), nrhs);
-  const dim3 block(kSapplyTargets * P);
+  const dim3 grid(cdiv(n, 16), nrhs);
+  const dim3 block(kSapplyThreads);
   const auto *xx = static_cast<const cv_t<T> *>(x);
-  const auto *pp = static_cast<const cv_t<T> *>(part);
+  const auto *aa = static_cast<const cv_t<T> *>(alpha);
   auto *yy = static_cast<cv_t<T> *>(y);
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_sapply<T, PP>), grid, block, 0, ctx->stream, xx, pp, chunks, S, rot, n, yy, pstride); break;
+  case PP: hipLaunchKernelGGL((k_sapply<T, PP>), grid, block, 0, ctx->stream, xx, aa, S, rot, n, yy, astride); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
@@ -869,10 +941,23 @@ static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *part, int c
   return MPSL_OK;
 }
 
-int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *part, int chunks, void *y, int nrhs,
-                  int64_t pstride) {
-  return prec == MPSL_FP64 ? launch_sapply_t<double>(ctx, x, part, chunks, y, nrhs, pstride)
-                           : launch_sapply_t<float>(ctx, x, part, chunks, y, nrhs, pstride);
+int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *alpha, void *y, int nrhs, int64_t astride) {
+  return prec == MPSL_FP64 ? launch_sapply_t<double>(ctx, x, alpha, y, nrhs, astride)
+                           : launch_sapply_t<float>(ctx, x, alpha, y, nrhs, astride);
+}
+
+int launch_fold_parts(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs, int64_t pstride) {
+  if (chunks <= 1) return MPSL_OK;
+  const int64_t len = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
+  const dim3 grid(cdiv(len, 256), nrhs);
+  if (prec == MPSL_FP64)
+    hipLaunchKernelGGL(k_fold_parts<double>, grid, dim3(256), 0, ctx->stream, static_cast<double2 *>(part), chunks,
+                       len, pstride);
+  else
+    hipLaunchKernelGGL(k_fold_parts<float>, grid, dim3(256), 0, ctx->stream, static_cast<float2 *>(part), chunks,
+                       len, pstride);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
 }
 
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *w, int64_t len,

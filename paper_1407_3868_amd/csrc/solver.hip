@@ -19,7 +19,8 @@ int rhs_device(mpsl_ctx *ctx, const double *src, void *dev) {
   if ((rc = launch_reflect(ctx, nullptr, src, ctx->sigma.p))) return rc;
   if ((rc = launch_s2l_coef(ctx, ctx->sigma.p))) return rc;
   if ((rc = launch_s2l(ctx, MPSL_FP64, ctx->part.p, cb))) return rc;
-  return launch_sapply(ctx, MPSL_FP64, nullptr, ctx->part.p, cb, dev);
+  if ((rc = launch_fold_parts(ctx, MPSL_FP64, ctx->part.p, cb))) return rc;
+  return launch_sapply(ctx, MPSL_FP64, nullptr, ctx->part.p, dev);
 }
 
 namespace {
