@@ -138,3 +138,58 @@ def test_fmm_auto_at_20000_sampled(big, prec):
     print("weighted err", err, flush=True)
     assert err < FP_TOL[prec], err
     assert np.all(np.isfinite(got))
+
+
+def test_fmm_multi_rhs_and_graph_batch_equal_single_applies():
+    """The FMM far field inside the batching forms: several right-hand sides in
+    one call agree with single applies (the layered part chunks its sums
+    differently with several right-hand sides), and the captured graph gives
+    bitwise the eager batched call on every replay."""
+    import torch
+    import paper_1407_3868_amd as mp
+    wl = make_workload("c2")
+    ctx = _fmm_ctx(wl)
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx.set_stream(stream)
+    for prec in (0, 1):
+        npdt = np.complex128 if prec == 0 else np.complex64
+        xs = np.stack([coeff_vector(wl, 40 + r) for r in range(3)]).astype(npdt)
+        xd = torch.from_numpy(xs).cuda()
+        yd = torch.zeros_like(xd)
+        ctx.apply_batch_dev(prec, 3, xd, yd)
+        single = torch.zeros_like(xd)
+        for r in range(3):
+            ctx.apply_dev(prec, xd[r], single[r])
+        torch.cuda.synchronize()
+        assert ctx.fmm_info(prec)["active"]
+        assert rel_err(yd.cpu().numpy(), single.cpu().numpy()) < (1e-13 if prec == 0 else 1e-5)
+        yg = torch.zeros_like(xd)
+        batch = mp.Batch([(ctx, prec, 3, xd, yg)])
+        for _ in range(3):
+            yg.zero_()
+            batch.launch(stream)
+            torch.cuda.synchronize()
+            assert torch.equal(yg, yd)
+            ctx.apply_dev(prec, xd[0], single[0])   # eager work between replays
+            torch.cuda.synchronize()
+        del batch
+
+
+def test_fmm_request_in_server_matches_standalone():
+    """A served request above 8000 particles takes the FMM by default and gives
+    bitwise the standalone solve of the same problem."""
+    import paper_1407_3868_amd as mp
+    from synth import rejection_layout
+    wl = make_workload("c3", n=9000)
+    S = prototype_S(wl)
+    req = dict(k=(wl.k1, wl.k2, wl.k3), d=wl.d, particle=2, shape=(), kp=wl.kp, p=wl.p, xy=wl.xy, rot=wl.rot,
+               n_nodes=wl.n_nodes, b=wl.b, t_max=wl.t_max, src=wl.src[0], precision=1, tol=1e-8, maxiter=15,
+               S=S, r_enclose=wl.r_enclose)
+    srv = mp.Server(0, hbm_budget=64 << 30, max_active=4)
+    res = srv.wait(srv.submit(**req))
+    srv.close()
+    ctx = gpu_context(wl)
+    beta, meta = ctx.solve(wl.src[0], precision=1, tol=1e-8, maxiter=15)
+    assert ctx.fmm_info(1)["active"]
+    assert res["iterations"] == meta["iterations"]
+    assert np.array_equal(res["beta"], beta)
