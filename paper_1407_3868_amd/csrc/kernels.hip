@@ -220,8 +220,10 @@ __global__ __launch_bounds__(kThreads) void k_m2l(const cv_t<T> *__restrict__ pa
 // lists.  One lane per target in leaf-box order; each lane walks its own
 // list of sources (pair entries [j][i][4] as in the all-pairs table, source
 // coefficients loaded per lane), and every wave loops to the longest list
-// among its 64 targets (padding entries are zeros).
-template <typename T, int p>
+// among its 64 targets (padding entries are zeros).  HALF as in k_m2l: -1
+// all outputs; 0 / 1 output slots [0, p] / (mirror) [p+1, 2p] in two
+// launches, which keeps FP64 within the register file.
+template <typename T, int p, int HALF>
 __global__ __launch_bounds__(kThreads) void k_fmm_near(const cv_t<T> *__restrict__ pairs,
                                                        const int *__restrict__ src, const int *__restrict__ perm,
                                                        const int *__restrict__ wave_cnt,
@@ -235,31 +237,34 @@ __global__ __launch_bounds__(kThreads) void k_fmm_near(const cv_t<T> *__restrict
   out += static_cast<int64_t>(blockIdx.y) * n * P;
   const bool valid = i < n;
   const int ic = valid ? i : n - 1;
-  cx<T> acc[P];
+  constexpr bool MIRROR = HALF == 1;
+  constexpr int O1 = HALF == 0 ? p : (HALF == 1 ? p - 1 : P - 1);  // outputs [0, O1]
+  cx<T> acc[O1 + 1];
 #pragma unroll
-  for (int k = 0; k < P; ++k) acc[k] = mk<T>(0, 0);
+  for (int k = 0; k <= O1; ++k) acc[k] = mk<T>(0, 0);
   constexpr int SPLIT = std::is_same<T, double>::value ? 1 : 0;
   for (int j = j_lo; j < j_hi; ++j) {
     const int64_t e = static_cast<int64_t>(j) * n + ic;
     const cv_t<T> *pe = pairs + 4 * e;
     cx<T> h0 = ld<T>(pe[0]), h1 = ld<T>(pe[1]);
-    const cx<T> t = ld<T>(pe[2]);
+    cx<T> t = ld<T>(pe[2]);
+    if (MIRROR) t.re = -t.re;
     const T two_over_z = pe[3].x;
     if (!valid) h0 = h1 = mk<T>(0, 0);
     const cv_t<T> *bm = beta + static_cast<int64_t>(src[e]) * P;
     if (SPLIT) {
-      m2l_block<T, p, 0, P - 1, 0, p, false>(acc, bm, h0, h1, t, two_over_z);
+      m2l_block<T, p, 0, O1, 0, p, MIRROR>(acc, bm, h0, h1, t, two_over_z);
       __builtin_amdgcn_sched_barrier(0);
-      m2l_block<T, p, 0, P - 1, p + 1, P - 1, false>(acc, bm, h0, h1, t, two_over_z);
+      m2l_block<T, p, 0, O1, p + 1, P - 1, MIRROR>(acc, bm, h0, h1, t, two_over_z);
       __builtin_amdgcn_sched_barrier(0);
     } else {
-      m2l_block<T, p, 0, P - 1, 0, P - 1, false>(acc, bm, h0, h1, t, two_over_z);
+      m2l_block<T, p, 0, O1, 0, P - 1, MIRROR>(acc, bm, h0, h1, t, two_over_z);
     }
   }
   if (valid) {
     const int64_t o = static_cast<int64_t>(perm[i]) * P;
 #pragma unroll
-    for (int k = 0; k < P; ++k) out[o + k] = st(acc[k]);
+    for (int k = 0; k <= O1; ++k) out[o + (MIRROR ? 2 * p - k : k)] = st(acc[k]);
   }
 }
 
@@ -815,9 +820,20 @@ static int launch_fmm_near_t(mpsl_ctx *ctx, const void *beta, void *out) {
   auto *o = static_cast<cv_t<T> *>(out);
   const int kc = cdiv(f.near_k, f.near_chunks);
   const dim3 grid(cdiv(n, kThreads), f.near_chunks);
+  // FP64: two output halves (register pressure); FP32: one launch
   switch (ctx->p) {
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_fmm_near<T, PP>), grid, dim3(kThreads), 0, ctx->stream, pairs, src, perm, wave, b, o, n, kc); break;
+#define X(PP)                                                                                                    \
+  case PP:                                                                                                       \
+    if constexpr (std::is_same<T, double>::value) {                                                              \
+      hipLaunchKernelGGL((k_fmm_near<T, PP, 0>), grid, dim3(kThreads), 0, ctx->stream, pairs, src, perm, wave, b, \
+                         o, n, kc);                                                                              \
+      hipLaunchKernelGGL((k_fmm_near<T, PP, 1>), grid, dim3(kThreads), 0, ctx->stream, pairs, src, perm, wave, b, \
+                         o, n, kc);                                                                              \
+    } else {                                                                                                     \
+      hipLaunchKernelGGL((k_fmm_near<T, PP, -1>), grid, dim3(kThreads), 0, ctx->stream, pairs, src, perm, wave,   \
+                         b, o, n, kc);                                                                           \
+    }                                                                                                            \
+    break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");

@@ -193,3 +193,17 @@ def test_fmm_request_in_server_matches_standalone():
     assert ctx.fmm_info(1)["active"]
     assert res["iterations"] == meta["iterations"]
     assert np.array_equal(res["beta"], beta)
+
+
+@pytest.mark.parametrize("n", [1, 2, 17])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fmm_forced_at_tiny_sizes(n, prec):
+    """Degenerate trees: one particle (no pairs), two, and a ragged handful."""
+    wl = make_workload("s70p8", n=n)
+    pr = oracle_problem(wl)
+    ctx = _fmm_ctx(wl)
+    x = coeff_vector(wl, 50 + n)
+    got = _run(ctx, "apply_dev", prec, x)
+    assert ctx.fmm_info(prec)["active"]
+    ref = pr.matvec(x)
+    assert rel_err(got, ref) < (1e-12 if prec == 0 else 2e-5)
