@@ -58,6 +58,7 @@ struct FmmStage {
   int pout = 0;                        // output expansion length
   int tps = 0, G = 0, l8 = 0;          // lanes per box, boxes per group, table tile / 8
   int tiles = 1;                       // output tiles of kRB * tps slots
+  int tj = 64;                         // input tile length
   int64_t task_off = 0;                // first group in FmmPlan::groups
   int nchunk = 1;                      // partial-local chunks summed after the launch
   int64_t sum_off = 0, sum_len = 0;    // chunk 0 and the length of one chunk

@@ -31,8 +31,10 @@ constexpr size_t kLdsBudget = 64 * 1024;
 constexpr int kMaxBoxOrder = 600;     // largest box order (LDS of one term in FP64)
 constexpr int kAutoThreshold = 8000;  // MPSL_FAR_AUTO: FMM above this many particles
 
-constexpr int kTileJ = 64;             // input tile of the translation kernel
+constexpr int kMaxTileJ = 256;         // longest input tile of the translation kernel
 constexpr int kMaxGroup = 32;          // boxes per group
+constexpr int kTargetBlocks = 2048;    // blocks a translation launch aims for (8 per CU)
+constexpr int kMaxChunks = 64;         // term chunks of one stage
 
 struct FmmGroup {
   int64_t outs;  // first of the group's output offsets (one per box)
@@ -325,12 +327,12 @@ __global__ __launch_bounds__(kToepMaxThreads) void k_fmm_group(const FmmGroup *_
                                                                 const cv_t<T> *__restrict__ xin,
                                                                 const cv_t<T> *__restrict__ tabs,
                                                                 cv_t<T> *__restrict__ xout, int pout, int tps, int G,
-                                                                int l8) {
+                                                                int l8, int tj) {
   extern __shared__ __align__(16) unsigned char grp_smem[];
   cx<T> *Hp = reinterpret_cast<cx<T> *>(grp_smem);
   const int hl = 8 * l8;
   const int sub = threadIdx.x / tps, lt = threadIdx.x - sub * tps;
-  cx<T> *Ms = Hp + hl + sub * kTileJ;
+  cx<T> *Ms = Hp + hl + sub * tj;
   const FmmGroup gr = groups[blockIdx.x];
   const bool box_ok = sub < gr.nbox;
   const int ngroups = cdiv(pout, kRB);
@@ -351,13 +353,14 @@ __global__ __launch_bounds__(kToepMaxThreads) void k_fmm_group(const FmmGroup *_
       const FmmGTerm tm = terms[t];
       const int64_t in = box_ok ? ins[tm.ins + sub] : -1;
       const int tl = tm.pin + pout - 1;
-      for (int j0 = 0; j0 < tm.pin; j0 += kTileJ) {
+      for (int j0 = 0; j0 < tm.pin; j0 += tj) {
         __syncthreads();
-        for (int pos = threadIdx.x; pos < hl; pos += blockDim.x) {
-          const int k = j0 + pout - o0 - TO + (pos % l8) * 8 + pos / l8;
-          Hp[pos] = (k >= 0 && k < tl) ? ld<T>(tabs[tm.tab + k]) : mk<T>(0, 0);
+        const int kb = j0 + pout - o0 - TO;  // table row of local index 0
+        for (int xl = threadIdx.x; xl < hl; xl += blockDim.x) {
+          const int k = kb + xl;
+          Hp[(xl & 7) * l8 + (xl >> 3)] = (k >= 0 && k < tl) ? ld<T>(tabs[tm.tab + k]) : mk<T>(0, 0);
         }
-        for (int i = lt; i < kTileJ; i += tps)
+        for (int i = lt; i < tj; i += tps)
           Ms[i] = (in >= 0 && j0 + i < tm.pin) ? ld<T>(xin[in + j0 + i]) : mk<T>(0, 0);
         __syncthreads();
         if (act && in >= 0) {
@@ -373,7 +376,7 @@ __global__ __launch_bounds__(kToepMaxThreads) void k_fmm_group(const FmmGroup *_
             const int x = a + u + 1;
             addr[u] = (x & 7) * l8 + (x >> 3);
           }
-          const int steps = cdiv(min(kTileJ, tm.pin - j0), 8);
+          const int steps = cdiv(min(tj, tm.pin - j0), 8);
           for (int s8 = 0; s8 < steps; ++s8) {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -490,7 +493,7 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
   // each), output tiles, boxes per group and term chunks (partial
   // expansions summed afterwards in a fixed order), chosen so that every
   // launch has enough blocks to fill the chip
-  auto plan = [&](int pout, const std::vector<int64_t> &cls, int nterms) {
+  auto plan = [&](int pout, int pin_max, const std::vector<int64_t> &cls, int nterms) {
     FmmStage s;
     const int ng = cdiv(pout, kRB);
     s.pout = pout;
@@ -503,9 +506,16 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
       return b * s.tiles;
     };
     // fewer boxes per group only while a block keeps two full waves
-    while (s.G > 1 && (s.G / 2) * s.tps >= 128 && blocks(s.G) < 1024) s.G /= 2;
-    s.nchunk = std::min(std::min(16, std::max(1, nterms)), std::max(1, cdiv(1024, std::max<int64_t>(1, blocks(s.G)))));
-    s.l8 = cdiv(kRB * s.tps + kTileJ + 8, 8);
+    while (s.G > 1 && (s.G / 2) * s.tps >= 128 && blocks(s.G) < kTargetBlocks) s.G /= 2;
+    s.nchunk = std::min({kMaxChunks, std::max(1, nterms),
+                         std::max(1, cdiv(kTargetBlocks, std::max<int64_t>(1, blocks(s.G))))});
+    // input tile: the whole input when it fits, at most kMaxTileJ, within the LDS budget
+    s.tj = std::min(kMaxTileJ, cdiv(pin_max, 8) * 8);
+    auto lds = [&](int tj) {
+      return (8.0 * cdiv(kRB * s.tps + tj + 8, 8) + static_cast<double>(s.G) * tj) * 16.0;  // FP64 bytes
+    };
+    while (s.tj > 64 && lds(s.tj) > static_cast<double>(kLdsBudget)) s.tj = cdiv(s.tj / 2, 8) * 8;
+    s.l8 = cdiv(kRB * s.tps + s.tj + 8, 8);
     return s;
   };
   std::vector<FmmStage> shp_up(top + 1), shp_dn(top + 1);
@@ -517,8 +527,8 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
         ++cls[l < top ? ((b % g.nx[l]) & 1) + 2 * ((b / g.nx[l]) & 1) : 0];
         ++nonempty;
       }
-    shp_dn[l] = plan(Pl[l], cls, l < top ? 28 : static_cast<int>(nonempty));
-    if (l > 0) shp_up[l] = plan(Pl[l], {nonempty}, 4);
+    shp_dn[l] = plan(Pl[l], l < top ? std::max(Pl[l], Pl[l + 1]) : Pl[l], cls, l < top ? 28 : static_cast<int>(nonempty));
+    if (l > 0) shp_up[l] = plan(Pl[l], Pl[l - 1], {nonempty}, 4);
   }
 
   // expansion buffer: multipoles of every level, then locals (chunk copies)
@@ -645,11 +655,10 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
         if (any) add_term(up_base[l] + c * static_cast<int64_t>(Pl[l] + Pl[l + 1] - 1), Pl[l], in);
       }
       const int t1 = static_cast<int>(terms.size());
-      const int per = cdiv(t1 - t0, st.nchunk);
-      for (int ch = 0; ch < st.nchunk; ++ch) {
+      for (int ch = 0; ch < st.nchunk; ++ch) {  // even split: sizes differ by at most one
         std::vector<int64_t> rows;
         for (size_t i = g0; i < g1; ++i) rows.push_back(f.lv[l + 1].moff[pi] + (ch * nbb + par[i]) * Pl[l + 1]);
-        add_group(st, rows, std::min(t1, t0 + ch * per), std::min(t1, t0 + (ch + 1) * per));
+        add_group(st, rows, t0 + ch * (t1 - t0) / st.nchunk, t0 + (ch + 1) * (t1 - t0) / st.nchunk);
       }
     }
     st.sum_off = f.lv[l + 1].moff[pi];
@@ -700,11 +709,10 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
                        in);
           }
         const int t1 = static_cast<int>(terms.size());
-        const int per = cdiv(t1 - t0, st.nchunk);
-        for (int ch = 0; ch < st.nchunk; ++ch) {
+        for (int ch = 0; ch < st.nchunk; ++ch) {  // even split: sizes differ by at most one
           std::vector<int64_t> rows;
           for (size_t i = g0; i < g1; ++i) rows.push_back(f.lv[l].loff[pi] + (ch * nbl + bx[i]) * Pl[l]);
-          add_group(st, rows, std::min(t1, t0 + ch * per), std::min(t1, t0 + (ch + 1) * per));
+          add_group(st, rows, t0 + ch * (t1 - t0) / st.nchunk, t0 + (ch + 1) * (t1 - t0) / st.nchunk);
         }
       }
     }
@@ -921,14 +929,14 @@ template <typename T>
 int launch_stage(mpsl_ctx *ctx, int pi, const FmmStage &st) {
   if (st.tasks == 0) return MPSL_OK;
   FmmPlan &f = ctx->fmm;
-  const size_t lds = (8 * static_cast<size_t>(st.l8) + static_cast<size_t>(st.G) * kTileJ) * sizeof(cx<T>);
+  const size_t lds = (8 * static_cast<size_t>(st.l8) + static_cast<size_t>(st.G) * st.tj) * sizeof(cx<T>);
   if (lds > kLdsBudget) return set_err(ctx, MPSL_EUNSUPPORTED, "FMM translation exceeds the LDS budget");
   hipLaunchKernelGGL(k_fmm_group<T>, dim3(st.tasks, st.tiles), dim3(st.G * st.tps), lds, ctx->stream,
                      static_cast<const FmmGroup *>(f.groups[pi].p) + st.task_off,
                      static_cast<const FmmGTerm *>(f.terms[pi].p), static_cast<const int64_t *>(f.ins[pi].p),
                      static_cast<const int64_t *>(f.outs[pi].p), static_cast<const cv_t<T> *>(f.xb.p),
                      static_cast<const cv_t<T> *>(f.tab[pi].p), static_cast<cv_t<T> *>(f.xb.p), st.pout, st.tps,
-                     st.G, st.l8);
+                     st.G, st.l8, st.tj);
   MPSL_HIP_TRY(ctx, hipGetLastError());
   if (st.nchunk > 1) {
     hipLaunchKernelGGL(k_fmm_chunk_sum<T>, dim3(cdiv(st.sum_len, 256)), dim3(256), 0, ctx->stream,
