@@ -439,15 +439,24 @@ def main():
         for name, prec in (("mixed", 1), ("fp64", 0)):
             beta, meta = ctx.solve(wl.src[0], precision=prec, tol=wl.tol, maxiter=args.solve_maxiter,
                                    inner_tol=1e-4)
+            its = max(1, meta["iterations"])
+            ms_it = meta["seconds"] * 1e3 / its
+            peak = PEAK_FP32 if prec == 1 else PEAK_FP64
             solves[name] = {"seconds": meta["seconds"], "iterations": meta["iterations"],
                             "fp64_matvecs": meta["fp64_matvecs"], "refinements": meta["refinements"],
                             "rel_residual": meta["rel_residual"], "converged": meta["status"] == 0,
-                            "tol": wl.tol}
+                            "tol": wl.tol, "ms_per_iteration": ms_it,
+                            # ideal time of the iteration's M2L at the vector peak / measured time
+                            "iteration_roofline_frac": flops / peak * 1e3 / ms_it}
             print(f"# solve {name}: {meta['iterations']} its, {meta['seconds']:.2f} s, "
                   f"res {meta['rel_residual']:.2e}", file=sys.stderr, flush=True)
         out["solve"] = solves
         if solves["mixed"]["converged"] and solves["fp64"]["converged"]:
             out["mixed_vs_fp64_solve_speedup"] = solves["fp64"]["seconds"] / solves["mixed"]["seconds"]
+        elif solves["mixed"]["iterations"] == solves["fp64"]["iterations"]:
+            # both stopped at the iteration limit: the same work in both precisions
+            out["mixed_vs_fp64_solve_speedup_equal_iterations"] = (solves["fp64"]["seconds"] /
+                                                                   solves["mixed"]["seconds"])
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(wl, S, x)

@@ -16,6 +16,7 @@
 #include <memory>
 #include <mutex>
 #include <thread>
+#include <algorithm>
 #include <vector>
 
 #include "solve_sm.h"
@@ -162,6 +163,11 @@ void finish(mpsl_server *s, const std::shared_ptr<Job> &j, int status) {
   j->state = Job::kDone;
   s->in_use -= j->bytes;
   ++s->completed;
+  // the finished request no longer holds a slot: drop it from the active
+  // list before admitting (the worker republishes the list only later, and
+  // a request submitted in between would otherwise wait for an admission
+  // that no later event triggers)
+  s->active.erase(std::remove(s->active.begin(), s->active.end(), j), s->active.end());
   admit_locked(s);
   s->done_cv.notify_all();
   s->cv.notify_all();
@@ -238,6 +244,8 @@ void worker_loop(mpsl_server *s) {
     act.swap(keep);
     std::lock_guard<std::mutex> lk(s->mu);
     s->active = act;
+    admit_locked(s);
+    s->cv.notify_all();
   }
 }
 

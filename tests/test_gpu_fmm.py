@@ -186,7 +186,8 @@ def test_fmm_request_in_server_matches_standalone():
                n_nodes=wl.n_nodes, b=wl.b, t_max=wl.t_max, src=wl.src[0], precision=1, tol=1e-8, maxiter=15,
                S=S, r_enclose=wl.r_enclose)
     srv = mp.Server(0, hbm_budget=64 << 30, max_active=4)
-    res = srv.wait(srv.submit(**req))
+    res = srv.wait(srv.submit(**req), timeout=300.0)
+    assert res is not None, "request still pending after 300 s"
     srv.close()
     ctx = gpu_context(wl)
     beta, meta = ctx.solve(wl.src[0], precision=1, tol=1e-8, maxiter=15)

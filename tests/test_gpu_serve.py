@@ -20,6 +20,13 @@ def _req(wl, precision=0, tol=1e-10, maxiter=600, src=None):
                 maxiter=maxiter, S=S, r_enclose=wl.r_enclose)
 
 
+def _wait(srv, ticket, timeout=120.0):
+    """Wait for one request; a request that never completes fails the test."""
+    res = srv.wait(ticket, timeout=timeout)
+    assert res is not None, "request still pending after %.0f s" % timeout
+    return res
+
+
 def _standalone(wl, r):
     ctx = gpu_context(wl, disk_from_library=True)
     beta, meta = ctx.solve(r["src"], precision=r["precision"], tol=r["tol"], maxiter=r["maxiter"])
@@ -33,11 +40,11 @@ def test_results_alone_and_in_mix_are_identical():
     alone = []
     srv = mp.Server(0, hbm_budget=32 << 30, max_active=1)
     for r in reqs:
-        alone.append(srv.wait(srv.submit(**r)))
+        alone.append(_wait(srv, srv.submit(**r)))
     srv.close()
     srv = mp.Server(0, hbm_budget=32 << 30, max_active=8)
     tickets = [srv.submit(**r) for r in reqs]
-    mix = [srv.wait(t) for t in tickets]
+    mix = [_wait(srv, t) for t in tickets]
     srv.close()
     for a, m, wl, r in zip(alone, mix, wls, reqs):
         assert a["status"] == 0 and m["status"] == 0
@@ -54,7 +61,7 @@ def test_served_solution_matches_oracle():
     import paper_1407_3868_amd as mp
     wl = make_workload("s70p8")
     srv = mp.Server(0)
-    res = srv.wait(srv.submit(**_req(wl, tol=1e-12, maxiter=800)))
+    res = _wait(srv, srv.submit(**_req(wl, tol=1e-12, maxiter=800)))
     srv.close()
     assert res["status"] == 0
     assert rel_err(res["beta"], oracle_problem(wl).solve_lu(wl.src[0])) < 1e-10
@@ -65,12 +72,12 @@ def test_admission_respects_budget_and_errors_are_reported():
     wl = make_workload("c1")
     r = _req(wl)
     probe = mp.Server(0, hbm_budget=1 << 40, max_active=4)
-    one = probe.wait(probe.submit(**r))
+    one = _wait(probe, probe.submit(**r))
     probe.close()
     need = one["hbm_bytes"]
     srv = mp.Server(0, hbm_budget=int(need * 1.5), max_active=4)   # room for one request at a time
     tickets = [srv.submit(**r) for _ in range(3)]
-    res = [srv.wait(t) for t in tickets]
+    res = [_wait(srv, t) for t in tickets]
     for a, b in zip(res, res[1:]):
         assert b["t_admit"] >= a["t_finish"] - 1e-6                 # admitted only after the previous finished
     with pytest.raises(mp.MpslError) as e:                          # alone larger than the budget
@@ -80,6 +87,6 @@ def test_admission_respects_budget_and_errors_are_reported():
     bad = dict(r)
     bad["xy"] = np.array([[0.0, -2.0], [0.1, -2.0]])                # overlapping particles
     bad["rot"] = None
-    out = srv.wait(srv.submit(**bad))
+    out = _wait(srv, srv.submit(**bad))
     assert out["status"] == -5 and "beta" not in out
     srv.close()
