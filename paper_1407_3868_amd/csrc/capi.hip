@@ -378,7 +378,11 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
   // the right-hand-side dimension already multiplies the grid: fewer chunks
   // (the FMM writes its own partials: near-field chunks and far field)
   const bool fmm = ctx->fmm.active;
-  const int ca = fmm ? fmm_slots(ctx) : std::max(1, chunks_m2l(ctx, prec) / nrhs), cb = chunks_s2l(ctx, nrhs);
+  // many FP32 right-hand sides: one Toeplitz GEMM per pair on the matrix cores
+  const bool mrhs = !fmm && prec == MPSL_FP32 && nrhs >= kMrhsMin;
+  const int ca = fmm ? fmm_slots(ctx)
+                     : (mrhs ? chunks_m2l_mrhs(ctx, nrhs) : std::max(1, chunks_m2l(ctx, prec) / nrhs));
+  const int cb = chunks_s2l(ctx, nrhs);
   const int cc = chunks_m2s(ctx, nrhs);
   const int P = 2 * ctx->p + 1;
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
@@ -408,6 +412,8 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
       if ((rc = fmm_apply(ctx, prec, static_cast<const char *>(x) + static_cast<size_t>(r) * len * esz,
                           part + static_cast<size_t>(r) * pstride * esz)))
         return rc;
+  } else if (mrhs) {
+    if ((rc = launch_m2l_mrhs(ctx, x, part, ca, nrhs, pstride))) return rc;
   } else if ((rc = launch_m2l(ctx, prec, x, part, ca, -1, nrhs, pstride))) {
     return rc;
   }
@@ -468,7 +474,7 @@ void mpsl_destroy(mpsl_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
   for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
-  DBuf *bufs[] = {&ctx->S64, &ctx->S32, &ctx->ct.R, &ctx->ct.srcfac, &ctx->ct.lam, &ctx->ct.gw,
+  DBuf *bufs[] = {&ctx->bt, &ctx->S64, &ctx->S32, &ctx->ct.R, &ctx->ct.srcfac, &ctx->ct.lam, &ctx->ct.gw,
                   &ctx->ct.cq, &ctx->ct.W64, &ctx->ct.W32, &ctx->ct.U64, &ctx->gt.xy, &ctx->gt.rot64,
                   &ctx->gt.rot32, &ctx->gt.pair64, &ctx->gt.pair32, &ctx->gt.E64, &ctx->gt.E32, &ctx->gt.F64, &ctx->gt.F32, &ctx->part,
                   &ctx->m2s_part, &ctx->spec, &ctx->sigma, &ctx->Up64, &ctx->Up32, &ctx->xbuf,

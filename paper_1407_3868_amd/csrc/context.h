@@ -136,6 +136,7 @@ struct mpsl_ctx {
   mpsl::DBuf sigma;       // double2[2 * ns]
   mpsl::DBuf Up64, Up32;  // [2][ns][P]: S2L coefficients scaled by c_q sigma
   mpsl::DBuf xbuf, ybuf;  // host-pointer apply staging
+  mpsl::DBuf bt;          // multi-RHS M2L: beta transposed to [n][P][r]
   mpsl::DBuf gm;          // GMRES workspace
   mpsl::DBuf scal;        // reductions
 

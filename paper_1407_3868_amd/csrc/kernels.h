@@ -22,6 +22,12 @@ constexpr int kM2LHalves = 1;
 // nrhs right-hand sides: beta [nrhs][n][P]; part of rhs r at part + r * pstride.
 int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant = -1,
                int nrhs = 1, int64_t pstride = 0);
+// Row a1, many right-hand sides (FP32, MFMA): beta [nrhs][n][P]; partials
+// of right-hand side r at part + r * pstride, chunks slots each.
+int launch_m2l_mrhs(mpsl_ctx *ctx, const void *beta, void *part, int chunks, int nrhs, int64_t pstride);
+int chunks_m2l_mrhs(const mpsl_ctx *ctx, int nrhs);
+// Right-hand sides from which the multi-RHS M2L runs on the matrix cores.
+constexpr int kMrhsMin = 16;
 // FMM near field (pairs in the same or adjacent leaf boxes) into out [n][P].
 int launch_fmm_near(mpsl_ctx *ctx, int prec, const void *beta, void *out);
 // Row b1: M2S partial spectra and their reduction to spec (double2[2*ns]).

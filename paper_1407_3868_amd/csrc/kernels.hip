@@ -534,6 +534,158 @@ __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Row a1 for many right-hand sides on the matrix cores (FP32): per pair the
+// Toeplitz translation T^{ml}[n'][nu] = h_{nu-n'} is built once and applied to
+// the coefficients of 64 right-hand sides as a GEMM  alpha_l[n'][r] +=
+// sum_nu T[n'][nu] beta_m[nu][r]  with 16x16x4 MFMA (M = n', K = nu, N = r),
+// the complex product as four real chains.  One wave per target, kMrhsWaves
+// targets per block, grid.y source chunks, grid.z groups of 64 right-hand
+// sides.  Lanes 0..7 of each wave run the Hankel recurrences of 8 sources
+// at a time (from the pair table, as in k_m2l) into zero-padded LDS rows;
+// the A operand is read from there.  The B operand, beta transposed to
+// [m][nu][r] (r fastest, zero rows and columns as padding), is staged per
+// source in LDS for all waves of the block, double-buffered: the next
+// source's loads are in flight during the current source's MFMAs.
+constexpr int kMrhsWaves = 8;
+constexpr int kMrhsBatch = 8;
+
+template <int p>
+__global__ __launch_bounds__(64 * kMrhsWaves) void k_m2l_mrhs(const float2 *__restrict__ pairs,
+                                                              const float2 *__restrict__ bt,
+                                                              float2 *__restrict__ part, int n, int chunk_len,
+                                                              int nrhs, int r_pad, int64_t pstride) {
+  constexpr int P = 2 * p + 1;
+  constexpr int MT = (P + 15) / 16;
+  constexpr int KP = (P + 3) / 4 * 4;
+  constexpr int NT = 4;                      // 64 right-hand sides per block
+  constexpr int OFF = 16 * MT - 1;           // H index of q = k - row is q + OFF
+  constexpr int HQ = KP + OFF;               // zero outside |q| <= 2p
+  constexpr int BE = KP * 64;                // B entries of one source
+  constexpr int BL = (BE + 64 * kMrhsWaves - 1) / (64 * kMrhsWaves);  // loads per thread
+  __shared__ float2 H[kMrhsWaves][kMrhsBatch][HQ];
+  __shared__ float2 Bs[2][KP][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l = blockIdx.x * kMrhsWaves + w;
+  const int c = blockIdx.y;
+  const int r0 = blockIdx.z * 64;
+  const int m0 = c * chunk_len;
+  const int m1 = min(n, m0 + chunk_len);
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  v4 are[MT][NT], aim[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) are[mt][ct] = aim[mt][ct] = v4{0, 0, 0, 0};
+  const int col = lane & 15, kq = lane >> 4;
+  // B of source m: rows k (zero rows k >= P in bt), 64 right-hand sides
+  float2 pre[BL];
+  auto load_b = [&](int m) {
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int e = threadIdx.x + 64 * kMrhsWaves * i;
+      pre[i] = (m < m1 && e < BE) ? bt[(static_cast<int64_t>(m) * KP + e / 64) * r_pad + r0 + (e & 63)]
+                                  : make_float2(0.f, 0.f);
+    }
+  };
+  auto store_b = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int e = threadIdx.x + 64 * kMrhsWaves * i;
+      if (e < BE) Bs[buf][e / 64][e & 63] = pre[i];
+    }
+  };
+  load_b(m0);
+  int it = 0;
+  for (int mb = m0; mb < m1; mb += kMrhsBatch) {
+    const int sb = min(kMrhsBatch, m1 - mb);
+    for (int i = lane; i < kMrhsBatch * HQ; i += 64) H[w][i / HQ][i % HQ] = make_float2(0.f, 0.f);
+    __syncthreads();
+    if (lane < sb) {  // h_q of pair (mb + lane -> l), q = -2p..2p
+      const int m = mb + lane;
+      float2 *h = H[w][lane] + OFF;
+      if (l < n && m != l) {
+        const float2 *pe = pairs + 4 * (static_cast<int64_t>(m) * n + l);
+        cx<float> hp = ld<float>(pe[0]), hc = ld<float>(pe[1]);
+        const cx<float> t = ld<float>(pe[2]);
+        const float tz = pe[3].x;
+        h[0] = st(hp);
+        cx<float> tq = t;
+        for (int q = 1; q <= 2 * p; ++q) {
+          if (q >= 2) {
+            const cx<float> hn = static_cast<float>(q - 1) * tz * hc - hp;
+            hp = hc;
+            hc = hn;
+            tq = tq * t;
+          }
+          h[q] = st(hc * tq);
+          cx<float> hm = hc * conj(tq);
+          if (q & 1) hm = mk<float>(-hm.re, -hm.im);
+          h[-q] = st(hm);
+        }
+      }
+    }
+    for (int s = 0; s < sb; ++s, ++it) {
+      const int buf = it & 1;
+      store_b(buf);          // B of source mb + s (loaded one iteration ahead)
+      __syncthreads();
+      load_b(mb + s + 1);    // next source's B in flight during the MFMAs
+      const float2 *hrow = H[w][s];
+#pragma unroll
+      for (int k0 = 0; k0 < KP; k0 += 4) {
+        const int k = k0 + kq;
+        float br[NT], bi[NT];
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          const float2 bv = Bs[buf][k][ct * 16 + col];
+          br[ct] = bv.x;
+          bi[ct] = bv.y;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const float2 a = hrow[k - (mt * 16 + col) + OFF];
+#pragma unroll
+          for (int ct = 0; ct < NT; ++ct) {
+            are[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, br[ct], are[mt][ct], 0, 0, 0);
+            are[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, bi[ct], are[mt][ct], 0, 0, 0);
+            aim[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bi[ct], aim[mt][ct], 0, 0, 0);
+            aim[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, br[ct], aim[mt][ct], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (l >= n) return;
+  // result register j of lane i: row 4 (i / 16) + j, column i % 16
+  const int64_t len = static_cast<int64_t>(n) * P;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = mt * 16 + 4 * kq + j;
+        const int r = r0 + ct * 16 + col;
+        if (row < P && r < nrhs)
+          part[r * pstride + c * len + static_cast<int64_t>(l) * P + row] = make_float2(are[mt][ct][j], aim[mt][ct][j]);
+      }
+}
+
+// beta [r][m][P] -> bt [m][KP][r_pad] (r fastest; zero rows k >= P and
+// zero columns r >= nrhs), FP32.
+__global__ void k_rhs_transpose(const float2 *__restrict__ x, float2 *__restrict__ bt, int n, int P, int KP,
+                                int nrhs, int r_pad) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const int64_t rows = static_cast<int64_t>(n) * KP;
+  if (i >= rows * r_pad) return;
+  const int64_t row = i / r_pad;
+  const int r = static_cast<int>(i % r_pad);
+  const int m = static_cast<int>(row / KP), k = static_cast<int>(row % KP);
+  bt[i] = (r < nrhs && k < P) ? x[r * static_cast<int64_t>(n) * P + static_cast<int64_t>(m) * P + k]
+                              : make_float2(0.f, 0.f);
+}
+
+// ---------------------------------------------------------------------------
 // GMRES helpers, FP64 complex.
 constexpr int kDotBlocks = 64;
 constexpr int kRed = 256;
@@ -805,6 +957,38 @@ int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks
   if (variant < 0) variant = ctx->tune[prec == MPSL_FP64 ? 0 : 1].variant;
   return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks, variant, nrhs, pstride)
                            : launch_m2l_t<float>(ctx, beta, part, chunks, variant, nrhs, pstride);
+}
+
+int chunks_m2l_mrhs(const mpsl_ctx *ctx, int nrhs) {
+  const int64_t blocks = static_cast<int64_t>(cdiv(ctx->n, kMrhsWaves)) * cdiv(nrhs, 64);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, blocks), cdiv(ctx->n, kMrhsBatch))));
+}
+
+int launch_m2l_mrhs(mpsl_ctx *ctx, const void *beta, void *part, int chunks, int nrhs, int64_t pstride) {
+  const int n = static_cast<int>(ctx->n);
+  const int P = 2 * ctx->p + 1;
+  const int KP = (P + 3) / 4 * 4;
+  const int64_t rows = static_cast<int64_t>(n) * KP;
+  const int r_pad = 64 * cdiv(nrhs, 64);
+  int rc = dev_alloc(ctx, ctx->bt, static_cast<size_t>(rows) * r_pad * sizeof(float2));
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rhs_transpose, dim3(cdiv(rows * r_pad, 256)), dim3(256), 0, ctx->stream,
+                     static_cast<const float2 *>(beta), static_cast<float2 *>(ctx->bt.p), n, P, KP, nrhs, r_pad);
+  LAUNCH_CHECK(ctx);
+  const int chunk_len = cdiv(n, chunks);
+  const dim3 grid(cdiv(n, kMrhsWaves), chunks, r_pad / 64);
+  const auto *pairs = static_cast<const float2 *>(ctx->gt.pair32.p);
+  const auto *bt = static_cast<const float2 *>(ctx->bt.p);
+  auto *pp = static_cast<float2 *>(part);
+  switch (ctx->p) {
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_m2l_mrhs<PP>), grid, dim3(64 * kMrhsWaves), 0, ctx->stream, pairs, bt, pp, n, chunk_len, nrhs, r_pad, pstride); break;
+    MPSL_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
 }
 
 template <typename T>

@@ -20,7 +20,7 @@ def torch():
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("nrhs", [1, 3, 8])
+@pytest.mark.parametrize("nrhs", [1, 3, 8, 16, 40, 70])
 def test_multi_rhs_matvec(prec, nrhs, torch):
     wl = make_workload("s150p12")
     pr = oracle_problem(wl)
