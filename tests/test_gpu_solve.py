@@ -95,3 +95,39 @@ def test_bad_inputs_are_rejected():
     with pytest.raises(mp.MpslError) as e:
         ctx.apply(0, np.zeros((1, 17), complex))                 # nothing set up yet
     assert e.value.status == -4
+
+
+def test_flux_balance_of_library_solution():
+    """The library's FP64 solve and field evaluation conserve power:
+    int_C Im(conj(u) du/dn) ds = 1/4 + Im u_s(x_s) on a rectangle around the
+    source and the particles that crosses both interfaces (512 contour nodes,
+    where the discrete model conserves power to ~2e-11)."""
+    from scipy.special import hankel1
+    from test_oracle_system import _gl_panels
+    wl = make_workload("c1")
+    wl.n_nodes = 512
+    ctx = gpu_context(wl, disk_from_library=True)
+    src = wl.src[0]
+    beta, meta = ctx.solve(src, precision=0, tol=1e-13, maxiter=400)
+    assert meta["status"] == 0
+    xa, xb, ya, yb = -6.0, 6.0, -wl.d - 2.0, 4.0
+    h = 5e-4
+    flux = 0.0
+    for side in range(4):
+        if side < 2:
+            t, wt = _gl_panels(xa, xb, (), 0.25)
+            pts = np.stack([t, np.full_like(t, ya if side == 0 else yb)], axis=1)
+            nvec = np.array([0.0, -1.0 if side == 0 else 1.0])
+        else:
+            t, wt = _gl_panels(ya, yb, (0.0, -wl.d), 0.25)
+            pts = np.stack([np.full_like(t, xa if side == 2 else xb), t], axis=1)
+            nvec = np.array([-1.0 if side == 2 else 1.0, 0.0])
+        f = [ctx.eval_field(src, beta, pts + s * h * nvec) for s in (-2, -1, 1, 2)]
+        du = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+        u = ctx.eval_field(src, beta, pts)
+        flux += float(np.sum(wt * np.imag(np.conj(u) * du)))
+    e = 1e-5
+    offs = np.array([[e, 0.0], [-e, 0.0], [0.0, e], [0.0, -e]])
+    us = ctx.eval_field(src, beta, src[None, :] + offs) - 0.25j * hankel1(0, wl.k1 * e)
+    expect = 0.25 + float(np.mean(us).imag)
+    assert abs(flux - expect) < 1e-9, (flux, expect)
