@@ -149,3 +149,36 @@ def test_flux_balance_lossless():
     us = pr.field(src, beta, src[None, :] + offs) - 0.25j * hankel1(0, wl.k1 * e)
     expect = 0.25 + float(np.mean(us).imag)
     assert abs(flux - expect) < 1e-9, (flux, expect)
+
+
+def test_single_disk_matches_mie_series():
+    """One disk in a homogeneous medium (k1 = k2 = k3) lit by the point source:
+    the total field outside the disk is G + sum_n S_n a_n H_n(kr) e^{in theta}
+    with the Mie coefficients S_n and Graf's incident coefficients
+    a_n = (i/4) H_n(k r_s) e^{-in theta_s} (|n| <= 40), independently of the
+    layered formulation, its contour and its solver."""
+    k, R, kp, d = 9.0, 0.25, 15.0, 8.0
+    c = np.array([0.3, -3.0])
+    src = np.array([-0.2, 2.0])
+    lam, w = contour.contour(96 + 32 * 50, 0.2, 60.0, [k, k, k])
+    p = 16
+    S = np.diag(mie.disk_smatrix(R, k, kp, p))
+    pr = system.Problem(k, k, k, d, p, S, c[None, :], np.zeros(1), lam, w)
+    beta = pr.solve_lu(src)
+    rng = np.random.default_rng(7)
+    ang = rng.uniform(0, 2 * np.pi, 24)
+    rad = rng.uniform(0.4, 2.5, 24)
+    rcv = c[None, :] + np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
+    rcv = rcv[np.hypot(rcv[:, 0] - src[0], rcv[:, 1] - src[1]) > 0.3]
+    got = pr.field(src, beta, rcv)
+    q = 40
+    n = np.arange(-q, q + 1)
+    rs, ths = np.hypot(*(src - c)), np.arctan2(*(src - c)[::-1])
+    a = 0.25j * hankel1(n, k * rs) * np.exp(-1j * n * ths)
+    Sq = mie.disk_smatrix(R, k, kp, q)
+    r = np.hypot(rcv[:, 0] - c[0], rcv[:, 1] - c[1])
+    th = np.arctan2(rcv[:, 1] - c[1], rcv[:, 0] - c[0])
+    scat = (hankel1(n[None, :], k * r[:, None]) * np.exp(1j * n[None, :] * th[:, None])) @ (Sq * a)
+    exact = 0.25j * hankel1(0, k * np.hypot(rcv[:, 0] - src[0], rcv[:, 1] - src[1])) + scat
+    err = np.max(np.abs(got - exact)) / np.max(np.abs(exact))
+    assert err < 1e-11, err
