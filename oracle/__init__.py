@@ -18,9 +18,11 @@ operators  M2L (Section 3.2, Lemma 3.1), M2S (Section 5.3, Theorem 5.1),
            S2L (Section 5.2.1, Lemma 5.1 / eq. (40)), rotated S (Section 4.1)
 system     Schur-complement system (Section 5.4, eq. (49)), dense LU solve,
            matrix-free matvec and GMRES, field evaluation (eq. (36))
+stack      the same system for any number of layers (interface conditions
+           (8)-(9) at every interface)
 
 Parity status of every function is listed in its docstring; the pins live in
 ``tests/test_oracle_*.py``.
 """
 
-__all__ = ["mie", "star", "contour", "layered", "operators", "system"]
+__all__ = ["mie", "star", "contour", "layered", "operators", "system", "stack"]
