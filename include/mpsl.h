@@ -81,9 +81,41 @@ void mpsl_destroy(mpsl_ctx *ctx);
  * stream); NULL selects the device's null stream. */
 int mpsl_set_stream(mpsl_ctx *ctx, void *stream);
 
-/* Layer wavenumbers and middle-layer thickness d > 0 (Section 1, Fig. 1).
- * Re k > 0 and Im k >= 0 (Section 3.1); this build requires Im k2 == 0. */
+/* Layer wavenumbers and middle-layer thickness d > 0 (Section 1, Fig. 1):
+ * the three-layer case of mpsl_set_layer_stack (k = {k1, k2, k3}, particle
+ * layer 1, interfaces y = 0 and y = -d).  Real k > 0 (this build requires
+ * Im k == 0 for every layer). */
 int mpsl_set_layers(mpsl_ctx *ctx, mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, double d);
+
+/* A stack of n_layers (3..64) layers, top to bottom, TM polarisation: the
+ * extension of Section 2 to any number of layers that the Introduction names,
+ * with u and du/dy continuous across every interface (eqs. (8)-(9)).
+ * k[j] (host, n_layers entries): wavenumber of layer j, real and > 0.
+ * thickness[j] (host, n_layers entries): thickness of the finite layer j
+ * (1 <= j <= n_layers - 2, > 0); entries 0 and n_layers - 1 (the two
+ * half-spaces) are ignored.  particle_layer c (1..n_layers - 2): the finite
+ * layer holding the particles; its top interface is y = 0 and its bottom
+ * y = -thickness[c], so particle geometry is given as for three layers and
+ * the other interfaces sit at y_i = sum of the thicknesses in between.  The
+ * point source of mpsl_rhs / mpsl_solve / mpsl_eval_field lies in layer 0,
+ * above the top interface.  The particle layer's densities keep the 2 x 2
+ * coupling of eq. (10) through generalized reflection coefficients of the
+ * layers above and below (host FP64 per contour node); the matvec's kernels
+ * and cost do not depend on n_layers.  Returns MPSL_EINVAL for a bad count,
+ * layer index, thickness or wavenumber, MPSL_EUNSUPPORTED for Im k != 0. */
+int mpsl_set_layer_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const double *thickness,
+                         int particle_layer);
+
+/* Host, no device: the per-node map that mpsl_set_layer_stack's stack gives
+ * the particle layer's densities (Section 2, eq. (10) and its extension to
+ * more layers), for n_lam nodes lam (host).  map (host, 6 * n_lam entries):
+ * map[6q + 0..3] = the 2 x 2 matrix, row-major, taking the particles' spectra
+ * (P+, P-) on the two interfaces of the particle layer to (sigma+, sigma-);
+ * map[6q + 4..5] = (sigma+, sigma-) per unit source amplitude at the top
+ * interface.  These are the values the device reflection step applies.
+ * Same argument rules and errors as mpsl_set_layer_stack. */
+int mpsl_compute_layer_map(int n_layers, const mpsl_c128 *k, const double *thickness, int particle_layer,
+                           int n_lam, const mpsl_c128 *lam, mpsl_c128 *map);
 
 /* Circular particles of radius R and wavenumber kp (real, > 0): the diagonal
  * Mie scattering matrix of Section 3.1, eqs. (17)-(18), order p (1..32).

@@ -80,6 +80,21 @@ def compute_contour(k1, k2, k3, n_nodes, b, t_max):
     return lam, w
 
 
+def compute_layer_map(ks, thickness, particle_layer, lam):
+    """Host: per-node map of a layer stack (mirrors mpsl_compute_layer_map),
+    (n_lam, 6): the 2 x 2 reflection map row-major, then the source factors."""
+    lib = _lib.load()
+    k = _carr(ks)
+    t = np.ascontiguousarray(thickness, dtype=np.float64)
+    if t.shape != k.shape:
+        raise ValueError("one thickness per layer")
+    lam = _carr(np.atleast_1d(lam))
+    out = np.zeros((lam.size, 6), np.complex128)
+    _host_check(lib.mpsl_compute_layer_map(int(k.size), k.ctypes.data, t.ctypes.data, int(particle_layer),
+                                           int(lam.size), lam.ctypes.data, out.ctypes.data), "layer map")
+    return out
+
+
 class Batch:
     """A captured multi-configuration batch of matvecs (mpsl_batch_*)."""
 
@@ -150,6 +165,17 @@ class Context:
 
     def set_layers(self, k1, k2, k3, d):
         return self._check(self.lib.mpsl_set_layers(self.h, _c(k1), _c(k2), _c(k3), float(d)))
+
+    def set_layer_stack(self, ks, thickness, particle_layer):
+        """Layers top to bottom (mpsl_set_layer_stack): wavenumbers ks, one
+        thickness per layer (the half-space entries are ignored), particles in
+        layer ``particle_layer``."""
+        k = _carr(ks)
+        t = np.ascontiguousarray(thickness, dtype=np.float64)
+        if t.shape != k.shape:
+            raise ValueError("one thickness per layer")
+        return self._check(self.lib.mpsl_set_layer_stack(self.h, int(k.size), k.ctypes.data, t.ctypes.data,
+                                                         int(particle_layer)))
 
     def set_particle_disk(self, R, kp, p):
         return self._check(self.lib.mpsl_set_particle_disk(self.h, float(R), _c(kp), int(p)))

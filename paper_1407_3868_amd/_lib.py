@@ -40,6 +40,8 @@ SIGNATURES = {
     "mpsl_destroy": (None, [P]),
     "mpsl_set_stream": (I, [P, P]),
     "mpsl_set_layers": (I, [P, c128, c128, c128, D]),
+    "mpsl_set_layer_stack": (I, [P, I, P, P, I]),
+    "mpsl_compute_layer_map": (I, [I, P, P, I, I, P, P]),
     "mpsl_set_particle_disk": (I, [P, D, c128, I]),
     "mpsl_set_particle_star": (I, [P, D, D, I, c128, I, I]),
     "mpsl_set_scattering_matrix": (I, [P, I, D, P]),

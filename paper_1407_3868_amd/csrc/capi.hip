@@ -117,13 +117,6 @@ bool panel_rule(int n_pan, double b, double t_max, const std::vector<double> &ks
   return true;
 }
 
-// gamma = sqrt(lam^2 - k^2), Re >= 0, and Im <= 0 on Re == 0.
-zc gamma_branch(zc lam, zc k) {
-  zc g = std::sqrt(lam * lam - k * k);
-  if (g.real() < 0.0) g = -g;
-  if (g.real() == 0.0 && g.imag() > 0.0) g = -g;
-  return g;
-}
 
 // Bessel J_n, Y_n of real argument for n >= 0 (C library), and derivatives.
 void bessel_jy(int n, double x, double &j, double &y, double &jp, double &yp) {
@@ -231,8 +224,13 @@ int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_
   return MPSL_OK;
 }
 
-namespace {
-}  // namespace
+// gamma = sqrt(lam^2 - k^2), Re >= 0, and Im <= 0 on Re == 0.
+zc gamma_branch(zc lam, zc k) {
+  zc g = std::sqrt(lam * lam - k * k);
+  if (g.real() < 0.0) g = -g;
+  if (g.real() == 0.0 && g.imag() > 0.0) g = -g;
+  return g;
+}
 
 // Contour tables (host, FP64) and geometry tables (device).
 int build_tables(mpsl_ctx *ctx) {
@@ -244,7 +242,6 @@ int build_tables(mpsl_ctx *ctx) {
   const int P = 2 * p + 1;
   const int64_t n = ctx->n;
   const zc k1 = ctx->k1, k2 = ctx->k2, k3 = ctx->k3;
-  const double d = ctx->d;
   const zc I(0.0, 1.0);
 
   std::vector<zc> R(4 * ns), sf(2 * ns), gw(4 * ns), cq(ns), W(2 * ns * P), U(2 * ns * P);
@@ -255,19 +252,11 @@ int build_tables(mpsl_ctx *ctx) {
     gw[ns + q] = g2;
     gw[2 * ns + q] = g3;
     gw[3 * ns + q] = ctx->w[q];
-    // closed-form solution of the 4x4 interface system for the middle-layer
-    // densities: sigma+ - r1 E sigma- = t g + r1 P+,  sigma- - r3 E sigma+ = r3 P-
-    const zc r1 = (g2 - g1) / (g2 + g1);
-    const zc r3 = (g2 - g3) / (g2 + g3);
-    const zc E = std::exp(-g2 * d);
-    const zc det = 1.0 - r1 * r3 * E * E;
-    const zc tg = 2.0 * g2 / (g1 + g2);
-    R[4 * q + 0] = r1 / det;
-    R[4 * q + 1] = r1 * r3 * E / det;
-    R[4 * q + 2] = r1 * r3 * E / det;
-    R[4 * q + 3] = r3 / det;
-    sf[2 * q + 0] = tg / det;
-    sf[2 * q + 1] = tg * r3 * E / det;
+    zc m[6];
+    layer_map(ctx, lam, m);
+    for (int i = 0; i < 4; ++i) R[4 * q + i] = m[i];
+    sf[2 * q + 0] = m[4];
+    sf[2 * q + 1] = m[5];
     cq[q] = ctx->w[q] / (4.0 * M_PI * g2);
     // u = (lam - g2)/k2 and v = (lam + g2)/k2 = 1/u; take the larger of lam +- g2
     // directly and the other as k2^2 / (...) to avoid cancellation.
@@ -490,24 +479,40 @@ int mpsl_set_stream(mpsl_ctx *ctx, void *stream) {
   return MPSL_OK;
 }
 
-int mpsl_set_layers(mpsl_ctx *ctx, mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, double d) {
+int mpsl_set_layer_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const double *thickness,
+                         int particle_layer) {
   if (!ctx) return MPSL_EINVAL;
-  const mpsl_c128 ks[3] = {k1, k2, k3};
-  for (const auto &k : ks) {
-    if (!(k.re > 0.0) || !(k.im >= 0.0) || !std::isfinite(k.re) || !std::isfinite(k.im))
-      return mpsl::set_err(ctx, MPSL_EINVAL, "wavenumbers need Re k > 0 and Im k >= 0");
-    if (k.im != 0.0)
-      return mpsl::set_err(ctx, MPSL_EUNSUPPORTED, "this build supports real layer wavenumbers only");
-  }
-  if (!(d > 0.0) || !std::isfinite(d)) return mpsl::set_err(ctx, MPSL_EINVAL, "layer thickness must be > 0");
-  ctx->k1 = zc(k1.re, k1.im);
-  ctx->k2 = zc(k2.re, k2.im);
-  ctx->k3 = zc(k3.re, k3.im);
-  ctx->d = d;
+  std::string err;
+  const int rc = mpsl::assign_stack(ctx, n_layers, k, thickness, particle_layer, err);
+  if (rc) return mpsl::set_err(ctx, rc, err);
   ctx->has_layers = true;
   ctx->gt.pairs_ok = false;
   mpsl::invalidate(ctx);
   return MPSL_OK;
+}
+
+int mpsl_compute_layer_map(int n_layers, const mpsl_c128 *k, const double *thickness, int particle_layer,
+                           int n_lam, const mpsl_c128 *lam, mpsl_c128 *map) {
+  if (!lam || !map || n_lam <= 0) return MPSL_EINVAL;
+  mpsl_ctx tmp;
+  std::string err;
+  const int rc = mpsl::assign_stack(&tmp, n_layers, k, thickness, particle_layer, err);
+  if (rc) return rc;
+  for (int q = 0; q < n_lam; ++q) {
+    const zc l(lam[q].re, lam[q].im);
+    if (!std::isfinite(l.real()) || !std::isfinite(l.imag())) return MPSL_EINVAL;
+    zc m[6];
+    mpsl::layer_map(&tmp, l, m);
+    for (int i = 0; i < 6; ++i) map[6 * q + i] = {m[i].real(), m[i].imag()};
+  }
+  return MPSL_OK;
+}
+
+int mpsl_set_layers(mpsl_ctx *ctx, mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, double d) {
+  if (!ctx) return MPSL_EINVAL;
+  const mpsl_c128 ks[3] = {k1, k2, k3};
+  const double th[3] = {0.0, d, 0.0};
+  return mpsl_set_layer_stack(ctx, 3, ks, th, 1);
 }
 
 static int upload_S(mpsl_ctx *ctx) {
@@ -646,7 +651,9 @@ int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max) {
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> lam, w;
   std::string err;
-  const int rc = mpsl::make_contour({ctx->k1.real(), ctx->k2.real(), ctx->k3.real()}, n_nodes, b, t_max, lam, w, err);
+  std::vector<double> kr;
+  for (const zc &k : ctx->ks) kr.push_back(k.real());
+  const int rc = mpsl::make_contour(kr, n_nodes, b, t_max, lam, w, err);
   if (rc) return mpsl::set_err(ctx, rc, err);
   ctx->lam = lam;
   ctx->w = w;

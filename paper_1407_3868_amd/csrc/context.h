@@ -99,10 +99,15 @@ struct mpsl_ctx {
   hipStream_t stream = nullptr;
   std::string err;
 
-  // layers
+  // layers, top to bottom: wavenumbers, thicknesses of the finite layers
+  // (half-space entries unused), interface heights y_0 > ... > y_{L-2}, and
+  // the particle layer c whose interfaces are y = 0 and y = -d
   bool has_layers = false;
-  mpsl::zc k1, k2, k3;
-  double d = 0.0;
+  std::vector<mpsl::zc> ks;
+  std::vector<double> thick, yint;
+  int layer_c = 1;
+  mpsl::zc k1, k2, k3;  // top half-space, particle layer, bottom half-space
+  double d = 0.0;       // particle-layer thickness
 
   // particle
   bool has_particle = false;
@@ -163,6 +168,26 @@ int set_err(mpsl_ctx *ctx, int code, const std::string &msg);
 int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, std::vector<zc> &S, std::string &err);
 int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry,
                          std::vector<zc> &S, std::string &err);
+// Layer stack per contour node lam (host, FP64).  Rup: generalized
+// reflection of the layers above the particle layer for an upgoing wave at
+// y = 0; Rdn: that of the layers below for a downgoing wave at y = -d; T:
+// downgoing amplitude at y = 0 per unit source amplitude at the top interface
+// when nothing comes up from below.  Amplitudes are divided by gamma of their
+// layer, as in the spectral representation of Section 5.2.
+void stack_node(const mpsl_ctx *ctx, zc lam, zc &Rup, zc &Rdn, zc &T);
+// Per-layer plane-wave amplitudes for field evaluation: A[j] the downgoing
+// wave at the top interface of layer j, B[j] the upgoing one at its bottom
+// (A[0] = B[L-1] = 0), g[j] gamma of layer j, from the particle-layer
+// densities sp, sm, the particle spectra Pp, Pm and the source amplitude gs.
+void stack_amplitudes(const mpsl_ctx *ctx, zc lam, zc gs, zc sp, zc sm, zc Pp, zc Pm, zc *A, zc *B, zc *g);
+// The 2 x 2 map (P+, P-) -> (sigma+, sigma-) row-major in m[0..3] and the
+// source factors in m[4..5] (sigma+/- per unit source amplitude).
+void layer_map(const mpsl_ctx *ctx, zc lam, zc m[6]);
+// Validate a layer stack and store it with its interface heights in ctx.
+int assign_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const double *thickness, int particle_layer,
+                 std::string &err);
+zc gamma_branch(zc lam, zc k);
+constexpr int kMaxLayers = 64;
 int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_max, std::vector<zc> &lam,
                  std::vector<zc> &w, std::string &err);
 int build_tables(mpsl_ctx *ctx);

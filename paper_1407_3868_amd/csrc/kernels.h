@@ -62,9 +62,11 @@ int launch_to_fp64(mpsl_ctx *ctx, const void *x32, void *x64, int64_t len);
 // Deterministic pseudo-random complex vector (n_complex entries) in precision prec.
 int launch_fill_hash(mpsl_ctx *ctx, int prec, void *v, int64_t n_complex, uint32_t seed);
 
-// Row a7: field at receivers.  sig4: double2[4][ns] (sigma_1, sigma_2^+, sigma_2^-, sigma_3).
-int launch_field(mpsl_ctx *ctx, const void *beta, const void *sig4, const double *src, int64_t nr,
-                 const void *rcv, void *u);
+// Row a7: field at receivers.  gl: double2[L][ns] gamma per layer; amp:
+// double2[L][2][ns] downgoing amplitude at the top and upgoing at the bottom
+// of each layer; yint: double[L-1] interface heights (all device).
+int launch_field(mpsl_ctx *ctx, const void *beta, const void *gl, const void *amp, const void *yint,
+                 const double *src, int64_t nr, const void *rcv, void *u);
 
 // Source chunks of the M2L grid for precision prec (tuned, set, or automatic).
 int chunks_m2l(const mpsl_ctx *ctx, int prec);

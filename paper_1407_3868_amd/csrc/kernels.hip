@@ -794,51 +794,46 @@ __global__ void k_to64(const float2 *__restrict__ a, double2 *__restrict__ b, in
 // Row a7: total field at receivers (eq. (36)), FP64.
 __global__ void k_field(const double2 *__restrict__ xy, const double2 *__restrict__ beta, int n, int p,
                         const double2 *__restrict__ lam, const double2 *__restrict__ w,
-                        const double2 *__restrict__ g1, const double2 *__restrict__ g2,
-                        const double2 *__restrict__ g3, const double2 *__restrict__ sig4, int ns,
-                        double k1, double k2, double d, double r_enc, double xs, double ys,
-                        const double2 *__restrict__ rcv, int64_t nr, double2 *__restrict__ u) {
+                        const double2 *__restrict__ gl, const double2 *__restrict__ amp,
+                        const double *__restrict__ yint, int L, int c, int ns, double k0, double kc, double r_enc,
+                        double xs, double ys, const double2 *__restrict__ rcv, int64_t nr,
+                        double2 *__restrict__ u) {
   const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (r >= nr) return;
   const double X = rcv[r].x, Y = rcv[r].y;
-  const int layer = (Y > 0.0) ? 1 : ((Y < -d) ? 3 : 2);
+  // layer of the receiver: interfaces above it; the particle layer keeps y = 0
+  int layer = 0;
+  for (int i = 0; i < L - 1; ++i) layer += (Y < yint[i]) ? 1 : 0;
+  if (Y == yint[c - 1]) layer = c;
+  const bool hasA = layer > 0, hasB = layer < L - 1;
+  const double ta = hasA ? Y - yint[layer - 1] : 0.0;  // <= 0
+  const double tb = hasB ? Y - yint[layer] : 0.0;      // >= 0
+  const double2 *g = gl + static_cast<int64_t>(layer) * ns;
+  const double2 *A = amp + static_cast<int64_t>(2 * layer) * ns;
+  const double2 *B = A + ns;
   cx<double> acc = mk(0.0, 0.0);
   for (int q = 0; q < ns; ++q) {
     const double lr = lam[q].x, li = lam[q].y;
-    const cx<double> wq = ld<double>(w[q]);
-    if (layer == 1) {
-      const cx<double> g = ld<double>(g1[q]);
-      const cx<double> e = cexp_d(-li * X - g.re * Y, lr * X - g.im * Y);
-      const cx<double> inv = mk(g.re, -g.im);
-      const double nn = g.re * g.re + g.im * g.im;
-      acc = acc + (1.0 / nn) * (wq * e * inv * ld<double>(sig4[q]));
-    } else if (layer == 3) {
-      const cx<double> g = ld<double>(g3[q]);
-      const cx<double> e = cexp_d(-li * X + g.re * (Y + d), lr * X + g.im * (Y + d));
-      const double nn = g.re * g.re + g.im * g.im;
-      acc = acc + (1.0 / nn) * (wq * e * mk(g.re, -g.im) * ld<double>(sig4[3 * ns + q]));
-    } else {
-      const cx<double> g = ld<double>(g2[q]);
-      const cx<double> ep = cexp_d(-li * X + g.re * Y, lr * X + g.im * Y);
-      const cx<double> em = cexp_d(-li * X - g.re * (Y + d), lr * X - g.im * (Y + d));
-      const double nn = g.re * g.re + g.im * g.im;
-      const cx<double> s = ep * ld<double>(sig4[ns + q]) + em * ld<double>(sig4[2 * ns + q]);
-      acc = acc + (1.0 / nn) * (wq * mk(g.re, -g.im) * s);
-    }
+    const cx<double> gq = ld<double>(g[q]);
+    cx<double> s = mk(0.0, 0.0);
+    if (hasA) s = s + ld<double>(A[q]) * cexp_d(-li * X + gq.re * ta, lr * X + gq.im * ta);
+    if (hasB) s = s + ld<double>(B[q]) * cexp_d(-li * X - gq.re * tb, lr * X - gq.im * tb);
+    const double nn = gq.re * gq.re + gq.im * gq.im;
+    acc = acc + (1.0 / nn) * (ld<double>(w[q]) * mk(gq.re, -gq.im) * s);
   }
   acc = (1.0 / (4.0 * M_PI)) * acc;
   bool inside = false;
-  if (layer == 1) {
+  if (layer == 0) {
     const double dx = X - xs, dy = Y - ys;
-    const double z = k1 * sqrt(dx * dx + dy * dy);
+    const double z = k0 * sqrt(dx * dx + dy * dy);
     acc = acc + mk(0.0, 0.25) * mk(j0(z), y0(z));
-  } else if (layer == 2) {
+  } else if (layer == c) {
     const int P = 2 * p + 1;
     for (int m = 0; m < n; ++m) {
       const double dx = X - xy[m].x, dy = Y - xy[m].y;
       const double rr = sqrt(dx * dx + dy * dy);
       if (rr < r_enc) inside = true;
-      const double z = k2 * rr;
+      const double z = kc * rr;
       const cx<double> t = mk(dx / rr, dy / rr);
       const double2 *b = beta + static_cast<int64_t>(m) * P;
       cx<double> hprev = mk(j0(z), y0(z));
@@ -1066,7 +1061,7 @@ int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sig
                      static_cast<const double2 *>(spec), static_cast<const double2 *>(ctx->ct.R.p),
                      static_cast<const double2 *>(ctx->ct.srcfac.p), static_cast<const double2 *>(ctx->ct.lam.p),
                      static_cast<const double2 *>(ctx->ct.gw.p), ns, src ? 1 : 0, src ? src[0] : 0.0,
-                     src ? src[1] : 0.0, static_cast<double2 *>(sigma));
+                     src ? src[1] - ctx->yint[0] : 0.0, static_cast<double2 *>(sigma));
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }
@@ -1217,15 +1212,15 @@ int launch_to_fp64(mpsl_ctx *ctx, const void *x32, void *x64, int64_t len) {
   return MPSL_OK;
 }
 
-int launch_field(mpsl_ctx *ctx, const void *beta, const void *sig4, const double *src, int64_t nr,
-                 const void *rcv, void *u) {
-  const double2 *g = static_cast<const double2 *>(ctx->ct.gw.p);
+int launch_field(mpsl_ctx *ctx, const void *beta, const void *gl, const void *amp, const void *yint,
+                 const double *src, int64_t nr, const void *rcv, void *u) {
   hipLaunchKernelGGL(k_field, dim3(cdiv(nr, 64)), dim3(64), 0, ctx->stream,
                      static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const double2 *>(beta),
                      static_cast<int>(ctx->n), ctx->p, static_cast<const double2 *>(ctx->ct.lam.p),
                      static_cast<const double2 *>(ctx->ct.gw.p) + 3 * ctx->ns,  // weights stored after g1,g2,g3
-                     g, g + ctx->ns, g + 2 * ctx->ns, static_cast<const double2 *>(sig4), ctx->ns,
-                     ctx->k1.real(), ctx->k2.real(), ctx->d, ctx->r_enc, src[0], src[1],
+                     static_cast<const double2 *>(gl), static_cast<const double2 *>(amp),
+                     static_cast<const double *>(yint), static_cast<int>(ctx->ks.size()), ctx->layer_c, ctx->ns,
+                     ctx->k1.real(), ctx->k2.real(), ctx->r_enc, src[0], src[1],
                      static_cast<const double2 *>(rcv), nr, static_cast<double2 *>(u));
   LAUNCH_CHECK(ctx);
   return MPSL_OK;

@@ -225,7 +225,8 @@ int mpsl_rhs(mpsl_ctx *ctx, const double *src, mpsl_c128 *rhs) {
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
-  if (!(src[1] > 0.0)) return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top layer (y > 0)");
+  if (!(src[1] > ctx->yint[0]))
+    return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top half-space (above the top interface)");
   const size_t bytes = static_cast<size_t>(ctx->n) * (2 * ctx->p + 1) * sizeof(double2);
   if ((rc = mpsl::dev_alloc(ctx, ctx->ybuf, bytes))) return rc;
   if ((rc = mpsl::rhs_device(ctx, src, ctx->ybuf.p))) return rc;
@@ -248,7 +249,8 @@ int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *
   int status = MPSL_OK;
   for (int r = 0; r < n_rhs; ++r) {
     const double *src = src_xy + 2 * r;
-    if (!(src[1] > 0.0)) return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top layer (y > 0)");
+    if (!(src[1] > ctx->yint[0]))
+      return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top half-space (above the top interface)");
     const auto t0 = std::chrono::steady_clock::now();
     if ((rc = mpsl::dev_alloc(ctx, ctx->ybuf, len * sizeof(double2)))) return rc;
     if ((rc = mpsl::rhs_device(ctx, src, ctx->ybuf.p))) return rc;
@@ -282,6 +284,8 @@ int mpsl_eval_field(mpsl_ctx *ctx, const double *src, const mpsl_c128 *beta, int
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
+  if (!(src[1] > ctx->yint[0]))
+    return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top half-space (above the top interface)");
   const int ns = ctx->ns;
   const int64_t len = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
   if ((rc = mpsl::dev_alloc(ctx, ctx->xbuf, len * sizeof(double2)))) return rc;
@@ -292,35 +296,38 @@ int mpsl_eval_field(mpsl_ctx *ctx, const double *src, const mpsl_c128 *beta, int
   MPSL_HIP_TRY(ctx, hipMemcpyAsync(spec.data(), ctx->spec.p, 2 * ns * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
   MPSL_HIP_TRY(ctx, hipMemcpyAsync(sig.data(), ctx->sigma.p, 2 * ns * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
   MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  // sigma_1 and sigma_3 from the interface conditions at y = 0 and y = -d
-  std::vector<zc> sig4(4 * ns);
+  // amplitudes of every layer from the interface conditions, outward from the
+  // particle layer (source amplitude referenced to the top interface)
+  const int L = static_cast<int>(ctx->ks.size());
+  std::vector<zc> gl(static_cast<size_t>(L) * ns), amp(static_cast<size_t>(2 * L) * ns);
+  std::vector<zc> A(L), B(L), g(L);
   const zc I(0.0, 1.0);
   for (int q = 0; q < ns; ++q) {
     const zc lam = ctx->lam[q];
-    auto br = [](zc l, zc k) {
-      zc g = std::sqrt(l * l - k * k);
-      if (g.real() < 0.0) g = -g;
-      if (g.real() == 0.0 && g.imag() > 0.0) g = -g;
-      return g;
-    };
-    const zc g1 = br(lam, ctx->k1), g2 = br(lam, ctx->k2), g3 = br(lam, ctx->k3);
-    const zc E = std::exp(-g2 * ctx->d);
-    const zc gs = std::exp(-I * lam * src[0] - g1 * src[1]);
-    const zc sp = sig[q], sm = sig[ns + q], Pp = spec[q], Pm = spec[ns + q];
-    sig4[q] = g1 * (sp + E * sm + Pp) / g2 - gs;
-    sig4[ns + q] = sp;
-    sig4[2 * ns + q] = sm;
-    sig4[3 * ns + q] = g3 * (E * sp + sm + Pm) / g2;
+    const zc g0 = mpsl::gamma_branch(lam, ctx->k1);
+    const zc gs = std::exp(-I * lam * src[0] - g0 * (src[1] - ctx->yint[0]));
+    mpsl::stack_amplitudes(ctx, lam, gs, sig[q], sig[ns + q], spec[q], spec[ns + q], A.data(), B.data(), g.data());
+    for (int j = 0; j < L; ++j) {
+      gl[static_cast<size_t>(j) * ns + q] = g[j];
+      amp[static_cast<size_t>(2 * j) * ns + q] = A[j];
+      amp[static_cast<size_t>(2 * j + 1) * ns + q] = B[j];
+    }
   }
   const size_t rb = static_cast<size_t>(n_rcv) * sizeof(double2);
-  if ((rc = mpsl::dev_alloc(ctx, ctx->ybuf, rb * 2 + 4 * ns * sizeof(double2)))) return rc;
+  const size_t gb = gl.size() * sizeof(double2), ab = amp.size() * sizeof(double2);
+  if ((rc = mpsl::dev_alloc(ctx, ctx->ybuf, 2 * rb + gb + ab + (L - 1) * sizeof(double)))) return rc;
   char *base = static_cast<char *>(ctx->ybuf.p);
   void *d_rcv = base;
   void *d_u = base + rb;
-  void *d_sig = base + 2 * rb;
+  void *d_gl = base + 2 * rb;
+  void *d_amp = base + 2 * rb + gb;
+  void *d_yint = base + 2 * rb + gb + ab;
   MPSL_HIP_TRY(ctx, hipMemcpyAsync(d_rcv, rcv, rb, hipMemcpyHostToDevice, ctx->stream));
-  MPSL_HIP_TRY(ctx, hipMemcpyAsync(d_sig, sig4.data(), 4 * ns * sizeof(double2), hipMemcpyHostToDevice, ctx->stream));
-  if ((rc = mpsl::launch_field(ctx, ctx->xbuf.p, d_sig, src, n_rcv, d_rcv, d_u))) return rc;
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(d_gl, gl.data(), gb, hipMemcpyHostToDevice, ctx->stream));
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(d_amp, amp.data(), ab, hipMemcpyHostToDevice, ctx->stream));
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(d_yint, ctx->yint.data(), (L - 1) * sizeof(double), hipMemcpyHostToDevice,
+                                   ctx->stream));
+  if ((rc = mpsl::launch_field(ctx, ctx->xbuf.p, d_gl, d_amp, d_yint, src, n_rcv, d_rcv, d_u))) return rc;
   MPSL_HIP_TRY(ctx, hipMemcpyAsync(u_out, d_u, rb, hipMemcpyDeviceToHost, ctx->stream));
   MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   for (int64_t i = 0; i < n_rcv; ++i)

@@ -7,6 +7,7 @@ import paper_1407_3868_amd as mp
 from oracle import contour as ocontour
 from oracle import mie as omie
 from oracle import star as ostar
+from oracle import stack as ostack
 
 
 @pytest.mark.parametrize("R,k2,kp,p", [(0.25, 9.0, 15.0, 8), (0.3, 3.0, 2.0, 12), (0.25, 9.0, 15.0, 20)])
@@ -45,3 +46,49 @@ def test_bad_host_arguments():
         mp.compute_star_smatrix(0.25, 0.3, 5, 9.0, 15.0, 8, 128)   # |a2| >= a1
     with pytest.raises(mp.MpslError):
         mp.compute_disk_smatrix(0.25, 9.0, 15.0, 40)               # order too high
+
+
+STACKS = [([6.0, 9.0, 12.0], [0, 1.0, 0], 1),
+          ([6.0, 7.5, 9.0, 11.0, 12.0], [0, 1.0, 8.0, 1.5, 0], 2),
+          ([4.0, 9.0, 5.0, 12.0], [0, 2.0, 0.7, 0], 1),
+          ([4.0, 9.0, 5.0, 12.0], [0, 0.3, 3.0, 0], 2),
+          ([3.0, 8.0, 5.0, 9.0, 6.0, 10.0, 2.0], [0, 0.4, 1.3, 5.0, 0.2, 2.5, 0], 3),
+          ([9.0, 9.0, 9.0, 9.0, 9.0], [0, 1.0, 2.0, 3.0, 0], 2)]
+
+
+@pytest.mark.parametrize("ks,th,c", STACKS)
+def test_layer_map_matches_oracle_node_solve(ks, th, c):
+    """The library's generalized reflection / transmission recursion against
+    the oracle's dense solve of every interface condition per node, for unit
+    particle spectra P+, P- and a unit source wave at the top interface."""
+    lam, _ = ocontour.contour(512, 0.05, 40.0, ks)
+    got = mp.compute_layer_map(ks, th, c, lam)
+    M = ostack.node_system(lam, ks, th, c)
+    one = np.ones(lam.size, complex)
+    A, B = ostack._col_A(c), ostack._col_B(c)
+    ref = np.zeros((lam.size, 6), complex)
+    for col, kw in ((0, dict(Pp=one)), (1, dict(Pm=one)), (2, dict(src=(0.0, ostack.interfaces(th, c)[0])))):
+        X = np.linalg.solve(M, ostack.rhs(lam, ks, th, c, **kw)[..., None])[..., 0]
+        if col < 2:
+            ref[:, col], ref[:, 2 + col] = X[:, A], X[:, B]
+        else:
+            ref[:, 4], ref[:, 5] = X[:, A], X[:, B]
+    assert np.max(np.abs(got - ref) / (1 + np.abs(ref))) < 1e-12
+
+
+def test_layer_map_without_contrast_is_free_space():
+    # every layer the same medium: nothing is reflected, the source passes unchanged
+    lam, _ = ocontour.contour(256, 0.2, 32.0, [9.0])
+    m = mp.compute_layer_map([9.0] * 5, [0, 1.0, 2.0, 3.0, 0], 2, lam)
+    g = ocontour.gamma(lam, 9.0)
+    assert np.max(np.abs(m[:, :4])) == 0.0 and np.max(np.abs(m[:, 5])) == 0.0
+    # the source wave arrives at y = 0 after the 1.0 thick layer above
+    assert np.max(np.abs(m[:, 4] - np.exp(-g * 1.0))) < 1e-14
+
+
+@pytest.mark.parametrize("ks,th,c", [([6.0, 9.0], [0, 0], 1), ([6.0, 9.0, 12.0], [0, 1.0, 0], 0),
+                                     ([6.0, 9.0, 12.0], [0, 1.0, 0], 2), ([6.0, 9.0, 12.0], [0, 0.0, 0], 1),
+                                     ([6.0, -9.0, 12.0], [0, 1.0, 0], 1), ([6.0, 9.0 + 1j, 12.0], [0, 1.0, 0], 1)])
+def test_layer_map_bad_arguments(ks, th, c):
+    with pytest.raises(mp.MpslError):
+        mp.compute_layer_map(ks, th, c, np.array([1.0 - 0.1j]))
