@@ -23,6 +23,22 @@ same weights.  The panel rule on [0, t_max] (the paper only says
 gamma_i(lambda) = sqrt(lambda^2 - k_i^2) takes the branch Re gamma >= 0 and,
 where Re gamma = 0, Im gamma <= 0 (outgoing / decaying waves).
 
+Span rule (contour_span).  For particles spread over a lateral extent X the
+integrands carry e^{i lambda (x_l - x_m)} with |x_l - x_m| up to X, which a
+fixed node count cannot resolve once X grows (the paper's node counts of
+Section 6 are for compact layouts).  contour_span fixes the panel length
+instead of the node count, on [0, t_max]:
+
+  1. breakpoints 0, t_max and Re k_i (0 < Re k_i < t_max), as above;
+  2. in each gap [a, c] with midpoint m, an end that is a branch point is
+     graded: cuts at a + b 2^j (j = 0, 1, ...) while below m (for a), and at
+     c - b 2^j while above m (for c); m itself is a cut when an end is graded;
+  3. every piece between cuts splits into ceil(length / h_max) equal panels.
+
+Gamma_2 and Gamma_3 as above.  b ~ 2/X keeps e^{b X} bounded; h_max ~ 6/X
+gives about 1e-11 on the layered interaction of two particles X apart
+(16-point panels), h_max ~ 12/X about 1e-6.
+
 Pins (tests/test_oracle_contour.py): the quadrature reproduces the Sommerfeld
 representation (3) of (i/4) H_0(k r) and of the multipoles of Theorem 5.1 on a
 refined contour; Gamma_3 mirrors Gamma_1 exactly; weights sum to the contour's
@@ -106,4 +122,50 @@ def contour(n_nodes, b, t_max, ks):
     w2 = -1j * ws2
     lam = np.concatenate([lam3, lam2, lam1]).astype(np.complex128)
     w = np.concatenate([w3, w2, w1.astype(np.complex128)])
+    return lam, w
+
+
+def span_breaks(b, t_max, h_max, ks):
+    """Panel end points on [0, t_max] for Gamma_1 under the span rule."""
+    sing = sorted({float(np.real(k)) for k in ks if 0.0 < float(np.real(k)) < t_max})
+    edges = sorted({0.0, float(t_max), *sing})
+    panels = []
+    for a, c in zip(edges[:-1], edges[1:]):
+        m = (a + c) / 2.0
+        cuts = {a, c}
+        if a in sing:
+            e = b
+            while a + e < m:
+                cuts.add(a + e)
+                e *= 2.0
+        if c in sing:
+            e = b
+            while c - e > m:
+                cuts.add(c - e)
+                e *= 2.0
+        if a in sing or c in sing:
+            cuts.add(m)
+        pts = sorted(cuts)
+        for u, v in zip(pts[:-1], pts[1:]):
+            k = int(np.ceil((v - u) / h_max))
+            for i in range(k):
+                panels.append((u + (v - u) * i / k, u + (v - u) * (i + 1) / k))
+    return panels
+
+
+def contour_span(b, t_max, h_max, ks):
+    """Nodes and weights of the span rule, in the path order of ``contour``."""
+    if not (b > 0 and t_max > 0 and h_max > 0):
+        raise ValueError("b, t_max and h_max must be positive")
+    x, wx = np.polynomial.legendre.leggauss(GL_ORDER)
+    pan = span_breaks(b, t_max, h_max, ks)
+    t1 = np.concatenate([(a + c) / 2.0 + (c - a) / 2.0 * x for a, c in pan])
+    w1 = np.concatenate([(c - a) / 2.0 * wx for a, c in pan])
+    lam1 = t1 - 1j * b
+    lam3 = -lam1[::-1]
+    w3 = w1[::-1].astype(np.complex128)
+    s2 = np.concatenate([-b / 2.0 + b / 2.0 * x, b / 2.0 + b / 2.0 * x])
+    ws2 = np.concatenate([b / 2.0 * wx, b / 2.0 * wx])
+    lam = np.concatenate([lam3, -1j * s2, lam1]).astype(np.complex128)
+    w = np.concatenate([w3, -1j * ws2, w1.astype(np.complex128)])
     return lam, w

@@ -63,3 +63,44 @@ def test_printed_theorem_factor_fails(fine):
                                                * ((g + k ** 2) / k ** 2) ** n)
     ref = hankel1(n, k * np.hypot(X, Y)) * np.exp(1j * n * np.arctan2(Y, X))
     assert abs(printed - ref) > 1e-2 * abs(ref)
+
+
+def test_span_rule_panels():
+    pan = contour.span_breaks(0.01, 32.0, 0.5, [6.0, 9.0, 12.0])
+    ends = {a for a, _ in pan} | {c for _, c in pan}
+    assert {0.0, 6.0, 9.0, 12.0, 32.0} <= ends
+    L = np.array([c - a for a, c in pan])
+    assert L.max() <= 0.5 + 1e-15
+    assert abs(L.sum() - 32.0) < 1e-12                        # the panels tile [0, t_max]
+    # graded towards the branch points: the panels touching 9 are b long
+    assert min(c - a for a, c in pan if c == 9.0 or a == 9.0) == pytest.approx(0.01)
+    lam, w = contour.contour_span(0.01, 32.0, 0.5, [6.0, 9.0, 12.0])
+    assert lam.size == 32 + 32 * len(pan)
+    assert abs(np.sum(w) - (64.0 - 0.02j)) < 1e-12
+
+
+@pytest.mark.parametrize("X,Y", [(60.0, 2.0), (-60.0, 1.5), (400.0, 2.0), (400.0, -3.0)])
+@pytest.mark.parametrize("n", [0, 3, -5])
+def test_span_rule_converges_at_wide_spans(X, Y, n):
+    """The plane-wave form of (i/4) H_n(kr) e^{in theta} at lateral distance
+    up to 400 with the span rule (b = 2/X, h_max = 6/X) against scipy."""
+    k = 9.0
+    Xs = abs(X)
+    lam, w = contour.contour_span(2.0 / Xs, 24.0, 6.0 / Xs, [6.0, 9.0, 12.0])
+    g = gamma(lam, k)
+    s = np.sign(Y)
+    integ = np.sum(w * np.exp(-g * abs(Y)) / g * np.exp(1j * lam * X)
+                   * (-1j) ** n * ((lam - s * g) / k) ** n) / (4 * np.pi)
+    ref = 0.25j * hankel1(n, k * np.hypot(X, Y)) * np.exp(1j * n * np.arctan2(Y, X))
+    assert abs(integ - ref) < 1e-10 * abs(ref), abs(integ - ref) / abs(ref)
+
+
+def test_count_rule_does_not_converge_at_wide_spans():
+    # the branch-point rule with as many nodes misses the oscillation at X = 400
+    k, X, Y = 9.0, 400.0, 2.0
+    lam_s, _ = contour.contour_span(2.0 / X, 24.0, 6.0 / X, [6.0, 9.0, 12.0])
+    lam, w = contour.contour(lam_s.size, 2.0 / X, 24.0, [6.0, 9.0, 12.0])
+    g = gamma(lam, k)
+    integ = np.sum(w * np.exp(-g * Y) / g * np.exp(1j * lam * X)) / (4 * np.pi)
+    ref = 0.25j * hankel1(0, k * np.hypot(X, Y))
+    assert abs(integ - ref) > 1e-3 * abs(ref)
