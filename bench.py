@@ -311,6 +311,47 @@ def _fmm_workload(args, torch, mp):
     return out
 
 
+def _span_leg(args, torch, mp, wl, x, y_count):
+    """The same 5000-particle matvec on span-rule contours (panels no longer
+    than h = 12/X and 6/X for the strip's extent X, b = 2/X, t_max = 24), which
+    resolve e^{i lambda x} across the strip; the workload's 1024-node contour
+    does not.  Reports rates and how far the 1024-node matvec is from the
+    converged one."""
+    import numpy as np
+
+    a1, a2, a3 = wl.shape_params
+    X = float(wl.xy[:, 0].max() - wl.xy[:, 0].min())
+    res = {"extent_x": X, "b": 2.0 / X, "t_max": 24.0}
+    y6 = None
+    for label, hf in (("h12", 12.0), ("h6", 6.0)):
+        ctx = mp.Context(0)
+        ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+        ctx.set_layers(wl.k1, wl.k2, wl.k3, wl.d)
+        ctx.set_particle_star(a1, a2, a3, wl.kp, wl.p, 256)
+        ctx.set_geometry(wl.xy, wl.rot)
+        ns = ctx.set_contour_span(min(0.2, 2.0 / X), 24.0, hf / X)
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.zeros_like(xd)
+        ctx.apply_dev(0, xd, yd)
+        torch.cuda.synchronize()
+        leg = {"h_max": hf / X, "n_nodes": ns}
+        for name, prec in (("fp32", 1), ("fp64", 0)):
+            dt, m2l_ms, _, fin = _matvec_rate(ctx, torch, prec, x, args.steps, args.warmup)
+            leg[name] = {"matvecs_per_s": args.steps / dt, "ms_per_matvec": dt / args.steps * 1e3,
+                         "m2l_ms": m2l_ms, "finite": fin}
+        if label == "h6":
+            y6 = yd.cpu().numpy()
+        else:
+            y12 = yd.cpu().numpy()
+        res[label] = leg
+        del ctx
+        torch.cuda.empty_cache()
+    ref = np.linalg.norm(y6)
+    res["fp64_matvec_rel_diff_h12_vs_h6"] = float(np.linalg.norm(y12 - y6) / ref)
+    res["fp64_matvec_rel_diff_1024_nodes_vs_h6"] = float(np.linalg.norm(y_count - y6) / ref)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +362,7 @@ def main():
     ap.add_argument("--solve-maxiter", type=int, default=1500)
     ap.add_argument("--no-autotune", action="store_true", help="use the default M2L launch shape")
     ap.add_argument("--no-fmm", action="store_true", help="skip the FMM far-field comparison")
+    ap.add_argument("--no-span", action="store_true", help="skip the span-rule contour legs")
     ap.add_argument("--workload", choices=["c3", "batch", "serve", "fmm"], default="c3",
                     help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching; "
                          "serve: Poisson request stream through the server; fmm: 20000 particles, FMM vs direct")
@@ -479,6 +521,16 @@ def main():
             # both stopped at the iteration limit: the same work in both precisions
             out["mixed_vs_fp64_solve_speedup_equal_iterations"] = (solves["fp64"]["seconds"] /
                                                                    solves["mixed"]["seconds"])
+
+    if not args.no_span:
+        yc = torch.zeros_like(xd)
+        ctx.apply_dev(0, xd, yc)
+        torch.cuda.synchronize()
+        y_count = yc.cpu().numpy()
+        del ctx
+        torch.cuda.empty_cache()
+        out["span_contour"] = _span_leg(args, torch, mp, wl, x, y_count)
+        print(f"# span legs: {json.dumps(out['span_contour'])}", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(wl, S, x)

@@ -162,6 +162,30 @@ int mpsl_compute_star_smatrix(double a1, double a2, int a3, mpsl_c128 k2, mpsl_c
 int mpsl_compute_contour(mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, int n_nodes, double b, double t_max,
                          mpsl_c128 *lam, mpsl_c128 *w);
 
+/* Sommerfeld contour of Section 5.1, eq. (37), with panels of bounded length
+ * instead of a fixed node count (span rule), for layouts spread laterally:
+ * the sums over nodes carry e^{i lambda (x_l - x_m)}, and |x_l - x_m| up to the
+ * lateral extent X of particles and sources must be resolved.  On
+ * [0, t_max]: breakpoints 0, t_max and every Re k_i in between; in each gap
+ * [a, c] with midpoint m, an end that is a Re k_i is graded (cuts at
+ * a + b 2^j while below m, at c - b 2^j while above m, and at m); every piece
+ * between cuts splits into ceil(length / h_max) equal 16-point Gauss-Legendre
+ * panels.  Gamma_2 (two panels) and Gamma_3 (mirror) as in mpsl_set_contour.
+ * Guide: b = min(0.2, 2 / X); h_max = 6 / X gives about 1e-11 on the layered
+ * interaction of two particles X apart, h_max = 12 / X about 1e-6; t_max
+ * such that e^{-sqrt(t_max^2 - max k^2) dy} is negligible for the smallest
+ * vertical distance dy of a reflected path (24 for dy >= 2 and k <= 12).
+ * N_S = 32 + 32 * (panels), at most 2^20; the matvec needs N * N_S <= 2^29
+ * (MPSL_EUNSUPPORTED otherwise).  Requires layers. */
+int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max);
+
+/* Host, no device: the span rule's nodes and weights for the real parts
+ * re_k[0 .. n_k) of the layer wavenumbers.  *n_nodes receives the count;
+ * with lam and w NULL nothing else is written, otherwise both must hold
+ * capacity >= *n_nodes entries (MPSL_EINVAL if not). */
+int mpsl_compute_contour_span(int n_k, const double *re_k, double b, double t_max, double h_max, int capacity,
+                              mpsl_c128 *lam, mpsl_c128 *w, int *n_nodes);
+
 /* Explicit contour: nodes lam[q] and weights w[q] (d lambda included). */
 int mpsl_set_contour_nodes(mpsl_ctx *ctx, int n_nodes, const mpsl_c128 *lam, const mpsl_c128 *w);
 

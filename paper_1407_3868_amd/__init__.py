@@ -80,6 +80,28 @@ def compute_contour(k1, k2, k3, n_nodes, b, t_max):
     return lam, w
 
 
+def compute_contour_span(ks, b, t_max, h_max):
+    """Host: span-rule contour nodes and weights (mirrors mpsl_compute_contour_span)."""
+    lib = _lib.load()
+    kr = np.ascontiguousarray(np.real(np.asarray(ks, dtype=np.complex128)), dtype=np.float64)
+    n = ctypes.c_int(0)
+    _host_check(lib.mpsl_compute_contour_span(int(kr.size), kr.ctypes.data, float(b), float(t_max), float(h_max),
+                                              0, None, None, ctypes.byref(n)), "contour span")
+    lam = np.zeros(n.value, np.complex128)
+    w = np.zeros(n.value, np.complex128)
+    _host_check(lib.mpsl_compute_contour_span(int(kr.size), kr.ctypes.data, float(b), float(t_max), float(h_max),
+                                              n.value, lam.ctypes.data, w.ctypes.data, ctypes.byref(n)),
+                "contour span")
+    return lam, w
+
+
+def span_contour_params(x_extent, tol=1e-10):
+    """(b, h_max) of the span rule for a layout of lateral extent x_extent:
+    b = min(0.2, 2 / X), h_max = 6 / X for tol <= 1e-8, else 12 / X."""
+    X = max(float(x_extent), 1.0)
+    return min(0.2, 2.0 / X), (6.0 if tol <= 1e-8 else 12.0) / X
+
+
 def compute_layer_map(ks, thickness, particle_layer, lam):
     """Host: per-node map of a layer stack (mirrors mpsl_compute_layer_map),
     (n_lam, 6): the 2 x 2 reflection map row-major, then the source factors."""
@@ -196,6 +218,11 @@ class Context:
 
     def set_contour(self, n_nodes, b, t_max):
         return self._check(self.lib.mpsl_set_contour(self.h, int(n_nodes), float(b), float(t_max)))
+
+    def set_contour_span(self, b, t_max, h_max):
+        """Span-rule contour (mpsl_set_contour_span); returns the node count."""
+        self._check(self.lib.mpsl_set_contour_span(self.h, float(b), float(t_max), float(h_max)))
+        return self.sizes()[2]
 
     def set_contour_nodes(self, lam, w):
         lam, w = _carr(lam), _carr(w)

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <set>
 
 #include "kernels.h"
 
@@ -182,20 +183,12 @@ int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, 
   return star_smatrix(a1, a2, a3, k2, kp.re, p, nb, S, err);
 }
 
-// Contour nodes and weights in path order (rule stated in mpsl.h).
-int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_max, std::vector<zc> &lam,
-                 std::vector<zc> &w, std::string &err) {
-  if (n_nodes < 96 || (n_nodes - 32) % 32 != 0 || !(b > 0.0) || !(t_max > 0.0)) {
-    err = "n_nodes = 32 + 32 m (m >= 2), b > 0, t_max > 0";
-    return MPSL_EINVAL;
-  }
+// Gauss-Legendre nodes on the Gamma_1 panels, the mirrored Gamma_3 and the
+// two Gamma_2 panels, in path order.
+void assemble_contour(const std::vector<std::pair<double, double>> &pan, double b, std::vector<zc> &lam,
+                      std::vector<zc> &w) {
   double gx[16], gwt[16];
   gauss_legendre16(gx, gwt);
-  std::vector<std::pair<double, double>> pan;
-  if (!panel_rule((n_nodes - 32) / 32, b, t_max, ks, pan)) {
-    err = "too few nodes for the branch-point breakpoints";
-    return MPSL_EINVAL;
-  }
   std::vector<double> t1, w1;
   for (const auto &pc : pan) {
     const double a = pc.first, c = pc.second;
@@ -221,6 +214,74 @@ int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_
     lam.emplace_back(t1[i], -b);
     w.emplace_back(w1[i], 0.0);
   }
+}
+
+// Contour nodes and weights in path order (rule stated in mpsl.h).
+int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_max, std::vector<zc> &lam,
+                 std::vector<zc> &w, std::string &err) {
+  if (n_nodes < 96 || (n_nodes - 32) % 32 != 0 || !(b > 0.0) || !(t_max > 0.0)) {
+    err = "n_nodes = 32 + 32 m (m >= 2), b > 0, t_max > 0";
+    return MPSL_EINVAL;
+  }
+  std::vector<std::pair<double, double>> pan;
+  if (!panel_rule((n_nodes - 32) / 32, b, t_max, ks, pan)) {
+    err = "too few nodes for the branch-point breakpoints";
+    return MPSL_EINVAL;
+  }
+  assemble_contour(pan, b, lam, w);
+  return MPSL_OK;
+}
+
+// Panels of bounded length on [0, t_max] (span rule stated in mpsl.h):
+// branch-point breakpoints, grading towards each branch point from b, then
+// every piece split into equal panels no longer than h_max.  Returns the
+// panel count; fills pan only when it stays within max_panels.
+int64_t span_panels(const std::vector<double> &ks, double b, double t_max, double h_max, int64_t max_panels,
+                    std::vector<std::pair<double, double>> &pan) {
+  std::set<double> sing, edges{0.0, t_max};
+  for (double k : ks)
+    if (k > 0.0 && k < t_max) sing.insert(k);
+  edges.insert(sing.begin(), sing.end());
+  std::vector<double> e(edges.begin(), edges.end());
+  int64_t count = 0;
+  pan.clear();
+  for (size_t g = 0; g + 1 < e.size(); ++g) {
+    const double a = e[g], c = e[g + 1], m = (a + c) / 2.0;
+    const bool ga = sing.count(a) > 0, gc = sing.count(c) > 0;
+    std::set<double> cuts{a, c};
+    if (ga)
+      for (double h = b; a + h < m; h *= 2.0) cuts.insert(a + h);
+    if (gc)
+      for (double h = b; c - h > m; h *= 2.0) cuts.insert(c - h);
+    if (ga || gc) cuts.insert(m);
+    std::vector<double> pts(cuts.begin(), cuts.end());
+    for (size_t i = 0; i + 1 < pts.size(); ++i) {
+      const double u = pts[i], v = pts[i + 1];
+      const int64_t k = static_cast<int64_t>(std::ceil((v - u) / h_max));
+      count += k;
+      if (count > max_panels) continue;
+      for (int64_t j = 0; j < k; ++j)
+        pan.emplace_back(u + (v - u) * static_cast<double>(j) / static_cast<double>(k),
+                         u + (v - u) * static_cast<double>(j + 1) / static_cast<double>(k));
+    }
+  }
+  return count;
+}
+
+int make_contour_span(const std::vector<double> &ks, double b, double t_max, double h_max, std::vector<zc> &lam,
+                      std::vector<zc> &w, std::string &err) {
+  if (!(b > 0.0) || !(t_max > 0.0) || !(h_max > 0.0) || !std::isfinite(b) || !std::isfinite(t_max) ||
+      !std::isfinite(h_max)) {
+    err = "b, t_max and h_max must be positive and finite";
+    return MPSL_EINVAL;
+  }
+  std::vector<std::pair<double, double>> pan;
+  const int64_t max_panels = (kMaxNodes - 32) / 32;
+  if (span_panels(ks, b, t_max, h_max, max_panels, pan) > max_panels) {
+    err = "the span rule needs more than " + std::to_string(kMaxNodes) + " contour nodes";
+    return MPSL_EINVAL;
+  }
+  assemble_contour(pan, b, lam, w);
   return MPSL_OK;
 }
 
@@ -237,6 +298,9 @@ int build_tables(mpsl_ctx *ctx) {
   if (!ctx->has_layers || !ctx->has_particle || !ctx->has_geom || !ctx->has_contour)
     return set_err(ctx, MPSL_ESTATE, "layers, particle, geometry and contour must all be set");
   if (ctx->tables_ok) return MPSL_OK;
+  if (ctx->n * static_cast<int64_t>(ctx->ns) > kMaxPlaneWaves)
+    return set_err(ctx, MPSL_EUNSUPPORTED,
+                   "particles x contour nodes above " + std::to_string(kMaxPlaneWaves) + " (plane-wave tables)");
   const int ns = ctx->ns;
   const int p = ctx->p;
   const int P = 2 * p + 1;
@@ -677,8 +741,44 @@ int mpsl_compute_contour(mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, int n_nodes, 
   return MPSL_OK;
 }
 
+int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max) {
+  if (!ctx) return MPSL_EINVAL;
+  if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
+  std::vector<zc> lam, w;
+  std::string err;
+  std::vector<double> kr;
+  for (const zc &k : ctx->ks) kr.push_back(k.real());
+  const int rc = mpsl::make_contour_span(kr, b, t_max, h_max, lam, w, err);
+  if (rc) return mpsl::set_err(ctx, rc, err);
+  ctx->lam = lam;
+  ctx->w = w;
+  ctx->ns = static_cast<int>(lam.size());
+  ctx->has_contour = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_compute_contour_span(int n_k, const double *re_k, double b, double t_max, double h_max, int capacity,
+                              mpsl_c128 *lam, mpsl_c128 *w, int *n_nodes) {
+  if (!re_k || n_k <= 0 || !n_nodes) return MPSL_EINVAL;
+  std::vector<double> kr(re_k, re_k + n_k);
+  std::vector<zc> l, ww;
+  std::string err;
+  const int rc = mpsl::make_contour_span(kr, b, t_max, h_max, l, ww, err);
+  if (rc) return rc;
+  *n_nodes = static_cast<int>(l.size());
+  if (!lam && !w) return MPSL_OK;
+  if (!lam || !w || capacity < *n_nodes) return MPSL_EINVAL;
+  for (int i = 0; i < *n_nodes; ++i) {
+    lam[i] = {l[i].real(), l[i].imag()};
+    w[i] = {ww[i].real(), ww[i].imag()};
+  }
+  return MPSL_OK;
+}
+
 int mpsl_set_contour_nodes(mpsl_ctx *ctx, int n_nodes, const mpsl_c128 *lam, const mpsl_c128 *w) {
   if (!ctx || !lam || !w || n_nodes <= 0) return MPSL_EINVAL;
+  if (n_nodes > mpsl::kMaxNodes) return mpsl::set_err(ctx, MPSL_EINVAL, "too many contour nodes");
   ctx->lam.resize(n_nodes);
   ctx->w.resize(n_nodes);
   for (int i = 0; i < n_nodes; ++i) {

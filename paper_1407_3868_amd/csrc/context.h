@@ -188,6 +188,9 @@ int assign_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const double *
                  std::string &err);
 zc gamma_branch(zc lam, zc k);
 constexpr int kMaxLayers = 64;
+// Contour under the span rule (panels of length <= h_max).
+int make_contour_span(const std::vector<double> &ks, double b, double t_max, double h_max, std::vector<zc> &lam,
+                      std::vector<zc> &w, std::string &err);
 int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_max, std::vector<zc> &lam,
                  std::vector<zc> &w, std::string &err);
 int build_tables(mpsl_ctx *ctx);

@@ -8,6 +8,10 @@ namespace mpsl {
 // Largest supported expansion order and the range instantiated.
 constexpr int kMinP = 1;
 constexpr int kMaxP = 20;
+// Largest contour, and largest particles x nodes product (the plane-wave
+// factor tables hold 2 N N_S entries per precision).
+constexpr int kMaxNodes = 1 << 20;
+constexpr int64_t kMaxPlaneWaves = int64_t(1) << 29;
 
 // Row a0: per-particle plane-wave factor tables of the contour (E, F) and
 // rotation phases.  FP64 master tables and FP32 copies.

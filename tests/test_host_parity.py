@@ -92,3 +92,21 @@ def test_layer_map_without_contrast_is_free_space():
 def test_layer_map_bad_arguments(ks, th, c):
     with pytest.raises(mp.MpslError):
         mp.compute_layer_map(ks, th, c, np.array([1.0 - 0.1j]))
+
+
+@pytest.mark.parametrize("ks,b,t_max,h_max", [([6, 9, 12], 0.01, 32.0, 0.5), ([6, 9, 12], 2 / 400, 24.0, 6 / 400),
+                                              ([3, 8, 5, 9, 6, 10, 2], 0.03, 32.0, 0.2), ([9, 9, 9], 0.2, 32.0, 3.0),
+                                              ([1, 3, 1], 0.05, 21.0, 40.0)])
+def test_contour_span(ks, b, t_max, h_max):
+    lam, w = mp.compute_contour_span(ks, b, t_max, h_max)
+    rl, rw = ocontour.contour_span(b, t_max, h_max, ks)
+    assert lam.size == rl.size
+    assert np.max(np.abs(lam - rl)) < 1e-13 * np.max(np.abs(rl))
+    assert np.max(np.abs(w - rw)) < 1e-13 * np.max(np.abs(rw))
+
+
+@pytest.mark.parametrize("b,t_max,h_max", [(0.0, 32.0, 0.1), (0.1, -1.0, 0.1), (0.1, 32.0, 0.0),
+                                           (0.1, 32.0, 1e-5)])          # the last needs > 2^20 nodes
+def test_contour_span_bad_arguments(b, t_max, h_max):
+    with pytest.raises(mp.MpslError):
+        mp.compute_contour_span([6, 9, 12], b, t_max, h_max)
