@@ -19,7 +19,9 @@ operators  M2L (Section 3.2, Lemma 3.1), M2S (Section 5.3, Theorem 5.1),
 system     Schur-complement system (Section 5.4, eq. (49)), dense LU solve,
            matrix-free matvec and GMRES, field evaluation (eq. (36))
 stack      the same system for any number of layers (interface conditions
-           (8)-(9) at every interface)
+           (8)-(9) at every interface), TM or TE
+Every module that depends on the interface conditions takes pol = "TM" (the
+paper's case) or "TE" ((1/k^2) du/dn continuous instead of du/dn).
 
 Parity status of every function is listed in its docstring; the pins live in
 ``tests/test_oracle_*.py``.

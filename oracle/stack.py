@@ -26,6 +26,9 @@ unknowns X = (B_0, A_1, B_1, ..., A_{L-2}, B_{L-2}, A_{L-1}) solve
 at every interface, by Gaussian elimination per node.  For L = 3 this is
 eq. (10) with (sigma_1, sigma_2^+, sigma_2^-, sigma_3) = (B_0, A_1, B_1, A_2).
 
+TE polarisation: the derivative rows carry the weight 1/k_j^2 of the layer
+each term lives in ((1/eps) du/dy continuous); TM has weight 1.
+
 Pins (tests/test_oracle_stack.py): L = 3 against the three-layer oracle;
 splitting a layer by an interface between equal wavenumbers changes nothing;
 u and du/dy continuous at every interface of the assembled field; power
@@ -62,11 +65,19 @@ def _col_B(j):
     return 0 if j == 0 else 2 * j   # unknown index of B_j (0 <= j <= L-2)
 
 
-def node_system(lam, ks, thick, c):
+def weights(ks, pol):
+    """Weight of du/dy in the interface conditions, per layer."""
+    if pol not in ("TM", "TE"):
+        raise ValueError("pol is 'TM' or 'TE'")
+    return [1.0 if pol == "TM" else 1.0 / complex(k) ** 2 for k in ks]
+
+
+def node_system(lam, ks, thick, c, pol="TM"):
     """Interface matrices per node, (N_S, 2L-2, 2L-2): row 2i is u, row 2i+1
-    is du/dy, both as (above) - (below) at interface i."""
+    is (weighted) du/dy, both as (above) - (below) at interface i."""
     lam = np.atleast_1d(np.asarray(lam, dtype=np.complex128))
     L = len(ks)
+    kap = weights(ks, pol)
     yint = interfaces(thick, c)
     g = [gamma(lam, k) for k in ks]
     n = 2 * L - 2
@@ -74,46 +85,48 @@ def node_system(lam, ks, thick, c):
     for i in range(L - 1):
         up, lo = i, i + 1
         # layer above (index up), evaluated at its bottom interface i
+        ku, kl = kap[up], kap[lo]
         if up == 0:
             M[:, 2 * i, _col_B(0)] += 1 / g[0]
-            M[:, 2 * i + 1, _col_B(0)] += -1.0
+            M[:, 2 * i + 1, _col_B(0)] += -ku
         else:
             e = np.exp(-g[up] * (yint[up - 1] - yint[up]))     # A_up at its bottom
             M[:, 2 * i, _col_A(up)] += e / g[up]
-            M[:, 2 * i + 1, _col_A(up)] += e
+            M[:, 2 * i + 1, _col_A(up)] += ku * e
             M[:, 2 * i, _col_B(up)] += 1 / g[up]
-            M[:, 2 * i + 1, _col_B(up)] += -1.0
+            M[:, 2 * i + 1, _col_B(up)] += -ku
         # layer below (index lo), evaluated at its top interface i, subtracted
         M[:, 2 * i, _col_A(lo)] -= 1 / g[lo]
-        M[:, 2 * i + 1, _col_A(lo)] -= 1.0
+        M[:, 2 * i + 1, _col_A(lo)] -= kl
         if lo < L - 1:
             e = np.exp(-g[lo] * (yint[lo - 1] - yint[lo]))     # B_lo at its top
             M[:, 2 * i, _col_B(lo)] -= e / g[lo]
-            M[:, 2 * i + 1, _col_B(lo)] -= -e
+            M[:, 2 * i + 1, _col_B(lo)] -= -kl * e
     return M
 
 
-def rhs(lam, ks, thick, c, Pp=None, Pm=None, src=None):
+def rhs(lam, ks, thick, c, Pp=None, Pm=None, src=None, pol="TM"):
     """Known terms moved to the right-hand side, (N_S, 2L-2)."""
     lam = np.atleast_1d(np.asarray(lam, dtype=np.complex128))
     L = len(ks)
+    kap = weights(ks, pol)
     yint = interfaces(thick, c)
     b = np.zeros((lam.size, 2 * L - 2), dtype=np.complex128)
     if src is not None:                     # layer 0, above interface 0: g/g0, derivative g
         g0 = gamma(lam, ks[0])
         gs = np.exp(-1j * lam * src[0] - g0 * (src[1] - yint[0]))
         b[:, 0] -= gs / g0
-        b[:, 1] -= gs
+        b[:, 1] -= kap[0] * gs
     if Pp is not None:                      # layer c below interface c-1: P+/gc, derivative -P+
         gc = gamma(lam, ks[c])
         i = c - 1
         b[:, 2 * i] += Pp / gc
-        b[:, 2 * i + 1] += -Pp
+        b[:, 2 * i + 1] += -kap[c] * Pp
     if Pm is not None:                      # layer c above interface c: P-/gc, derivative +P-
         gc = gamma(lam, ks[c])
         i = c
         b[:, 2 * i] -= Pm / gc
-        b[:, 2 * i + 1] -= Pm
+        b[:, 2 * i + 1] -= kap[c] * Pm
     return b
 
 
@@ -126,7 +139,8 @@ class StackProblem(Problem):
         Pp = Pm = None
         if beta is not None:
             Pp, Pm = operators.m2s(beta, self.xy, self.lam, self.k2, self.d)
-        return np.linalg.solve(self.M, rhs(self.lam, self.ks, self.thick, self.c, Pp, Pm, src)[..., None])[..., 0]
+        b = rhs(self.lam, self.ks, self.thick, self.c, Pp, Pm, src, self.pol)
+        return np.linalg.solve(self.M, b[..., None])[..., 0]
 
     def layer_local(self, beta=None, src=None, targets=None):
         X = self.sigma(beta, src)
@@ -176,15 +190,15 @@ class StackProblem(Problem):
         return out
 
 
-def stack_problem(ks, thick, c, p, S, xy, rot, lam, w):
+def stack_problem(ks, thick, c, p, S, xy, rot, lam, w, pol="TM"):
     """StackProblem for wavenumbers ks (top to bottom), finite-layer
-    thicknesses thick (same length; entries 0 and L-1 unused) and particle
-    layer c."""
+    thicknesses thick (same length; entries 0 and L-1 unused), particle
+    layer c and polarisation pol (S must be the matching scattering matrix)."""
     ks = [complex(k) for k in ks]
     thick = [float(t) for t in thick]
     if not (1 <= c <= len(ks) - 2) or len(thick) != len(ks):
         raise ValueError("need 1 <= c <= L-2 and one thickness per layer")
     pr = StackProblem(ks[0], ks[c], ks[-1], thick[c], p, S, xy, rot, lam, w)
-    pr.ks, pr.thick, pr.c = ks, thick, c
-    pr.M = node_system(pr.lam, ks, thick, c)
+    pr.ks, pr.thick, pr.c, pr.pol = ks, thick, c, pol
+    pr.M = node_system(pr.lam, ks, thick, c, pol)
     return pr

@@ -15,6 +15,17 @@ the smooth remainder, and Maue's identity
 T_k mu = d/ds S_k (d mu/ds) + k^2 n_x . S_k (n_y mu) for the hypersingular
 operator, with the tangential derivative taken spectrally.
 
+TE polarisation: (1/k^2) du/dn is continuous instead of du/dn.  With
+rho = k2^2 / kp^2 the interior field is represented as
+S^{kp} sigma + (1/rho) D^{kp} mu, so that the hypersingular operators still
+appear as the difference T2 - Tp:
+
+    (1 + 1/rho)/2 mu + (S2 - Sp) sigma + (D2 - Dp / rho) mu   = -u_inc
+   -(1 + rho)/2 sigma + (N2 - rho Np) sigma + (T2 - Tp) mu    = -d u_inc / dn
+
+(rho = 1 is eqs. (31)-(32)); the exterior representation, and hence eq. (35),
+is unchanged.
+
 Right-hand sides are the regular waves J_n(k2 r) e^{in theta} on the boundary
 (Section 4.1, with k = k2 and r = |y|), and the outgoing coefficients follow
 eq. (35) with w read as k2 and the factor i/4 of G = (i/4) H_0 restored:
@@ -125,13 +136,16 @@ def _layer_matrices(k, x, xp, xpp, t, Rw):
     return S, D, Np, S0, nrm, speed
 
 
-def star_smatrix(a1, a2, a3, k2, kp, p, nb=256, return_densities=False):
+def star_smatrix(a1, a2, a3, k2, kp, p, nb=256, return_densities=False, pol="TM"):
     """Prototype scattering matrix S (shape (2p+1, 2p+1), S[l+p, n+p]).
 
     ``nb`` boundary points (even).  Orientation psi = 0 as in eq. (50).
     """
     if nb % 2:
         raise ValueError("nb must be even")
+    if pol not in ("TM", "TE"):
+        raise ValueError("pol is 'TM' or 'TE'")
+    rho = 1.0 if pol == "TM" else (k2 / kp) ** 2
     t, rad, x, xp, xpp = star_boundary(a1, a2, a3, nb)
     Rw = _kress_weights(nb)
     F = _fourier_diff(nb)
@@ -143,8 +157,8 @@ def star_smatrix(a1, a2, a3, k2, kp, p, nb=256, return_densities=False):
     Tdiff = (inv_speed[:, None] * (F @ (S02 - S0p) @ F)
              + nn * (k2 ** 2 * S2 - kp ** 2 * Sp))
     I = np.eye(nb)
-    A = np.block([[S2 - Sp, I + D2 - Dp],
-                  [-I + N2 - Npp, Tdiff]])
+    A = np.block([[S2 - Sp, 0.5 * (1.0 + 1.0 / rho) * I + D2 - Dp / rho],
+                  [-0.5 * (1.0 + rho) * I + N2 - rho * Npp, Tdiff]])
 
     n = np.arange(-p, p + 1)
     theta = t

@@ -67,12 +67,14 @@ def test_interface_between_equal_wavenumbers_changes_nothing(split):
     assert np.max(np.abs(fa - fb)) < 1e-11 * np.max(np.abs(fb))
 
 
-def _five_layers():
+def _five_layers(pol="TM"):
     wl, S = _disks()
+    if pol == "TE":
+        S = np.diag(mie.disk_smatrix(wl.shape_params[0], wl.k2, wl.kp, wl.p, pol="TE"))
     ks = [6.0, 7.5, wl.k2, 11.0, 12.0]
     thick = [0, 1.0, wl.d, 1.5, 0]
     lam, w = _contour(ks, 768)
-    return wl, stack_problem(ks, thick, 2, wl.p, S, wl.xy, wl.rot, lam, w)
+    return wl, stack_problem(ks, thick, 2, wl.p, S, wl.xy, wl.rot, lam, w, pol=pol)
 
 
 def test_field_continuous_at_every_interface():
@@ -88,11 +90,16 @@ def test_field_continuous_at_every_interface():
         assert np.max(np.abs(ua - ub)) < 1e-7 * np.max(np.abs(ua))
 
 
-def test_flux_balance_five_layers():
+@pytest.mark.parametrize("pol", ["TM", "TE"])
+def test_flux_balance_five_layers(pol):
     """Power balance (as for three layers) on a rectangle crossing all four
-    interfaces of a five-layer stack."""
+    interfaces of a five-layer stack.  TE: the flux density is
+    (1/k^2) Im(conj(u) du/dn) with k of the layer it is taken in, and the
+    source term carries 1/k_0^2 (the weighted equation div((1/k^2) grad u)
+    + u = -(1/k_0^2) delta)."""
     from test_oracle_system import _gl_panels
-    wl, st = _five_layers()
+    wl, st = _five_layers(pol)
+    kap = [1.0 if pol == "TM" else 1.0 / k.real ** 2 for k in st.ks]
     src = np.array([0.3, 2.5])
     beta = st.solve_lu(src)
     y = interfaces(st.thick, st.c)
@@ -114,9 +121,11 @@ def test_flux_balance_five_layers():
             pts = np.stack([np.full_like(t, xa if side == 2 else xb), t], axis=1)
             nvec = np.array([-1.0 if side == 2 else 1.0, 0.0])
         u = st.field(src, beta, pts)
-        flux += float(np.sum(wt * np.imag(np.conj(u) * dn(pts, nvec))))
+        lay = np.sum(pts[:, 1][:, None] < y[None, :], axis=1)
+        wk = np.array([kap[j] for j in lay])
+        flux += float(np.sum(wk * wt * np.imag(np.conj(u) * dn(pts, nvec))))
     e = 1e-5
     offs = np.array([[e, 0.0], [-e, 0.0], [0.0, e], [0.0, -e]])
     us = st.field(src, beta, src[None, :] + offs) - 0.25j * hankel1(0, st.ks[0].real * e)
-    expect = 0.25 + float(np.mean(us).imag)
-    assert abs(flux - expect) < 1e-9, (flux, expect)
+    expect = kap[0] * (0.25 + float(np.mean(us).imag))
+    assert abs(flux - expect) < 1e-9 * abs(expect), (flux, expect)   # measured 2e-10 (TM), 1e-10 (TE)

@@ -56,3 +56,33 @@ def test_rotation_formula_matches_rotated_boundary():
     S = star.star_smatrix(0.25, 0.05, 5, 9.0, 15.0, 8, nb=128)
     Sm = star.star_smatrix(0.25, -0.05, 5, 9.0, 15.0, 8, nb=128)
     assert np.max(np.abs(rotated_smatrix(S, np.pi / 5) - Sm)) < 1e-13
+
+
+# ---- TE polarisation -----------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def S_star_te():
+    return star.star_smatrix(0.25, 0.05, 5, 9.0, 15.0, 16, nb=256, pol="TE")
+
+
+def test_te_disk_limit_matches_te_mie():
+    S = star.star_smatrix(0.25, 0.0, 5, 9.0, 15.0, 10, nb=128, pol="TE")
+    assert np.max(np.abs(S - np.diag(mie.disk_smatrix(0.25, 9.0, 15.0, 10, pol="TE")))) < 1e-13
+
+
+def test_te_unitary_selection_and_reciprocity(S_star_te):
+    S = S_star_te
+    U = np.eye(S.shape[0]) + 2 * S
+    assert np.max(np.abs(U.conj().T @ U - np.eye(U.shape[0]))) < 1e-12
+    p = (S.shape[0] - 1) // 2
+    n = np.arange(-p, p + 1)
+    assert np.max(np.abs(S[((n[:, None] - n[None, :]) % 5) != 0])) < 1e-13
+    sgn = (-1.0) ** (n[:, None] + n[None, :])
+    assert np.max(np.abs(S - sgn * S[::-1, ::-1].T)) < 1e-13
+
+
+def test_te_converged_and_distinct_from_tm(S_star_te):
+    S2 = star.star_smatrix(0.25, 0.05, 5, 9.0, 15.0, 16, nb=384, pol="TE")
+    assert np.max(np.abs(S_star_te - S2)) < 1e-13
+    tm = star.star_smatrix(0.25, 0.05, 5, 9.0, 15.0, 16, nb=256)
+    assert np.max(np.abs(S_star_te - tm)) > 1e-2
