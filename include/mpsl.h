@@ -63,6 +63,15 @@ enum {
   MPSL_PENDING = 1         /* server: the request has not finished yet          */
 };
 
+/* Polarisation (Section 1): with the permeability constant and the
+ * permittivity piecewise constant, TM keeps u and du/dn continuous across
+ * every interface and particle boundary (eqs. (8)-(9)); TE keeps u and
+ * (1/k^2) du/dn continuous. */
+enum {
+  MPSL_TM = 0,   /* the paper's case (default) */
+  MPSL_TE = 1
+};
+
 /* Arithmetic of the hot path. */
 enum {
   MPSL_FP64 = 0,   /* complex128 translations, FP64 accumulation            */
@@ -80,6 +89,14 @@ void mpsl_destroy(mpsl_ctx *ctx);
 /* Run all later device work on `stream` (a hipStream_t, e.g. torch's current
  * stream); NULL selects the device's null stream. */
 int mpsl_set_stream(mpsl_ctx *ctx, void *stream);
+
+/* Polarisation of the context (MPSL_TM or MPSL_TE; MPSL_EINVAL otherwise).
+ * It enters the reflection map of the layers and the scattering matrices of
+ * disks and stars, so a change clears the particle: call
+ * mpsl_set_particle_* (or mpsl_set_scattering_matrix with a matrix of this
+ * polarisation) again afterwards.  The matvec's kernels are the same. */
+int mpsl_set_polarization(mpsl_ctx *ctx, int polarization);
+int mpsl_get_polarization(const mpsl_ctx *ctx);
 
 /* Layer wavenumbers and middle-layer thickness d > 0 (Section 1, Fig. 1):
  * the three-layer case of mpsl_set_layer_stack (k = {k1, k2, k3}, particle
@@ -115,7 +132,7 @@ int mpsl_set_layer_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const 
  * interface.  These are the values the device reflection step applies.
  * Same argument rules and errors as mpsl_set_layer_stack. */
 int mpsl_compute_layer_map(int n_layers, const mpsl_c128 *k, const double *thickness, int particle_layer,
-                           int n_lam, const mpsl_c128 *lam, mpsl_c128 *map);
+                           int polarization, int n_lam, const mpsl_c128 *lam, mpsl_c128 *map);
 
 /* Circular particles of radius R and wavenumber kp (real, > 0): the diagonal
  * Mie scattering matrix of Section 3.1, eqs. (17)-(18), order p (1..32).
@@ -155,10 +172,13 @@ int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max);
 
 /* Context-free host computations (no device needed), same arithmetic as the
  * set_* calls above: the disk and star scattering matrices (P x P, row-major)
+ * for polarization MPSL_TM or MPSL_TE (TE: Mie coefficients with the
+ * derivative condition weighted by 1/k^2; Mueller's system with the interior
+ * double layer scaled by kp^2/k2^2 so that T2 - Tp stays weakly singular),
  * and the contour nodes and weights for layer wavenumbers k1, k2, k3. */
-int mpsl_compute_disk_smatrix(double R, mpsl_c128 k2, mpsl_c128 kp, int p, mpsl_c128 *S);
+int mpsl_compute_disk_smatrix(double R, mpsl_c128 k2, mpsl_c128 kp, int p, int polarization, mpsl_c128 *S);
 int mpsl_compute_star_smatrix(double a1, double a2, int a3, mpsl_c128 k2, mpsl_c128 kp, int p, int n_bdry,
-                              mpsl_c128 *S);
+                              int polarization, mpsl_c128 *S);
 int mpsl_compute_contour(mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, int n_nodes, double b, double t_max,
                          mpsl_c128 *lam, mpsl_c128 *w);
 

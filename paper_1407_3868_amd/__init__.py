@@ -16,6 +16,7 @@ from . import _lib
 FP64 = 0
 FP32 = 1
 FAR_AUTO, FAR_DIRECT, FAR_FMM = 0, 1, 2
+TM, TE = 0, 1
 
 STATUS = {0: "MPSL_OK", -1: "MPSL_EINVAL", -2: "MPSL_ENOMEM", -3: "MPSL_EHIP", -4: "MPSL_ESTATE",
           -5: "MPSL_EGEOM", -6: "MPSL_ENOCONV", -7: "MPSL_EUNSUPPORTED", -8: "MPSL_EINSIDE",
@@ -53,20 +54,21 @@ def _host_check(rc, what):
         raise MpslError(rc, what)
 
 
-def compute_disk_smatrix(R, k2, kp, p):
+def compute_disk_smatrix(R, k2, kp, p, polarization=TM):
     """Host: Mie scattering matrix of a disk (mirrors mpsl_compute_disk_smatrix)."""
     lib = _lib.load()
     S = np.zeros((2 * p + 1, 2 * p + 1), np.complex128)
-    _host_check(lib.mpsl_compute_disk_smatrix(float(R), _c(k2), _c(kp), int(p), S.ctypes.data), "disk matrix")
+    _host_check(lib.mpsl_compute_disk_smatrix(float(R), _c(k2), _c(kp), int(p), int(polarization), S.ctypes.data),
+                "disk matrix")
     return S
 
 
-def compute_star_smatrix(a1, a2, a3, k2, kp, p, n_bdry=0):
+def compute_star_smatrix(a1, a2, a3, k2, kp, p, n_bdry=0, polarization=TM):
     """Host: star scattering matrix by the boundary-integral precompute."""
     lib = _lib.load()
     S = np.zeros((2 * p + 1, 2 * p + 1), np.complex128)
     _host_check(lib.mpsl_compute_star_smatrix(float(a1), float(a2), int(a3), _c(k2), _c(kp), int(p), int(n_bdry),
-                                              S.ctypes.data), "star matrix")
+                                              int(polarization), S.ctypes.data), "star matrix")
     return S
 
 
@@ -102,7 +104,7 @@ def span_contour_params(x_extent, tol=1e-10):
     return min(0.2, 2.0 / X), (6.0 if tol <= 1e-8 else 12.0) / X
 
 
-def compute_layer_map(ks, thickness, particle_layer, lam):
+def compute_layer_map(ks, thickness, particle_layer, lam, polarization=TM):
     """Host: per-node map of a layer stack (mirrors mpsl_compute_layer_map),
     (n_lam, 6): the 2 x 2 reflection map row-major, then the source factors."""
     lib = _lib.load()
@@ -113,7 +115,8 @@ def compute_layer_map(ks, thickness, particle_layer, lam):
     lam = _carr(np.atleast_1d(lam))
     out = np.zeros((lam.size, 6), np.complex128)
     _host_check(lib.mpsl_compute_layer_map(int(k.size), k.ctypes.data, t.ctypes.data, int(particle_layer),
-                                           int(lam.size), lam.ctypes.data, out.ctypes.data), "layer map")
+                                           int(polarization), int(lam.size), lam.ctypes.data, out.ctypes.data),
+                "layer map")
     return out
 
 
@@ -184,6 +187,13 @@ class Context:
     # -- setup ----------------------------------------------------------
     def set_stream(self, stream):
         return self._check(self.lib.mpsl_set_stream(self.h, ctypes.c_void_p(stream)))
+
+    def set_polarization(self, polarization):
+        """MPSL_TM or MPSL_TE (mpsl_set_polarization); clears the particle."""
+        return self._check(self.lib.mpsl_set_polarization(self.h, int(polarization)))
+
+    def polarization(self):
+        return self.lib.mpsl_get_polarization(self.h)
 
     def set_layers(self, k1, k2, k3, d):
         return self._check(self.lib.mpsl_set_layers(self.h, _c(k1), _c(k2), _c(k3), float(d)))

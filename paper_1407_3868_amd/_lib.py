@@ -41,14 +41,16 @@ SIGNATURES = {
     "mpsl_set_stream": (I, [P, P]),
     "mpsl_set_layers": (I, [P, c128, c128, c128, D]),
     "mpsl_set_layer_stack": (I, [P, I, P, P, I]),
-    "mpsl_compute_layer_map": (I, [I, P, P, I, I, P, P]),
+    "mpsl_set_polarization": (I, [P, I]),
+    "mpsl_get_polarization": (I, [P]),
+    "mpsl_compute_layer_map": (I, [I, P, P, I, I, I, P, P]),
     "mpsl_set_particle_disk": (I, [P, D, c128, I]),
     "mpsl_set_particle_star": (I, [P, D, D, I, c128, I, I]),
     "mpsl_set_scattering_matrix": (I, [P, I, D, P]),
     "mpsl_set_geometry": (I, [P, L, P, P]),
     "mpsl_set_contour": (I, [P, I, D, D]),
-    "mpsl_compute_disk_smatrix": (I, [D, c128, c128, I, P]),
-    "mpsl_compute_star_smatrix": (I, [D, D, I, c128, c128, I, I, P]),
+    "mpsl_compute_disk_smatrix": (I, [D, c128, c128, I, I, P]),
+    "mpsl_compute_star_smatrix": (I, [D, D, I, c128, c128, I, I, I, P]),
     "mpsl_compute_contour": (I, [c128, c128, c128, I, D, D, P, P]),
     "mpsl_set_contour_span": (I, [P, D, D, D]),
     "mpsl_compute_contour_span": (I, [I, P, D, D, D, I, P, P, P]),

@@ -135,8 +135,10 @@ void invalidate(mpsl_ctx *ctx) { ctx->tables_ok = false; }
 }  // namespace
 
 // Diagonal Mie scattering matrix of a disk (Section 3.1, eq. (18) with the
-// denominator read as J_n(kp R)); S_{-n} = S_n.
-int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, std::vector<zc> &S, std::string &err) {
+// denominator read as J_n(kp R)); S_{-n} = S_n.  TE weights the derivative
+// condition by 1/k^2 of each side, so k2 and kp become 1/k2 and 1/kp where
+// they multiply a derivative.
+int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, int pol, std::vector<zc> &S, std::string &err) {
   if (!(R > 0.0) || !(kp.re > 0.0) || p < kMinP || p > kMaxP) {
     err = "disk needs R > 0, kp > 0 and 1 <= p <= 20";
     return MPSL_EINVAL;
@@ -145,16 +147,22 @@ int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, std::vector<zc> &S, s
     err = "disk particles need a real kp";
     return MPSL_EUNSUPPORTED;
   }
+  if (pol != MPSL_TM && pol != MPSL_TE) {
+    err = "polarization must be MPSL_TM or MPSL_TE";
+    return MPSL_EINVAL;
+  }
   const int P = 2 * p + 1;
   const double kpr = kp.re;
+  // derivative factors: k (TM) or k / k^2 (TE)
+  const double c2 = (pol == MPSL_TE) ? 1.0 / k2 : k2, cp = (pol == MPSL_TE) ? 1.0 / kpr : kpr;
   S.assign(static_cast<size_t>(P) * P, zc(0.0, 0.0));
   for (int n = 0; n <= p; ++n) {
     double ja, ya, jap, yap, jb, yb, jbp, ybp;
     bessel_jy(n, k2 * R, ja, ya, jap, yap);
     bessel_jy(n, kpr * R, jb, yb, jbp, ybp);
     const zc H(ja, ya), Hp(jap, yap);
-    const zc num = kpr * ja * jbp - k2 * jap * jb;
-    const zc den = k2 * Hp * jb - kpr * jbp * H;
+    const zc num = cp * ja * jbp - c2 * jap * jb;
+    const zc den = c2 * Hp * jb - cp * jbp * H;
     const zc s = num / den;
     S[static_cast<size_t>(p + n) * P + (p + n)] = s;
     S[static_cast<size_t>(p - n) * P + (p - n)] = s;
@@ -162,11 +170,15 @@ int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, std::vector<zc> &S, s
   return MPSL_OK;
 }
 
-int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, std::vector<zc> &S,
+int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, int pol, std::vector<zc> &S,
                  std::string &err);
 
-int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry,
+int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry, int pol,
                          std::vector<zc> &S, std::string &err) {
+  if (pol != MPSL_TM && pol != MPSL_TE) {
+    err = "polarization must be MPSL_TM or MPSL_TE";
+    return MPSL_EINVAL;
+  }
   if (!(a1 > 0.0) || !(std::fabs(a2) < a1) || a3 < 0 || !(kp.re > 0.0) || p < kMinP || p > kMaxP) {
     err = "star needs a1 > |a2|, a3 >= 0, kp > 0 and 1 <= p <= 20";
     return MPSL_EINVAL;
@@ -180,7 +192,7 @@ int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, 
     err = "n_bdry must be even, 64..2048";
     return MPSL_EINVAL;
   }
-  return star_smatrix(a1, a2, a3, k2, kp.re, p, nb, S, err);
+  return star_smatrix(a1, a2, a3, k2, kp.re, p, nb, pol, S, err);
 }
 
 // Gauss-Legendre nodes on the Gamma_1 panels, the mirrored Gamma_3 and the
@@ -556,9 +568,11 @@ int mpsl_set_layer_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const 
 }
 
 int mpsl_compute_layer_map(int n_layers, const mpsl_c128 *k, const double *thickness, int particle_layer,
-                           int n_lam, const mpsl_c128 *lam, mpsl_c128 *map) {
+                           int polarization, int n_lam, const mpsl_c128 *lam, mpsl_c128 *map) {
   if (!lam || !map || n_lam <= 0) return MPSL_EINVAL;
+  if (polarization != MPSL_TM && polarization != MPSL_TE) return MPSL_EINVAL;
   mpsl_ctx tmp;
+  tmp.pol = polarization;
   std::string err;
   const int rc = mpsl::assign_stack(&tmp, n_layers, k, thickness, particle_layer, err);
   if (rc) return rc;
@@ -571,6 +585,19 @@ int mpsl_compute_layer_map(int n_layers, const mpsl_c128 *k, const double *thick
   }
   return MPSL_OK;
 }
+
+int mpsl_set_polarization(mpsl_ctx *ctx, int polarization) {
+  if (!ctx) return MPSL_EINVAL;
+  if (polarization != MPSL_TM && polarization != MPSL_TE)
+    return mpsl::set_err(ctx, MPSL_EINVAL, "polarization must be MPSL_TM or MPSL_TE");
+  if (polarization == ctx->pol) return MPSL_OK;
+  ctx->pol = polarization;
+  ctx->has_particle = false;  // its scattering matrix belongs to the other polarisation
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_get_polarization(const mpsl_ctx *ctx) { return ctx ? ctx->pol : MPSL_EINVAL; }
 
 int mpsl_set_layers(mpsl_ctx *ctx, mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, double d) {
   if (!ctx) return MPSL_EINVAL;
@@ -598,7 +625,7 @@ int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> S;
   std::string err;
-  const int rc0 = mpsl::disk_smatrix(R, ctx->k2.real(), kp, p, S, err);
+  const int rc0 = mpsl::disk_smatrix(R, ctx->k2.real(), kp, p, ctx->pol, S, err);
   if (rc0) return mpsl::set_err(ctx, rc0, err);
   ctx->p = p;
   ctx->r_enc = R;
@@ -615,7 +642,7 @@ int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c12
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> S;
   std::string err;
-  const int rc0 = mpsl::star_smatrix_checked(a1, a2, a3, ctx->k2.real(), kp, p, n_bdry, S, err);
+  const int rc0 = mpsl::star_smatrix_checked(a1, a2, a3, ctx->k2.real(), kp, p, n_bdry, ctx->pol, S, err);
   if (rc0) return mpsl::set_err(ctx, rc0, err);
   ctx->p = p;
   ctx->r_enc = a1 + std::fabs(a2);
@@ -627,22 +654,22 @@ int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c12
   return MPSL_OK;
 }
 
-int mpsl_compute_disk_smatrix(double R, mpsl_c128 k2, mpsl_c128 kp, int p, mpsl_c128 *S) {
+int mpsl_compute_disk_smatrix(double R, mpsl_c128 k2, mpsl_c128 kp, int p, int polarization, mpsl_c128 *S) {
   if (!S || k2.im != 0.0 || !(k2.re > 0.0)) return MPSL_EINVAL;
   std::vector<zc> v;
   std::string err;
-  const int rc = mpsl::disk_smatrix(R, k2.re, kp, p, v, err);
+  const int rc = mpsl::disk_smatrix(R, k2.re, kp, p, polarization, v, err);
   if (rc) return rc;
   for (size_t i = 0; i < v.size(); ++i) S[i] = {v[i].real(), v[i].imag()};
   return MPSL_OK;
 }
 
 int mpsl_compute_star_smatrix(double a1, double a2, int a3, mpsl_c128 k2, mpsl_c128 kp, int p, int n_bdry,
-                              mpsl_c128 *S) {
+                              int polarization, mpsl_c128 *S) {
   if (!S || k2.im != 0.0 || !(k2.re > 0.0)) return MPSL_EINVAL;
   std::vector<zc> v;
   std::string err;
-  const int rc = mpsl::star_smatrix_checked(a1, a2, a3, k2.re, kp, p, n_bdry, v, err);
+  const int rc = mpsl::star_smatrix_checked(a1, a2, a3, k2.re, kp, p, n_bdry, polarization, v, err);
   if (rc) return rc;
   for (size_t i = 0; i < v.size(); ++i) S[i] = {v[i].real(), v[i].imag()};
   return MPSL_OK;

@@ -106,6 +106,7 @@ struct mpsl_ctx {
   std::vector<mpsl::zc> ks;
   std::vector<double> thick, yint;
   int layer_c = 1;
+  int pol = MPSL_TM;    // MPSL_TE: (1/k^2) du/dn continuous instead of du/dn
   mpsl::zc k1, k2, k3;  // top half-space, particle layer, bottom half-space
   double d = 0.0;       // particle-layer thickness
 
@@ -165,8 +166,8 @@ namespace mpsl {
 int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes);
 void dev_free(DBuf &b);
 int set_err(mpsl_ctx *ctx, int code, const std::string &msg);
-int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, std::vector<zc> &S, std::string &err);
-int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry,
+int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, int pol, std::vector<zc> &S, std::string &err);
+int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry, int pol,
                          std::vector<zc> &S, std::string &err);
 // Layer stack per contour node lam (host, FP64).  Rup: generalized
 // reflection of the layers above the particle layer for an upgoing wave at

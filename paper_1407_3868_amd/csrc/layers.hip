@@ -1,4 +1,5 @@
-// Layer stacks of any number of layers around the particle layer (host, FP64).
+// Layer stacks of any number of layers around the particle layer (host, FP64),
+// TM or TE polarisation.
 //
 // The three-layer system of Section 2, eq. (10), couples the two particle-layer
 // densities through one reflection coefficient per interface.  With more
@@ -9,7 +10,9 @@
 // over the layers, outward from the half-spaces:
 //   R_j = (r + rho) / (1 + r rho),   rho = R_{j-1} e^{-2 gamma_{j-1} h_{j-1}},
 // with r the single-interface coefficient; every factor is bounded because
-// Re gamma >= 0 on the contour.
+// Re gamma >= 0 on the contour.  TE weights du/dy by 1/k^2 of its layer
+// (permittivity piecewise constant, permeability constant), which enters r
+// and t through kappa gamma.
 #include <cmath>
 
 #include "context.h"
@@ -18,12 +21,14 @@ namespace mpsl {
 
 namespace {
 
-// Single-interface coefficient for a wave in the layer with gamma ga meeting
-// the layer with gamma gb: reflected / incident (amplitudes divided by gamma).
-inline zc refl(zc ga, zc gb) { return (ga - gb) / (ga + gb); }
+// Single-interface coefficient for a wave in the layer with weighted gamma
+// za = kappa_a gamma_a meeting the layer with zb: reflected / incident
+// (amplitudes divided by gamma; kappa = 1 for TM, 1/k^2 for TE).
+inline zc refl(zc za, zc zb) { return (za - zb) / (za + zb); }
 
 struct StackWork {
   std::vector<zc> g, e, ru, tau, rd;
+  std::vector<double> kap;  // weight of du/dy per layer
 };
 
 // Recursions above and below the particle layer c; ru[j], tau[j] for
@@ -35,22 +40,30 @@ void stack_recursion(const mpsl_ctx *ctx, zc lam, StackWork &w) {
   w.ru.assign(L, zc(0.0, 0.0));
   w.tau.assign(L, zc(0.0, 0.0));
   w.rd.assign(L, zc(0.0, 0.0));
-  for (int j = 0; j < L; ++j) w.g[j] = gamma_branch(lam, ctx->ks[j]);
+  w.kap.assign(L, 1.0);
+  for (int j = 0; j < L; ++j) {
+    w.g[j] = gamma_branch(lam, ctx->ks[j]);
+    if (ctx->pol == MPSL_TE) w.kap[j] = 1.0 / (ctx->ks[j].real() * ctx->ks[j].real());
+  }
   for (int j = 1; j < L - 1; ++j) w.e[j] = std::exp(-w.g[j] * ctx->thick[j]);
-  // above: layer 1 under the top half-space, then one finite layer at a time
-  w.ru[1] = refl(w.g[1], w.g[0]);
-  w.tau[1] = 2.0 * w.g[1] / (w.g[0] + w.g[1]);
+  const std::vector<double> &kp = w.kap;
+  // above: layer 1 under the top half-space, then one finite layer at a time;
+  // the transmitted amplitude follows from u and kappa du/dy continuous:
+  // t = 2 kappa_j gamma_{j+1} / (kappa_j gamma_j + kappa_{j+1} gamma_{j+1})
+  w.ru[1] = refl(kp[1] * w.g[1], kp[0] * w.g[0]);
+  w.tau[1] = 2.0 * kp[0] * w.g[1] / (kp[0] * w.g[0] + kp[1] * w.g[1]);
   for (int j = 1; j < c; ++j) {
-    const zc r = refl(w.g[j + 1], w.g[j]);
+    const zc r = refl(kp[j + 1] * w.g[j + 1], kp[j] * w.g[j]);
+    const zc t = 2.0 * kp[j] * w.g[j + 1] / (kp[j] * w.g[j] + kp[j + 1] * w.g[j + 1]);
     const zc rho = w.ru[j] * w.e[j] * w.e[j];
     const zc den = 1.0 + r * rho;
     w.ru[j + 1] = (r + rho) / den;
-    w.tau[j + 1] = (1.0 + r) * w.e[j] * w.tau[j] / den;
+    w.tau[j + 1] = t * w.e[j] * w.tau[j] / den;
   }
   // below: layer L-2 over the bottom half-space, then upwards
-  w.rd[L - 2] = refl(w.g[L - 2], w.g[L - 1]);
+  w.rd[L - 2] = refl(kp[L - 2] * w.g[L - 2], kp[L - 1] * w.g[L - 1]);
   for (int j = L - 3; j >= c; --j) {
-    const zc r = refl(w.g[j], w.g[j + 1]);
+    const zc r = refl(kp[j] * w.g[j], kp[j + 1] * w.g[j + 1]);
     const zc rho = w.rd[j + 1] * w.e[j + 1] * w.e[j + 1];
     w.rd[j] = (r + rho) / (1.0 + r * rho);
   }
@@ -140,7 +153,7 @@ void stack_amplitudes(const mpsl_ctx *ctx, zc lam, zc gs, zc sp, zc sm, zc Pp, z
   for (int j = c - 1; j >= 1; --j) {
     // u and du/dy continuous across interface j give the upgoing wave at the
     // bottom of layer j; its downgoing wave follows from the layers above
-    const zc s = w.g[j] / w.g[j + 1] * (a + b), dl = b - a;
+    const zc s = w.g[j] / w.g[j + 1] * (a + b), dl = (w.kap[j + 1] / w.kap[j]) * (b - a);
     B[j] = 0.5 * (s - dl);
     a = B[j] * w.e[j];
     b = w.ru[j] * a + w.tau[j] * gs;
@@ -150,7 +163,7 @@ void stack_amplitudes(const mpsl_ctx *ctx, zc lam, zc gs, zc sp, zc sm, zc Pp, z
   // downwards: (down dn, up up) at the bottom interface of layer j - 1
   zc dn = w.e[c] * sp + Pm, up = sm;
   for (int j = c + 1; j <= L - 2; ++j) {
-    A[j] = 0.5 * (w.g[j] / w.g[j - 1] * (dn + up) + (dn - up));
+    A[j] = 0.5 * (w.g[j] / w.g[j - 1] * (dn + up) + (w.kap[j - 1] / w.kap[j]) * (dn - up));
     dn = A[j] * w.e[j];
     up = w.rd[j] * dn;
     B[j] = up;

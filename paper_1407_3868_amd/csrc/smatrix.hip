@@ -157,7 +157,7 @@ void besj(int n, double x, double &j, double &jp) {
 
 }  // namespace
 
-int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, std::vector<zc> &Sout,
+int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, int pol, std::vector<zc> &Sout,
                  std::string &err) {
   if (nb % 2 || nb < 16) {
     err = "n_bdry must be even and >= 16";
@@ -205,6 +205,11 @@ int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int 
       const double nn = c.nx[i] * c.nx[j] + c.ny[i] * c.ny[j];
       T[ij] = s / c.speed[i] + nn * (k2 * k2 * S2[ij] - kp * kp * Sp[ij]);
     }
+  // TE: (1/k^2) du/dn continuous.  With rho = k2^2 / kp^2 the interior field
+  // is S_p sigma + D_p mu / rho, which keeps the difference T2 - Tp and moves
+  // rho into the identity, Dp and Np terms (rho = 1: the TM system).
+  const double rho = (pol == MPSL_TE) ? (k2 * k2) / (kp * kp) : 1.0;
+  const double id_mu = 0.5 * (1.0 + 1.0 / rho), id_sig = 0.5 * (1.0 + rho);
   const int M = 2 * nb;
   std::vector<cd> A(static_cast<size_t>(M) * M, 0.0);
   for (int i = 0; i < nb; ++i)
@@ -212,8 +217,8 @@ int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int 
       const size_t ij = static_cast<size_t>(i) * nb + j;
       const double id = (i == j) ? 1.0 : 0.0;
       A[static_cast<size_t>(i) * M + j] = S2[ij] - Sp[ij];
-      A[static_cast<size_t>(i) * M + nb + j] = id + D2[ij] - Dp[ij];
-      A[static_cast<size_t>(nb + i) * M + j] = -id + N2[ij] - Np[ij];
+      A[static_cast<size_t>(i) * M + nb + j] = id_mu * id + D2[ij] - Dp[ij] / rho;
+      A[static_cast<size_t>(nb + i) * M + j] = -id_sig * id + N2[ij] - rho * Np[ij];
       A[static_cast<size_t>(nb + i) * M + nb + j] = T[ij];
     }
   // right-hand sides: -u_inc, -du_inc/dn for u_inc = J_n(k2 r) e^{in theta}

@@ -11,6 +11,8 @@ import pytest
 import paper_1407_3868_amd as mp
 from gpu_common import coeff_vector, make_workload, prototype_S, rel_err
 from oracle import contour as ocontour
+from oracle import mie as omie
+from oracle import star as ostar
 from oracle.stack import interfaces, stack_problem
 from synth import receivers
 
@@ -32,15 +34,32 @@ def _stack(kind, wl):
     raise ValueError(kind)
 
 
-def _setup(name, kind):
+_TE_S = {}
+
+
+def prototype_S_te(wl):
+    """TE prototype scattering matrix from the oracle."""
+    key = (wl.shape, wl.shape_params, wl.k2, wl.kp, wl.p)
+    if key not in _TE_S:
+        if wl.shape == "disk":
+            _TE_S[key] = np.diag(omie.disk_smatrix(wl.shape_params[0], wl.k2, wl.kp, wl.p, pol="TE"))
+        else:
+            a1, a2, a3 = wl.shape_params
+            _TE_S[key] = ostar.star_smatrix(a1, a2, a3, wl.k2, wl.kp, wl.p, nb=256, pol="TE")
+    return _TE_S[key]
+
+
+def _setup(name, kind, pol="TM"):
     wl = make_workload(name)
     ks, th, c = _stack(kind, wl)
     # one 16-node panel per interval between branch points, then refinement
     wl.n_nodes = max(wl.n_nodes, 32 * (len(ks) + 4))
-    S = prototype_S(wl)
+    S = prototype_S(wl) if pol == "TM" else prototype_S_te(wl)
     lam, w = ocontour.contour(wl.n_nodes, wl.b, wl.t_max, ks)
-    pr = stack_problem(ks, th, c, wl.p, S, wl.xy, wl.rot, lam, w)
+    pr = stack_problem(ks, th, c, wl.p, S, wl.xy, wl.rot, lam, w, pol=pol)
     ctx = mp.Context(0)
+    if pol == "TE":
+        ctx.set_polarization(mp.TE)
     ctx.set_layer_stack(ks, th, c)
     ctx.set_scattering_matrix(wl.p, wl.r_enclose, S)
     ctx.set_geometry(wl.xy, wl.rot)
@@ -144,3 +163,77 @@ def test_stack_arguments_are_checked():
     ctx.set_contour(wl.n_nodes, wl.b, wl.t_max)
     with pytest.raises(mp.MpslError):
         ctx.rhs(np.array([0.0, 0.5]))        # above the particle layer but below the top interface (y = 1)
+
+
+# ---- TE polarisation: (1/k^2) du/dn continuous ---------------------------------
+
+KINDS_TE = ["three", "five", "seven"]
+
+
+def _setup_te(name, kind):
+    if kind == "three":
+        wl = make_workload(name)
+        S = prototype_S_te(wl)
+        ks, th, c = [wl.k1, wl.k2, wl.k3], [0.0, wl.d, 0.0], 1
+        lam, w = ocontour.contour(wl.n_nodes, wl.b, wl.t_max, ks)
+        pr = stack_problem(ks, th, c, wl.p, S, wl.xy, wl.rot, lam, w, pol="TE")
+        ctx = mp.Context(0)
+        ctx.set_polarization(mp.TE)
+        ctx.set_layers(wl.k1, wl.k2, wl.k3, wl.d)
+        ctx.set_scattering_matrix(wl.p, wl.r_enclose, S)
+        ctx.set_geometry(wl.xy, wl.rot)
+        ctx.set_contour(wl.n_nodes, wl.b, wl.t_max)
+        return wl, (ks, th, c), pr, ctx
+    return _setup(name, kind, pol="TE")
+
+
+@pytest.mark.parametrize("name", ["s70p8", "s150p12"])
+@pytest.mark.parametrize("kind", KINDS_TE)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_te_matvec(name, kind, prec):
+    wl, _, pr, ctx = _setup_te(name, kind)
+    x = coeff_vector(wl, 6, S=pr.S)
+    got = ctx.apply(prec, x.astype(np.complex128 if prec == 0 else np.complex64))
+    err = rel_err(got, pr.matvec(x))
+    assert err < (1e-12 if prec == 0 else 2e-5), err
+
+
+@pytest.mark.parametrize("kind", KINDS_TE)
+def test_te_solve_and_field_match_lu(kind):
+    wl, (ks, th, c), pr, ctx = _setup_te("c1", kind)
+    src = np.array([0.4, interfaces(th, c)[0] + 1.0])
+    ref = pr.solve_lu(src)
+    beta, meta = ctx.solve(src, precision=0, tol=1e-13, maxiter=600)
+    assert meta["status"] == 0, meta
+    assert rel_err(beta, ref) < 1e-10
+    r = _rcv_all_layers(wl, th, c, src)
+    assert rel_err(ctx.eval_field(src, beta, r), pr.field(src, ref, r)) < 1e-10
+
+
+def test_te_library_particles_match_oracle():
+    """Disk and star matrices computed by the library under TE."""
+    ctx = mp.Context(0)
+    ctx.set_polarization(mp.TE)
+    ctx.set_layers(6.0, 9.0, 12.0, 8.0)
+    ctx.set_particle_disk(0.25, 15.0, 8)
+    assert np.max(np.abs(ctx.get_scattering_matrix()
+                         - np.diag(omie.disk_smatrix(0.25, 9.0, 15.0, 8, pol="TE")))) < 1e-13
+    ctx.set_particle_star(0.25, 0.05, 5, 15.0, 12, 256)
+    assert np.max(np.abs(ctx.get_scattering_matrix()
+                         - ostar.star_smatrix(0.25, 0.05, 5, 9.0, 15.0, 12, nb=256, pol="TE"))) < 1e-12
+
+
+def test_polarization_change_clears_the_particle():
+    wl = make_workload("c1")
+    ctx = mp.Context(0)
+    ctx.set_layers(wl.k1, wl.k2, wl.k3, wl.d)
+    ctx.set_particle_disk(0.25, wl.kp, wl.p)
+    ctx.set_geometry(wl.xy, wl.rot)
+    ctx.set_contour(wl.n_nodes, wl.b, wl.t_max)
+    ctx.apply(0, np.zeros((wl.n, wl.P), complex))
+    ctx.set_polarization(mp.TE)
+    assert ctx.polarization() == mp.TE
+    with pytest.raises(mp.MpslError):
+        ctx.apply(0, np.zeros((wl.n, wl.P), complex))
+    with pytest.raises(mp.MpslError):
+        ctx.set_polarization(7)

@@ -110,3 +110,40 @@ def test_contour_span(ks, b, t_max, h_max):
 def test_contour_span_bad_arguments(b, t_max, h_max):
     with pytest.raises(mp.MpslError):
         mp.compute_contour_span([6, 9, 12], b, t_max, h_max)
+
+
+# ---- TE polarisation ------------------------------------------------------------
+
+@pytest.mark.parametrize("R,k2,kp,p", [(0.25, 9.0, 15.0, 8), (0.3, 3.0, 2.0, 12)])
+def test_disk_matrix_te(R, k2, kp, p):
+    S = mp.compute_disk_smatrix(R, k2, kp, p, polarization=mp.TE)
+    assert np.max(np.abs(S - np.diag(omie.disk_smatrix(R, k2, kp, p, pol="TE")))) < 1e-13
+
+
+@pytest.mark.parametrize("a2,p,nb", [(0.05, 8, 128), (0.05, 12, 256), (0.0, 10, 128)])
+def test_star_matrix_te(a2, p, nb):
+    S = mp.compute_star_smatrix(0.25, a2, 5, 9.0, 15.0, p, nb, polarization=mp.TE)
+    ref = ostar.star_smatrix(0.25, a2, 5, 9.0, 15.0, p, nb=nb, pol="TE")
+    assert np.max(np.abs(S - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("ks,th,c", STACKS)
+def test_layer_map_te_matches_oracle_node_solve(ks, th, c):
+    lam, _ = ocontour.contour(512, 0.05, 40.0, ks)
+    got = mp.compute_layer_map(ks, th, c, lam, polarization=mp.TE)
+    M = ostack.node_system(lam, ks, th, c, pol="TE")
+    one = np.ones(lam.size, complex)
+    A, B = ostack._col_A(c), ostack._col_B(c)
+    ref = np.zeros((lam.size, 6), complex)
+    for col, kw in ((0, dict(Pp=one)), (1, dict(Pm=one)), (2, dict(src=(0.0, ostack.interfaces(th, c)[0])))):
+        X = np.linalg.solve(M, ostack.rhs(lam, ks, th, c, pol="TE", **kw)[..., None])[..., 0]
+        if col < 2:
+            ref[:, col], ref[:, 2 + col] = X[:, A], X[:, B]
+        else:
+            ref[:, 4], ref[:, 5] = X[:, A], X[:, B]
+    assert np.max(np.abs(got - ref) / (1 + np.abs(ref))) < 1e-12
+
+
+def test_bad_polarization():
+    with pytest.raises(mp.MpslError):
+        mp.compute_disk_smatrix(0.25, 9.0, 15.0, 8, polarization=2)
