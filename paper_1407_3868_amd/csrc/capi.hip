@@ -6,6 +6,7 @@
 #include <new>
 #include <set>
 
+#include "bie.h"
 #include "kernels.h"
 
 using mpsl::DBuf;
@@ -173,8 +174,8 @@ int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, int pol, std::vector<
 int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, int pol, std::vector<zc> &S,
                  std::string &err);
 
-int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry, int pol,
-                         std::vector<zc> &S, std::string &err) {
+// Argument rules of the star precompute; on success nb holds the boundary points.
+int star_args(double a1, double a2, int a3, mpsl_c128 kp, int p, int n_bdry, int pol, int &nb, std::string &err) {
   if (pol != MPSL_TM && pol != MPSL_TE) {
     err = "polarization must be MPSL_TM or MPSL_TE";
     return MPSL_EINVAL;
@@ -187,11 +188,19 @@ int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, 
     err = "star particles need a real kp";
     return MPSL_EUNSUPPORTED;
   }
-  const int nb = n_bdry > 0 ? n_bdry : 256;
+  nb = n_bdry > 0 ? n_bdry : 256;
   if (nb % 2 || nb < 64 || nb > 2048) {
     err = "n_bdry must be even, 64..2048";
     return MPSL_EINVAL;
   }
+  return MPSL_OK;
+}
+
+int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry, int pol,
+                         std::vector<zc> &S, std::string &err) {
+  int nb = 0;
+  const int rc = star_args(a1, a2, a3, kp, p, n_bdry, pol, nb, err);
+  if (rc) return rc;
   return star_smatrix(a1, a2, a3, k2, kp.re, p, nb, pol, S, err);
 }
 
@@ -642,8 +651,15 @@ int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c12
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> S;
   std::string err;
-  const int rc0 = mpsl::star_smatrix_checked(a1, a2, a3, ctx->k2.real(), kp, p, n_bdry, ctx->pol, S, err);
+  int nb = 0;
+  int rc0 = mpsl::star_args(a1, a2, a3, kp, p, n_bdry, ctx->pol, nb, err);
   if (rc0) return mpsl::set_err(ctx, rc0, err);
+  // host boundary tables, device assembly and solve
+  mpsl::StarParts parts;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc0 = mpsl::star_parts(a1, a2, a3, ctx->k2.real(), p, nb, parts, err)) ||
+      (rc0 = mpsl::star_smatrix_device(ctx, parts, ctx->k2.real(), kp.re, ctx->pol, S, err)))
+    return mpsl::set_err(ctx, rc0, err);
   ctx->p = p;
   ctx->r_enc = a1 + std::fabs(a2);
   ctx->S = S;

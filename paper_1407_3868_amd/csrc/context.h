@@ -167,6 +167,7 @@ int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes);
 void dev_free(DBuf &b);
 int set_err(mpsl_ctx *ctx, int code, const std::string &msg);
 int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, int pol, std::vector<zc> &S, std::string &err);
+int star_args(double a1, double a2, int a3, mpsl_c128 kp, int p, int n_bdry, int pol, int &nb, std::string &err);
 int star_smatrix_checked(double a1, double a2, int a3, double k2, mpsl_c128 kp, int p, int n_bdry, int pol,
                          std::vector<zc> &S, std::string &err);
 // Layer stack per contour node lam (host, FP64).  Rup: generalized

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "bie.h"
 #include "context.h"
 
 namespace mpsl {
@@ -157,34 +158,101 @@ void besj(int n, double x, double &j, double &jp) {
 
 }  // namespace
 
-int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, int pol, std::vector<zc> &Sout,
-                 std::string &err) {
+int star_parts(double a1, double a2, int a3, double k2, int p, int nb, StarParts &sp, std::string &err) {
   if (nb % 2 || nb < 16) {
     err = "n_bdry must be even and >= 16";
     return MPSL_EINVAL;
   }
-  const int P = 2 * p + 1;
+  const int P = 2 * p + 1, M = 2 * nb;
   const Curve c = star_curve(a1, a2, a3, nb);
   for (int j = 0; j < nb; ++j)
     if (!(c.r[j] > 0.0)) {
       err = "star radius must stay positive";
       return MPSL_EINVAL;
     }
+  sp.nb = nb;
+  sp.p = p;
+  sp.t = c.t;
+  sp.r = c.r;
+  sp.x = c.x;
+  sp.y = c.y;
+  sp.dx = c.dx;
+  sp.dy = c.dy;
+  sp.ddx = c.ddx;
+  sp.ddy = c.ddy;
+  sp.speed = c.speed;
+  sp.nx = c.nx;
+  sp.ny = c.ny;
   // Kress weights and the spectral derivative
   const int hn = nb / 2;
-  std::vector<double> Rk(nb);
+  sp.Rk.assign(nb, 0.0);
   for (int k = 0; k < nb; ++k) {
     double s = 0.0;
     for (int m = 1; m < hn; ++m) s += std::cos(m * k * M_PI / hn) / m;
-    Rk[k] = -(2.0 * M_PI / hn) * s - (M_PI / (static_cast<double>(hn) * hn)) * std::cos(k * M_PI);
+    sp.Rk[k] = -(2.0 * M_PI / hn) * s - (M_PI / (static_cast<double>(hn) * hn)) * std::cos(k * M_PI);
   }
-  std::vector<double> Fd(static_cast<size_t>(nb) * nb, 0.0);
+  sp.Fd.assign(static_cast<size_t>(nb) * nb, 0.0);
   for (int i = 0; i < nb; ++i)
     for (int j = 0; j < nb; ++j)
       if (i != j) {
         const int d = i - j;
-        Fd[static_cast<size_t>(i) * nb + j] = 0.5 * ((d % 2) ? -1.0 : 1.0) / std::tan(d * M_PI / nb);
+        sp.Fd[static_cast<size_t>(i) * nb + j] = 0.5 * ((d % 2) ? -1.0 : 1.0) / std::tan(d * M_PI / nb);
       }
+  // right-hand sides: -u_inc, -du_inc/dn for u_inc = J_n(k2 r) e^{in theta}
+  sp.B.assign(static_cast<size_t>(P) * M, 0.0);
+  std::vector<double> Jv(static_cast<size_t>(nb) * (p + 1)), Jd(Jv.size());
+  for (int j = 0; j < nb; ++j)
+    for (int n = 0; n <= p; ++n) besj(n, k2 * c.r[j], Jv[j * (p + 1) + n], Jd[j * (p + 1) + n]);
+  auto jval = [&](int j, int n, double &v, double &d) {  // J_n, J_n' with J_{-n} = (-1)^n J_n
+    const int a = n < 0 ? -n : n;
+    const double sg = (n < 0 && (a & 1)) ? -1.0 : 1.0;
+    v = sg * Jv[j * (p + 1) + a];
+    d = sg * Jd[j * (p + 1) + a];
+  };
+  const double h = 2.0 * M_PI / nb;
+  sp.Fs.assign(static_cast<size_t>(P) * nb, 0.0);
+  sp.Fm = sp.Fs;
+  for (int r = 0; r < P; ++r) {
+    const int n = r - p;
+    for (int j = 0; j < nb; ++j) {
+      double v, dv;
+      jval(j, n, v, dv);
+      const double th = c.t[j];
+      const double nr = c.nx[j] * std::cos(th) + c.ny[j] * std::sin(th);
+      const double nt = -c.nx[j] * std::sin(th) + c.ny[j] * std::cos(th);
+      const cd e = std::polar(1.0, n * th);
+      sp.B[static_cast<size_t>(r) * M + j] = -v * e;
+      sp.B[static_cast<size_t>(r) * M + nb + j] = -e * (k2 * dv * nr + cd(0.0, n / c.r[j]) * v * nt);
+      // eq. (35): beta^n_l = (i/4) sum_j w_j [J_l e^{-il theta} sigma + d/dn(J_l e^{-il theta}) mu]
+      const int l = n;
+      const cd em = std::polar(1.0, -l * th);
+      const cd w = cd(0.0, 0.25) * (h * c.speed[j]);
+      sp.Fs[static_cast<size_t>(r) * nb + j] = w * (v * em);
+      sp.Fm[static_cast<size_t>(r) * nb + j] = w * (em * (k2 * dv * nr - cd(0.0, l / c.r[j]) * v * nt));
+    }
+  }
+  return MPSL_OK;
+}
+
+int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int nb, int pol, std::vector<zc> &Sout,
+                 std::string &err) {
+  StarParts sp;
+  int rc = star_parts(a1, a2, a3, k2, p, nb, sp, err);
+  if (rc) return rc;
+  const int P = 2 * p + 1;
+  Curve c;
+  c.t = sp.t;
+  c.r = sp.r;
+  c.x = sp.x;
+  c.y = sp.y;
+  c.dx = sp.dx;
+  c.dy = sp.dy;
+  c.ddx = sp.ddx;
+  c.ddy = sp.ddy;
+  c.speed = sp.speed;
+  c.nx = sp.nx;
+  c.ny = sp.ny;
+  const std::vector<double> &Rk = sp.Rk, &Fd = sp.Fd;
   std::vector<cd> S2, D2, N2, S02, Sp, Dp, Np, S0p;
   layer_ops(k2, c, Rk, S2, D2, N2, S02);
   layer_ops(kp, c, Rk, Sp, Dp, Np, S0p);
@@ -221,57 +289,21 @@ int star_smatrix(double a1, double a2, int a3, double k2, double kp, int p, int 
       A[static_cast<size_t>(nb + i) * M + j] = -id_sig * id + N2[ij] - rho * Np[ij];
       A[static_cast<size_t>(nb + i) * M + nb + j] = T[ij];
     }
-  // right-hand sides: -u_inc, -du_inc/dn for u_inc = J_n(k2 r) e^{in theta}
-  std::vector<cd> B(static_cast<size_t>(P) * M);
-  std::vector<double> Jv(static_cast<size_t>(nb) * (p + 1)), Jd(Jv.size());
-  for (int j = 0; j < nb; ++j)
-    for (int n = 0; n <= p; ++n) besj(n, k2 * c.r[j], Jv[j * (p + 1) + n], Jd[j * (p + 1) + n]);
-  auto jval = [&](int j, int n, double &v, double &d) {  // J_n, J_n' with J_{-n} = (-1)^n J_n
-    const int a = n < 0 ? -n : n;
-    const double sg = (n < 0 && (a & 1)) ? -1.0 : 1.0;
-    v = sg * Jv[j * (p + 1) + a];
-    d = sg * Jd[j * (p + 1) + a];
-  };
-  for (int r = 0; r < P; ++r) {
-    const int n = r - p;
-    for (int j = 0; j < nb; ++j) {
-      double v, dv;
-      jval(j, n, v, dv);
-      const double th = c.t[j];
-      const cd e = std::polar(1.0, n * th);
-      const double nr = c.nx[j] * std::cos(th) + c.ny[j] * std::sin(th);
-      const double nt = -c.nx[j] * std::sin(th) + c.ny[j] * std::cos(th);
-      B[static_cast<size_t>(r) * M + j] = -v * e;
-      B[static_cast<size_t>(r) * M + nb + j] = -e * (k2 * dv * nr + cd(0.0, n / c.r[j]) * v * nt);
-    }
-  }
+  std::vector<cd> B = sp.B;
   if (!lu_solve(M, A, P, B)) {
     err = "singular boundary-integral system";
     return MPSL_ENUMERIC;
   }
-  // eq. (35): beta^n_l = (i/4) sum_j w_j [J_l e^{-il theta} sigma + d/dn(J_l e^{-il theta}) mu]
   Sout.assign(static_cast<size_t>(P) * P, 0.0);
-  const double h = 2.0 * M_PI / nb;
-  for (int li = 0; li < P; ++li) {
-    const int l = li - p;
+  for (int li = 0; li < P; ++li)
     for (int r = 0; r < P; ++r) {
       cd s = 0.0;
       const cd *sig = &B[static_cast<size_t>(r) * M];
       const cd *mu = sig + nb;
-      for (int j = 0; j < nb; ++j) {
-        double v, dv;
-        jval(j, l, v, dv);
-        const double th = c.t[j];
-        const cd e = std::polar(1.0, -l * th);
-        const double nr = c.nx[j] * std::cos(th) + c.ny[j] * std::sin(th);
-        const double nt = -c.nx[j] * std::sin(th) + c.ny[j] * std::cos(th);
-        const cd fs = v * e;
-        const cd fm = e * (k2 * dv * nr - cd(0.0, l / c.r[j]) * v * nt);
-        s += h * c.speed[j] * (fs * sig[j] + fm * mu[j]);
-      }
-      Sout[static_cast<size_t>(li) * P + r] = cd(0.0, 0.25) * s;
+      for (int j = 0; j < nb; ++j)
+        s += sp.Fs[static_cast<size_t>(li) * nb + j] * sig[j] + sp.Fm[static_cast<size_t>(li) * nb + j] * mu[j];
+      Sout[static_cast<size_t>(li) * P + r] = s;
     }
-  }
   return MPSL_OK;
 }
 
