@@ -42,11 +42,16 @@ class Problem:
     rot: np.ndarray        # (N,)
     lam: np.ndarray        # contour nodes (N_S,)
     w: np.ndarray          # contour weights (N_S,)
+    types: np.ndarray = None   # several particle types: S is (T, P, P), types[l] in 0..T-1
 
     def __post_init__(self):
         self.xy = np.asarray(self.xy, dtype=np.float64)
         self.rot = np.asarray(self.rot, dtype=np.float64)
         self.S = np.asarray(self.S, dtype=np.complex128)
+        if self.types is not None:
+            self.types = np.asarray(self.types, dtype=np.int64)
+            if self.S.ndim != 3 or self.types.shape != (self.xy.shape[0],):
+                raise ValueError("with types, S is (T, P, P) and types has one entry per particle")
         self.lam = np.asarray(self.lam, dtype=np.complex128)
         self.w = np.asarray(self.w, dtype=np.complex128)
         self.A = layered.node_matrix(self.lam, self.k1, self.k2, self.k3, self.d)
@@ -60,12 +65,16 @@ class Problem:
         return 2 * self.p + 1
 
     # -- building blocks -------------------------------------------------
+    def S_of(self, l):
+        """Prototype matrix of particle l (its type's, Section 4.2 Remark)."""
+        return self.S if self.types is None else self.S[self.types[l]]
+
     def apply_S(self, alpha, targets=None):
         """beta_l = S_{psi_l} alpha_l for each particle (eq. (21), Section 4.1)."""
         idx = np.arange(self.N) if targets is None else np.asarray(list(targets))
         out = np.empty((idx.size, self.P), dtype=np.complex128)
         for a, l in enumerate(idx):
-            out[a] = operators.rotated_smatrix(self.S, self.rot[l]) @ alpha[a]
+            out[a] = operators.rotated_smatrix(self.S_of(l), self.rot[l]) @ alpha[a]
         return out
 
     def sigma(self, beta=None, src=None):
@@ -145,7 +154,7 @@ class Problem:
         TR = Cp @ sig[:, 1, :] + Cm @ sig[:, 2, :]
         Sblk = np.zeros((N * P, N * P), dtype=np.complex128)
         for l in range(N):
-            Sblk[l * P:(l + 1) * P, l * P:(l + 1) * P] = operators.rotated_smatrix(self.S, self.rot[l])
+            Sblk[l * P:(l + 1) * P, l * P:(l + 1) * P] = operators.rotated_smatrix(self.S_of(l), self.rot[l])
         return np.eye(N * P) - Sblk @ (T + TR)
 
     def solve_lu(self, src):

@@ -103,7 +103,8 @@ def _gl_panels(a, b, breaks, panel):
     return np.concatenate(xs), np.concatenate(ws)
 
 
-def test_flux_balance_lossless():
+@pytest.mark.parametrize("kinds", [1, 2])
+def test_flux_balance_lossless(kinds):
     """Power balance for real wavenumbers: by Green's identity (u and its normal
     derivative continuous across every interface, Delta u + k^2 u = -delta at
     the source), the outgoing flux through any closed contour C around the
@@ -119,7 +120,12 @@ def test_flux_balance_lossless():
     wl = make_workload("c1")
     lam, w = oc.contour(512, wl.b, wl.t_max, [wl.k1, wl.k2, wl.k3])
     S = np.diag(mie.disk_smatrix(wl.shape_params[0], wl.k2, wl.kp, wl.p))
-    pr = system.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, S, wl.xy, wl.rot, lam, w)
+    if kinds == 1:
+        pr = system.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, S, wl.xy, wl.rot, lam, w)
+    else:   # two particle types (Section 4.2 Remark): every other disk smaller and softer
+        S2 = np.diag(mie.disk_smatrix(0.2, wl.k2, 11.0, wl.p))
+        pr = system.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, np.stack([S, S2]), wl.xy, wl.rot, lam, w,
+                            types=np.arange(wl.n) % 2)
     src = wl.src[0]
     beta = pr.solve_lu(src)
     xa, xb, ya, yb = -6.0, 6.0, -wl.d - 2.0, 4.0
@@ -182,3 +188,35 @@ def test_single_disk_matches_mie_series():
     exact = 0.25j * hankel1(0, k * np.hypot(rcv[:, 0] - src[0], rcv[:, 1] - src[1])) + scat
     err = np.max(np.abs(got - exact)) / np.max(np.abs(exact))
     assert err < 1e-11, err
+
+
+def test_types_with_one_matrix_equal_the_single_type_problem():
+    from synth import make_workload
+    from oracle import contour as oc, mie
+    wl = make_workload("c1")
+    lam, w = oc.contour(wl.n_nodes, wl.b, wl.t_max, [wl.k1, wl.k2, wl.k3])
+    S = np.diag(mie.disk_smatrix(wl.shape_params[0], wl.k2, wl.kp, wl.p))
+    a = system.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, S, wl.xy, wl.rot, lam, w)
+    b = system.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, np.stack([S, 0 * S]), wl.xy, wl.rot, lam, w,
+                       types=np.zeros(wl.n, int))
+    x = np.random.default_rng(0).standard_normal((wl.n, wl.P)) + 0j
+    assert np.array_equal(a.matvec(x), b.matvec(x))
+
+
+def test_a_type_that_does_not_scatter_removes_its_particles():
+    """Particles whose type has S = 0 radiate nothing: their beta vanish and
+    the others solve the problem without them."""
+    from synth import make_workload
+    from oracle import contour as oc, mie
+    wl = make_workload("c1")
+    lam, w = oc.contour(wl.n_nodes, wl.b, wl.t_max, [wl.k1, wl.k2, wl.k3])
+    S = np.diag(mie.disk_smatrix(wl.shape_params[0], wl.k2, wl.kp, wl.p))
+    types = (np.arange(wl.n) % 3 == 0).astype(int)
+    mixed = system.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, np.stack([S, 0 * S]), wl.xy, wl.rot, lam, w,
+                           types=types)
+    keep = types == 0
+    sub = system.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, S, wl.xy[keep], wl.rot[keep], lam, w)
+    src = wl.src[0]
+    b_mixed, b_sub = mixed.solve_lu(src), sub.solve_lu(src)
+    assert np.max(np.abs(b_mixed[~keep])) < 1e-14 * np.max(np.abs(b_sub))      # rounding of the dense solve
+    assert np.max(np.abs(b_mixed[keep] - b_sub)) < 1e-12 * np.max(np.abs(b_sub))
