@@ -155,6 +155,21 @@ int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c12
  * disk enclosing the prototype (used by geometry checks). */
 int mpsl_set_scattering_matrix(mpsl_ctx *ctx, int p, double r_enclose, const mpsl_c128 *S);
 
+/* Several particle types (Section 4.2, Remark): n_types (1..1024) prototype
+ * scattering matrices, S[t * P * P + (l + p) * P + (n + p)] for type t (the
+ * layout of mpsl_set_scattering_matrix per type), with enclosing radii
+ * r_enclose[t] > 0 (host arrays, copied).  All types share the order p.
+ * Particles get their types from mpsl_set_geometry_typed (mpsl_set_geometry:
+ * all type 0).  A geometry whose types no longer exist is dropped (set it
+ * again).  The scattering-matrix apply visits, per tile of 16 particles, only
+ * the types present in it: ordering particles by type keeps it one pass. */
+int mpsl_set_particle_types(mpsl_ctx *ctx, int n_types, int p, const double *r_enclose, const mpsl_c128 *S);
+
+/* mpsl_set_geometry with a type per particle: type[j] in 0..n_types-1 (host,
+ * n entries; NULL: all type 0).  The geometry checks use each particle's own
+ * enclosing radius. */
+int mpsl_set_geometry_typed(mpsl_ctx *ctx, int64_t n, const double *xy, const double *rot, const int32_t *type);
+
 /* Particle centres xy[2 * j], xy[2 * j + 1] and CCW rotations rot[j] (NULL
  * for all zero), j < n.  Fails with MPSL_EGEOM when two enclosing disks
  * overlap or an enclosing disk crosses y = 0 or y = -d.  Requires layers and

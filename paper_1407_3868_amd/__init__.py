@@ -220,11 +220,27 @@ class Context:
         S = _carr(S)
         return self._check(self.lib.mpsl_set_scattering_matrix(self.h, int(p), float(r_enclose), S.ctypes.data))
 
-    def set_geometry(self, xy, rot=None):
+    def set_geometry(self, xy, rot=None, types=None):
+        """Centres, rotations and (with several particle types) a type per particle."""
         xy = np.ascontiguousarray(xy, dtype=np.float64)
         r = None if rot is None else np.ascontiguousarray(rot, dtype=np.float64)
-        return self._check(self.lib.mpsl_set_geometry(self.h, int(xy.shape[0]), xy.ctypes.data,
-                                                      None if r is None else r.ctypes.data))
+        if types is None:
+            return self._check(self.lib.mpsl_set_geometry(self.h, int(xy.shape[0]), xy.ctypes.data,
+                                                          None if r is None else r.ctypes.data))
+        t = np.ascontiguousarray(types, dtype=np.int32)
+        if t.shape != (xy.shape[0],):
+            raise ValueError("one type per particle")
+        return self._check(self.lib.mpsl_set_geometry_typed(self.h, int(xy.shape[0]), xy.ctypes.data,
+                                                            None if r is None else r.ctypes.data, t.ctypes.data))
+
+    def set_particle_types(self, p, r_enclose, S):
+        """Several prototype matrices, S of shape (n_types, P, P) (mpsl_set_particle_types)."""
+        S = _carr(S)
+        r = np.ascontiguousarray(r_enclose, dtype=np.float64)
+        if S.ndim != 3 or S.shape[0] != r.size or S.shape[1:] != (2 * p + 1, 2 * p + 1):
+            raise ValueError("S is (n_types, P, P) with one radius per type")
+        return self._check(self.lib.mpsl_set_particle_types(self.h, int(r.size), int(p), r.ctypes.data,
+                                                            S.ctypes.data))
 
     def set_contour(self, n_nodes, b, t_max):
         return self._check(self.lib.mpsl_set_contour(self.h, int(n_nodes), float(b), float(t_max)))

@@ -42,6 +42,8 @@ SIGNATURES = {
     "mpsl_set_layers": (I, [P, c128, c128, c128, D]),
     "mpsl_set_layer_stack": (I, [P, I, P, P, I]),
     "mpsl_set_polarization": (I, [P, I]),
+    "mpsl_set_particle_types": (I, [P, I, I, P, P]),
+    "mpsl_set_geometry_typed": (I, [P, L, P, P, P]),
     "mpsl_get_polarization": (I, [P]),
     "mpsl_compute_layer_map": (I, [I, P, P, I, I, I, P, P]),
     "mpsl_set_particle_disk": (I, [P, D, c128, I]),

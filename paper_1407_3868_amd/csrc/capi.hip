@@ -548,7 +548,7 @@ void mpsl_destroy(mpsl_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto e : ctx->ev_start) (void)hipEventDestroy(e);
   for (auto e : ctx->ev_stop) (void)hipEventDestroy(e);
-  DBuf *bufs[] = {&ctx->bt, &ctx->S64, &ctx->S32, &ctx->ct.R, &ctx->ct.srcfac, &ctx->ct.lam, &ctx->ct.gw,
+  DBuf *bufs[] = {&ctx->bt, &ctx->S64, &ctx->S32, &ctx->types_dev, &ctx->rtype_dev, &ctx->ct.R, &ctx->ct.srcfac, &ctx->ct.lam, &ctx->ct.gw,
                   &ctx->ct.cq, &ctx->ct.W64, &ctx->ct.W32, &ctx->ct.U64, &ctx->gt.xy, &ctx->gt.rot64,
                   &ctx->gt.rot32, &ctx->gt.pair64, &ctx->gt.pair32, &ctx->gt.E64, &ctx->gt.E32, &ctx->gt.F64, &ctx->gt.F32, &ctx->part,
                   &ctx->m2s_part, &ctx->spec, &ctx->sigma, &ctx->Up64, &ctx->Up32, &ctx->xbuf,
@@ -629,6 +629,30 @@ static int upload_S(mpsl_ctx *ctx) {
   return MPSL_OK;
 }
 
+// Install n_types prototype matrices (n_types x P x P in S) with their
+// enclosing radii.  A geometry whose type ids no longer fit is dropped.
+static int install_prototypes(mpsl_ctx *ctx, int p, int n_types, const std::vector<double> &r_type,
+                              std::vector<zc> &&S) {
+  ctx->p = p;
+  ctx->n_types = n_types;
+  ctx->r_type = r_type;
+  ctx->r_enc = *std::max_element(r_type.begin(), r_type.end());
+  ctx->S = std::move(S);
+  int rc = upload_S(ctx);
+  if (rc) return rc;
+  if ((rc = mpsl::dev_alloc(ctx, ctx->rtype_dev, n_types * sizeof(double)))) return rc;
+  MPSL_HIP_TRY(ctx, hipMemcpy(ctx->rtype_dev.p, r_type.data(), n_types * sizeof(double), hipMemcpyHostToDevice));
+  for (int32_t t : ctx->ptype)
+    if (t >= n_types) {
+      ctx->ptype.clear();
+      ctx->has_geom = false;
+      break;
+    }
+  ctx->has_particle = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
 int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
   if (!ctx) return MPSL_EINVAL;
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
@@ -636,14 +660,7 @@ int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
   std::string err;
   const int rc0 = mpsl::disk_smatrix(R, ctx->k2.real(), kp, p, ctx->pol, S, err);
   if (rc0) return mpsl::set_err(ctx, rc0, err);
-  ctx->p = p;
-  ctx->r_enc = R;
-  ctx->S = S;
-  int rc = upload_S(ctx);
-  if (rc) return rc;
-  ctx->has_particle = true;
-  mpsl::invalidate(ctx);
-  return MPSL_OK;
+  return install_prototypes(ctx, p, 1, {R}, std::move(S));
 }
 
 int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c128 kp, int p, int n_bdry) {
@@ -660,14 +677,7 @@ int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c12
   if ((rc0 = mpsl::star_parts(a1, a2, a3, ctx->k2.real(), p, nb, parts, err)) ||
       (rc0 = mpsl::star_smatrix_device(ctx, parts, ctx->k2.real(), kp.re, ctx->pol, S, err)))
     return mpsl::set_err(ctx, rc0, err);
-  ctx->p = p;
-  ctx->r_enc = a1 + std::fabs(a2);
-  ctx->S = S;
-  int rc = upload_S(ctx);
-  if (rc) return rc;
-  ctx->has_particle = true;
-  mpsl::invalidate(ctx);
-  return MPSL_OK;
+  return install_prototypes(ctx, p, 1, {a1 + std::fabs(a2)}, std::move(S));
 }
 
 int mpsl_compute_disk_smatrix(double R, mpsl_c128 k2, mpsl_c128 kp, int p, int polarization, mpsl_c128 *S) {
@@ -691,36 +701,46 @@ int mpsl_compute_star_smatrix(double a1, double a2, int a3, mpsl_c128 k2, mpsl_c
   return MPSL_OK;
 }
 
-int mpsl_set_scattering_matrix(mpsl_ctx *ctx, int p, double r_enclose, const mpsl_c128 *S) {
-  if (!ctx || !S) return MPSL_EINVAL;
-  if (p < mpsl::kMinP || p > mpsl::kMaxP || !(r_enclose > 0.0))
-    return mpsl::set_err(ctx, MPSL_EINVAL, "need 1 <= p <= 20 and r_enclose > 0");
+int mpsl_set_particle_types(mpsl_ctx *ctx, int n_types, int p, const double *r_enclose, const mpsl_c128 *S) {
+  if (!ctx || !S || !r_enclose) return MPSL_EINVAL;
+  if (n_types < 1 || n_types > mpsl::kMaxTypes)
+    return mpsl::set_err(ctx, MPSL_EINVAL, "need 1 to " + std::to_string(mpsl::kMaxTypes) + " particle types");
+  if (p < mpsl::kMinP || p > mpsl::kMaxP) return mpsl::set_err(ctx, MPSL_EINVAL, "need 1 <= p <= 20");
+  std::vector<double> r(r_enclose, r_enclose + n_types);
+  for (double v : r)
+    if (!(v > 0.0) || !std::isfinite(v)) return mpsl::set_err(ctx, MPSL_EINVAL, "enclosing radii must be > 0");
   const int P = 2 * p + 1;
-  ctx->S.resize(static_cast<size_t>(P) * P);
-  for (size_t i = 0; i < ctx->S.size(); ++i) {
+  std::vector<zc> v(static_cast<size_t>(n_types) * P * P);
+  for (size_t i = 0; i < v.size(); ++i) {
     if (!std::isfinite(S[i].re) || !std::isfinite(S[i].im))
       return mpsl::set_err(ctx, MPSL_EINVAL, "scattering matrix has non-finite entries");
-    ctx->S[i] = zc(S[i].re, S[i].im);
+    v[i] = zc(S[i].re, S[i].im);
   }
-  ctx->p = p;
-  ctx->r_enc = r_enclose;
-  int rc = upload_S(ctx);
-  if (rc) return rc;
-  ctx->has_particle = true;
-  mpsl::invalidate(ctx);
-  return MPSL_OK;
+  return install_prototypes(ctx, p, n_types, r, std::move(v));
 }
 
-int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *rot) {
+int mpsl_set_scattering_matrix(mpsl_ctx *ctx, int p, double r_enclose, const mpsl_c128 *S) {
+  return mpsl_set_particle_types(ctx, 1, p, &r_enclose, S);
+}
+
+int mpsl_set_geometry_typed(mpsl_ctx *ctx, int64_t n, const double *xy, const double *rot, const int32_t *type) {
   if (!ctx || !xy || n <= 0) return MPSL_EINVAL;
   if (!ctx->has_layers || !ctx->has_particle) return mpsl::set_err(ctx, MPSL_ESTATE, "layers and particle first");
   if (n > (int64_t(1) << 30)) return mpsl::set_err(ctx, MPSL_EINVAL, "too many particles");
-  const double R = ctx->r_enc, d = ctx->d;
+  const double d = ctx->d, rmax = ctx->r_enc;
+  std::vector<int32_t> ty(static_cast<size_t>(n), 0);
+  if (type)
+    for (int64_t j = 0; j < n; ++j) {
+      if (type[j] < 0 || type[j] >= ctx->n_types)
+        return mpsl::set_err(ctx, MPSL_EINVAL, "particle " + std::to_string(j) + " has no such type");
+      ty[j] = type[j];
+    }
+  auto rad = [&](int64_t j) { return ctx->r_type[ty[j]]; };
   for (int64_t j = 0; j < n; ++j) {
     const double x = xy[2 * j], y = xy[2 * j + 1];
     if (!std::isfinite(x) || !std::isfinite(y) || (rot && !std::isfinite(rot[j])))
       return mpsl::set_err(ctx, MPSL_EINVAL, "non-finite centre or rotation");
-    if (y + R > 0.0 || y - R < -d)
+    if (y + rad(j) > 0.0 || y - rad(j) < -d)
       return mpsl::set_err(ctx, MPSL_EGEOM, "particle " + std::to_string(j) + " leaves the middle layer");
   }
   // enclosing disks must be disjoint: sweep in x
@@ -732,9 +752,10 @@ int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *
     for (int64_t b = a + 1; b < n; ++b) {
       const int64_t j = ord[b];
       const double dx = xy[2 * j] - xy[2 * i];
-      if (dx >= 2.0 * R) break;
+      if (dx >= rad(i) + rmax) break;
       const double dy = xy[2 * j + 1] - xy[2 * i + 1];
-      if (dx * dx + dy * dy < 4.0 * R * R)
+      const double rr = rad(i) + rad(j);
+      if (dx * dx + dy * dy < rr * rr)
         return mpsl::set_err(ctx, MPSL_EGEOM,
                              "enclosing disks of particles " + std::to_string(i) + " and " + std::to_string(j) +
                                  " overlap");
@@ -747,10 +768,21 @@ int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *
   int rc = mpsl::dev_alloc(ctx, ctx->gt.xy, static_cast<size_t>(n) * sizeof(double2));
   if (rc) return rc;
   MPSL_HIP_TRY(ctx, hipMemcpy(ctx->gt.xy.p, xy, static_cast<size_t>(n) * sizeof(double2), hipMemcpyHostToDevice));
+  ctx->ptype.clear();
+  if (ctx->n_types > 1) {
+    ctx->ptype = ty;
+    if ((rc = mpsl::dev_alloc(ctx, ctx->types_dev, static_cast<size_t>(n) * sizeof(int32_t)))) return rc;
+    MPSL_HIP_TRY(ctx, hipMemcpy(ctx->types_dev.p, ty.data(), static_cast<size_t>(n) * sizeof(int32_t),
+                                hipMemcpyHostToDevice));
+  }
   ctx->has_geom = true;
   ctx->gt.pairs_ok = false;
   mpsl::invalidate(ctx);
   return MPSL_OK;
+}
+
+int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *rot) {
+  return mpsl_set_geometry_typed(ctx, n, xy, rot, nullptr);
 }
 
 int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max) {

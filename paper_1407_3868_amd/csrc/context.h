@@ -114,8 +114,13 @@ struct mpsl_ctx {
   bool has_particle = false;
   int p = 0;
   double r_enc = 0.0;
-  std::vector<mpsl::zc> S;  // P x P row-major
+  std::vector<mpsl::zc> S;  // n_types x P x P row-major
   mpsl::DBuf S64, S32;
+  // several particle types (one prototype matrix each); r_enc is their maximum
+  int n_types = 1;
+  std::vector<double> r_type;       // enclosing radius per type
+  std::vector<int32_t> ptype;       // type per particle (empty: all type 0)
+  mpsl::DBuf types_dev, rtype_dev;  // int32[n] (only with n_types > 1), double[n_types]
 
   // geometry
   bool has_geom = false;

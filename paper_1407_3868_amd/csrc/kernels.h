@@ -11,6 +11,8 @@ constexpr int kMaxP = 20;
 // Largest contour, and largest particles x nodes product (the plane-wave
 // factor tables hold 2 N N_S entries per precision).
 constexpr int kMaxNodes = 1 << 20;
+// Largest number of particle types (prototype scattering matrices).
+constexpr int kMaxTypes = 1024;
 constexpr int64_t kMaxPlaneWaves = int64_t(1) << 29;
 
 // Row a0: per-particle plane-wave factor tables of the contour (E, F) and

@@ -469,7 +469,8 @@ __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__rest
                                                            const cv_t<T> *__restrict__ alpha,
                                                            const cv_t<T> *__restrict__ S,
                                                            const cv_t<T> *__restrict__ rot, int n,
-                                                           cv_t<T> *__restrict__ y, int64_t astride) {
+                                                           cv_t<T> *__restrict__ y, int64_t astride,
+                                                           const int32_t *__restrict__ types, int ntypes) {
   constexpr int P = 2 * p + 1;
   constexpr int MT = (P + 15) / 16;   // row tiles of S
   constexpr int KP = (P + 3) / 4 * 4; // K padded to the MFMA depth
@@ -483,18 +484,14 @@ __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__rest
   __shared__ T Sre[MT * 16][KP], Sim[MT * 16][KP];
   __shared__ T Bre[KP][16], Bim[KP][16];
   __shared__ cx<T> Yt[16 * P];
+  __shared__ int32_t tt[16];  // particle types of the tile (-1 past the end)
   const int tid = threadIdx.x;
   const int l0 = blockIdx.x * 16;
-  for (int i = tid; i < MT * 16 * KP; i += kSapplyThreads) {
-    const int r = i / KP, c = i % KP;
-    const cx<T> v = (r < P && c < P) ? ld<T>(S[r * P + c]) : mk<T>(0, 0);
-    Sre[r][c] = v.re;
-    Sim[r][c] = v.im;
-  }
   for (int i = tid; i < KP * 16; i += kSapplyThreads) {
     Bre[i / 16][i % 16] = 0;
     Bim[i / 16][i % 16] = 0;
   }
+  if (tid < 16) tt[tid] = (l0 + tid < n) ? (types ? types[l0 + tid] : 0) : -1;
   __syncthreads();
   const int cnt = min(16, n - l0) * P;  // entries of the tile
   const int64_t base = static_cast<int64_t>(l0) * P;
@@ -503,22 +500,43 @@ __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__rest
     Bre[i % P][i / P] = s.re;
     Bim[i % P][i / P] = s.im;
   }
-  __syncthreads();
   const int w = tid >> 6, lane = tid & 63;
-  if (w < MT) {
-    typename mfma4<T>::v4 are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
-    const int row = w * 16 + (lane & 15);
-    const int col = lane & 15;
-#pragma unroll
-    for (int k0 = 0; k0 < KP; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      const T sr = Sre[row][k], si = Sim[row][k];
-      const T br = Bre[k][col], bi = Bim[k][col];
-      are = mfma4<T>::mac(sr, br, are);
-      are = mfma4<T>::mac(-si, bi, are);
-      aim = mfma4<T>::mac(sr, bi, aim);
-      aim = mfma4<T>::mac(si, br, aim);
+  const int row = w * 16 + (lane & 15);
+  const int col = lane & 15;
+  typename mfma4<T>::v4 are = {0, 0, 0, 0}, aim = {0, 0, 0, 0};
+  // several particle types: one pass per type present in the tile, with the
+  // other columns of B masked out, so each column meets its own matrix
+  const int nt = types ? ntypes : 1;
+  for (int t = 0; t < nt; ++t) {
+    if (types) {
+      bool present = false;
+      for (int c = 0; c < 16; ++c) present |= (tt[c] == t);
+      if (!present) continue;  // uniform over the block
     }
+    __syncthreads();  // B written (first pass) or the previous S consumed
+    const cv_t<T> *St = S + static_cast<int64_t>(t) * P * P;
+    for (int i = tid; i < MT * 16 * KP; i += kSapplyThreads) {
+      const int r = i / KP, c = i % KP;
+      const cx<T> v = (r < P && c < P) ? ld<T>(St[r * P + c]) : mk<T>(0, 0);
+      Sre[r][c] = v.re;
+      Sim[r][c] = v.im;
+    }
+    __syncthreads();
+    if (w < MT) {
+      const bool on = !types || tt[col] == t;
+#pragma unroll
+      for (int k0 = 0; k0 < KP; k0 += 4) {
+        const int k = k0 + (lane >> 4);
+        const T sr = Sre[row][k], si = Sim[row][k];
+        const T br = on ? Bre[k][col] : T(0), bi = on ? Bim[k][col] : T(0);
+        are = mfma4<T>::mac(sr, br, are);
+        are = mfma4<T>::mac(-si, bi, are);
+        aim = mfma4<T>::mac(sr, bi, aim);
+        aim = mfma4<T>::mac(si, br, aim);
+      }
+    }
+  }
+  if (w < MT) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int nn = w * 16 + mfma4<T>::row(lane, j);
@@ -796,8 +814,8 @@ __global__ void k_field(const double2 *__restrict__ xy, const double2 *__restric
                         const double2 *__restrict__ lam, const double2 *__restrict__ w,
                         const double2 *__restrict__ gl, const double2 *__restrict__ amp,
                         const double *__restrict__ yint, int L, int c, int ns, double k0, double kc, double r_enc,
-                        double xs, double ys, const double2 *__restrict__ rcv, int64_t nr,
-                        double2 *__restrict__ u) {
+                        const int32_t *__restrict__ types, const double *__restrict__ rtype, double xs, double ys,
+                        const double2 *__restrict__ rcv, int64_t nr, double2 *__restrict__ u) {
   const int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (r >= nr) return;
   const double X = rcv[r].x, Y = rcv[r].y;
@@ -832,7 +850,7 @@ __global__ void k_field(const double2 *__restrict__ xy, const double2 *__restric
     for (int m = 0; m < n; ++m) {
       const double dx = X - xy[m].x, dy = Y - xy[m].y;
       const double rr = sqrt(dx * dx + dy * dy);
-      if (rr < r_enc) inside = true;
+      if (rr < (types ? rtype[types[m]] : r_enc)) inside = true;
       const double z = kc * rr;
       const cx<double> t = mk(dx / rr, dy / rr);
       const double2 *b = beta + static_cast<int64_t>(m) * P;
@@ -1125,9 +1143,13 @@ static int launch_sapply_t(mpsl_ctx *ctx, const void *x, const void *alpha, void
   const auto *xx = static_cast<const cv_t<T> *>(x);
   const auto *aa = static_cast<const cv_t<T> *>(alpha);
   auto *yy = static_cast<cv_t<T> *>(y);
+  // per-particle types only when several prototypes and a typed geometry
+  const bool typed = ctx->n_types > 1 && !ctx->ptype.empty();
+  const int32_t *ty = typed ? static_cast<const int32_t *>(ctx->types_dev.p) : nullptr;
+  const int nt = typed ? ctx->n_types : 1;
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_sapply<T, PP>), grid, block, 0, ctx->stream, xx, aa, S, rot, n, yy, astride); break;
+  case PP: hipLaunchKernelGGL((k_sapply<T, PP>), grid, block, 0, ctx->stream, xx, aa, S, rot, n, yy, astride, ty, nt); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
@@ -1220,7 +1242,10 @@ int launch_field(mpsl_ctx *ctx, const void *beta, const void *gl, const void *am
                      static_cast<const double2 *>(ctx->ct.gw.p) + 3 * ctx->ns,  // weights stored after g1,g2,g3
                      static_cast<const double2 *>(gl), static_cast<const double2 *>(amp),
                      static_cast<const double *>(yint), static_cast<int>(ctx->ks.size()), ctx->layer_c, ctx->ns,
-                     ctx->k1.real(), ctx->k2.real(), ctx->r_enc, src[0], src[1],
+                     ctx->k1.real(), ctx->k2.real(), ctx->r_enc,
+                     (ctx->n_types > 1 && !ctx->ptype.empty()) ? static_cast<const int32_t *>(ctx->types_dev.p)
+                                                                : nullptr,
+                     static_cast<const double *>(ctx->rtype_dev.p), src[0], src[1],
                      static_cast<const double2 *>(rcv), nr, static_cast<double2 *>(u));
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
