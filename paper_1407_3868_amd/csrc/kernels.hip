@@ -362,44 +362,6 @@ __global__ void k_s2l_coef(const double2 *__restrict__ sigma, const double2 *__r
   Up32[i] = make_float2(static_cast<float>(v.re), static_cast<float>(v.im));
 }
 
-// ---------------------------------------------------------------------------
-// Row b3: S2L.  One lane per target; each block walks a chunk of nodes:
-// alpha_n += F+[q][l] Up+[q][n] + F-[q][l] Up-[q][n]  (Up wave-uniform).
-template <typename T, int p>
-__global__ __launch_bounds__(kThreads) void k_s2l(const cv_t<T> *__restrict__ F,
-                                                  const cv_t<T> *__restrict__ Up,
-                                                  cv_t<T> *__restrict__ part, int n, int ns,
-                                                  int chunk_len, int64_t pstride) {
-  constexpr int P = 2 * p + 1;
-  const int l = blockIdx.x * kThreads + threadIdx.x;
-  const int c = blockIdx.y;
-  Up += 2 * static_cast<int64_t>(ns) * P * blockIdx.z;  // right-hand side
-  part += blockIdx.z * pstride;
-  const int q0 = c * chunk_len;
-  const int q1 = min(ns, q0 + chunk_len);
-  const bool valid = l < n;
-  const int lc = valid ? l : 0;
-  cx<T> acc[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
-  const int64_t side = static_cast<int64_t>(ns) * n;
-  for (int q = q0; q < q1; ++q) {
-    const cx<T> fp = ld<T>(F[static_cast<int64_t>(q) * n + lc]);
-    const cx<T> fm = ld<T>(F[side + static_cast<int64_t>(q) * n + lc]);
-    const cv_t<T> *up = Up + static_cast<int64_t>(q) * P;
-    const cv_t<T> *um = Up + (static_cast<int64_t>(ns) + q) * P;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      cmac(acc[i], fp, ld<T>(up[i]));
-      cmac(acc[i], fm, ld<T>(um[i]));
-    }
-  }
-  if (valid) {
-    cv_t<T> *o = part + (static_cast<int64_t>(c) * n + l) * P;
-#pragma unroll
-    for (int i = 0; i < P; ++i) o[i] = st(acc[i]);
-  }
-}
 
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -548,6 +510,95 @@ __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__rest
     cx<T> r = conj(ld<T>(rot[base + i])) * Yt[i];
     if (x) r = ld<T>(x[base + i]) - r;
     y[base + i] = st(r);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row b3 on the matrix cores: S2L as a GEMM over the nodes of both interfaces,
+//   part[c][l][n] = sum_{side, q in chunk c} F[side][q][l] Up[side][q][n]
+// (M = particle, N = order, K = node).  One wave per 16 particles and all
+// order tiles; lane i supplies A[i % 16][i / 16] = F of particle l0 + i % 16 at
+// node q0 + i / 16 (16 consecutive particles per node: coalesced) and
+// B[i / 16][i % 16] = the S2L coefficient of that node and order; the complex
+// product runs as four real chains per tile.
+constexpr int kS2lWaves = 4;
+template <typename T, int p>
+__global__ __launch_bounds__(64 * kS2lWaves) void k_s2l_mfma(const cv_t<T> *__restrict__ F,
+                                                             const cv_t<T> *__restrict__ Up,
+                                                             cv_t<T> *__restrict__ part, int n, int ns,
+                                                             int chunk_len, int64_t pstride) {
+  constexpr int P = 2 * p + 1;
+  constexpr int NT = (P + 15) / 16;  // order tiles
+  Up += 2 * static_cast<int64_t>(ns) * P * blockIdx.z;  // right-hand side
+  part += blockIdx.z * pstride;
+  const int c = blockIdx.y;
+  const int q0 = c * chunk_len;
+  const int q1 = min(ns, q0 + chunk_len);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l0 = (blockIdx.x * kS2lWaves + w) * 16;
+  if (l0 >= n) return;  // the whole wave lies past the last particle (no barriers below)
+  const int li = l0 + (lane & 15);
+  const bool lv = li < n;
+  const int kr = lane >> 4;
+  typename mfma4<T>::v4 are[NT], aim[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    are[t] = typename mfma4<T>::v4{0, 0, 0, 0};
+    aim[t] = typename mfma4<T>::v4{0, 0, 0, 0};
+  }
+  if (q0 >= q1) goto store;  // empty chunk
+  {
+    // operands of node group qb (loads clamped into range, zeros selected
+    // outside it), the next group fetched while the current one multiplies
+    const int lic = lv ? li : n - 1;
+    auto fetch = [&](int side, int qb, cv_t<T> &a, cv_t<T> (&b)[NT]) {
+      const int q = qb + kr;
+      const int qc = min(q, q1 - 1);
+      a = F[(side * static_cast<int64_t>(ns) + qc) * n + lic];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int col = min(t * 16 + (lane & 15), P - 1);
+        b[t] = Up[(side * static_cast<int64_t>(ns) + qc) * P + col];
+      }
+    };
+    cv_t<T> an, bn[NT];
+    fetch(0, q0, an, bn);
+    for (int side = 0, qb = q0; side < 2;) {
+      const cv_t<T> ac = an;
+      cv_t<T> bc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bc[t] = bn[t];
+      const bool qv = qb + kr < q1;
+      int ns_side = side, ns_qb = qb + 4;
+      if (ns_qb >= q1) {
+        ns_side = side + 1;
+        ns_qb = q0;
+      }
+      if (ns_side < 2) fetch(ns_side, ns_qb, an, bn);
+      const T zr = (qv && lv) ? ac.x : T(0), zi = (qv && lv) ? ac.y : T(0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bool cv = qv && (t * 16 + (lane & 15)) < P;
+        const T br = cv ? bc[t].x : T(0), bi = cv ? bc[t].y : T(0);
+        are[t] = mfma4<T>::mac(zr, br, are[t]);
+        are[t] = mfma4<T>::mac(-zi, bi, are[t]);
+        aim[t] = mfma4<T>::mac(zr, bi, aim[t]);
+        aim[t] = mfma4<T>::mac(zi, br, aim[t]);
+      }
+      side = ns_side;
+      qb = ns_qb;
+    }
+  }
+store:
+  cv_t<T> *o = part + static_cast<int64_t>(c) * n * P;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int l = l0 + mfma4<T>::row(lane, j);
+      if (l < n && col < P) o[static_cast<int64_t>(l) * P + col] = st(mk<T>(are[t][j], aim[t][j]));
+    }
   }
 }
 
@@ -1099,14 +1150,14 @@ template <typename T>
 static int launch_s2l_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstride) {
   const int n = static_cast<int>(ctx->n);
   const int chunk_len = cdiv(ctx->ns, chunks);
-  const dim3 grid(cdiv(n, kThreads), chunks, nrhs);
+  const dim3 grid(cdiv(n, 16 * kS2lWaves), chunks, nrhs);
   const bool f64 = std::is_same<T, double>::value;
   const auto *F = static_cast<const cv_t<T> *>(f64 ? ctx->gt.F64.p : ctx->gt.F32.p);
   const auto *Up = static_cast<const cv_t<T> *>(f64 ? ctx->Up64.p : ctx->Up32.p);
   auto *o = static_cast<cv_t<T> *>(part);
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_s2l<T, PP>), grid, dim3(kThreads), 0, ctx->stream, F, Up, o, n, ctx->ns, chunk_len, pstride); break;
+  case PP: hipLaunchKernelGGL((k_s2l_mfma<T, PP>), grid, dim3(64 * kS2lWaves), 0, ctx->stream, F, Up, o, n, ctx->ns, chunk_len, pstride); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
