@@ -268,41 +268,6 @@ __global__ __launch_bounds__(kThreads) void k_fmm_near(const cv_t<T> *__restrict
   }
 }
 
-// ---------------------------------------------------------------------------
-// Row b1: M2S.  One lane per contour node q and side s; each block walks a
-// chunk of particles: acc_nu = sum_m E_s[m][q] beta^m_nu (beta wave-uniform),
-// then partial = sum_nu W_s[q][nu] acc_nu.
-template <typename T, int p>
-__global__ __launch_bounds__(kThreads) void k_m2s_part(const cv_t<T> *__restrict__ E,
-                                                       const cv_t<T> *__restrict__ beta,
-                                                       const cv_t<T> *__restrict__ W,
-                                                       cv_t<T> *__restrict__ part, int n, int ns,
-                                                       int chunk_len, int chunks) {
-  constexpr int P = 2 * p + 1;
-  const int q = blockIdx.x * kThreads + threadIdx.x;
-  const int c = blockIdx.y;
-  const int s = blockIdx.z & 1;  // side
-  const int r = blockIdx.z >> 1; // right-hand side
-  beta += static_cast<int64_t>(r) * n * P;
-  if (q >= ns) return;
-  const int m0 = c * chunk_len;
-  const int m1 = min(n, m0 + chunk_len);
-  const cv_t<T> *Es = E + static_cast<int64_t>(s) * n * ns;
-  cx<T> acc[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) acc[i] = mk<T>(0, 0);
-  for (int m = m0; m < m1; ++m) {
-    const cx<T> e = ld<T>(Es[static_cast<int64_t>(m) * ns + q]);
-    const cv_t<T> *bm = beta + static_cast<int64_t>(m) * P;
-#pragma unroll
-    for (int i = 0; i < P; ++i) cmac(acc[i], e, ld<T>(bm[i]));
-  }
-  const cv_t<T> *Wq = W + (static_cast<int64_t>(s) * ns + q) * P;
-  cx<T> acc_r = mk<T>(0, 0);
-#pragma unroll
-  for (int i = 0; i < P; ++i) cmac(acc_r, acc[i], ld<T>(Wq[i]));
-  part[((2 * static_cast<int64_t>(r) + s) * chunks + c) * ns + q] = st(acc_r);
-}
 
 template <typename T>
 __global__ void k_m2s_reduce(const cv_t<T> *__restrict__ part, int ns, int chunks, int nrhs,
@@ -510,6 +475,93 @@ __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__rest
     cx<T> r = conj(ld<T>(rot[base + i])) * Yt[i];
     if (x) r = ld<T>(x[base + i]) - r;
     y[base + i] = st(r);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row b1 on the matrix cores: M2S as a GEMM over the particles of a chunk,
+//   G[q][nu] = sum_{m in chunk c} E[s][m][q] beta[m][nu]   (M = node, N = order,
+// K = particle), then part[r][s][c][q] = sum_nu W[s][q][nu] G[q][nu] in the
+// epilogue (a reduction over the 16 lanes that hold one node's orders).  One
+// wave per 16 nodes; lane i supplies A[i % 16][i / 16] = E of node q0 + i % 16
+// for particle m0 + i / 16 (16 consecutive nodes: coalesced) and
+// B[i / 16][i % 16] = beta of that particle and order.
+constexpr int kM2sWaves = 4;
+template <typename T, int p>
+__global__ __launch_bounds__(64 * kM2sWaves) void k_m2s_mfma(const cv_t<T> *__restrict__ E,
+                                                             const cv_t<T> *__restrict__ beta,
+                                                             const cv_t<T> *__restrict__ W,
+                                                             cv_t<T> *__restrict__ part, int n, int ns,
+                                                             int chunk_len, int chunks) {
+  constexpr int P = 2 * p + 1;
+  constexpr int NT = (P + 15) / 16;  // order tiles
+  const int c = blockIdx.y;
+  const int s = blockIdx.z & 1;   // side
+  const int r = blockIdx.z >> 1;  // right-hand side
+  beta += static_cast<int64_t>(r) * n * P;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q0 = (blockIdx.x * kM2sWaves + w) * 16;
+  if (q0 >= ns) return;  // the whole wave lies past the last node (no barriers below)
+  const int m0 = c * chunk_len;
+  const int m1 = min(n, m0 + chunk_len);
+  const int qi = q0 + (lane & 15);
+  const int qic = min(qi, ns - 1);
+  const int kr = lane >> 4;
+  const cv_t<T> *Es = E + static_cast<int64_t>(s) * n * ns;
+  typename mfma4<T>::v4 are[NT], aim[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    are[t] = typename mfma4<T>::v4{0, 0, 0, 0};
+    aim[t] = typename mfma4<T>::v4{0, 0, 0, 0};
+  }
+  if (m0 < m1) {
+    // operands of particle group mb (loads clamped into range, zeros selected
+    // past the chunk), the next group fetched while the current one multiplies
+    auto fetch = [&](int mb, cv_t<T> &a, cv_t<T> (&b)[NT]) {
+      const int mc = min(mb + kr, m1 - 1);
+      a = Es[static_cast<int64_t>(mc) * ns + qic];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b[t] = beta[static_cast<int64_t>(mc) * P + min(t * 16 + (lane & 15), P - 1)];
+    };
+    cv_t<T> an, bn[NT];
+    fetch(m0, an, bn);
+    for (int mb = m0; mb < m1; mb += 4) {
+      const cv_t<T> ac = an;
+      cv_t<T> bc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bc[t] = bn[t];
+      if (mb + 4 < m1) fetch(mb + 4, an, bn);
+      const bool mv = mb + kr < m1;
+      const T zr = mv ? ac.x : T(0), zi = mv ? ac.y : T(0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        are[t] = mfma4<T>::mac(zr, bc[t].x, are[t]);
+        are[t] = mfma4<T>::mac(-zi, bc[t].y, are[t]);
+        aim[t] = mfma4<T>::mac(zr, bc[t].y, aim[t]);
+        aim[t] = mfma4<T>::mac(zi, bc[t].x, aim[t]);
+      }
+    }
+  }
+  // epilogue: contract each node's orders with W, reduce over the 16 lanes
+  // holding that node's columns, one lane per node stores
+  const cv_t<T> *Ws = W + static_cast<int64_t>(s) * ns * P;
+  cv_t<T> *o = part + ((2 * static_cast<int64_t>(r) + s) * chunks + c) * ns;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int q = q0 + mfma4<T>::row(lane, j);
+    const int qc = min(q, ns - 1);
+    cx<T> acc = mk<T>(0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = t * 16 + (lane & 15);
+      if (col < P) cmac(acc, mk<T>(are[t][j], aim[t][j]), ld<T>(Ws[static_cast<int64_t>(qc) * P + col]));
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+      acc.re += __shfl_xor(acc.re, off, 16);
+      acc.im += __shfl_xor(acc.im, off, 16);
+    }
+    if ((lane & 15) == 0 && q < ns) o[q] = st(acc);
   }
 }
 
@@ -1099,7 +1151,7 @@ static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
   const int n = static_cast<int>(ctx->n);
   const int chunks = chunks_m2s(ctx, nrhs);
   const int chunk_len = cdiv(n, chunks);
-  const dim3 grid(cdiv(ctx->ns, kThreads), chunks, 2 * nrhs);
+  const dim3 grid(cdiv(ctx->ns, 16 * kM2sWaves), chunks, 2 * nrhs);
   const bool f64 = std::is_same<T, double>::value;
   const auto *E = static_cast<const cv_t<T> *>(f64 ? ctx->gt.E64.p : ctx->gt.E32.p);
   const auto *W = static_cast<const cv_t<T> *>(f64 ? ctx->ct.W64.p : ctx->ct.W32.p);
@@ -1107,7 +1159,7 @@ static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
   auto *part = static_cast<cv_t<T> *>(ctx->m2s_part.p);
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_m2s_part<T, PP>), grid, dim3(kThreads), 0, ctx->stream, E, b, W, part, n, ctx->ns, chunk_len, chunks); break;
+  case PP: hipLaunchKernelGGL((k_m2s_mfma<T, PP>), grid, dim3(64 * kM2sWaves), 0, ctx->stream, E, b, W, part, n, ctx->ns, chunk_len, chunks); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
