@@ -237,3 +237,66 @@ def test_polarization_change_clears_the_particle():
         ctx.apply(0, np.zeros((wl.n, wl.P), complex))
     with pytest.raises(mp.MpslError):
         ctx.set_polarization(7)
+
+
+def test_te_power_balance_through_the_library():
+    """Weighted power balance (1/k^2 of each layer on the flux density, 1/k_0^2
+    on the source term) for the library's TE solve and field on five layers."""
+    from scipy.special import hankel1
+    from test_oracle_system import _gl_panels
+    wl = make_workload("c1")
+    ks, th, c = _stack("five", wl)
+    ctx = mp.Context(0)
+    ctx.set_polarization(mp.TE)
+    ctx.set_layer_stack(ks, th, c)
+    ctx.set_particle_disk(wl.shape_params[0], wl.kp, wl.p)
+    ctx.set_geometry(wl.xy, wl.rot)
+    ctx.set_contour(768, 0.2, 32.0)
+    src = np.array([0.3, 2.5])
+    beta, meta = ctx.solve(src, precision=0, tol=1e-13, maxiter=400)
+    assert meta["status"] == 0
+    kap = [1.0 / k ** 2 for k in ks]
+    y = interfaces(th, c)
+    xa, xb, ya, yb = -6.0, 6.0, y[-1] - 1.5, y[0] + 2.5
+    h = 5e-4
+    flux = 0.0
+    for side in range(4):
+        if side < 2:
+            t, wt = _gl_panels(xa, xb, (), 0.25)
+            pts = np.stack([t, np.full_like(t, ya if side == 0 else yb)], axis=1)
+            nvec = np.array([0.0, -1.0 if side == 0 else 1.0])
+        else:
+            t, wt = _gl_panels(ya, yb, tuple(y), 0.25)
+            pts = np.stack([np.full_like(t, xa if side == 2 else xb), t], axis=1)
+            nvec = np.array([-1.0 if side == 2 else 1.0, 0.0])
+        f = [ctx.eval_field(src, beta, pts + s * h * nvec) for s in (-2, -1, 1, 2)]
+        du = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+        u = ctx.eval_field(src, beta, pts)
+        lay = np.sum(pts[:, 1][:, None] < y[None, :], axis=1)
+        flux += float(np.sum(np.array([kap[j] for j in lay]) * wt * np.imag(np.conj(u) * du)))
+    e = 1e-5
+    offs = np.array([[e, 0.0], [-e, 0.0], [0.0, e], [0.0, -e]])
+    us = ctx.eval_field(src, beta, src[None, :] + offs) - 0.25j * hankel1(0, ks[0] * e)
+    expect = kap[0] * (0.25 + float(np.mean(us).imag))
+    assert abs(flux - expect) < 1e-9 * abs(expect), (flux, expect)
+
+
+def test_stack_on_span_contour():
+    """A five-layer stack on a span-rule contour (breakpoints at every
+    layer's wavenumber): nodes and matvec against the stack oracle."""
+    wl = make_workload("s150p12")
+    ks, th, c = _stack("five", wl)
+    X = float(wl.xy[:, 0].max() - wl.xy[:, 0].min())
+    b, h = min(0.2, 2.0 / X), 6.0 / X
+    lam, w = ocontour.contour_span(b, 24.0, h, ks)
+    S = prototype_S(wl)
+    pr = stack_problem(ks, th, c, wl.p, S, wl.xy, wl.rot, lam, w)
+    ctx = mp.Context(0)
+    ctx.set_layer_stack(ks, th, c)
+    ctx.set_scattering_matrix(wl.p, wl.r_enclose, S)
+    ctx.set_geometry(wl.xy, wl.rot)
+    assert ctx.set_contour_span(b, 24.0, h) == lam.size
+    x = coeff_vector(wl, 4)
+    for prec, tol in ((0, 1e-12), (1, 2e-5)):
+        err = rel_err(ctx.apply(prec, x.astype(np.complex128 if prec == 0 else np.complex64)), pr.matvec(x))
+        assert err < tol, err
