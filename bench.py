@@ -323,8 +323,10 @@ def _span_leg(args, torch, mp, wl, x, y_count):
     X = float(wl.xy[:, 0].max() - wl.xy[:, 0].min())
     res = {"extent_x": X, "b": 2.0 / X, "t_max": 24.0}
     y6 = None
-    for label, hf in (("h12", 12.0), ("h6", 6.0)):
+    for label, hf, method in (("h12", 12.0, mp.SOMM_DIRECT), ("h6", 6.0, mp.SOMM_DIRECT),
+                              ("h12_interp", 12.0, mp.SOMM_INTERP), ("h6_interp", 6.0, mp.SOMM_INTERP)):
         ctx = mp.Context(0)
+        ctx.set_sommerfeld_method(method)
         ctx.set_stream(torch.cuda.current_stream().cuda_stream)
         ctx.set_layers(wl.k1, wl.k2, wl.k3, wl.d)
         ctx.set_particle_star(a1, a2, a3, wl.kp, wl.p, 256)
@@ -334,15 +336,19 @@ def _span_leg(args, torch, mp, wl, x, y_count):
         yd = torch.zeros_like(xd)
         ctx.apply_dev(0, xd, yd)
         torch.cuda.synchronize()
-        leg = {"h_max": hf / X, "n_nodes": ns}
+        leg = {"h_max": hf / X, "n_nodes": ns, "sommerfeld": "interp" if method == mp.SOMM_INTERP else "direct"}
         for name, prec in (("fp32", 1), ("fp64", 0)):
             dt, m2l_ms, _, fin = _matvec_rate(ctx, torch, prec, x, args.steps, args.warmup)
             leg[name] = {"matvecs_per_s": args.steps / dt, "ms_per_matvec": dt / args.steps * 1e3,
                          "m2l_ms": m2l_ms, "finite": fin}
         if label == "h6":
             y6 = yd.cpu().numpy()
-        else:
+        elif label == "h12":
             y12 = yd.cpu().numpy()
+        else:
+            leg["fp64_matvec_rel_diff_vs_direct"] = float(
+                np.linalg.norm(yd.cpu().numpy() - (y6 if label == "h6_interp" else y12)) /
+                np.linalg.norm(y6 if label == "h6_interp" else y12))
         res[label] = leg
         del ctx
         torch.cuda.empty_cache()

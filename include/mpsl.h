@@ -214,6 +214,22 @@ int mpsl_compute_contour(mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, int n_nodes, 
  * (MPSL_EUNSUPPORTED otherwise).  Requires layers. */
 int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max);
 
+/* How M2S and S2L (Sections 5.2.1 and 5.3) sum over the contour nodes:
+ * MPSL_SOMM_DIRECT: every particle with every node (O(N N_S P), default);
+ * MPSL_SOMM_INTERP: particles grouped in tiles of 8 x 4 (lengths); per tile
+ * the part of the plane waves that varies slowly in lambda (the phase
+ * relative to the tile centre and the order weights) is evaluated at 24
+ * Chebyshev nodes of each lambda-interval of length 1 and interpolated to the
+ * contour nodes (barycentric form); nodes within 0.3 of +-k2 and on the
+ * vertical segment are summed directly.  Work O(N N_C P + N_S T 24) for N_C
+ * coarse nodes and T tiles instead of O(N N_S P); accurate to about 1e-13 in
+ * the M2S spectra for the calibrated case (k2 = 9, p = 16, span-rule contour),
+ * as the paper's NUFFT forms (Section 5.2.2, 5.3.1) are for large N_S.  This
+ * replaces the paper's FFT grids by interpolation, which maps to dense GPU
+ * loops.  MPSL_EINVAL for other values. */
+enum { MPSL_SOMM_DIRECT = 0, MPSL_SOMM_INTERP = 1 };
+int mpsl_set_sommerfeld_method(mpsl_ctx *ctx, int method);
+
 /* Host, no device: the span rule's nodes and weights for the real parts
  * re_k[0 .. n_k) of the layer wavenumbers.  *n_nodes receives the count;
  * with lam and w NULL nothing else is written, otherwise both must hold

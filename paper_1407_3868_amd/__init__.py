@@ -17,6 +17,7 @@ FP64 = 0
 FP32 = 1
 FAR_AUTO, FAR_DIRECT, FAR_FMM = 0, 1, 2
 TM, TE = 0, 1
+SOMM_DIRECT, SOMM_INTERP = 0, 1
 
 STATUS = {0: "MPSL_OK", -1: "MPSL_EINVAL", -2: "MPSL_ENOMEM", -3: "MPSL_EHIP", -4: "MPSL_ESTATE",
           -5: "MPSL_EGEOM", -6: "MPSL_ENOCONV", -7: "MPSL_EUNSUPPORTED", -8: "MPSL_EINSIDE",
@@ -249,6 +250,10 @@ class Context:
         """Span-rule contour (mpsl_set_contour_span); returns the node count."""
         self._check(self.lib.mpsl_set_contour_span(self.h, float(b), float(t_max), float(h_max)))
         return self.sizes()[2]
+
+    def set_sommerfeld_method(self, method):
+        """SOMM_DIRECT (default) or SOMM_INTERP (mpsl_set_sommerfeld_method)."""
+        return self._check(self.lib.mpsl_set_sommerfeld_method(self.h, int(method)))
 
     def set_contour_nodes(self, lam, w):
         lam, w = _carr(lam), _carr(w)

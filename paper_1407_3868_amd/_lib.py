@@ -55,6 +55,7 @@ SIGNATURES = {
     "mpsl_compute_star_smatrix": (I, [D, D, I, c128, c128, I, I, I, P]),
     "mpsl_compute_contour": (I, [c128, c128, c128, I, D, D, P, P]),
     "mpsl_set_contour_span": (I, [P, D, D, D]),
+    "mpsl_set_sommerfeld_method": (I, [P, I]),
     "mpsl_compute_contour_span": (I, [I, P, D, D, D, I, P, P, P]),
     "mpsl_set_contour_nodes": (I, [P, I, P, P]),
     "mpsl_get_contour": (I, [P, I, P, P]),

@@ -314,12 +314,46 @@ zc gamma_branch(zc lam, zc k) {
   return g;
 }
 
+// M2S order weights -4i (-i)^nu u^nu (side +) and -4i (-i)^nu v^nu (side -), and
+// the S2L powers i^n u^n, i^n v^n, n = -p..p, with u = (lam - g2)/k2 and
+// v = (lam + g2)/k2 = 1/u (Theorem 5.1, Lemma 5.1).  The larger of lam +- g2 is
+// taken directly and the other as k2^2 / (...) to avoid cancellation.
+void order_weights(zc lam, zc g2, zc k2, int p, zc *Wp, zc *Wm, zc *Up, zc *Um) {
+  const zc I(0.0, 1.0);
+  const int P = 2 * p + 1;
+  zc u, v;
+  if (std::abs(lam + g2) >= std::abs(lam - g2)) {
+    v = (lam + g2) / k2;
+    u = k2 / (lam + g2);
+  } else {
+    u = (lam - g2) / k2;
+    v = k2 / (lam - g2);
+  }
+  // powers u^nu, v^nu for nu = -p..p by repeated multiplication from nu = 0
+  std::vector<zc> up(P), vp(P);
+  up[p] = vp[p] = 1.0;
+  for (int j = 1; j <= p; ++j) {
+    up[p + j] = up[p + j - 1] * u;
+    up[p - j] = up[p - j + 1] * v;
+    vp[p + j] = vp[p + j - 1] * v;
+    vp[p - j] = vp[p - j + 1] * u;
+  }
+  for (int j = 0; j < P; ++j) {
+    const int nu = j - p;
+    const zc mi = std::pow(-I, nu), pi = std::pow(I, nu);  // (-i)^nu and i^nu
+    Wp[j] = -4.0 * I * mi * up[j];
+    Wm[j] = -4.0 * I * mi * vp[j];
+    Up[j] = pi * up[j];
+    Um[j] = pi * vp[j];
+  }
+}
+
 // Contour tables (host, FP64) and geometry tables (device).
 int build_tables(mpsl_ctx *ctx) {
   if (!ctx->has_layers || !ctx->has_particle || !ctx->has_geom || !ctx->has_contour)
     return set_err(ctx, MPSL_ESTATE, "layers, particle, geometry and contour must all be set");
   if (ctx->tables_ok) return MPSL_OK;
-  if (ctx->n * static_cast<int64_t>(ctx->ns) > kMaxPlaneWaves)
+  if (ctx->somm_method == MPSL_SOMM_DIRECT && ctx->n * static_cast<int64_t>(ctx->ns) > kMaxPlaneWaves)
     return set_err(ctx, MPSL_EUNSUPPORTED,
                    "particles x contour nodes above " + std::to_string(kMaxPlaneWaves) + " (plane-wave tables)");
   const int ns = ctx->ns;
@@ -327,7 +361,6 @@ int build_tables(mpsl_ctx *ctx) {
   const int P = 2 * p + 1;
   const int64_t n = ctx->n;
   const zc k1 = ctx->k1, k2 = ctx->k2, k3 = ctx->k3;
-  const zc I(0.0, 1.0);
 
   std::vector<zc> R(4 * ns), sf(2 * ns), gw(4 * ns), cq(ns), W(2 * ns * P), U(2 * ns * P);
   for (int q = 0; q < ns; ++q) {
@@ -343,34 +376,8 @@ int build_tables(mpsl_ctx *ctx) {
     sf[2 * q + 0] = m[4];
     sf[2 * q + 1] = m[5];
     cq[q] = ctx->w[q] / (4.0 * M_PI * g2);
-    // u = (lam - g2)/k2 and v = (lam + g2)/k2 = 1/u; take the larger of lam +- g2
-    // directly and the other as k2^2 / (...) to avoid cancellation.
-    zc u, v;
-    if (std::abs(lam + g2) >= std::abs(lam - g2)) {
-      v = (lam + g2) / k2;
-      u = k2 / (lam + g2);
-    } else {
-      u = (lam - g2) / k2;
-      v = k2 / (lam - g2);
-    }
-    // powers u^nu, v^nu for nu = -p..p by repeated multiplication from nu = 0
-    std::vector<zc> up(P), vp(P);
-    up[p] = vp[p] = 1.0;
-    for (int j = 1; j <= p; ++j) {
-      up[p + j] = up[p + j - 1] * u;
-      up[p - j] = up[p - j + 1] * v;
-      vp[p + j] = vp[p + j - 1] * v;
-      vp[p - j] = vp[p - j + 1] * u;
-    }
-    for (int j = 0; j < P; ++j) {
-      const int nu = j - p;
-      // (-i)^nu and i^nu
-      const zc mi = std::pow(-I, nu), pi = std::pow(I, nu);
-      W[(0 * ns + q) * P + j] = -4.0 * I * mi * up[j];
-      W[(1 * ns + q) * P + j] = -4.0 * I * mi * vp[j];
-      U[(0 * ns + q) * P + j] = pi * up[j];
-      U[(1 * ns + q) * P + j] = pi * vp[j];
-    }
+    order_weights(lam, g2, k2, p, &W[(0 * ns + q) * P], &W[(1 * ns + q) * P], &U[(0 * ns + q) * P],
+                  &U[(1 * ns + q) * P]);
   }
   auto up64 = [&](DBuf &b, const std::vector<zc> &v) -> int {
     int rc = dev_alloc(ctx, b, v.size() * sizeof(double2));
@@ -402,13 +409,19 @@ int build_tables(mpsl_ctx *ctx) {
     }
   if ((rc = up64(ctx->gt.rot64, rot)) || (rc = up32(ctx->gt.rot32, rot))) return rc;
 
-  const size_t tab = 2ull * static_cast<size_t>(n) * ns;
-  if ((rc = dev_alloc(ctx, ctx->gt.E64, tab * sizeof(double2))) ||
-      (rc = dev_alloc(ctx, ctx->gt.F64, tab * sizeof(double2))) ||
-      (rc = dev_alloc(ctx, ctx->gt.E32, tab * sizeof(float2))) ||
-      (rc = dev_alloc(ctx, ctx->gt.F32, tab * sizeof(float2))))
-    return rc;
-  if ((rc = launch_geom_tables(ctx))) return rc;
+  if (ctx->somm_method == MPSL_SOMM_DIRECT) {  // per (particle, node) plane-wave tables
+    const size_t tab = 2ull * static_cast<size_t>(n) * ns;
+    if ((rc = dev_alloc(ctx, ctx->gt.E64, tab * sizeof(double2))) ||
+        (rc = dev_alloc(ctx, ctx->gt.F64, tab * sizeof(double2))) ||
+        (rc = dev_alloc(ctx, ctx->gt.E32, tab * sizeof(float2))) ||
+        (rc = dev_alloc(ctx, ctx->gt.F32, tab * sizeof(float2))))
+      return rc;
+    if ((rc = launch_geom_tables(ctx))) return rc;
+  } else {
+    const DBuf *tabs[] = {&ctx->gt.E64, &ctx->gt.F64, &ctx->gt.E32, &ctx->gt.F32};
+    for (const DBuf *t : tabs) dev_free(*const_cast<DBuf *>(t));
+  }
+  if ((rc = somm_build(ctx))) return rc;
   if (fmm_wanted(ctx)) {
     if ((rc = fmm_build(ctx))) return rc;
   } else if (!ctx->gt.pairs_ok) {
@@ -555,6 +568,7 @@ void mpsl_destroy(mpsl_ctx *ctx) {
                   &ctx->ybuf, &ctx->gm, &ctx->scal};
   for (DBuf *b : bufs) mpsl::dev_free(*b);
   mpsl::fmm_free(ctx);
+  mpsl::somm_free(ctx);
   delete ctx;
 }
 
@@ -829,6 +843,16 @@ int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max) {
   ctx->w = w;
   ctx->ns = static_cast<int>(lam.size());
   ctx->has_contour = true;
+  mpsl::invalidate(ctx);
+  return MPSL_OK;
+}
+
+int mpsl_set_sommerfeld_method(mpsl_ctx *ctx, int method) {
+  if (!ctx) return MPSL_EINVAL;
+  if (method != MPSL_SOMM_DIRECT && method != MPSL_SOMM_INTERP)
+    return mpsl::set_err(ctx, MPSL_EINVAL, "method must be MPSL_SOMM_DIRECT or MPSL_SOMM_INTERP");
+  if (method == ctx->somm_method) return MPSL_OK;
+  ctx->somm_method = method;
   mpsl::invalidate(ctx);
   return MPSL_OK;
 }

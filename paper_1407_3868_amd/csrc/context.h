@@ -64,6 +64,32 @@ struct FmmStage {
   int64_t sum_off = 0, sum_len = 0;    // chunk 0 and the length of one chunk
 };
 
+// Sommerfeld transforms by tile-local interpolation in lambda (M2S and S2L at
+// large node counts).  Particles are grouped in rectangular tiles; per tile the
+// smooth factor of the plane-wave sums is sampled at Chebyshev nodes of short
+// lambda-intervals and interpolated to the contour nodes; nodes near +-k2 and
+// on the vertical segment are kept as their own coarse nodes.
+struct SommPlan {
+  bool active = false;
+  int nT = 0, nc = 0, nint = 0, ndir = 0;
+  double tile_w = 0.0, tile_h = 0.0, L_I = 0.0, d_dir = 0.0;
+  DBuf perm;        // int32[n]: particles ordered by tile
+  DBuf tstart;      // int32[nT + 1]
+  DBuf txy;         // double2[nT]: tile centres
+  DBuf ptile;       // int32[n]: tile of each particle
+  DBuf lamc, gc;    // double2[nc]: coarse nodes and gamma2 there
+  DBuf Wc64, Wc32;  // [2][nc][P]: M2S weights at the coarse nodes
+  DBuf Zc64, Zc32;  // [2][nc][P]: S2L powers at the coarse nodes
+  DBuf run_c0;      // int32[ns]: first coarse node of each contour node's run
+  DBuf run_len;     // int32[ns]: run length (kSommNc, or 1 for a direct node)
+  DBuf Lw;          // double[ns][kSommNc]: interpolation weights
+  DBuf ivl;         // int32[nint][4]: fine start (in fperm), fine count, coarse start, unused
+  DBuf fperm;       // int32[ns]: contour nodes of the intervals, interval by interval
+  DBuf dir;         // int32[ndir][2]: contour node and coarse node of each direct node
+  DBuf G;           // work [nrhs][2][nT][nc] in the matvec precision
+  const void *sigma = nullptr;  // S2L densities recorded by the coefficient step
+};
+
 struct FmmPlan {
   bool active = false;
   int top = 0;                // index of the top level
@@ -137,6 +163,8 @@ struct mpsl_ctx {
   int far_method = MPSL_FAR_AUTO;
   double far_tol = 1e-10;
   mpsl::FmmPlan fmm;
+  int somm_method = MPSL_SOMM_DIRECT;
+  mpsl::SommPlan somm;
   mpsl::ContourTables ct;
   mpsl::GeomTables gt;
 
@@ -195,6 +223,11 @@ int assign_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const double *
                  std::string &err);
 zc gamma_branch(zc lam, zc k);
 constexpr int kMaxLayers = 64;
+int somm_build(mpsl_ctx *ctx);
+void somm_free(mpsl_ctx *ctx);
+constexpr int kSommNc = 24;  // Chebyshev nodes per lambda-interval
+// M2S weights and S2L powers of one node (P entries each): see capi.hip.
+void order_weights(zc lam, zc g2, zc k2, int p, zc *Wp, zc *Wm, zc *Up, zc *Um);
 // Contour under the span rule (panels of length <= h_max).
 int make_contour_span(const std::vector<double> &ks, double b, double t_max, double h_max, std::vector<zc> &lam,
                       std::vector<zc> &w, std::string &err);

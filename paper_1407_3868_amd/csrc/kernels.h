@@ -81,4 +81,10 @@ inline int m2l_slots(const mpsl_ctx *ctx, int prec) { return chunks_m2l(ctx, pre
 int chunks_s2l(const mpsl_ctx *ctx, int nrhs = 1);
 int chunks_m2s(const mpsl_ctx *ctx, int nrhs = 1);
 
+// Sommerfeld transforms by tile-local interpolation (somm.hip): M2S spectra
+// into spec ([nrhs][2][ns], FP64) and S2L local expansions into one part slot
+// per chunk of coarse nodes and right-hand side.
+int launch_m2s_interp(mpsl_ctx *ctx, int prec, const void *beta, void *spec, int nrhs);
+int launch_s2l_interp(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs, int64_t pstride);
+
 }  // namespace mpsl

@@ -995,6 +995,10 @@ int chunks_m2l(const mpsl_ctx *ctx, int prec) {
 }
 
 int chunks_s2l(const mpsl_ctx *ctx, int nrhs) {
+  if (ctx->somm.active) {  // the interpolated S2L: chunks of coarse nodes, one slot each
+    const int tb = cdiv(ctx->n, 128) * nrhs;
+    return std::max(1, std::min(64, std::min(cdiv(1024, tb), 2 * ctx->somm.nc)));
+  }
   if (ctx->s2l_chunks > 0) return std::min(ctx->s2l_chunks, ctx->ns);
   const int tb = cdiv(ctx->n, kThreads) * nrhs;
   const int c = cdiv(1024, tb);
@@ -1172,6 +1176,7 @@ static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
 }
 
 int launch_m2s(mpsl_ctx *ctx, int prec, const void *beta, void *spec, int nrhs) {
+  if (ctx->somm.active) return launch_m2s_interp(ctx, prec, beta, spec, nrhs);
   return prec == MPSL_FP64 ? launch_m2s_t<double>(ctx, beta, spec, nrhs)
                            : launch_m2s_t<float>(ctx, beta, spec, nrhs);
 }
@@ -1188,6 +1193,10 @@ int launch_reflect(mpsl_ctx *ctx, const void *spec, const double *src, void *sig
 }
 
 int launch_s2l_coef(mpsl_ctx *ctx, const void *sigma, int nrhs) {
+  if (ctx->somm.active) {  // the interpolated S2L reads the densities directly
+    ctx->somm.sigma = sigma;
+    return MPSL_OK;
+  }
   const int P = 2 * ctx->p + 1;
   const int64_t tot = 2LL * ctx->ns * P * nrhs;
   hipLaunchKernelGGL(k_s2l_coef, dim3(cdiv(tot, 256)), dim3(256), 0, ctx->stream,
@@ -1219,6 +1228,7 @@ static int launch_s2l_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t
 }
 
 int launch_s2l(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs, int64_t pstride) {
+  if (ctx->somm.active) return launch_s2l_interp(ctx, prec, part, chunks, nrhs, pstride);
   return prec == MPSL_FP64 ? launch_s2l_t<double>(ctx, part, chunks, nrhs, pstride)
                            : launch_s2l_t<float>(ctx, part, chunks, nrhs, pstride);
 }

@@ -1,0 +1,500 @@
+// M2S and S2L by tile-local interpolation in lambda (Sections 5.2.1, 5.3).
+//
+// The direct transforms couple every particle m with every contour node q
+// through e^{-i lam_q x_m +- g2_q y_m} (M2S) and e^{i lam_q x_l +- g2_q y_l}
+// (S2L).  With the particles grouped in tiles of centre (x_T, y_T) the factor
+// splits into a tile part e^{-+i lam x_T +- g2 y_T} and a local part whose
+// phase is at most |lam| times the tile size: together with the order weights
+// (powers of (lam -+ g2)/k2) the local part is smooth in lambda away from
+// lam = +-k2.  Per tile it is evaluated at kSommNc Chebyshev nodes of each
+// lambda-interval of length L_I on the contour's lines and interpolated to the
+// contour nodes in barycentric form; nodes within d_dir of +-k2 and the nodes
+// of the vertical segment are their own coarse nodes (interpolation weight 1).
+//
+//   M2S: G[T][c]   = sum_{m in T} local_m(c) (beta_m . W(c))
+//        spec[q]   = sum_T E_T(q) sum_k L[q][k] G[T][c0(q) + k]
+//   S2L: B[T][c]   = sum_{q in run(c)} L[q][k(c)] c_q sigma(q) E'_T(q)
+//        alpha_l[n] = sum_c local_l(c) B[T(l)][c] Z_n(c)
+//
+// Exponentials are evaluated in FP64 (their phases reach |lam| times the strip
+// width); sums run in the matvec precision.  The paper's NUFFT forms
+// (Sections 5.2.2, 5.3.1) reach the same O(N + N_S) scaling with FFT grids;
+// interpolation keeps every step a dense loop.
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+#include "kernels.h"
+
+namespace mpsl {
+
+namespace {
+
+constexpr double kTileW = 8.0, kTileH = 4.0, kIntervalL = 1.0, kDirect = 0.3;
+
+// the expansion orders instantiated (1..20)
+#define SOMM_P_CASES(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
+
+__device__ inline cx<double> cexp64(double a, double b) {
+  double s, c;
+  sincos(b, &s, &c);
+  const double e = exp(a);
+  return {e * c, e * s};
+}
+template <typename T> __device__ inline cx<T> cvt(cx<double> v) { return {static_cast<T>(v.re), static_cast<T>(v.im)}; }
+template <typename T> __device__ inline cx<double> up(cx<T> v) { return {static_cast<double>(v.re), static_cast<double>(v.im)}; }
+
+// M2S, step 1: one lane per (tile, coarse node), blockIdx.z = 2 rhs + side.
+template <typename T, int p>
+__global__ __launch_bounds__(256) void k_si_tileG(const cv_t<T> *__restrict__ beta, const double2 *__restrict__ xy,
+                                                  const int *__restrict__ perm, const int *__restrict__ tstart,
+                                                  const double2 *__restrict__ txy, const double2 *__restrict__ lamc,
+                                                  const double2 *__restrict__ gc, const cv_t<T> *__restrict__ Wc,
+                                                  int n, int nT, int nc, cv_t<T> *__restrict__ G) {
+  constexpr int P = 2 * p + 1;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int t = blockIdx.y;
+  const int s = blockIdx.z & 1, r = blockIdx.z >> 1;
+  if (c >= nc) return;
+  beta += static_cast<int64_t>(r) * n * P;
+  const double lr = lamc[c].x, li = lamc[c].y, gr = gc[c].x, gi = gc[c].y;
+  const cv_t<T> *W = Wc + (static_cast<int64_t>(s) * nc + c) * P;
+  cx<T> w[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) w[j] = ld<T>(W[j]);
+  const double sg = s == 0 ? 1.0 : -1.0;
+  const double xT = txy[t].x, yT = txy[t].y;
+  cx<T> acc = mk<T>(0, 0);
+  for (int k = tstart[t]; k < tstart[t + 1]; ++k) {
+    const int m = perm[k];
+    const double dx = xy[m].x - xT, dy = xy[m].y - yT;
+    // e^{-i lam dx + sg g2 dy}
+    const cx<T> e = cvt<T>(cexp64(li * dx + sg * gr * dy, -lr * dx + sg * gi * dy));
+    const cv_t<T> *b = beta + static_cast<int64_t>(m) * P;
+    cx<T> bw = mk<T>(0, 0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) cmac(bw, ld<T>(b[j]), w[j]);
+    cmac(acc, e, bw);
+  }
+  G[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c] = st(acc);
+}
+
+// M2S, step 2: one lane per contour node; spectra in FP64 as the direct path.
+template <typename T>
+__global__ __launch_bounds__(256) void k_si_fine(const cv_t<T> *__restrict__ G, const double2 *__restrict__ lam,
+                                                 const double2 *__restrict__ g2, const double2 *__restrict__ txy,
+                                                 const int *__restrict__ run_c0, const int *__restrict__ run_len,
+                                                 const double *__restrict__ Lw, int ns, int nT, int nc, double d,
+                                                 double2 *__restrict__ spec) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y & 1, r = blockIdx.y >> 1;
+  if (q >= ns) return;
+  const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
+  const int c0 = run_c0[q], len = run_len[q];
+  double wq[kSommNc];
+#pragma unroll
+  for (int k = 0; k < kSommNc; ++k) wq[k] = k < len ? Lw[static_cast<int64_t>(q) * kSommNc + k] : 0.0;
+  const cv_t<T> *Gs = G + (static_cast<int64_t>(r) * 2 + s) * nT * nc;
+  cx<double> acc = mk(0.0, 0.0);
+  for (int t = 0; t < nT; ++t) {
+    const double xT = txy[t].x, yT = txy[t].y;
+    const double yy = s == 0 ? yT : -(d + yT);  // e^{-i lam x_T + g2 y_T}, e^{-i lam x_T - g2 (d + y_T)}
+    const cx<double> E = cexp64(li * xT + gr * yy, -lr * xT + gi * yy);
+    const cv_t<T> *Gt = Gs + static_cast<int64_t>(t) * nc + c0;
+    cx<T> h = mk<T>(0, 0);
+#pragma unroll
+    for (int k = 0; k < kSommNc; ++k)
+      if (k < len) h = h + static_cast<T>(wq[k]) * ld<T>(Gt[k]);
+    acc = acc + E * up<T>(h);
+  }
+  spec[(static_cast<int64_t>(r) * 2 + s) * ns + q] = st(acc);
+}
+
+// S2L, step 1 for the Chebyshev intervals: one block per (interval, tile),
+// blockIdx.z = 2 rhs + side; every lane keeps kSommNc partial sums.
+template <typename T>
+__global__ __launch_bounds__(256) void k_si_coarseB(const double2 *__restrict__ sigma, const double2 *__restrict__ cq,
+                                                    const double2 *__restrict__ lam, const double2 *__restrict__ g2,
+                                                    const double2 *__restrict__ txy, const int *__restrict__ ivl,
+                                                    const int *__restrict__ fperm, const double *__restrict__ Lw,
+                                                    int ns, int nT, int nc, double d, cv_t<T> *__restrict__ B) {
+  __shared__ double red[4][kSommNc][2];
+  const int iv = blockIdx.x, t = blockIdx.y, s = blockIdx.z & 1, r = blockIdx.z >> 1;
+  const int f0 = ivl[4 * iv], nf = ivl[4 * iv + 1], c0 = ivl[4 * iv + 2];
+  sigma += static_cast<int64_t>(r) * 2 * ns;
+  const double xT = txy[t].x, yT = txy[t].y;
+  const double yy = s == 0 ? yT : -(yT + d);  // e^{i lam x_T + g2 y_T}, e^{i lam x_T - g2 (y_T + d)}
+  double are[kSommNc], aim[kSommNc];
+#pragma unroll
+  for (int k = 0; k < kSommNc; ++k) are[k] = aim[k] = 0.0;
+  for (int i = threadIdx.x; i < nf; i += 256) {
+    const int q = fperm[f0 + i];
+    const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
+    const cx<double> u = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]);
+    const cx<double> v = u * cexp64(-li * xT + gr * yy, lr * xT + gi * yy);
+    const double *L = Lw + static_cast<int64_t>(q) * kSommNc;
+#pragma unroll
+    for (int k = 0; k < kSommNc; ++k) {
+      are[k] = fma(L[k], v.re, are[k]);
+      aim[k] = fma(L[k], v.im, aim[k]);
+    }
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kSommNc; ++k) {
+    for (int off = 32; off > 0; off >>= 1) {
+      are[k] += __shfl_xor(are[k], off, 64);
+      aim[k] += __shfl_xor(aim[k], off, 64);
+    }
+    if (lane == 0) {
+      red[w][k][0] = are[k];
+      red[w][k][1] = aim[k];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kSommNc) {
+    const int k = threadIdx.x;
+    const double re = red[0][k][0] + red[1][k][0] + red[2][k][0] + red[3][k][0];
+    const double im = red[0][k][1] + red[1][k][1] + red[2][k][1] + red[3][k][1];
+    B[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c0 + k] = st(mk<T>(static_cast<T>(re), static_cast<T>(im)));
+  }
+}
+
+// S2L, step 1 for the direct nodes: one lane per (direct node, tile).
+template <typename T>
+__global__ __launch_bounds__(256) void k_si_coarseB_dir(const double2 *__restrict__ sigma,
+                                                        const double2 *__restrict__ cq,
+                                                        const double2 *__restrict__ lam,
+                                                        const double2 *__restrict__ g2,
+                                                        const double2 *__restrict__ txy, const int *__restrict__ dir,
+                                                        int ndir, int ns, int nT, int nc, double d,
+                                                        cv_t<T> *__restrict__ B) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int t = blockIdx.y, s = blockIdx.z & 1, r = blockIdx.z >> 1;
+  if (i >= ndir) return;
+  sigma += static_cast<int64_t>(r) * 2 * ns;
+  const int q = dir[2 * i], c = dir[2 * i + 1];
+  const double xT = txy[t].x, yT = txy[t].y;
+  const double yy = s == 0 ? yT : -(yT + d);
+  const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
+  const cx<double> v = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]) *
+                       cexp64(-li * xT + gr * yy, lr * xT + gi * yy);
+  B[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c] = st(cvt<T>(v));
+}
+
+// S2L, step 2: one lane per particle, all orders in registers; blockIdx.y
+// takes a chunk of the (side, coarse node) pairs and writes its own partial
+// slot (summed with the other partial expansions afterwards).
+template <typename T, int p>
+__global__ __launch_bounds__(128) void k_si_alpha(const cv_t<T> *__restrict__ B, const double2 *__restrict__ xy,
+                                                  const int *__restrict__ ptile, const double2 *__restrict__ txy,
+                                                  const double2 *__restrict__ lamc, const double2 *__restrict__ gc,
+                                                  const cv_t<T> *__restrict__ Zc, int n, int nT, int nc,
+                                                  int chunk_len, cv_t<T> *__restrict__ part, int64_t pstride) {
+  constexpr int P = 2 * p + 1;
+  const int l = blockIdx.x * 128 + threadIdx.x;
+  const int ch = blockIdx.y;
+  const int r = blockIdx.z;
+  const int k0 = ch * chunk_len, k1 = min(2 * nc, k0 + chunk_len);
+  const bool valid = l < n;
+  const int lc = valid ? l : 0;
+  const int t = ptile[lc];
+  const double dx = xy[lc].x - txy[t].x, dy = xy[lc].y - txy[t].y;
+  cx<T> acc[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) acc[j] = mk<T>(0, 0);
+  for (int k = k0; k < k1; ++k) {
+    const int s = k >= nc ? 1 : 0, c = k - s * nc;
+    const cv_t<T> *Bt = B + ((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc;
+    const cv_t<T> *Zs = Zc + static_cast<int64_t>(s) * nc * P;
+    const double sg = s == 0 ? 1.0 : -1.0;
+    {
+      // e^{i lam_c dx + sg g2_c dy}
+      const double lr = lamc[c].x, li = lamc[c].y, gr = gc[c].x, gi = gc[c].y;
+      const cx<T> eb = cvt<T>(cexp64(-li * dx + sg * gr * dy, lr * dx + sg * gi * dy)) * ld<T>(Bt[c]);
+      const cv_t<T> *z = Zs + static_cast<int64_t>(c) * P;
+#pragma unroll
+      for (int j = 0; j < P; ++j) cmac(acc[j], eb, ld<T>(z[j]));
+    }
+  }
+  if (valid) {
+    cv_t<T> *o = part + r * pstride + (static_cast<int64_t>(ch) * n + l) * P;
+#pragma unroll
+    for (int j = 0; j < P; ++j) o[j] = st(acc[j]);
+  }
+}
+
+inline int cdv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+template <typename T>
+int ensure_G(mpsl_ctx *ctx, int nrhs) {
+  const SommPlan &pl = ctx->somm;
+  return dev_alloc(ctx, ctx->somm.G, 2ull * nrhs * pl.nT * pl.nc * sizeof(cv_t<T>));
+}
+
+template <typename T>
+int m2s_interp_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
+  SommPlan &pl = ctx->somm;
+  int rc = ensure_G<T>(ctx, nrhs);
+  if (rc) return rc;
+  const bool f64 = std::is_same<T, double>::value;
+  const auto *Wc = static_cast<const cv_t<T> *>(f64 ? pl.Wc64.p : pl.Wc32.p);
+  auto *G = static_cast<cv_t<T> *>(pl.G.p);
+  const int n = static_cast<int>(ctx->n);
+  const dim3 g1(cdv(pl.nc, 256), pl.nT, 2 * nrhs);
+  switch (ctx->p) {
+#define X(PP)                                                                                                      \
+  case PP:                                                                                                         \
+    hipLaunchKernelGGL((k_si_tileG<T, PP>), g1, dim3(256), 0, ctx->stream, static_cast<const cv_t<T> *>(beta),     \
+                       static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const int *>(pl.perm.p),             \
+                       static_cast<const int *>(pl.tstart.p), static_cast<const double2 *>(pl.txy.p),               \
+                       static_cast<const double2 *>(pl.lamc.p), static_cast<const double2 *>(pl.gc.p), Wc, n,      \
+                       pl.nT, pl.nc, G);                                                                            \
+    break;
+    SOMM_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  hipLaunchKernelGGL(k_si_fine<T>, dim3(cdv(ctx->ns, 256), 2 * nrhs), dim3(256), 0, ctx->stream, G,
+                     static_cast<const double2 *>(ctx->ct.lam.p),
+                     static_cast<const double2 *>(ctx->ct.gw.p) + ctx->ns,  // g2 stored after g1
+                     static_cast<const double2 *>(pl.txy.p), static_cast<const int *>(pl.run_c0.p),
+                     static_cast<const int *>(pl.run_len.p), static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT,
+                     pl.nc, ctx->d, static_cast<double2 *>(spec));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, MPSL_EHIP, std::string("interpolated M2S: ") + hipGetErrorString(e));
+  return MPSL_OK;
+}
+
+template <typename T>
+int s2l_interp_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstride) {
+  SommPlan &pl = ctx->somm;
+  if (!pl.sigma) return set_err(ctx, MPSL_ESTATE, "interpolated S2L without densities");
+  int rc = ensure_G<T>(ctx, nrhs);
+  if (rc) return rc;
+  const bool f64 = std::is_same<T, double>::value;
+  const auto *Zc = static_cast<const cv_t<T> *>(f64 ? pl.Zc64.p : pl.Zc32.p);
+  auto *B = static_cast<cv_t<T> *>(pl.G.p);
+  const auto *sig = static_cast<const double2 *>(pl.sigma);
+  const auto *cq = static_cast<const double2 *>(ctx->ct.cq.p);
+  const auto *lam = static_cast<const double2 *>(ctx->ct.lam.p);
+  const auto *g2 = static_cast<const double2 *>(ctx->ct.gw.p) + ctx->ns;
+  const auto *txy = static_cast<const double2 *>(pl.txy.p);
+  if (pl.nint > 0)
+    hipLaunchKernelGGL(k_si_coarseB<T>, dim3(pl.nint, pl.nT, 2 * nrhs), dim3(256), 0, ctx->stream, sig, cq, lam, g2,
+                       txy, static_cast<const int *>(pl.ivl.p), static_cast<const int *>(pl.fperm.p),
+                       static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT, pl.nc, ctx->d, B);
+  if (pl.ndir > 0)
+    hipLaunchKernelGGL(k_si_coarseB_dir<T>, dim3(cdv(pl.ndir, 256), pl.nT, 2 * nrhs), dim3(256), 0, ctx->stream,
+                       sig, cq, lam, g2, txy, static_cast<const int *>(pl.dir.p), pl.ndir, ctx->ns, pl.nT, pl.nc,
+                       ctx->d, B);
+  const int n = static_cast<int>(ctx->n);
+  const int chunk_len = cdv(2 * static_cast<int64_t>(pl.nc), chunks);
+  const dim3 g2d(cdv(n, 128), chunks, nrhs);
+  auto *o = static_cast<cv_t<T> *>(part);
+  switch (ctx->p) {
+#define X(PP)                                                                                                       \
+  case PP:                                                                                                          \
+    hipLaunchKernelGGL((k_si_alpha<T, PP>), g2d, dim3(128), 0, ctx->stream, B,                                      \
+                       static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const int *>(pl.ptile.p), txy,       \
+                       static_cast<const double2 *>(pl.lamc.p), static_cast<const double2 *>(pl.gc.p), Zc, n,       \
+                       pl.nT, pl.nc, chunk_len, o, pstride);                                                         \
+    break;
+    SOMM_P_CASES(X)
+#undef X
+    default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(ctx, MPSL_EHIP, std::string("interpolated S2L: ") + hipGetErrorString(e));
+  return MPSL_OK;
+}
+
+}  // namespace
+
+int launch_m2s_interp(mpsl_ctx *ctx, int prec, const void *beta, void *spec, int nrhs) {
+  return prec == MPSL_FP64 ? m2s_interp_t<double>(ctx, beta, spec, nrhs) : m2s_interp_t<float>(ctx, beta, spec, nrhs);
+}
+
+int launch_s2l_interp(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs, int64_t pstride) {
+  return prec == MPSL_FP64 ? s2l_interp_t<double>(ctx, part, chunks, nrhs, pstride)
+                           : s2l_interp_t<float>(ctx, part, chunks, nrhs, pstride);
+}
+
+void somm_free(mpsl_ctx *ctx) {
+  SommPlan &pl = ctx->somm;
+  DBuf *b[] = {&pl.perm, &pl.tstart, &pl.txy, &pl.ptile, &pl.lamc, &pl.gc, &pl.Wc64, &pl.Wc32, &pl.Zc64,
+               &pl.Zc32, &pl.run_c0, &pl.run_len, &pl.Lw, &pl.ivl, &pl.fperm, &pl.dir, &pl.G};
+  for (DBuf *x : b) dev_free(*x);
+  pl.active = false;
+  pl.sigma = nullptr;
+}
+
+// Tiles, intervals, coarse nodes and interpolation weights (host, FP64).
+int somm_build(mpsl_ctx *ctx) {
+  somm_free(ctx);
+  SommPlan &pl = ctx->somm;
+  if (ctx->somm_method != MPSL_SOMM_INTERP) return MPSL_OK;
+  const int64_t n = ctx->n;
+  const int ns = ctx->ns, p = ctx->p, P = 2 * p + 1;
+  pl.tile_w = kTileW;
+  pl.tile_h = kTileH;
+  pl.L_I = kIntervalL;
+  pl.d_dir = kDirect;
+  // tiles of the particle bounding box
+  double x0 = 1e300, y0 = 1e300;
+  for (int64_t m = 0; m < n; ++m) {
+    x0 = std::min(x0, ctx->xy[2 * m]);
+    y0 = std::min(y0, ctx->xy[2 * m + 1]);
+  }
+  std::map<std::pair<int64_t, int64_t>, int> tiles;
+  std::vector<std::pair<int64_t, int64_t>> key(n);
+  for (int64_t m = 0; m < n; ++m) {
+    key[m] = {static_cast<int64_t>(std::floor((ctx->xy[2 * m] - x0) / kTileW)),
+              static_cast<int64_t>(std::floor((ctx->xy[2 * m + 1] - y0) / kTileH))};
+    tiles.emplace(key[m], 0);
+  }
+  int id = 0;
+  std::vector<double2> txy;
+  for (auto &kv : tiles) {
+    kv.second = id++;
+    txy.push_back(make_double2(x0 + (kv.first.first + 0.5) * kTileW, y0 + (kv.first.second + 0.5) * kTileH));
+  }
+  pl.nT = id;
+  std::vector<int> ptile(n), tstart(pl.nT + 1, 0), perm(n);
+  for (int64_t m = 0; m < n; ++m) {
+    ptile[m] = tiles[key[m]];
+    ++tstart[ptile[m] + 1];
+  }
+  for (int t = 0; t < pl.nT; ++t) tstart[t + 1] += tstart[t];
+  {
+    std::vector<int> fill(tstart.begin(), tstart.end() - 1);
+    for (int64_t m = 0; m < n; ++m) perm[fill[ptile[m]]++] = static_cast<int>(m);
+  }
+  // contour nodes: direct near +-k2 and on the vertical segment, intervals elsewhere
+  const double k2r = ctx->k2.real();
+  std::vector<char> direct(ns, 0);
+  for (int q = 0; q < ns; ++q) {
+    const double tr = ctx->lam[q].real();
+    direct[q] = (std::fabs(tr) < 1e-14) || (std::fabs(std::fabs(tr) - k2r) < kDirect);
+  }
+  std::vector<std::vector<int>> groups;
+  for (int q = 0; q < ns;) {
+    if (direct[q]) {
+      ++q;
+      continue;
+    }
+    const double a = ctx->lam[q].real(), im = ctx->lam[q].imag();
+    std::vector<int> g{q};
+    int e = q + 1;
+    while (e < ns && !direct[e] && ctx->lam[e].imag() == im && (ctx->lam[e].real() > 0) == (a > 0) &&
+           std::fabs(ctx->lam[e].real() - a) <= kIntervalL)
+      g.push_back(e++);
+    if (static_cast<int>(g.size()) <= kSommNc)
+      for (int x : g) direct[x] = 1;
+    else
+      groups.push_back(g);
+    q = e;
+  }
+  // coarse nodes: kSommNc Chebyshev nodes per interval, then one per direct node
+  std::vector<zc> lamc;
+  std::vector<int> run_c0(ns, 0), run_len(ns, 0), ivl, fperm, dir;
+  std::vector<double> Lw(static_cast<size_t>(ns) * kSommNc, 0.0);
+  double xs[kSommNc], bw[kSommNc];
+  for (int j = 0; j < kSommNc; ++j) {
+    xs[j] = std::cos((2 * j + 1) * M_PI / (2.0 * kSommNc));
+    bw[j] = ((j & 1) ? -1.0 : 1.0) * std::sin((2 * j + 1) * M_PI / (2.0 * kSommNc));
+  }
+  for (const auto &g : groups) {
+    double a = 1e300, c = -1e300;
+    for (int q : g) {
+      a = std::min(a, ctx->lam[q].real());
+      c = std::max(c, ctx->lam[q].real());
+    }
+    const double im = ctx->lam[g[0]].imag();
+    const int c0 = static_cast<int>(lamc.size());
+    double tc[kSommNc];
+    for (int j = 0; j < kSommNc; ++j) {
+      tc[j] = 0.5 * (a + c) + 0.5 * (c - a) * xs[j];
+      lamc.emplace_back(tc[j], im);
+    }
+    ivl.push_back(static_cast<int>(fperm.size()));
+    ivl.push_back(static_cast<int>(g.size()));
+    ivl.push_back(c0);
+    ivl.push_back(0);
+    for (int q : g) {
+      fperm.push_back(q);
+      run_c0[q] = c0;
+      run_len[q] = kSommNc;
+      const double t = ctx->lam[q].real();
+      double *L = &Lw[static_cast<size_t>(q) * kSommNc];
+      int hit = -1;
+      double sum = 0.0;
+      for (int j = 0; j < kSommNc; ++j) {
+        const double dd = t - tc[j];
+        if (dd == 0.0) hit = j;
+        L[j] = (dd == 0.0) ? 0.0 : bw[j] / dd;
+        sum += L[j];
+      }
+      if (hit >= 0) {
+        for (int j = 0; j < kSommNc; ++j) L[j] = (j == hit) ? 1.0 : 0.0;
+      } else {
+        for (int j = 0; j < kSommNc; ++j) L[j] /= sum;
+      }
+    }
+  }
+  pl.nint = static_cast<int>(groups.size());
+  for (int q = 0; q < ns; ++q)
+    if (direct[q]) {
+      const int c = static_cast<int>(lamc.size());
+      lamc.push_back(ctx->lam[q]);
+      run_c0[q] = c;
+      run_len[q] = 1;
+      Lw[static_cast<size_t>(q) * kSommNc] = 1.0;
+      dir.push_back(q);
+      dir.push_back(c);
+    }
+  pl.ndir = static_cast<int>(dir.size() / 2);
+  pl.nc = static_cast<int>(lamc.size());
+  // coarse-node tables
+  std::vector<zc> gc(pl.nc), Wc(2ull * pl.nc * P), Zc(2ull * pl.nc * P);
+  for (int c = 0; c < pl.nc; ++c) {
+    gc[c] = gamma_branch(lamc[c], ctx->k2);
+    order_weights(lamc[c], gc[c], ctx->k2, p, &Wc[static_cast<size_t>(c) * P],
+                  &Wc[(static_cast<size_t>(pl.nc) + c) * P], &Zc[static_cast<size_t>(c) * P],
+                  &Zc[(static_cast<size_t>(pl.nc) + c) * P]);
+  }
+  auto upload = [&](DBuf &b, const void *src, size_t bytes) -> int {
+    int rc = dev_alloc(ctx, b, bytes > 0 ? bytes : 16);  // an empty table keeps a valid, unused allocation
+    if (rc) return rc;
+    if (bytes > 0) MPSL_HIP_TRY(ctx, hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+    return MPSL_OK;
+  };
+  std::vector<float2> Wc32(Wc.size()), Zc32(Zc.size());
+  for (size_t i = 0; i < Wc.size(); ++i) {
+    Wc32[i] = make_float2(static_cast<float>(Wc[i].real()), static_cast<float>(Wc[i].imag()));
+    Zc32[i] = make_float2(static_cast<float>(Zc[i].real()), static_cast<float>(Zc[i].imag()));
+  }
+  int rc;
+  if ((rc = upload(pl.perm, perm.data(), perm.size() * sizeof(int))) ||
+      (rc = upload(pl.tstart, tstart.data(), tstart.size() * sizeof(int))) ||
+      (rc = upload(pl.txy, txy.data(), txy.size() * sizeof(double2))) ||
+      (rc = upload(pl.ptile, ptile.data(), ptile.size() * sizeof(int))) ||
+      (rc = upload(pl.lamc, lamc.data(), lamc.size() * sizeof(double2))) ||
+      (rc = upload(pl.gc, gc.data(), gc.size() * sizeof(double2))) ||
+      (rc = upload(pl.Wc64, Wc.data(), Wc.size() * sizeof(double2))) ||
+      (rc = upload(pl.Wc32, Wc32.data(), Wc32.size() * sizeof(float2))) ||
+      (rc = upload(pl.Zc64, Zc.data(), Zc.size() * sizeof(double2))) ||
+      (rc = upload(pl.Zc32, Zc32.data(), Zc32.size() * sizeof(float2))) ||
+      (rc = upload(pl.run_c0, run_c0.data(), run_c0.size() * sizeof(int))) ||
+      (rc = upload(pl.run_len, run_len.data(), run_len.size() * sizeof(int))) ||
+      (rc = upload(pl.Lw, Lw.data(), Lw.size() * sizeof(double))) ||
+      (rc = upload(pl.ivl, ivl.data(), ivl.size() * sizeof(int))) ||
+      (rc = upload(pl.fperm, fperm.data(), fperm.size() * sizeof(int))) ||
+      (rc = upload(pl.dir, dir.data(), dir.size() * sizeof(int))))
+    return rc;
+  pl.active = true;
+  return MPSL_OK;
+}
+
+}  // namespace mpsl
