@@ -23,33 +23,47 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32 = 157.3e12   # MI355X FP32 vector, TFLOP/s
-PEAK_FP64 = 78.6e12    # MI355X FP64 vector
+PEAK_FP32 = 157.3e12   # MI355X FP32, TFLOP/s (vector and dense matrix cores alike)
+PEAK_FP64 = 78.6e12    # MI355X FP64, TFLOP/s (vector and dense matrix cores alike)
+
+# M2L launch variants (mpsl_set_tuning): kernel, bound, committed HBM-traffic
+# summary and the source region its hash covers
+M2L_VARIANTS = {
+    0: ("k_m2l<{t},16,-1> (all-pairs M2L, one lane per target)", "alu", "m2l_5000stars_p16_hbm_traffic.md",
+        ("// Row a1: all-pairs free-space M2L", "// FMM near field:")),
+    1: ("k_m2l<{t},16,0|1> (all-pairs M2L, output halves)", "alu", None, None),
+    2: ("k_m2l_mfma<{t},16,1> (all-pairs M2L on the matrix cores)", "mfma",
+        "m2l_mfma_5000stars_p16_hbm_traffic.md",
+        ("// Row a1 on the matrix cores, one right-hand side.", "// Row a1 for many right-hand sides")),
+    3: ("k_m2l_mfma<{t},16,2> (all-pairs M2L on the matrix cores, 32 targets per wave)", "mfma", None, None),
+}
 
 
-M2L_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "m2l_5000stars_p16_hbm_traffic.md")
-
-
-def m2l_source_sha256():
-    """Hash of the source of the all-pairs M2L kernel (its device functions and launch)."""
+def m2l_source_sha256(variant=0):
+    """Hash of the source of one M2L kernel variant (its device code)."""
+    region = M2L_VARIANTS[variant][3]
     with open(os.path.join(ROOT, "paper_1407_3868_amd", "csrc", "kernels.hip")) as fh:
         src = fh.read()
-    a = src.index("// Row a1: all-pairs free-space M2L")
-    b = src.index("// FMM near field:")
+    a = src.index(region[0])
+    b = src.index(region[1], a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def _m2l_traffic():
-    """Scaled HBM bytes per launch of k_m2l<float,16> at this workload from the committed
-    rocprofv3 counter summary; None when the kernel source has changed since."""
+def _m2l_traffic(variant):
+    """Scaled HBM bytes per launch of the FP32 M2L kernel of this variant at this workload
+    from the committed rocprofv3 counter summary; None when there is none or the kernel
+    source has changed since."""
+    name = M2L_VARIANTS[variant][2]
+    if name is None:
+        return None
     try:
-        with open(M2L_TRAFFIC_SUMMARY) as fh:
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
             text = fh.read()
     except OSError:
         return None
     m = re.search(r"m2l_traffic_bytes_fp32: (\d+)", text)
     h = re.search(r"m2l_source_sha256: ([0-9a-f]+)", text)
-    if not m or not h or h.group(1) != m2l_source_sha256():
+    if not m or not h or h.group(1) != m2l_source_sha256(variant):
         return None
     return int(m.group(1))
 
@@ -435,6 +449,7 @@ def main():
     el32, m2l32, cnt32, fin32 = _matvec_rate(ctx, torch, 1, x, args.steps, args.warmup)
     el64, m2l64, cnt64, fin64 = _matvec_rate(ctx, torch, 0, x, args.steps, args.warmup)
     flops = 8.0 * wl.P ** 2 * wl.n * (wl.n - 1)
+    v32, v64 = tuning["fp32"]["variant"], tuning["fp64"]["variant"]
     ach32 = flops / (m2l32 * 1e-3)
     ach64 = flops / (m2l64 * 1e-3)
     value = args.steps / el32
@@ -459,20 +474,21 @@ def main():
             "n_particles": wl.n, "p": wl.p, "n_nodes": wl.n_nodes, "parallelism": "single GPU",
         },
         "roofline": {
-            "kernel": "k_m2l<float,16> (all-pairs M2L, FP32)",
-            "bound": "alu",
+            "kernel": M2L_VARIANTS[v32][0].format(t="float"),
+            "bound": M2L_VARIANTS[v32][1],
             "achieved": ach32 / 1e12,
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": ach32 / PEAK_FP32,
-            "traffic": _m2l_traffic(),
+            "traffic": _m2l_traffic(v32),
             "avg_ms": m2l32,
             "launches": cnt32,
             "algorithmic_flops_per_launch": flops,
         },
         "fp64": {
             "value": value64, "unit": "matvecs/s", "ms_per_step": el64 / args.steps * 1e3,
-            "roofline": {"kernel": "k_m2l<double,16>", "bound": "alu", "achieved": ach64 / 1e12,
+            "roofline": {"kernel": M2L_VARIANTS[v64][0].format(t="double"), "bound": M2L_VARIANTS[v64][1],
+                         "achieved": ach64 / 1e12,
                          "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach64 / PEAK_FP64,
                          "avg_ms": m2l64, "launches": cnt64},
         },

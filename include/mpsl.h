@@ -358,8 +358,12 @@ int mpsl_eval_field(mpsl_ctx *ctx, const double *src_xy, const mpsl_c128 *beta,
 /* Launch-shape tuning of the M2L kernel (row a1), per precision.  Variants:
  * 0 = one lane per target holding all P accumulators; 1 = two lanes per target
  * (output halves, the upper half through the mirror symmetry of the Toeplitz
- * translation) for more waves per SIMD at twice the recurrence work.
- * mpsl_autotune times both variants at 1/2, 1 and 2 times the default number
+ * translation) for more waves per SIMD at twice the recurrence work;
+ * 2, 3 = matrix cores (the translation as a GEMM over (source, order shift)
+ * with the source coefficients in shifted form, 16 or 32 targets per wave),
+ * for p <= 16 only (a stored 2 or 3 runs as 0 at larger p, and the autotuner
+ * skips them there).
+ * mpsl_autotune times the variants at 1/2, 1 and 2 times the default number
  * of source chunks on the current problem (pseudo-random input, HIP events on
  * the context stream) and keeps the fastest; mpsl_set_tuning forces a choice
  * (chunks 0 = default).  Tuning is kept until changed; it never changes

@@ -1019,7 +1019,7 @@ int mpsl_profile_read(mpsl_ctx *ctx, double *ms_avg, int *count) {
 }
 
 int mpsl_set_tuning(mpsl_ctx *ctx, int prec, int variant, int chunks) {
-  if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32) || (variant != mpsl::kM2LWhole && variant != mpsl::kM2LHalves) ||
+  if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32) || variant < mpsl::kM2LWhole || variant > mpsl::kM2LMfmaWide ||
       chunks < 0)
     return MPSL_EINVAL;
   auto &t = ctx->tune[prec == MPSL_FP64 ? 0 : 1];
@@ -1032,7 +1032,7 @@ int mpsl_set_tuning(mpsl_ctx *ctx, int prec, int variant, int chunks) {
 int mpsl_get_tuning(const mpsl_ctx *ctx, int prec, int *variant, int *chunks, double *ms) {
   if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
   const auto &t = ctx->tune[prec == MPSL_FP64 ? 0 : 1];
-  if (variant) *variant = t.variant;
+  if (variant) *variant = t.variant >= 0 ? t.variant : mpsl::m2l_default_variant(ctx->p, prec);
   if (chunks) *chunks = mpsl::chunks_m2l(ctx, prec);
   if (ms) *ms = t.ms;
   return MPSL_OK;
@@ -1058,8 +1058,9 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
   MPSL_HIP_TRY(ctx, hipEventCreate(&e1));
   double best = 1e300;
   int bv = mpsl::kM2LWhole, bc = base;
-  for (int variant = mpsl::kM2LWhole; variant <= mpsl::kM2LHalves; ++variant)
+  for (int variant = mpsl::kM2LWhole; variant <= mpsl::kM2LMfmaWide; ++variant)
     for (int c : cands) {
+      if (variant >= mpsl::kM2LMfma && ctx->p > mpsl::kM2LMfmaMaxP) break;
       if ((rc = mpsl::dev_alloc(ctx, ctx->part, static_cast<size_t>(c) * len * esz))) break;
       if ((rc = mpsl::launch_m2l(ctx, prec, ctx->xbuf.p, ctx->part.p, c, variant))) break;  // warm-up
       if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = MPSL_EHIP; break; }

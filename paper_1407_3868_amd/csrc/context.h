@@ -182,7 +182,7 @@ struct mpsl_ctx {
   // launch shapes
   int m2l_chunks = 0;     // source chunks of the M2L grid (0: automatic)
   struct Tune {
-    int variant = 0;      // M2L variant (kM2LWhole / kM2LHalves)
+    int variant = -1;     // M2L variant (kM2LWhole ... kM2LMfmaWide), -1 = by order and precision
     int chunks = 0;       // M2L source chunks (0: automatic)
     double ms = 0.0;      // measured M2L time of the choice
   } tune[2];              // [0]: FP64, [1]: FP32

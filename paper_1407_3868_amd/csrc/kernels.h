@@ -22,9 +22,16 @@ int launch_geom_tables(mpsl_ctx *ctx);
 int launch_pair_tables(mpsl_ctx *ctx);
 
 // Row a1: partial local expansions of the all-pairs M2L into
-// part[0 .. chunks).  variant: kM2LWhole, kM2LHalves, or -1 for the tuned one.
+// part[0 .. chunks).  variant: kM2LWhole, kM2LHalves, kM2LMfma, kM2LMfmaWide
+// (matrix cores, 16 or 32 targets per wave, p <= kM2LMfmaMaxP), or -1 for the
+// tuned one.
 constexpr int kM2LWhole = 0;
 constexpr int kM2LHalves = 1;
+constexpr int kM2LMfma = 2;
+constexpr int kM2LMfmaWide = 3;
+constexpr int kM2LMfmaMaxP = 16;
+// Variant used before any tuning: by expansion order and precision.
+int m2l_default_variant(int p, int prec);
 // nrhs right-hand sides: beta [nrhs][n][P]; part of rhs r at part + r * pstride.
 int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant = -1,
                int nrhs = 1, int64_t pstride = 0);

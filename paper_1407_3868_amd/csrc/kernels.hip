@@ -655,6 +655,212 @@ store:
 }
 
 // ---------------------------------------------------------------------------
+// Row a1 on the matrix cores, one right-hand side.  The translation
+// alpha_{n'} = sum_q h_q beta_{n'+q} (q = nu - n', |q| <= 2p) is a product
+// with the source coefficients in shifted form: with A_m[n'][q] = beta_m[n'+q]
+// (zero where |n' + q| > p) and B[(m, q)][l] = h_q of the pair (m -> l),
+//   alpha_l[n'] = sum_{m, q} A_m[n'][q] B[(m, q)][l],
+// a GEMM with M = output orders, N = targets and K = (source, q).  Each
+// 16x16x4 MFMA takes four sources at one q: lane i runs the Hankel recurrence
+// of the pair (source i / 16 of the group -> target i % 16) and supplies its
+// h_q as the B operand; A, the shifted coefficients of one 16-row block of
+// output orders, is read from LDS.  Orders n' in [-p, -1] ("lo") and [1, p]
+// ("hi") are two 16-row blocks (for p < 16 the rows beyond p compute
+// values that are never stored; their reads stay inside the row); n' = 0 is
+// accumulated on the vector units and summed over the four sources of a
+// group at the end.  q runs from 0 to 2p; h_q and h_{-q} go to the blocks
+// whose rows they reach: 96 complex MFMAs per group at p = 16, against the
+// 68 that the nonzero band needs.  Complex products take three real MFMAs
+// (Gauss): P1 = sum Ar Br, P2 = sum Ai Bi, P3 = sum (Ar + Ai)(Br + Bi);
+// re = P1 - P2, im = P3 - P1 - P2.  LDS holds the coefficients of
+// kM2lMfmaBatch sources of the chunk as (re, im, re + im) with zero padding
+// on both sides of every row.  Each wave owns NT tiles of 16 targets; the A
+// reads are shared across its tiles.
+constexpr int kM2lMfmaWaves = 4;
+constexpr int kM2lMfmaBatch = 32;
+
+template <typename T, int p, int NT>
+__global__ __launch_bounds__(64 * kM2lMfmaWaves) void k_m2l_mfma(const cv_t<T> *__restrict__ pairs,
+                                                                 const cv_t<T> *__restrict__ beta,
+                                                                 cv_t<T> *__restrict__ part, int n, int chunk_len,
+                                                                 int64_t bstride, int64_t pstride) {
+  static_assert(p >= 1 && p <= 16, "one 16-row block per sign of n'");
+  constexpr int P = 2 * p + 1;
+  constexpr int OFS = p - 1;       // LDS index of coefficient slot s (s >= 1 - p)
+  // Row length: slots [1 - p, 2p + 15].  FP32 rows are padded to 16 mod 64
+  // words, so that the four source rows one read touches start in different
+  // LDS banks (a stride of 0 mod 32 words serialises them four ways).
+  constexpr int LR0 = 3 * p + 16;
+  constexpr int LR = sizeof(T) == 4 ? LR0 + ((16 - LR0) % 64 + 64) % 64 : LR0;
+  constexpr int SB = kM2lMfmaBatch;
+  typedef typename mfma4<T>::v4 v4;
+  __shared__ T sa[3][SB][LR];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int c = blockIdx.y;
+  beta += blockIdx.z * bstride;
+  part += blockIdx.z * pstride;
+  const int m0 = c * chunk_len;
+  const int m1 = min(n, m0 + chunk_len);
+  const int lt0 = (blockIdx.x * kM2lMfmaWaves + w) * 16 * NT;
+
+  for (int e = threadIdx.x; e < 3 * SB * LR; e += 64 * kM2lMfmaWaves) (&sa[0][0][0])[e] = T(0);
+
+  v4 lo[NT][3], hi[NT][3];
+  cx<T> zc[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lo[tt][k] = hi[tt][k] = v4{0, 0, 0, 0};
+    zc[tt] = mk<T>(0, 0);
+  }
+  // pair entries of the first group (source m0 + g)
+  cv_t<T> pa[NT][4];
+  auto load_pairs = [&](int m) {
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+      const int l = lt0 + tt * 16 + r;
+      if (m < m1 && l < n) {
+        const cv_t<T> *pe = pairs + 4 * (static_cast<int64_t>(m) * n + l);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pa[tt][k] = pe[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) pa[tt][k] = st(mk<T>(0, 0));
+      }
+    }
+  };
+  load_pairs(m0 + g);
+
+  for (int mb = m0; mb < m1; mb += SB) {
+    const int sb = min(SB, m1 - mb);
+    __syncthreads();  // previous batch consumed (and the zero fill done)
+    for (int e = threadIdx.x; e < SB * P; e += 64 * kM2lMfmaWaves) {
+      const int s = e / P, v = e - s * P;
+      const cx<T> b = s < sb ? ld<T>(beta[static_cast<int64_t>(mb + s) * P + v]) : mk<T>(0, 0);
+      sa[0][s][v + OFS] = b.re;
+      sa[1][s][v + OFS] = b.im;
+      sa[2][s][v + OFS] = b.re + b.im;
+    }
+    __syncthreads();
+    for (int g0 = 0; g0 < sb; g0 += 4) {
+      const int s = g0 + g;  // this lane's source within the batch
+      cx<T> hp[NT], hc[NT], t[NT], tq[NT];
+      T tz[NT];
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) {
+        hp[tt] = ld<T>(pa[tt][0]);
+        hc[tt] = ld<T>(pa[tt][1]);
+        t[tt] = ld<T>(pa[tt][2]);
+        tq[tt] = t[tt];
+        tz[tt] = pa[tt][3].x;
+      }
+      load_pairs(mb + s + 4);  // next group's entries in flight
+      const T *ar = sa[0][s], *ai = sa[1][s], *as = sa[2][s];
+      // A operands of step q.  lo rows: n' = r - p, coefficient slot r + q
+      // (h_q) and r - q (h_{-q}); hi rows: n' = r + 1, slots r + 1 + p + q and
+      // r + 1 + p - q; row n' = 0: slots p + q and p - q.
+      struct Ops {
+        T al[3], ah[3], bl[3], bh[3];
+        cx<T> bp, bn;
+      };
+      auto fetch = [&](int q) {
+        Ops o;
+        const int il = r + q + OFS, ih = r + 1 + p + q + OFS;
+        const int jl = r - q + OFS, jh = r + 1 + p - q + OFS;
+        o.al[0] = ar[il], o.al[1] = ai[il], o.al[2] = as[il];
+        if (q <= p - 1) o.ah[0] = ar[ih], o.ah[1] = ai[ih], o.ah[2] = as[ih];
+        if (q >= 1 && q <= p - 1) o.bl[0] = ar[jl], o.bl[1] = ai[jl], o.bl[2] = as[jl];
+        if (q >= 1) o.bh[0] = ar[jh], o.bh[1] = ai[jh], o.bh[2] = as[jh];
+        if (q <= p) {
+          o.bp = mk<T>(ar[p + q + OFS], ai[p + q + OFS]);
+          o.bn = mk<T>(ar[p - q + OFS], ai[p - q + OFS]);
+        }
+        return o;
+      };
+      Ops cur = fetch(0);
+#pragma unroll
+      for (int q = 0; q <= 2 * p; ++q) {
+        Ops nxt;
+        if (q < 2 * p) nxt = fetch(q + 1);  // the next step's LDS reads in flight
+        cx<T> hq[NT], hm[NT];
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+          if (q == 0) {
+            hq[tt] = hp[tt];  // H_0
+          } else {
+            if (q >= 2) {
+              const cx<T> hn = static_cast<T>(q - 1) * tz[tt] * hc[tt] - hp[tt];
+              hp[tt] = hc[tt];
+              hc[tt] = hn;
+              tq[tt] = tq[tt] * t[tt];
+            }
+            hq[tt] = hc[tt] * tq[tt];
+            hm[tt] = hc[tt] * conj(tq[tt]);
+            if (q & 1) hm[tt] = mk<T>(-hm[tt].re, -hm[tt].im);
+          }
+        }
+        // n' = 0 on the vector units: alpha_0 += h_q beta_q + h_{-q} beta_{-q}
+        if (q <= p) {
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) cmac(zc[tt], hq[tt], cur.bp);
+          if (q > 0) {
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) cmac(zc[tt], hm[tt], cur.bn);
+          }
+        }
+        // the two blocks alternate so that no MFMA waits on the one before it
+        const bool lom = q >= 1 && q <= p - 1, hip_ = q <= p - 1, him = q >= 1;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+          const T sq = hq[tt].re + hq[tt].im;
+          lo[tt][0] = mfma4<T>::mac(cur.al[0], hq[tt].re, lo[tt][0]);
+          if (hip_) hi[tt][0] = mfma4<T>::mac(cur.ah[0], hq[tt].re, hi[tt][0]);
+          lo[tt][1] = mfma4<T>::mac(cur.al[1], hq[tt].im, lo[tt][1]);
+          if (hip_) hi[tt][1] = mfma4<T>::mac(cur.ah[1], hq[tt].im, hi[tt][1]);
+          lo[tt][2] = mfma4<T>::mac(cur.al[2], sq, lo[tt][2]);
+          if (hip_) hi[tt][2] = mfma4<T>::mac(cur.ah[2], sq, hi[tt][2]);
+          if (q >= 1) {
+            const T sm = hm[tt].re + hm[tt].im;
+            if (him) hi[tt][0] = mfma4<T>::mac(cur.bh[0], hm[tt].re, hi[tt][0]);
+            if (lom) lo[tt][0] = mfma4<T>::mac(cur.bl[0], hm[tt].re, lo[tt][0]);
+            if (him) hi[tt][1] = mfma4<T>::mac(cur.bh[1], hm[tt].im, hi[tt][1]);
+            if (lom) lo[tt][1] = mfma4<T>::mac(cur.bl[1], hm[tt].im, lo[tt][1]);
+            if (him) hi[tt][2] = mfma4<T>::mac(cur.bh[2], sm, hi[tt][2]);
+            if (lom) lo[tt][2] = mfma4<T>::mac(cur.bl[2], sm, lo[tt][2]);
+          }
+        }
+        cur = nxt;
+        // one q step at a time: keeps the live registers to two steps' operands
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  cv_t<T> *o = part + static_cast<int64_t>(c) * n * P;
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    const int l = lt0 + tt * 16 + r;
+    cx<T> z = zc[tt];
+    z.re += __shfl_xor(z.re, 16);
+    z.im += __shfl_xor(z.im, 16);
+    z.re += __shfl_xor(z.re, 32);
+    z.im += __shfl_xor(z.im, 32);
+    if (l >= n) continue;
+    if (g == 0) o[static_cast<int64_t>(l) * P + p] = st(z);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = mfma4<T>::row(lane, j);
+      if (row < p) {
+        const T p1 = lo[tt][0][j], p2 = lo[tt][1][j], p3 = lo[tt][2][j];
+        o[static_cast<int64_t>(l) * P + row] = st(mk<T>(p1 - p2, p3 - p1 - p2));
+        const T q1 = hi[tt][0][j], q2 = hi[tt][1][j], q3 = hi[tt][2][j];
+        o[static_cast<int64_t>(l) * P + p + 1 + row] = st(mk<T>(q1 - q2, q3 - q1 - q2));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Row a1 for many right-hand sides on the matrix cores (FP32): per pair the
 // Toeplitz translation T^{ml}[n'][nu] = h_{nu-n'} is built once and applied to
 // the coefficients of 64 right-hand sides as a GEMM  alpha_l[n'][r] +=
@@ -985,12 +1191,29 @@ __global__ void k_field(const double2 *__restrict__ xy, const double2 *__restric
 
 }  // namespace
 
+int m2l_default_variant(int p, int prec) {
+  // measured crossovers at 5000 particles: the matrix-core form wins from
+  // p = 12 in FP32 and at p = 16 in FP64 (its FP64 MFMA rate equals the vector
+  // rate, so only the larger translations gain)
+  const int from = prec == MPSL_FP64 ? 15 : 12;
+  return (p >= from && p <= kM2LMfmaMaxP) ? kM2LMfma : kM2LWhole;
+}
+
+static int m2l_variant(const mpsl_ctx *ctx, int prec) {
+  int v = ctx->tune[prec == MPSL_FP64 ? 0 : 1].variant;
+  if (v < 0) v = m2l_default_variant(ctx->p, prec);
+  if (v >= kM2LMfma && ctx->p > kM2LMfmaMaxP) v = kM2LWhole;
+  return v;
+}
+
 int chunks_m2l(const mpsl_ctx *ctx, int prec) {
   const int tuned = ctx->tune[prec == MPSL_FP64 ? 0 : 1].chunks;
   if (tuned > 0) return static_cast<int>(std::min<int64_t>(tuned, ctx->n));
   if (ctx->m2l_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2l_chunks, ctx->n));
-  const int tb = cdiv(ctx->n, kThreads);
-  const int c = cdiv(2560, tb);
+  // about 2560 blocks of 128 lanes, or 10240 of 4 waves on the matrix cores
+  const int v = m2l_variant(ctx, prec);
+  const int c = v >= kM2LMfma ? cdiv(10240, cdiv(ctx->n, 64 * (v == kM2LMfmaWide ? 2 : 1)))
+                              : cdiv(2560, cdiv(ctx->n, kThreads));
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
 }
 
@@ -1051,6 +1274,28 @@ static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks,
   const auto *b = static_cast<const cv_t<T> *>(beta);
   auto *o = static_cast<cv_t<T> *>(part);
   const int64_t bs = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
+  if (variant == kM2LMfma || variant == kM2LMfmaWide) {
+    if (ctx->p > kM2LMfmaMaxP) return set_err(ctx, MPSL_EUNSUPPORTED, "matrix-core M2L needs p <= 16");
+    const int nt = variant == kM2LMfma ? 1 : 2;
+    const dim3 g(cdiv(n, 16 * nt * kM2lMfmaWaves), chunks, nrhs);
+    const dim3 blk(64 * kM2lMfmaWaves);
+    switch (ctx->p) {
+#define X(PP)                                                                                               \
+  case PP:                                                                                                  \
+    if constexpr (PP <= kM2LMfmaMaxP) {                                                                     \
+      if (nt == 1)                                                                                          \
+        hipLaunchKernelGGL((k_m2l_mfma<T, PP, 1>), g, blk, 0, ctx->stream, pairs, b, o, n, chunk_len, bs, pstride); \
+      else                                                                                                  \
+        hipLaunchKernelGGL((k_m2l_mfma<T, PP, 2>), g, blk, 0, ctx->stream, pairs, b, o, n, chunk_len, bs, pstride); \
+    }                                                                                                       \
+    break;
+      MPSL_P_CASES(X)
+#undef X
+      default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
+    }
+    LAUNCH_CHECK(ctx);
+    return MPSL_OK;
+  }
   switch (ctx->p) {
 #define X(PP)                                                                                               \
   case PP:                                                                                                  \
@@ -1074,7 +1319,7 @@ static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks,
 
 int launch_m2l(mpsl_ctx *ctx, int prec, const void *beta, void *part, int chunks, int variant, int nrhs,
                int64_t pstride) {
-  if (variant < 0) variant = ctx->tune[prec == MPSL_FP64 ? 0 : 1].variant;
+  if (variant < 0) variant = m2l_variant(ctx, prec);  // tuned or default; matrix cores up to p = 16
   return prec == MPSL_FP64 ? launch_m2l_t<double>(ctx, beta, part, chunks, variant, nrhs, pstride)
                            : launch_m2l_t<float>(ctx, beta, part, chunks, variant, nrhs, pstride);
 }

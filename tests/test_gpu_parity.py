@@ -226,10 +226,11 @@ def test_highest_order(torch_dev):
 
 @pytest.mark.parametrize("name", ["s70p8", "s150p12", "s200p16"])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("variant,chunks", [(0, 3), (1, 0), (1, 7)])
+@pytest.mark.parametrize("variant,chunks", [(0, 3), (1, 0), (1, 7), (2, 0), (2, 7), (3, 0), (3, 5)])
 def test_m2l_variants(name, prec, variant, chunks, torch_dev):
-    # both launch shapes (whole / output halves through the mirror identity) and
-    # several source-chunk counts give the oracle's translation
+    # every launch shape (whole / output halves through the mirror identity /
+    # matrix cores with 16 or 32 targets per wave) and several source-chunk
+    # counts give the oracle's translation
     torch = torch_dev
     wl, pr, ctx = _setup(name)
     ctx.set_tuning(prec, variant, chunks)
@@ -255,8 +256,44 @@ def test_autotune_keeps_results(prec, torch_dev):
     before = ctx.apply(prec, x.astype(npdt))
     ctx.autotune(prec)
     t = ctx.get_tuning(prec)
-    assert t["variant"] in (0, 1) and t["chunks"] >= 1 and t["m2l_ms"] > 0
+    assert t["variant"] in (0, 1, 2, 3) and t["chunks"] >= 1 and t["m2l_ms"] > 0
     after = ctx.apply(prec, x.astype(npdt))
     tol = FP64_TOL if prec == 0 else FP32_TOL
     assert rel_err(after, pr.matvec(x)) < tol
     assert rel_err(after, before) < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_m2l_matrix_cores_multi_rhs_and_empty_chunks(prec, torch_dev):
+    """The matrix-core M2L over several right-hand sides (grid.z) and with more
+    source chunks than fill (trailing chunks empty: their partial slots must
+    come out zero), 150 stars at p = 12 (rows 12..15 of each 16-row block
+    masked)."""
+    torch = torch_dev
+    wl, pr, ctx = _setup("s150p12")
+    ctx.set_tuning(prec, 2, 149)   # chunk length 2: the last chunk is empty
+    X = np.stack([coeff_vector(wl, 20 + r) for r in range(3)])
+    npdt = np.complex128 if prec == 0 else np.complex64
+    xd = torch.from_numpy(X.astype(npdt)).cuda()
+    yd = torch.zeros_like(xd)
+    ctx.set_stream(torch.cuda.current_stream().cuda_stream)
+    ctx.apply_batch_dev(prec, 3, xd, yd)
+    torch.cuda.synchronize()
+    tol = FP64_TOL if prec == 0 else FP32_TOL
+    for r in range(3):
+        assert rel_err(yd[r].cpu().numpy(), pr.matvec(X[r])) < tol
+
+
+def test_m2l_matrix_cores_order_limit(torch_dev):
+    """p = 20 is beyond the matrix-core form: a stored matrix-core variant
+    runs as the one-lane-per-target kernel, and the autotuner skips it."""
+    wl = make_workload("s70p8")
+    wl.p = 20
+    pr = oracle_problem(wl)
+    ctx = gpu_context(wl)
+    x = coeff_vector(wl, 9)
+    ctx.set_tuning(0, 3, 0)
+    assert rel_err(ctx.apply(0, x), pr.matvec(x)) < FP64_TOL
+    ctx.autotune(0)
+    assert ctx.get_tuning(0)["variant"] in (0, 1)
+    assert rel_err(ctx.apply(0, x), pr.matvec(x)) < FP64_TOL
