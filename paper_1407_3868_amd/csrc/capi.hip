@@ -1062,10 +1062,15 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
     for (int c : cands) {
       if (variant >= mpsl::kM2LMfma && ctx->p > mpsl::kM2LMfmaMaxP) break;
       if ((rc = mpsl::dev_alloc(ctx, ctx->part, static_cast<size_t>(c) * len * esz))) break;
-      if ((rc = mpsl::launch_m2l(ctx, prec, ctx->xbuf.p, ctx->part.p, c, variant))) break;  // warm-up
+      // timed with the fold of its c partial slots, which grows with c
+      auto run = [&]() {
+        int e = mpsl::launch_m2l(ctx, prec, ctx->xbuf.p, ctx->part.p, c, variant);
+        return e ? e : mpsl::launch_fold_parts(ctx, prec, ctx->part.p, c);
+      };
+      if ((rc = run())) break;  // warm-up
       if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = MPSL_EHIP; break; }
       const int reps = 3;
-      for (int r = 0; r < reps && !rc; ++r) rc = mpsl::launch_m2l(ctx, prec, ctx->xbuf.p, ctx->part.p, c, variant);
+      for (int r = 0; r < reps && !rc; ++r) rc = run();
       if (rc) break;
       float ms = 0.f;
       if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
