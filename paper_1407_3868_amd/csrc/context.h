@@ -71,7 +71,7 @@ struct FmmStage {
 // on the vertical segment are kept as their own coarse nodes.
 struct SommPlan {
   bool active = false;
-  int nT = 0, nc = 0, nint = 0, ndir = 0;
+  int nT = 0, nc = 0, nint = 0, ndir = 0, nfb = 0;
   double tile_w = 0.0, tile_h = 0.0, L_I = 0.0, d_dir = 0.0;
   DBuf perm;        // int32[n]: particles ordered by tile
   DBuf tstart;      // int32[nT + 1]
@@ -80,13 +80,13 @@ struct SommPlan {
   DBuf lamc, gc;    // double2[nc]: coarse nodes and gamma2 there
   DBuf Wc64, Wc32;  // [2][nc][P]: M2S weights at the coarse nodes
   DBuf Zc64, Zc32;  // [2][nc][P]: S2L powers at the coarse nodes
-  DBuf run_c0;      // int32[ns]: first coarse node of each contour node's run
-  DBuf run_len;     // int32[ns]: run length (kSommNc, or 1 for a direct node)
   DBuf Lw;          // double[ns][kSommNc]: interpolation weights
   DBuf ivl;         // int32[nint][4]: fine start (in fperm), fine count, coarse start, unused
   DBuf fperm;       // int32[ns]: contour nodes of the intervals, interval by interval
   DBuf dir;         // int32[ndir][2]: contour node and coarse node of each direct node
   DBuf G;           // work [nrhs][2][nT][nc] in the matvec precision
+  DBuf fblk;        // M2S interval-node blocks: (interval, first node)
+  DBuf Bp;          // S2L node-chunk partials [chunk][nrhs][2][nT][24 nint] in the matvec precision
   const void *sigma = nullptr;  // S2L densities recorded by the coefficient step
 };
 

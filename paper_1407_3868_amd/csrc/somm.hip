@@ -80,55 +80,117 @@ __global__ __launch_bounds__(256) void k_si_tileG(const cv_t<T> *__restrict__ be
   G[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c] = st(acc);
 }
 
-// M2S, step 2: one lane per contour node; spectra in FP64 as the direct path.
+// M2S, step 2, interval nodes: one block per (interval, run of kSiFineNodes
+// of its nodes) from the table fblk; kSiFineSplit lanes per node, each
+// summing every kSiFineSplit-th tile, combined through LDS in a fixed order.
+// The interval's coarse values G[T][c0 .. c0 + kSommNc) and weights come
+// through wave-uniform loads; spectra in FP64 as the direct path.
+constexpr int kSiFineSplit = 4;
+constexpr int kSiFineNodes = 64;  // nodes per block (block: kSiFineNodes * kSiFineSplit lanes)
 template <typename T>
-__global__ __launch_bounds__(256) void k_si_fine(const cv_t<T> *__restrict__ G, const double2 *__restrict__ lam,
-                                                 const double2 *__restrict__ g2, const double2 *__restrict__ txy,
-                                                 const int *__restrict__ run_c0, const int *__restrict__ run_len,
-                                                 const double *__restrict__ Lw, int ns, int nT, int nc, double d,
-                                                 double2 *__restrict__ spec) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine(
+    const cv_t<T> *__restrict__ G, const double2 *__restrict__ lam, const double2 *__restrict__ g2,
+    const double2 *__restrict__ txy, const int *__restrict__ ivl, const int *__restrict__ fperm,
+    const int *__restrict__ fblk, const double *__restrict__ Lw, int ns, int nT, int nc, double d,
+    double2 *__restrict__ spec) {
+  static_assert(kSiFineNodes == 64, "one wave per tile share");
+  __shared__ double2 red[kSiFineSplit][kSiFineNodes];
+  // the tile share is the wave index: wave-uniform, so the tile loop's loads are scalar
+  const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / kSiFineNodes), ql = threadIdx.x - j * kSiFineNodes;
+  const int iv = fblk[2 * blockIdx.x], off = fblk[2 * blockIdx.x + 1];
+  const int f0 = ivl[4 * iv], nf = ivl[4 * iv + 1], c0 = ivl[4 * iv + 2];
+  const bool act = off + ql < nf;
+  const int q = fperm[f0 + (act ? off + ql : 0)];
   const int s = blockIdx.y & 1, r = blockIdx.y >> 1;
-  if (q >= ns) return;
   const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
-  const int c0 = run_c0[q], len = run_len[q];
-  double wq[kSommNc];
+  T wq[kSommNc];
 #pragma unroll
-  for (int k = 0; k < kSommNc; ++k) wq[k] = k < len ? Lw[static_cast<int64_t>(q) * kSommNc + k] : 0.0;
-  const cv_t<T> *Gs = G + (static_cast<int64_t>(r) * 2 + s) * nT * nc;
+  for (int k = 0; k < kSommNc; ++k) wq[k] = static_cast<T>(Lw[static_cast<int64_t>(q) * kSommNc + k]);
+  const cv_t<T> *Gs = G + ((static_cast<int64_t>(r) * 2 + s) * nT) * nc + c0;
   cx<double> acc = mk(0.0, 0.0);
-  for (int t = 0; t < nT; ++t) {
+  for (int t = j; t < nT; t += kSiFineSplit) {
     const double xT = txy[t].x, yT = txy[t].y;
     const double yy = s == 0 ? yT : -(d + yT);  // e^{-i lam x_T + g2 y_T}, e^{-i lam x_T - g2 (d + y_T)}
     const cx<double> E = cexp64(li * xT + gr * yy, -lr * xT + gi * yy);
-    const cv_t<T> *Gt = Gs + static_cast<int64_t>(t) * nc + c0;
+    const cv_t<T> *Gt = Gs + static_cast<int64_t>(t) * nc;
     cx<T> h = mk<T>(0, 0);
 #pragma unroll
-    for (int k = 0; k < kSommNc; ++k)
-      if (k < len) h = h + static_cast<T>(wq[k]) * ld<T>(Gt[k]);
+    for (int k = 0; k < kSommNc; ++k) h = h + wq[k] * ld<T>(Gt[k]);
     acc = acc + E * up<T>(h);
   }
-  spec[(static_cast<int64_t>(r) * 2 + s) * ns + q] = st(acc);
+  red[j][ql] = st(acc);
+  __syncthreads();
+  if (j == 0 && act) {
+    cx<double> sum = ld<double>(red[0][ql]);
+#pragma unroll
+    for (int u = 1; u < kSiFineSplit; ++u) sum = sum + ld<double>(red[u][ql]);
+    spec[(static_cast<int64_t>(r) * 2 + s) * ns + q] = st(sum);
+  }
 }
 
-// S2L, step 1 for the Chebyshev intervals: one block per (interval, tile),
-// blockIdx.z = 2 rhs + side; every lane keeps kSommNc partial sums.
+// M2S, step 2, direct nodes (their own coarse node, weight 1): one lane per
+// node and tile share as above.
 template <typename T>
-__global__ __launch_bounds__(256) void k_si_coarseB(const double2 *__restrict__ sigma, const double2 *__restrict__ cq,
-                                                    const double2 *__restrict__ lam, const double2 *__restrict__ g2,
-                                                    const double2 *__restrict__ txy, const int *__restrict__ ivl,
-                                                    const int *__restrict__ fperm, const double *__restrict__ Lw,
-                                                    int ns, int nT, int nc, double d, cv_t<T> *__restrict__ B) {
-  __shared__ double red[4][kSommNc][2];
-  const int iv = blockIdx.x, t = blockIdx.y, s = blockIdx.z & 1, r = blockIdx.z >> 1;
+__global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine_dir(
+    const cv_t<T> *__restrict__ G, const double2 *__restrict__ lam, const double2 *__restrict__ g2,
+    const double2 *__restrict__ txy, const int *__restrict__ dir, int ndir, int ns, int nT, int nc, double d,
+    double2 *__restrict__ spec) {
+  __shared__ double2 red[kSiFineSplit][kSiFineNodes];
+  const int j = threadIdx.x / kSiFineNodes, ql = threadIdx.x - j * kSiFineNodes;
+  const int i = blockIdx.x * kSiFineNodes + ql;
+  const bool act = i < ndir;
+  const int q = act ? dir[2 * i] : 0, c = act ? dir[2 * i + 1] : 0;
+  const int s = blockIdx.y & 1, r = blockIdx.y >> 1;
+  const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
+  const cv_t<T> *Gs = G + ((static_cast<int64_t>(r) * 2 + s) * nT) * nc + c;
+  cx<double> acc = mk(0.0, 0.0);
+  if (act) {
+    for (int t = j; t < nT; t += kSiFineSplit) {
+      const double xT = txy[t].x, yT = txy[t].y;
+      const double yy = s == 0 ? yT : -(d + yT);
+      acc = acc + cexp64(li * xT + gr * yy, -lr * xT + gi * yy) * up<T>(ld<T>(Gs[static_cast<int64_t>(t) * nc]));
+    }
+  }
+  red[j][ql] = st(acc);
+  __syncthreads();
+  if (j == 0 && act) {
+    cx<double> sum = ld<double>(red[0][ql]);
+#pragma unroll
+    for (int u = 1; u < kSiFineSplit; ++u) sum = sum + ld<double>(red[u][ql]);
+    spec[(static_cast<int64_t>(r) * 2 + s) * ns + q] = st(sum);
+  }
+}
+
+// S2L, step 1 for the Chebyshev intervals: one lane per tile, every lane of
+// a block walking the same fine nodes of one interval (node data and the
+// interpolation weights are wave-uniform loads), kSommNc sums per lane in
+// FP64.  grid: (interval, tile block, chunk of the interval's nodes +
+// nchunk * (2 rhs + side)); chunk cz writes its own partial slot
+// Bp[cz][rhs, side][t][k], k over the intervals' coarse nodes (which come
+// first in the coarse-node order), summed by k_si_coarseB_sum.
+constexpr int kSiCoarseLanes = 256;
+template <typename T>
+__global__ __launch_bounds__(kSiCoarseLanes) void k_si_coarseB(
+    const double2 *__restrict__ sigma, const double2 *__restrict__ cq, const double2 *__restrict__ lam,
+    const double2 *__restrict__ g2, const double2 *__restrict__ txy, const int *__restrict__ ivl,
+    const int *__restrict__ fperm, const double *__restrict__ Lw, int ns, int nT, int nci, int nchunk,
+    double d, cv_t<T> *__restrict__ Bp) {
+  const int iv = blockIdx.x;
+  const int t = blockIdx.y * kSiCoarseLanes + threadIdx.x;
+  const int cz = blockIdx.z % nchunk, rs = blockIdx.z / nchunk;
+  const int s = rs & 1, r = rs >> 1;
   const int f0 = ivl[4 * iv], nf = ivl[4 * iv + 1], c0 = ivl[4 * iv + 2];
+  const int i0 = static_cast<int>((static_cast<int64_t>(nf) * cz) / nchunk);
+  const int i1 = static_cast<int>((static_cast<int64_t>(nf) * (cz + 1)) / nchunk);
   sigma += static_cast<int64_t>(r) * 2 * ns;
-  const double xT = txy[t].x, yT = txy[t].y;
-  const double yy = s == 0 ? yT : -(yT + d);  // e^{i lam x_T + g2 y_T}, e^{i lam x_T - g2 (y_T + d)}
+  const bool act = t < nT;
+  const double2 tc = txy[act ? t : 0];
+  const double xT = tc.x;
+  const double yy = s == 0 ? tc.y : -(tc.y + d);  // e^{i lam x_T + g2 y_T}, e^{i lam x_T - g2 (y_T + d)}
   double are[kSommNc], aim[kSommNc];
 #pragma unroll
   for (int k = 0; k < kSommNc; ++k) are[k] = aim[k] = 0.0;
-  for (int i = threadIdx.x; i < nf; i += 256) {
+  for (int i = i0; i < i1; ++i) {
     const int q = fperm[f0 + i];
     const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
     const cx<double> u = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]);
@@ -140,25 +202,25 @@ __global__ __launch_bounds__(256) void k_si_coarseB(const double2 *__restrict__ 
       aim[k] = fma(L[k], v.im, aim[k]);
     }
   }
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (!act) return;
+  cv_t<T> *o = Bp + ((static_cast<int64_t>(cz) * gridDim.z / nchunk + rs) * nT + t) * nci + c0;
 #pragma unroll
-  for (int k = 0; k < kSommNc; ++k) {
-    for (int off = 32; off > 0; off >>= 1) {
-      are[k] += __shfl_xor(are[k], off, 64);
-      aim[k] += __shfl_xor(aim[k], off, 64);
-    }
-    if (lane == 0) {
-      red[w][k][0] = are[k];
-      red[w][k][1] = aim[k];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < kSommNc) {
-    const int k = threadIdx.x;
-    const double re = red[0][k][0] + red[1][k][0] + red[2][k][0] + red[3][k][0];
-    const double im = red[0][k][1] + red[1][k][1] + red[2][k][1] + red[3][k][1];
-    B[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c0 + k] = st(mk<T>(static_cast<T>(re), static_cast<T>(im)));
-  }
+  for (int k = 0; k < kSommNc; ++k) o[k] = st(mk<T>(static_cast<T>(are[k]), static_cast<T>(aim[k])));
+}
+
+// Sum of the node-chunk partials of k_si_coarseB into B[rhs, side][t][c],
+// c < nci, in chunk order.
+template <typename T>
+__global__ void k_si_coarseB_sum(const cv_t<T> *__restrict__ Bp, int nchunk, int64_t rows, int nT, int nc, int nci,
+                                 cv_t<T> *__restrict__ B) {
+  const int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (e >= rows * nci) return;
+  const int64_t row = e / nci;  // (rhs, side, tile)
+  const int c = static_cast<int>(e - row * nci);
+  const int64_t plane = rows * nci;
+  cx<T> a = ld<T>(Bp[e]);
+  for (int cz = 1; cz < nchunk; ++cz) a = a + ld<T>(Bp[cz * plane + e]);
+  B[row * nc + c] = st(a);
 }
 
 // S2L, step 1 for the direct nodes: one lane per (direct node, tile).
@@ -256,12 +318,19 @@ int m2s_interp_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
   }
-  hipLaunchKernelGGL(k_si_fine<T>, dim3(cdv(ctx->ns, 256), 2 * nrhs), dim3(256), 0, ctx->stream, G,
-                     static_cast<const double2 *>(ctx->ct.lam.p),
-                     static_cast<const double2 *>(ctx->ct.gw.p) + ctx->ns,  // g2 stored after g1
-                     static_cast<const double2 *>(pl.txy.p), static_cast<const int *>(pl.run_c0.p),
-                     static_cast<const int *>(pl.run_len.p), static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT,
-                     pl.nc, ctx->d, static_cast<double2 *>(spec));
+  const auto *lam = static_cast<const double2 *>(ctx->ct.lam.p);
+  const auto *g2 = static_cast<const double2 *>(ctx->ct.gw.p) + ctx->ns;  // g2 stored after g1
+  const auto *txy = static_cast<const double2 *>(pl.txy.p);
+  const dim3 blk(kSiFineNodes * kSiFineSplit);
+  if (pl.nfb > 0)
+    hipLaunchKernelGGL(k_si_fine<T>, dim3(pl.nfb, 2 * nrhs), blk, 0, ctx->stream, G, lam, g2, txy,
+                       static_cast<const int *>(pl.ivl.p), static_cast<const int *>(pl.fperm.p),
+                       static_cast<const int *>(pl.fblk.p), static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT,
+                       pl.nc, ctx->d, static_cast<double2 *>(spec));
+  if (pl.ndir > 0)
+    hipLaunchKernelGGL(k_si_fine_dir<T>, dim3(cdv(pl.ndir, kSiFineNodes), 2 * nrhs), blk, 0, ctx->stream, G, lam,
+                       g2, txy, static_cast<const int *>(pl.dir.p), pl.ndir, ctx->ns, pl.nT, pl.nc, ctx->d,
+                       static_cast<double2 *>(spec));
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_err(ctx, MPSL_EHIP, std::string("interpolated M2S: ") + hipGetErrorString(e));
   return MPSL_OK;
@@ -281,10 +350,20 @@ int s2l_interp_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstrid
   const auto *lam = static_cast<const double2 *>(ctx->ct.lam.p);
   const auto *g2 = static_cast<const double2 *>(ctx->ct.gw.p) + ctx->ns;
   const auto *txy = static_cast<const double2 *>(pl.txy.p);
-  if (pl.nint > 0)
-    hipLaunchKernelGGL(k_si_coarseB<T>, dim3(pl.nint, pl.nT, 2 * nrhs), dim3(256), 0, ctx->stream, sig, cq, lam, g2,
-                       txy, static_cast<const int *>(pl.ivl.p), static_cast<const int *>(pl.fperm.p),
-                       static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT, pl.nc, ctx->d, B);
+  if (pl.nint > 0) {
+    // node chunks so that the launch has about 2048 blocks
+    const int nci = kSommNc * pl.nint, tb = cdv(pl.nT, kSiCoarseLanes);
+    const int nchunk = std::max(1, std::min(16, cdv(2048, static_cast<int64_t>(pl.nint) * tb * 2 * nrhs)));
+    const int64_t rows = 2ll * nrhs * pl.nT;
+    if ((rc = dev_alloc(ctx, pl.Bp, static_cast<size_t>(nchunk) * rows * nci * sizeof(cv_t<T>)))) return rc;
+    auto *Bp = static_cast<cv_t<T> *>(pl.Bp.p);
+    hipLaunchKernelGGL(k_si_coarseB<T>, dim3(pl.nint, tb, nchunk * 2 * nrhs), dim3(kSiCoarseLanes), 0, ctx->stream,
+                       sig, cq, lam, g2, txy, static_cast<const int *>(pl.ivl.p),
+                       static_cast<const int *>(pl.fperm.p), static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT,
+                       nci, nchunk, ctx->d, Bp);
+    hipLaunchKernelGGL(k_si_coarseB_sum<T>, dim3(cdv(rows * nci, 256)), dim3(256), 0, ctx->stream, Bp, nchunk, rows,
+                       pl.nT, pl.nc, nci, B);
+  }
   if (pl.ndir > 0)
     hipLaunchKernelGGL(k_si_coarseB_dir<T>, dim3(cdv(pl.ndir, 256), pl.nT, 2 * nrhs), dim3(256), 0, ctx->stream,
                        sig, cq, lam, g2, txy, static_cast<const int *>(pl.dir.p), pl.ndir, ctx->ns, pl.nT, pl.nc,
@@ -324,7 +403,7 @@ int launch_s2l_interp(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs,
 void somm_free(mpsl_ctx *ctx) {
   SommPlan &pl = ctx->somm;
   DBuf *b[] = {&pl.perm, &pl.tstart, &pl.txy, &pl.ptile, &pl.lamc, &pl.gc, &pl.Wc64, &pl.Wc32, &pl.Zc64,
-               &pl.Zc32, &pl.run_c0, &pl.run_len, &pl.Lw, &pl.ivl, &pl.fperm, &pl.dir, &pl.G};
+               &pl.Zc32, &pl.Lw, &pl.ivl, &pl.fperm, &pl.dir, &pl.G, &pl.Bp, &pl.fblk};
   for (DBuf *x : b) dev_free(*x);
   pl.active = false;
   pl.sigma = nullptr;
@@ -398,7 +477,7 @@ int somm_build(mpsl_ctx *ctx) {
   }
   // coarse nodes: kSommNc Chebyshev nodes per interval, then one per direct node
   std::vector<zc> lamc;
-  std::vector<int> run_c0(ns, 0), run_len(ns, 0), ivl, fperm, dir;
+  std::vector<int> ivl, fperm, dir;
   std::vector<double> Lw(static_cast<size_t>(ns) * kSommNc, 0.0);
   double xs[kSommNc], bw[kSommNc];
   for (int j = 0; j < kSommNc; ++j) {
@@ -424,8 +503,6 @@ int somm_build(mpsl_ctx *ctx) {
     ivl.push_back(0);
     for (int q : g) {
       fperm.push_back(q);
-      run_c0[q] = c0;
-      run_len[q] = kSommNc;
       const double t = ctx->lam[q].real();
       double *L = &Lw[static_cast<size_t>(q) * kSommNc];
       int hit = -1;
@@ -444,12 +521,18 @@ int somm_build(mpsl_ctx *ctx) {
     }
   }
   pl.nint = static_cast<int>(groups.size());
+  // blocks of the interval-node M2S step: (interval, first node) per run of kSiFineNodes
+  std::vector<int> fblk;
+  for (int iv = 0; iv < pl.nint; ++iv)
+    for (int o = 0; o < ivl[4 * iv + 1]; o += kSiFineNodes) {
+      fblk.push_back(iv);
+      fblk.push_back(o);
+    }
+  pl.nfb = static_cast<int>(fblk.size() / 2);
   for (int q = 0; q < ns; ++q)
     if (direct[q]) {
       const int c = static_cast<int>(lamc.size());
       lamc.push_back(ctx->lam[q]);
-      run_c0[q] = c;
-      run_len[q] = 1;
       Lw[static_cast<size_t>(q) * kSommNc] = 1.0;
       dir.push_back(q);
       dir.push_back(c);
@@ -486,12 +569,11 @@ int somm_build(mpsl_ctx *ctx) {
       (rc = upload(pl.Wc32, Wc32.data(), Wc32.size() * sizeof(float2))) ||
       (rc = upload(pl.Zc64, Zc.data(), Zc.size() * sizeof(double2))) ||
       (rc = upload(pl.Zc32, Zc32.data(), Zc32.size() * sizeof(float2))) ||
-      (rc = upload(pl.run_c0, run_c0.data(), run_c0.size() * sizeof(int))) ||
-      (rc = upload(pl.run_len, run_len.data(), run_len.size() * sizeof(int))) ||
       (rc = upload(pl.Lw, Lw.data(), Lw.size() * sizeof(double))) ||
       (rc = upload(pl.ivl, ivl.data(), ivl.size() * sizeof(int))) ||
       (rc = upload(pl.fperm, fperm.data(), fperm.size() * sizeof(int))) ||
-      (rc = upload(pl.dir, dir.data(), dir.size() * sizeof(int))))
+      (rc = upload(pl.dir, dir.data(), dir.size() * sizeof(int))) ||
+      (rc = upload(pl.fblk, fblk.data(), fblk.size() * sizeof(int))))
     return rc;
   pl.active = true;
   return MPSL_OK;

@@ -206,13 +206,18 @@ def test_free_space_limit_has_no_reflection(torch_dev):
     assert float(out.abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("n", [1, 2, 129])
-def test_small_and_ragged_counts(n, torch_dev):
+@pytest.mark.parametrize("n", [1, 2, 17, 129])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_small_and_ragged_counts(n, prec, torch_dev):
+    # p = 16: the default M2L is the matrix-core form in both precisions (one
+    # partial 16-target tile, partial source groups of four)
     wl = make_workload("s200p16", n=n)
     pr = oracle_problem(wl)
     ctx = gpu_context(wl)
     x = coeff_vector(wl, 8)
-    assert rel_err(ctx.apply(0, x), pr.matvec(x)) < FP64_TOL
+    assert ctx.get_tuning(prec)["variant"] == 2
+    got = ctx.apply(prec, x.astype(np.complex128 if prec == 0 else np.complex64))
+    assert rel_err(got, pr.matvec(x)) < (FP64_TOL if prec == 0 else FP32_TOL)
 
 
 def test_highest_order(torch_dev):
