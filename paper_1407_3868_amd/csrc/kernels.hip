@@ -676,14 +676,8 @@ store:
 // kM2lMfmaBatch sources of the chunk as (re, im, re + im) with zero padding
 // on both sides of every row.  Each wave owns NT tiles of 16 targets; the A
 // reads are shared across its tiles.
-#ifndef MPSL_M2L_MFMA_WAVES
-#define MPSL_M2L_MFMA_WAVES 4
-#endif
-#ifndef MPSL_M2L_MFMA_BATCH
-#define MPSL_M2L_MFMA_BATCH 32
-#endif
-constexpr int kM2lMfmaWaves = MPSL_M2L_MFMA_WAVES;
-constexpr int kM2lMfmaBatch = MPSL_M2L_MFMA_BATCH;
+constexpr int kM2lMfmaWaves = 4;
+constexpr int kM2lMfmaBatch = 32;
 
 template <typename T, int p, int NT>
 __global__ __launch_bounds__(64 * kM2lMfmaWaves) void k_m2l_mfma(const cv_t<T> *__restrict__ pairs,
