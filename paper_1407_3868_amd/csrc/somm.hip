@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_si_tileG(const cv_t<T> *__restrict__ be
 
 // M2S, step 2, interval nodes: one block per (interval, run of kSiFineNodes
 // of its nodes) from the table fblk; kSiFineSplit lanes per node, each
-// summing every kSiFineSplit-th tile, combined through LDS in a fixed order.
+// summing a quarter of the tile list, combined through LDS in a fixed order.
 // The interval's coarse values G[T][c0 .. c0 + kSommNc) and weights come
 // through wave-uniform loads; spectra in FP64 as the direct path.
 constexpr int kSiFineSplit = 4;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine(
     const cv_t<T> *__restrict__ G, const double2 *__restrict__ lam, const double2 *__restrict__ g2,
     const double2 *__restrict__ txy, const int *__restrict__ ivl, const int *__restrict__ fperm,
     const int *__restrict__ fblk, const double *__restrict__ Lw, int ns, int nT, int nc, double d,
-    double2 *__restrict__ spec) {
+    double tile_h, double2 *__restrict__ spec) {
   static_assert(kSiFineNodes == 64, "one wave per tile share");
   __shared__ double2 red[kSiFineSplit][kSiFineNodes];
   // the tile share is the wave index: wave-uniform, so the tile loop's loads are scalar
@@ -107,11 +107,27 @@ __global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine(
 #pragma unroll
   for (int k = 0; k < kSommNc; ++k) wq[k] = static_cast<T>(Lw[static_cast<int64_t>(q) * kSommNc + k]);
   const cv_t<T> *Gs = G + ((static_cast<int64_t>(r) * 2 + s) * nT) * nc + c0;
-  cx<double> acc = mk(0.0, 0.0);
-  for (int t = j; t < nT; t += kSiFineSplit) {
+  // e^{-i lam x_T + g2 y_T} (side 0), e^{-i lam x_T - g2 (d + y_T)} (side 1).  Wave j
+  // walks a contiguous range of the tile list, which is column by column (x, then y):
+  // along a column the factor changes by Fy^k for a step of k tile heights, so the
+  // exponential is evaluated only where a column starts or a gap is long.
+  const double sg = s == 0 ? 1.0 : -1.0;
+  const cx<double> Fy = cexp64(sg * gr * tile_h, sg * gi * tile_h);
+  const int ta = static_cast<int>((static_cast<int64_t>(nT) * j) / kSiFineSplit);
+  const int tb = static_cast<int>((static_cast<int64_t>(nT) * (j + 1)) / kSiFineSplit);
+  cx<double> acc = mk(0.0, 0.0), E = mk(0.0, 0.0);
+  double xp = 0.0, yp = 0.0;
+  for (int t = ta; t < tb; ++t) {
     const double xT = txy[t].x, yT = txy[t].y;
-    const double yy = s == 0 ? yT : -(d + yT);  // e^{-i lam x_T + g2 y_T}, e^{-i lam x_T - g2 (d + y_T)}
-    const cx<double> E = cexp64(li * xT + gr * yy, -lr * xT + gi * yy);
+    const int k = t > ta && xT == xp ? static_cast<int>(lrint((yT - yp) / tile_h)) : 0;
+    if (k >= 1 && k <= 4) {
+      for (int u = 0; u < k; ++u) E = E * Fy;
+    } else {
+      const double yy = s == 0 ? yT : -(d + yT);
+      E = cexp64(li * xT + gr * yy, -lr * xT + gi * yy);
+    }
+    xp = xT;
+    yp = yT;
     const cv_t<T> *Gt = Gs + static_cast<int64_t>(t) * nc;
     cx<T> h = mk<T>(0, 0);
 #pragma unroll
@@ -326,7 +342,7 @@ int m2s_interp_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
     hipLaunchKernelGGL(k_si_fine<T>, dim3(pl.nfb, 2 * nrhs), blk, 0, ctx->stream, G, lam, g2, txy,
                        static_cast<const int *>(pl.ivl.p), static_cast<const int *>(pl.fperm.p),
                        static_cast<const int *>(pl.fblk.p), static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT,
-                       pl.nc, ctx->d, static_cast<double2 *>(spec));
+                       pl.nc, ctx->d, pl.tile_h, static_cast<double2 *>(spec));
   if (pl.ndir > 0)
     hipLaunchKernelGGL(k_si_fine_dir<T>, dim3(cdv(pl.ndir, kSiFineNodes), 2 * nrhs), blk, 0, ctx->stream, G, lam,
                        g2, txy, static_cast<const int *>(pl.dir.p), pl.ndir, ctx->ns, pl.nT, pl.nc, ctx->d,
