@@ -353,15 +353,28 @@ __global__ void k_fold_parts(cv_t<T> *__restrict__ part, int chunks, int64_t len
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= len) return;
   part += blockIdx.y * pstride;
-  T re = 0, im = 0;
-  for (int c = 0; c < chunks; ++c) {
+  // eight independent sums (slot c mod 8), so that eight loads are in flight,
+  // combined pairwise at the end: a fixed order for every launch
+  T re[8] = {0, 0, 0, 0, 0, 0, 0, 0}, im[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (; c + 8 <= chunks; c += 8) {
+    cv_t<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(c + u) * len + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      re[u] += v[u].x;
+      im[u] += v[u].y;
+    }
+  }
+  for (int u = 0; c < chunks; ++c, ++u) {
     const cv_t<T> v = part[c * len + i];
-    re += v.x;
-    im += v.y;
+    re[u] += v.x;
+    im[u] += v.y;
   }
   cv_t<T> o;
-  o.x = re;
-  o.y = im;
+  o.x = ((re[0] + re[1]) + (re[2] + re[3])) + ((re[4] + re[5]) + (re[6] + re[7]));
+  o.y = ((im[0] + im[1]) + (im[2] + im[3])) + ((im[4] + im[5]) + (im[6] + im[7]));
   part[i] = o;
 }
 
