@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine_dir(
 // S2L, step 1 for the Chebyshev intervals: one lane per tile, every lane of
 // a block walking the same fine nodes of one interval (node data and the
 // interpolation weights are wave-uniform loads), kSommNc sums per lane in
-// FP64.  grid: (interval, tile block, chunk of the interval's nodes +
+// the matvec precision (each term formed in FP64).  grid: (interval, tile block, chunk of the interval's nodes +
 // nchunk * (2 rhs + side)); chunk cz writes its own partial slot
 // Bp[cz][rhs, side][t][k], k over the intervals' coarse nodes (which come
 // first in the coarse-node order), summed by k_si_coarseB_sum.
@@ -203,25 +203,27 @@ __global__ __launch_bounds__(kSiCoarseLanes) void k_si_coarseB(
   const double2 tc = txy[act ? t : 0];
   const double xT = tc.x;
   const double yy = s == 0 ? tc.y : -(tc.y + d);  // e^{i lam x_T + g2 y_T}, e^{i lam x_T - g2 (y_T + d)}
-  double are[kSommNc], aim[kSommNc];
+  // sums in the matvec precision (the factor itself is formed in FP64)
+  T are[kSommNc], aim[kSommNc];
 #pragma unroll
-  for (int k = 0; k < kSommNc; ++k) are[k] = aim[k] = 0.0;
+  for (int k = 0; k < kSommNc; ++k) are[k] = aim[k] = T(0);
   for (int i = i0; i < i1; ++i) {
     const int q = fperm[f0 + i];
     const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
     const cx<double> u = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]);
-    const cx<double> v = u * cexp64(-li * xT + gr * yy, lr * xT + gi * yy);
+    const cx<T> v = cvt<T>(u * cexp64(-li * xT + gr * yy, lr * xT + gi * yy));
     const double *L = Lw + static_cast<int64_t>(q) * kSommNc;
 #pragma unroll
     for (int k = 0; k < kSommNc; ++k) {
-      are[k] = fma(L[k], v.re, are[k]);
-      aim[k] = fma(L[k], v.im, aim[k]);
+      const T w = static_cast<T>(L[k]);
+      are[k] = fma(w, v.re, are[k]);
+      aim[k] = fma(w, v.im, aim[k]);
     }
   }
   if (!act) return;
   cv_t<T> *o = Bp + ((static_cast<int64_t>(cz) * gridDim.z / nchunk + rs) * nT + t) * nci + c0;
 #pragma unroll
-  for (int k = 0; k < kSommNc; ++k) o[k] = st(mk<T>(static_cast<T>(are[k]), static_cast<T>(aim[k])));
+  for (int k = 0; k < kSommNc; ++k) o[k] = st(mk<T>(are[k], aim[k]));
 }
 
 // Sum of the node-chunk partials of k_si_coarseB into B[rhs, side][t][c],
