@@ -263,49 +263,93 @@ __global__ __launch_bounds__(256) void k_si_coarseB_dir(const double2 *__restric
   B[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c] = st(cvt<T>(v));
 }
 
-// S2L, step 2: one lane per particle, all orders in registers; blockIdx.y
-// takes a chunk of the (side, coarse node) pairs and writes its own partial
-// slot (summed with the other partial expansions afterwards).
+
+inline int cdv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
+
+// S2L, step 2 on the matrix cores: alpha_l[n] = sum_c e_l(c) Z_n(c) with
+// e_l(c) = e^{i lam_c dx_l + sg g2_c dy_l} B[T(l)][c] is a GEMM with M =
+// particle, N = order, K = (side, coarse node).  Each 16x16x4 MFMA takes 16
+// particles and four coarse nodes: lane i forms e for (particle i % 16, node
+// i / 16) — one FP64 exponential per (particle, node), as before — and loads
+// Z_n(c) for (node i / 16, order i % 16) as the B operand.  Complex products in
+// three real MFMAs (Gauss).  One wave per 16 particles, kSiAlphaWaves waves per
+// block; blockIdx.y takes a chunk of the (side, coarse node) pairs and writes
+// its own partial slot.
+constexpr int kSiAlphaWaves = 4;
+template <typename T> struct si_mfma;
+template <> struct si_mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
+template <> struct si_mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
+};
+
 template <typename T, int p>
-__global__ __launch_bounds__(128) void k_si_alpha(const cv_t<T> *__restrict__ B, const double2 *__restrict__ xy,
-                                                  const int *__restrict__ ptile, const double2 *__restrict__ txy,
-                                                  const double2 *__restrict__ lamc, const double2 *__restrict__ gc,
-                                                  const cv_t<T> *__restrict__ Zc, int n, int nT, int nc,
-                                                  int chunk_len, cv_t<T> *__restrict__ part, int64_t pstride) {
+__global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_alpha_mfma(
+    const cv_t<T> *__restrict__ B, const double2 *__restrict__ xy, const int *__restrict__ ptile,
+    const double2 *__restrict__ txy, const double2 *__restrict__ lamc, const double2 *__restrict__ gc,
+    const cv_t<T> *__restrict__ Zc, int n, int nT, int nc, int chunk_len, cv_t<T> *__restrict__ part,
+    int64_t pstride) {
   constexpr int P = 2 * p + 1;
-  const int l = blockIdx.x * 128 + threadIdx.x;
-  const int ch = blockIdx.y;
-  const int r = blockIdx.z;
+  constexpr int NTN = (P + 15) / 16;
+  typedef typename si_mfma<T>::v4 v4;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int ch = blockIdx.y, rr = blockIdx.z;
   const int k0 = ch * chunk_len, k1 = min(2 * nc, k0 + chunk_len);
+  const int lw = (blockIdx.x * kSiAlphaWaves + w) * 16;  // first particle of this wave
+  const int l = lw + r;                                   // this lane's particle (A row)
   const bool valid = l < n;
   const int lc = valid ? l : 0;
   const int t = ptile[lc];
   const double dx = xy[lc].x - txy[t].x, dy = xy[lc].y - txy[t].y;
-  cx<T> acc[P];
+  v4 acc[NTN][3];
 #pragma unroll
-  for (int j = 0; j < P; ++j) acc[j] = mk<T>(0, 0);
-  for (int k = k0; k < k1; ++k) {
-    const int s = k >= nc ? 1 : 0, c = k - s * nc;
-    const cv_t<T> *Bt = B + ((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc;
-    const cv_t<T> *Zs = Zc + static_cast<int64_t>(s) * nc * P;
-    const double sg = s == 0 ? 1.0 : -1.0;
-    {
-      // e^{i lam_c dx + sg g2_c dy}
+  for (int nt = 0; nt < NTN; ++nt)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[nt][k] = v4{0, 0, 0, 0};
+  for (int kk = k0; kk < k1; kk += 4) {
+    const int k = kk + g;  // this lane's coarse node (K index)
+    const bool kv = k < k1;
+    const int s = kv && k >= nc ? 1 : 0, c = kv ? k - s * nc : 0;
+    cx<T> a = mk<T>(0, 0);
+    if (kv && valid) {
+      // e^{i lam_c dx + sg g2_c dy} B[T][c]
+      const double sg = s == 0 ? 1.0 : -1.0;
       const double lr = lamc[c].x, li = lamc[c].y, gr = gc[c].x, gi = gc[c].y;
-      const cx<T> eb = cvt<T>(cexp64(-li * dx + sg * gr * dy, lr * dx + sg * gi * dy)) * ld<T>(Bt[c]);
-      const cv_t<T> *z = Zs + static_cast<int64_t>(c) * P;
+      a = cvt<T>(cexp64(-li * dx + sg * gr * dy, lr * dx + sg * gi * dy)) *
+          ld<T>(B[((static_cast<int64_t>(rr) * 2 + s) * nT + t) * nc + c]);
+    }
+    const T as = a.re + a.im;
+    const cv_t<T> *z = Zc + (static_cast<int64_t>(s) * nc + c) * P;
 #pragma unroll
-      for (int j = 0; j < P; ++j) cmac(acc[j], eb, ld<T>(z[j]));
+    for (int nt = 0; nt < NTN; ++nt) {
+      const int o = nt * 16 + r;  // this lane's order (B column)
+      const cx<T> zz = (kv && o < P) ? ld<T>(z[o]) : mk<T>(0, 0);
+      acc[nt][0] = si_mfma<T>::mac(a.re, zz.re, acc[nt][0]);
+      acc[nt][1] = si_mfma<T>::mac(a.im, zz.im, acc[nt][1]);
+      acc[nt][2] = si_mfma<T>::mac(as, zz.re + zz.im, acc[nt][2]);
     }
   }
-  if (valid) {
-    cv_t<T> *o = part + r * pstride + (static_cast<int64_t>(ch) * n + l) * P;
+  // result register j of lane i: particle lw + row(i, j), order nt * 16 + i % 16
+  cv_t<T> *out = part + rr * pstride + static_cast<int64_t>(ch) * n * P;
 #pragma unroll
-    for (int j = 0; j < P; ++j) o[j] = st(acc[j]);
+  for (int nt = 0; nt < NTN; ++nt) {
+    const int o = nt * 16 + r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int pl = lw + si_mfma<T>::row(lane, j);
+      if (pl < n && o < P) {
+        const T p1 = acc[nt][0][j], p2 = acc[nt][1][j], p3 = acc[nt][2][j];
+        out[static_cast<int64_t>(pl) * P + o] = st(mk<T>(p1 - p2, p3 - p1 - p2));
+      }
+    }
   }
 }
-
-inline int cdv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b); }
 
 template <typename T>
 int ensure_G(mpsl_ctx *ctx, int nrhs) {
@@ -388,12 +432,12 @@ int s2l_interp_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstrid
                        ctx->d, B);
   const int n = static_cast<int>(ctx->n);
   const int chunk_len = cdv(2 * static_cast<int64_t>(pl.nc), chunks);
-  const dim3 g2d(cdv(n, 128), chunks, nrhs);
+  const dim3 g2d(cdv(n, 16 * kSiAlphaWaves), chunks, nrhs);
   auto *o = static_cast<cv_t<T> *>(part);
   switch (ctx->p) {
 #define X(PP)                                                                                                       \
   case PP:                                                                                                          \
-    hipLaunchKernelGGL((k_si_alpha<T, PP>), g2d, dim3(128), 0, ctx->stream, B,                                      \
+    hipLaunchKernelGGL((k_si_alpha_mfma<T, PP>), g2d, dim3(64 * kSiAlphaWaves), 0, ctx->stream, B,                 \
                        static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const int *>(pl.ptile.p), txy,       \
                        static_cast<const double2 *>(pl.lamc.p), static_cast<const double2 *>(pl.gc.p), Zc, n,       \
                        pl.nT, pl.nc, chunk_len, o, pstride);                                                         \
