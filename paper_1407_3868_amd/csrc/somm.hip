@@ -45,7 +45,9 @@ __device__ inline cx<double> cexp64(double a, double b) {
 template <typename T> __device__ inline cx<T> cvt(cx<double> v) { return {static_cast<T>(v.re), static_cast<T>(v.im)}; }
 template <typename T> __device__ inline cx<double> up(cx<T> v) { return {static_cast<double>(v.re), static_cast<double>(v.im)}; }
 
-// M2S, step 1: one lane per (tile, coarse node), blockIdx.z = 2 rhs + side.
+
+// M2S, step 1 (FP32): one lane per (tile, coarse node), blockIdx.z = 2 rhs + side.
+// (The matrix-core form below is slower in FP32 at ~10 particles per tile.)
 template <typename T, int p>
 __global__ __launch_bounds__(256) void k_si_tileG(const cv_t<T> *__restrict__ beta, const double2 *__restrict__ xy,
                                                   const int *__restrict__ perm, const int *__restrict__ tstart,
@@ -351,6 +353,71 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_alpha_mfma(
   }
 }
 
+// M2S, step 1 on the matrix cores (FP64): per tile, D[m][c] = sum_n beta_m[n] W_n(c)
+// is a GEMM with M = the tile's particles (16 at a time), N = coarse nodes, K =
+// orders; then G[T][c] = sum_m e_m(c) D[m][c] with the local factor
+// e_m(c) = e^{-i lam_c dx_m + sg g2_c dy_m}, one FP64 exponential per
+// (particle, node) as before, summed over the lane's rows and across the four
+// row groups.  One wave per 16 coarse nodes, kSiAlphaWaves waves per block;
+// grid: (node blocks, tile, 2 rhs + side).
+template <typename T, int p>
+__global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_tileG_mfma(
+    const cv_t<T> *__restrict__ beta, const double2 *__restrict__ xy, const int *__restrict__ perm,
+    const int *__restrict__ tstart, const double2 *__restrict__ txy, const double2 *__restrict__ lamc,
+    const double2 *__restrict__ gc, const cv_t<T> *__restrict__ Wc, int n, int nT, int nc,
+    cv_t<T> *__restrict__ G) {
+  constexpr int P = 2 * p + 1;
+  constexpr int KP = (P + 3) / 4 * 4;
+  typedef typename si_mfma<T>::v4 v4;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int t = blockIdx.y;
+  const int s = blockIdx.z & 1, rr = blockIdx.z >> 1;
+  const int c0 = (blockIdx.x * kSiAlphaWaves + w) * 16;
+  const int c = c0 + r;  // this lane's coarse node (B column, output)
+  const bool cv = c < nc;
+  beta += static_cast<int64_t>(rr) * n * P;
+  const cv_t<T> *W = Wc + (static_cast<int64_t>(s) * nc + (cv ? c : 0)) * P;
+  const double sg = s == 0 ? 1.0 : -1.0;
+  const double xT = txy[t].x, yT = txy[t].y;
+  const int m0 = tstart[t], m1 = tstart[t + 1];
+  cx<double> acc = mk(0.0, 0.0);
+  for (int mb = m0; mb < m1; mb += 16) {
+    // A row of this lane: particle mb + r
+    const int ma = mb + r < m1 ? perm[mb + r] : -1;
+    const cv_t<T> *b = beta + static_cast<int64_t>(ma < 0 ? 0 : ma) * P;
+    v4 d0 = v4{0, 0, 0, 0}, d1 = v4{0, 0, 0, 0}, d2 = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < KP; kk += 4) {
+      const int j = kk + g;  // order (K index) of this lane
+      const cx<T> a = (ma >= 0 && j < P) ? ld<T>(b[j]) : mk<T>(0, 0);
+      const cx<T> z = (cv && j < P) ? ld<T>(W[j]) : mk<T>(0, 0);
+      d0 = si_mfma<T>::mac(a.re, z.re, d0);
+      d1 = si_mfma<T>::mac(a.im, z.im, d1);
+      d2 = si_mfma<T>::mac(a.re + a.im, z.re + z.im, d2);
+    }
+    if (cv) {
+      const double lr = lamc[c].x, li = lamc[c].y, gr = gc[c].x, gi = gc[c].y;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = mb + si_mfma<T>::row(lane, q);  // particle of result register q
+        if (k < m1) {
+          const int m = perm[k];
+          const double dx = xy[m].x - xT, dy = xy[m].y - yT;
+          const cx<double> e = cexp64(li * dx + sg * gr * dy, -lr * dx + sg * gi * dy);
+          const double p1 = d0[q], p2 = d1[q], p3 = d2[q];
+          acc = acc + e * mk(p1 - p2, p3 - p1 - p2);
+        }
+      }
+    }
+  }
+  acc.re += __shfl_xor(acc.re, 16);
+  acc.im += __shfl_xor(acc.im, 16);
+  acc.re += __shfl_xor(acc.re, 32);
+  acc.im += __shfl_xor(acc.im, 32);
+  if (g == 0 && cv) G[((static_cast<int64_t>(rr) * 2 + s) * nT + t) * nc + c] = st(cvt<T>(acc));
+}
+
 template <typename T>
 int ensure_G(mpsl_ctx *ctx, int nrhs) {
   const SommPlan &pl = ctx->somm;
@@ -366,15 +433,23 @@ int m2s_interp_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
   const auto *Wc = static_cast<const cv_t<T> *>(f64 ? pl.Wc64.p : pl.Wc32.p);
   auto *G = static_cast<cv_t<T> *>(pl.G.p);
   const int n = static_cast<int>(ctx->n);
-  const dim3 g1(cdv(pl.nc, 256), pl.nT, 2 * nrhs);
+  const bool f64m = std::is_same<T, double>::value;  // matrix-core step 1 in FP64 only
+  const dim3 g1(cdv(pl.nc, f64m ? 16 * kSiAlphaWaves : 256), pl.nT, 2 * nrhs);
   switch (ctx->p) {
 #define X(PP)                                                                                                      \
   case PP:                                                                                                         \
-    hipLaunchKernelGGL((k_si_tileG<T, PP>), g1, dim3(256), 0, ctx->stream, static_cast<const cv_t<T> *>(beta),     \
-                       static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const int *>(pl.perm.p),             \
-                       static_cast<const int *>(pl.tstart.p), static_cast<const double2 *>(pl.txy.p),               \
-                       static_cast<const double2 *>(pl.lamc.p), static_cast<const double2 *>(pl.gc.p), Wc, n,      \
-                       pl.nT, pl.nc, G);                                                                            \
+    if (f64m)                                                                                                      \
+      hipLaunchKernelGGL((k_si_tileG_mfma<T, PP>), g1, dim3(64 * kSiAlphaWaves), 0, ctx->stream,                  \
+                         static_cast<const cv_t<T> *>(beta), static_cast<const double2 *>(ctx->gt.xy.p),            \
+                         static_cast<const int *>(pl.perm.p), static_cast<const int *>(pl.tstart.p),                \
+                         static_cast<const double2 *>(pl.txy.p), static_cast<const double2 *>(pl.lamc.p),           \
+                         static_cast<const double2 *>(pl.gc.p), Wc, n, pl.nT, pl.nc, G);                            \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_si_tileG<T, PP>), g1, dim3(256), 0, ctx->stream, static_cast<const cv_t<T> *>(beta),   \
+                         static_cast<const double2 *>(ctx->gt.xy.p), static_cast<const int *>(pl.perm.p),           \
+                         static_cast<const int *>(pl.tstart.p), static_cast<const double2 *>(pl.txy.p),             \
+                         static_cast<const double2 *>(pl.lamc.p), static_cast<const double2 *>(pl.gc.p), Wc, n,    \
+                         pl.nT, pl.nc, G);                                                                          \
     break;
     SOMM_P_CASES(X)
 #undef X
