@@ -346,6 +346,8 @@ class Context:
         return self._check(self.lib.mpsl_autotune(self.h, int(prec)))
 
     def set_tuning(self, prec, variant, chunks=0):
+        """M2L launch variant (0 one lane per target, 1 output halves, 2 / 3 matrix cores
+        with 16 / 32 targets per wave, p <= 16) and source chunks (0 = default)."""
         return self._check(self.lib.mpsl_set_tuning(self.h, int(prec), int(variant), int(chunks)))
 
     def get_tuning(self, prec):
