@@ -49,10 +49,11 @@ def m2l_source_sha256(variant=0):
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def _m2l_traffic(variant):
+def _m2l_traffic(variant, chunks=None):
     """Scaled HBM bytes per launch of the FP32 M2L kernel of this variant at this workload
-    from the committed rocprofv3 counter summary; None when there is none or the kernel
-    source has changed since."""
+    from the committed rocprofv3 counter summary; None when there is none, when the kernel
+    source has changed since, or when the summary was taken at another number of source
+    chunks than this run uses (the partial outputs scale with it)."""
     name = M2L_VARIANTS[variant][2]
     if name is None:
         return None
@@ -64,6 +65,9 @@ def _m2l_traffic(variant):
     m = re.search(r"m2l_traffic_bytes_fp32: (\d+)", text)
     h = re.search(r"m2l_source_sha256: ([0-9a-f]+)", text)
     if not m or not h or h.group(1) != m2l_source_sha256(variant):
+        return None
+    c = re.search(r"m2l_chunks_fp32: (\d+)", text)
+    if chunks is not None and c and int(c.group(1)) != chunks:
         return None
     return int(m.group(1))
 
@@ -480,7 +484,7 @@ def main():
             "peak": PEAK_FP32 / 1e12,
             "unit": "TFLOP/s",
             "frac": ach32 / PEAK_FP32,
-            "traffic": _m2l_traffic(v32),
+            "traffic": _m2l_traffic(v32, tuning["fp32"]["chunks"]),
             "avg_ms": m2l32,
             "launches": cnt32,
             "algorithmic_flops_per_launch": flops,

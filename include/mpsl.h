@@ -366,7 +366,7 @@ int mpsl_eval_field(mpsl_ctx *ctx, const double *src_xy, const mpsl_c128 *beta,
  * mpsl_autotune times the variants at 1/2, 1 and 2 times the default number
  * of source chunks on the current problem (pseudo-random input, HIP events on
  * the context stream, each launch with the summation of its partial slots)
- * and keeps the fastest; mpsl_set_tuning forces a choice
+ * and keeps the fastest (a later candidate must be more than 1 % faster); mpsl_set_tuning forces a choice
  * (chunks 0 = default).  Tuning is kept until changed; it never changes
  * results beyond floating-point summation order. */
 int mpsl_autotune(mpsl_ctx *ctx, int prec);

@@ -1079,7 +1079,9 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
         break;
       }
       const double avg = ms / reps;
-      if (avg < best) {
+      // a later candidate must win by more than 1 %: near-ties keep the earlier
+      // (fewer chunks, less partial-sum traffic) and the choice stays stable
+      if (avg < 0.99 * best) {
         best = avg;
         bv = variant;
         bc = c;

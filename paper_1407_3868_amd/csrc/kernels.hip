@@ -683,12 +683,12 @@ store:
 // accumulated on the vector units and summed over the four sources of a
 // group at the end.  q runs from 0 to 2p; h_q and h_{-q} go to the blocks
 // whose rows they reach: 96 complex MFMAs per group at p = 16, against the
-// 68 that the nonzero band needs.  Complex products take three real MFMAs
+// 66 that the nonzero band of the 32 block rows needs.  Complex products take three real MFMAs
 // (Gauss): P1 = sum Ar Br, P2 = sum Ai Bi, P3 = sum (Ar + Ai)(Br + Bi);
 // re = P1 - P2, im = P3 - P1 - P2.  LDS holds the coefficients of
 // kM2lMfmaBatch sources of the chunk as (re, im, re + im) with zero padding
-// on both sides of every row.  Each wave owns NT tiles of 16 targets; the A
-// reads are shared across its tiles.
+// on both sides of every row.  Each wave owns NT tiles of 16 targets (NT = 1
+// or 2); the A reads are shared across its tiles.
 constexpr int kM2lMfmaWaves = 4;
 constexpr int kM2lMfmaBatch = 32;
 
