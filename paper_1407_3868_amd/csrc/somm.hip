@@ -179,54 +179,6 @@ __global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine_dir(
   }
 }
 
-// S2L, step 1 for the Chebyshev intervals: one lane per tile, every lane of
-// a block walking the same fine nodes of one interval (node data and the
-// interpolation weights are wave-uniform loads), kSommNc sums per lane in
-// the matvec precision (each term formed in FP64).  grid: (interval, tile block, chunk of the interval's nodes +
-// nchunk * (2 rhs + side)); chunk cz writes its own partial slot
-// Bp[cz][rhs, side][t][k], k over the intervals' coarse nodes (which come
-// first in the coarse-node order), summed by k_si_coarseB_sum.
-constexpr int kSiCoarseLanes = 256;
-template <typename T>
-__global__ __launch_bounds__(kSiCoarseLanes) void k_si_coarseB(
-    const double2 *__restrict__ sigma, const double2 *__restrict__ cq, const double2 *__restrict__ lam,
-    const double2 *__restrict__ g2, const double2 *__restrict__ txy, const int *__restrict__ ivl,
-    const int *__restrict__ fperm, const double *__restrict__ Lw, int ns, int nT, int nci, int nchunk,
-    double d, cv_t<T> *__restrict__ Bp) {
-  const int iv = blockIdx.x;
-  const int t = blockIdx.y * kSiCoarseLanes + threadIdx.x;
-  const int cz = blockIdx.z % nchunk, rs = blockIdx.z / nchunk;
-  const int s = rs & 1, r = rs >> 1;
-  const int f0 = ivl[4 * iv], nf = ivl[4 * iv + 1], c0 = ivl[4 * iv + 2];
-  const int i0 = static_cast<int>((static_cast<int64_t>(nf) * cz) / nchunk);
-  const int i1 = static_cast<int>((static_cast<int64_t>(nf) * (cz + 1)) / nchunk);
-  sigma += static_cast<int64_t>(r) * 2 * ns;
-  const bool act = t < nT;
-  const double2 tc = txy[act ? t : 0];
-  const double xT = tc.x;
-  const double yy = s == 0 ? tc.y : -(tc.y + d);  // e^{i lam x_T + g2 y_T}, e^{i lam x_T - g2 (y_T + d)}
-  // sums in the matvec precision (the factor itself is formed in FP64)
-  T are[kSommNc], aim[kSommNc];
-#pragma unroll
-  for (int k = 0; k < kSommNc; ++k) are[k] = aim[k] = T(0);
-  for (int i = i0; i < i1; ++i) {
-    const int q = fperm[f0 + i];
-    const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
-    const cx<double> u = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]);
-    const cx<T> v = cvt<T>(u * cexp64(-li * xT + gr * yy, lr * xT + gi * yy));
-    const double *L = Lw + static_cast<int64_t>(q) * kSommNc;
-#pragma unroll
-    for (int k = 0; k < kSommNc; ++k) {
-      const T w = static_cast<T>(L[k]);
-      are[k] = fma(w, v.re, are[k]);
-      aim[k] = fma(w, v.im, aim[k]);
-    }
-  }
-  if (!act) return;
-  cv_t<T> *o = Bp + ((static_cast<int64_t>(cz) * gridDim.z / nchunk + rs) * nT + t) * nci + c0;
-#pragma unroll
-  for (int k = 0; k < kSommNc; ++k) o[k] = st(mk<T>(are[k], aim[k]));
-}
 
 // Sum of the node-chunk partials of k_si_coarseB into B[rhs, side][t][c],
 // c < nci, in chunk order.
@@ -418,6 +370,74 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_tileG_mfma(
   if (g == 0 && cv) G[((static_cast<int64_t>(rr) * 2 + s) * nT + t) * nc + c] = st(cvt<T>(acc));
 }
 
+// S2L, step 1 for the Chebyshev intervals on the matrix cores:
+// B[T][k] = sum_q V_T(q) L[q][k] with V_T(q) = c_q sigma(q) e^{i lam_q x_T + sg g2_q y_T}
+// is a GEMM with M = tile, N = interpolation column k (24, two 16-column
+// tiles), K = the interval's fine nodes.  Lane i forms V for (tile i % 16,
+// node i / 16 of the step) — one FP64 exponential per (tile, node) — as the A
+// operand and loads L[q][k] for (node i / 16, column i % 16) as B; complex A
+// times real B in two real MFMAs.  grid: (interval, blocks of 16 * kSiAlphaWaves
+// tiles, chunk of the interval's nodes + nchunk * (2 rhs + side)); chunk cz
+// writes its own partial slot Bp[cz][rhs, side][t][k], k over the intervals'
+// coarse nodes (which come first in the coarse-node order), summed in order by
+// k_si_coarseB_sum.
+template <typename T>
+__global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_coarseB_mfma(
+    const double2 *__restrict__ sigma, const double2 *__restrict__ cq, const double2 *__restrict__ lam,
+    const double2 *__restrict__ g2, const double2 *__restrict__ txy, const int *__restrict__ ivl,
+    const int *__restrict__ fperm, const double *__restrict__ Lw, int ns, int nT, int nci, int nchunk,
+    double d, cv_t<T> *__restrict__ Bp) {
+  typedef typename si_mfma<T>::v4 v4;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const int iv = blockIdx.x;
+  const int tw = (blockIdx.y * kSiAlphaWaves + w) * 16;  // first tile of this wave
+  const int cz = blockIdx.z % nchunk, rs = blockIdx.z / nchunk;
+  const int s = rs & 1, rr = rs >> 1;
+  const int f0 = ivl[4 * iv], nf = ivl[4 * iv + 1], c0 = ivl[4 * iv + 2];
+  const int i0 = static_cast<int>((static_cast<int64_t>(nf) * cz) / nchunk);
+  const int i1 = static_cast<int>((static_cast<int64_t>(nf) * (cz + 1)) / nchunk);
+  sigma += static_cast<int64_t>(rr) * 2 * ns;
+  const int ta = tw + r;  // this lane's tile (A row)
+  const bool tv = ta < nT;
+  const double2 tc = txy[tv ? ta : 0];
+  const double xT = tc.x;
+  const double yy = s == 0 ? tc.y : -(tc.y + d);
+  v4 acc[2][2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) acc[nt][0] = acc[nt][1] = v4{0, 0, 0, 0};
+  for (int i = i0; i < i1; i += 4) {
+    const int ii = i + g;  // this lane's node (K index)
+    const bool kv = ii < i1;
+    const int q = fperm[f0 + (kv ? ii : i0)];
+    cx<T> v = mk<T>(0, 0);
+    if (kv && tv) {
+      const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
+      const cx<double> u = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]);
+      v = cvt<T>(u * cexp64(-li * xT + gr * yy, lr * xT + gi * yy));
+    }
+    const double *L = Lw + static_cast<int64_t>(q) * kSommNc;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int k = nt * 16 + r;
+      const T lq = (kv && k < kSommNc) ? static_cast<T>(L[k]) : T(0);
+      acc[nt][0] = si_mfma<T>::mac(v.re, lq, acc[nt][0]);
+      acc[nt][1] = si_mfma<T>::mac(v.im, lq, acc[nt][1]);
+    }
+  }
+  // result register j of lane i: tile tw + row(i, j), column nt * 16 + i % 16
+  cv_t<T> *o = Bp + (static_cast<int64_t>(cz) * (gridDim.z / nchunk) + rs) * nT * static_cast<int64_t>(nci) + c0;
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int k = nt * 16 + r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = tw + si_mfma<T>::row(lane, j);
+      if (t < nT && k < kSommNc) o[static_cast<int64_t>(t) * nci + k] = st(mk<T>(acc[nt][0][j], acc[nt][1][j]));
+    }
+  }
+}
+
 template <typename T>
 int ensure_G(mpsl_ctx *ctx, int nrhs) {
   const SommPlan &pl = ctx->somm;
@@ -489,15 +509,15 @@ int s2l_interp_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstrid
   const auto *txy = static_cast<const double2 *>(pl.txy.p);
   if (pl.nint > 0) {
     // node chunks so that the launch has about 2048 blocks
-    const int nci = kSommNc * pl.nint, tb = cdv(pl.nT, kSiCoarseLanes);
+    const int nci = kSommNc * pl.nint, tb = cdv(pl.nT, 16 * kSiAlphaWaves);
     const int nchunk = std::max(1, std::min(16, cdv(2048, static_cast<int64_t>(pl.nint) * tb * 2 * nrhs)));
     const int64_t rows = 2ll * nrhs * pl.nT;
     if ((rc = dev_alloc(ctx, pl.Bp, static_cast<size_t>(nchunk) * rows * nci * sizeof(cv_t<T>)))) return rc;
     auto *Bp = static_cast<cv_t<T> *>(pl.Bp.p);
-    hipLaunchKernelGGL(k_si_coarseB<T>, dim3(pl.nint, tb, nchunk * 2 * nrhs), dim3(kSiCoarseLanes), 0, ctx->stream,
-                       sig, cq, lam, g2, txy, static_cast<const int *>(pl.ivl.p),
-                       static_cast<const int *>(pl.fperm.p), static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT,
-                       nci, nchunk, ctx->d, Bp);
+    hipLaunchKernelGGL(k_si_coarseB_mfma<T>, dim3(pl.nint, cdv(pl.nT, 16 * kSiAlphaWaves), nchunk * 2 * nrhs),
+                       dim3(64 * kSiAlphaWaves), 0, ctx->stream, sig, cq, lam, g2, txy,
+                       static_cast<const int *>(pl.ivl.p), static_cast<const int *>(pl.fperm.p),
+                       static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT, nci, nchunk, ctx->d, Bp);
     hipLaunchKernelGGL(k_si_coarseB_sum<T>, dim3(cdv(rows * nci, 256)), dim3(256), 0, ctx->stream, Bp, nchunk, rows,
                        pl.nT, pl.nc, nci, B);
   }
