@@ -269,10 +269,17 @@ int mpsl_apply_batch_dev(mpsl_ctx *ctx, int prec, int nrhs, const void *x_dev, v
  * them into one HIP graph with one parallel branch per item; mpsl_batch_launch
  * replays the whole batch with a single graph launch on `stream` (a
  * hipStream_t, NULL for the null stream), reading the current contents of the
- * x buffers.  The contexts and buffers must stay alive and unchanged in size
- * while the batch exists; a context must not appear twice in one batch (its
- * work buffers are shared).  Results are bitwise those of mpsl_apply_batch_dev
- * on each item. */
+ * x buffers.  The graph holds the addresses of each context's tables and work
+ * buffers, so while a batch exists its contexts are pinned: calls that would
+ * rebuild or move them (mpsl_set_layers, _layer_stack, _polarization,
+ * _particle_*, _particle_types, _scattering_matrix, _geometry*, _contour*,
+ * _sommerfeld_method, _far_field, _tuning, mpsl_autotune, and a batched matvec
+ * with more right-hand sides than any call before) return MPSL_ESTATE until
+ * mpsl_batch_destroy.  Solves, right-hand sides, field evaluation and matvecs
+ * of the sizes already used stay allowed.  A context appearing twice in one
+ * batch is rejected (MPSL_EINVAL: its work buffers are shared).  The x and y
+ * buffers must stay allocated, and every batch must be destroyed before its
+ * contexts.  Results are bitwise those of mpsl_apply_batch_dev on each item. */
 typedef struct mpsl_batch mpsl_batch;
 int mpsl_batch_create(mpsl_batch **out, int n_items, mpsl_ctx *const *ctxs, const int *precs, const int *nrhs,
                       const void *const *x, void *const *y);
@@ -325,7 +332,10 @@ typedef struct {
                          FP64 iterative refinement (Arnoldi always FP64)      */
   double tol;         /* relative residual target ||r|| / ||b||             */
   int maxiter;        /* total matvec budget of the Krylov solver           */
-  int restart;        /* Krylov dimension before restart (0: maxiter)      */
+  int restart;        /* Krylov dimension before restart (0: maxiter, i.e.
+                         unrestarted).  At most 20000 (MPSL_EINVAL above);
+                         the basis holds (dimension + 1) N P complex128 in
+                         device memory (MPSL_ENOMEM when it does not fit)   */
   double inner_tol;   /* MPSL_FP32 only: inner GMRES tolerance (0: 1e-5)   */
 } mpsl_opts;
 

@@ -10,6 +10,7 @@ struct mpsl_batch {
   hipGraphExec_t exec = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
+  std::vector<mpsl_ctx *> ctxs;  // pinned while the batch exists
   int device = 0;
   std::string err;
 };
@@ -18,6 +19,7 @@ namespace {
 
 void batch_free(mpsl_batch *b) {
   if (!b) return;
+  for (auto c : b->ctxs) --c->pinned;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto s : b->streams) (void)hipStreamDestroy(s);
@@ -38,6 +40,9 @@ int mpsl_batch_create(mpsl_batch **out, int n_items, mpsl_ctx *const *ctxs, cons
     if (!ctxs[i] || !x[i] || !y[i] || (precs[i] != MPSL_FP64 && precs[i] != MPSL_FP32) ||
         (nrhs && nrhs[i] < 1) || ctxs[i]->device != dev)
       return MPSL_EINVAL;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i])
+        return mpsl::set_err(ctxs[i], MPSL_EINVAL, "a context appears twice in one batch (its work buffers are shared)");
   }
   if (hipSetDevice(dev) != hipSuccess) return MPSL_EHIP;
   // warm-up: builds tables and sizes every work buffer, so that nothing is
@@ -101,6 +106,11 @@ int mpsl_batch_create(mpsl_batch **out, int n_items, mpsl_ctx *const *ctxs, cons
   if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
     batch_free(b);
     return MPSL_EHIP;
+  }
+  // the graph holds the addresses of every item's tables and work buffers
+  for (int i = 0; i < n_items; ++i) {
+    b->ctxs.push_back(ctxs[i]);
+    ++ctxs[i]->pinned;
   }
   *out = b;
   return MPSL_OK;

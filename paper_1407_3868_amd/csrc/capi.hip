@@ -19,8 +19,20 @@ int set_err(mpsl_ctx *ctx, int code, const std::string &msg) {
   return code;
 }
 
+int check_unpinned(mpsl_ctx *ctx) {
+  if (ctx->pinned > 0)
+    return set_err(ctx, MPSL_ESTATE,
+                   "a batch holds this context's buffers: destroy the batch before changing the context");
+  return MPSL_OK;
+}
+
 int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes) {
   if (bytes <= b.bytes && b.p) return MPSL_OK;
+  // a captured batch reads the tables and matvec work buffers by address; only
+  // the host-call staging and the solver's own buffers may move meanwhile
+  if (ctx->pinned > 0 && &b != &ctx->xbuf && &b != &ctx->ybuf && &b != &ctx->gm && &b != &ctx->scal &&
+      &b != &ctx->pc_blk && &b != &ctx->pc_idx)
+    return check_unpinned(ctx);
   if (b.p) {
     (void)hipFree(b.p);
     b.p = nullptr;
@@ -581,6 +593,7 @@ int mpsl_set_stream(mpsl_ctx *ctx, void *stream) {
 int mpsl_set_layer_stack(mpsl_ctx *ctx, int n_layers, const mpsl_c128 *k, const double *thickness,
                          int particle_layer) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   std::string err;
   const int rc = mpsl::assign_stack(ctx, n_layers, k, thickness, particle_layer, err);
   if (rc) return mpsl::set_err(ctx, rc, err);
@@ -611,6 +624,7 @@ int mpsl_compute_layer_map(int n_layers, const mpsl_c128 *k, const double *thick
 
 int mpsl_set_polarization(mpsl_ctx *ctx, int polarization) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (polarization != MPSL_TM && polarization != MPSL_TE)
     return mpsl::set_err(ctx, MPSL_EINVAL, "polarization must be MPSL_TM or MPSL_TE");
   if (polarization == ctx->pol) return MPSL_OK;
@@ -669,6 +683,7 @@ static int install_prototypes(mpsl_ctx *ctx, int p, int n_types, const std::vect
 
 int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> S;
   std::string err;
@@ -679,6 +694,7 @@ int mpsl_set_particle_disk(mpsl_ctx *ctx, double R, mpsl_c128 kp, int p) {
 
 int mpsl_set_particle_star(mpsl_ctx *ctx, double a1, double a2, int a3, mpsl_c128 kp, int p, int n_bdry) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> S;
   std::string err;
@@ -717,6 +733,7 @@ int mpsl_compute_star_smatrix(double a1, double a2, int a3, mpsl_c128 k2, mpsl_c
 
 int mpsl_set_particle_types(mpsl_ctx *ctx, int n_types, int p, const double *r_enclose, const mpsl_c128 *S) {
   if (!ctx || !S || !r_enclose) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (n_types < 1 || n_types > mpsl::kMaxTypes)
     return mpsl::set_err(ctx, MPSL_EINVAL, "need 1 to " + std::to_string(mpsl::kMaxTypes) + " particle types");
   if (p < mpsl::kMinP || p > mpsl::kMaxP) return mpsl::set_err(ctx, MPSL_EINVAL, "need 1 <= p <= 20");
@@ -739,6 +756,7 @@ int mpsl_set_scattering_matrix(mpsl_ctx *ctx, int p, double r_enclose, const mps
 
 int mpsl_set_geometry_typed(mpsl_ctx *ctx, int64_t n, const double *xy, const double *rot, const int32_t *type) {
   if (!ctx || !xy || n <= 0) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (!ctx->has_layers || !ctx->has_particle) return mpsl::set_err(ctx, MPSL_ESTATE, "layers and particle first");
   if (n > (int64_t(1) << 30)) return mpsl::set_err(ctx, MPSL_EINVAL, "too many particles");
   const double d = ctx->d, rmax = ctx->r_enc;
@@ -801,6 +819,7 @@ int mpsl_set_geometry(mpsl_ctx *ctx, int64_t n, const double *xy, const double *
 
 int mpsl_set_contour(mpsl_ctx *ctx, int n_nodes, double b, double t_max) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> lam, w;
   std::string err;
@@ -832,6 +851,7 @@ int mpsl_compute_contour(mpsl_c128 k1, mpsl_c128 k2, mpsl_c128 k3, int n_nodes, 
 
 int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (!ctx->has_layers) return mpsl::set_err(ctx, MPSL_ESTATE, "set_layers first");
   std::vector<zc> lam, w;
   std::string err;
@@ -849,6 +869,7 @@ int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max) {
 
 int mpsl_set_sommerfeld_method(mpsl_ctx *ctx, int method) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (method != MPSL_SOMM_DIRECT && method != MPSL_SOMM_INTERP)
     return mpsl::set_err(ctx, MPSL_EINVAL, "method must be MPSL_SOMM_DIRECT or MPSL_SOMM_INTERP");
   if (method == ctx->somm_method) return MPSL_OK;
@@ -877,6 +898,7 @@ int mpsl_compute_contour_span(int n_k, const double *re_k, double b, double t_ma
 
 int mpsl_set_contour_nodes(mpsl_ctx *ctx, int n_nodes, const mpsl_c128 *lam, const mpsl_c128 *w) {
   if (!ctx || !lam || !w || n_nodes <= 0) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (n_nodes > mpsl::kMaxNodes) return mpsl::set_err(ctx, MPSL_EINVAL, "too many contour nodes");
   ctx->lam.resize(n_nodes);
   ctx->w.resize(n_nodes);
@@ -1022,6 +1044,7 @@ int mpsl_set_tuning(mpsl_ctx *ctx, int prec, int variant, int chunks) {
   if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32) || variant < mpsl::kM2LWhole || variant > mpsl::kM2LMfmaWide ||
       chunks < 0)
     return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   auto &t = ctx->tune[prec == MPSL_FP64 ? 0 : 1];
   t.variant = variant;
   t.chunks = chunks;
@@ -1040,6 +1063,7 @@ int mpsl_get_tuning(const mpsl_ctx *ctx, int prec, int *variant, int *chunks, do
 
 int mpsl_autotune(mpsl_ctx *ctx, int prec) {
   if (!ctx || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
@@ -1058,7 +1082,7 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
   MPSL_HIP_TRY(ctx, hipEventCreate(&e1));
   double best = 1e300;
   int bv = mpsl::kM2LWhole, bc = base;
-  for (int variant = mpsl::kM2LWhole; variant <= mpsl::kM2LMfmaWide; ++variant)
+  for (int variant = mpsl::kM2LWhole; variant <= mpsl::kM2LMfmaWide && !rc; ++variant)
     for (int c : cands) {
       if (variant >= mpsl::kM2LMfma && ctx->p > mpsl::kM2LMfmaMaxP) break;
       if ((rc = mpsl::dev_alloc(ctx, ctx->part, static_cast<size_t>(c) * len * esz))) break;

@@ -178,6 +178,8 @@ struct mpsl_ctx {
   mpsl::DBuf bt;          // multi-RHS M2L: beta transposed to [n][P][r]
   mpsl::DBuf gm;          // GMRES workspace
   mpsl::DBuf scal;        // reductions
+  mpsl::DBuf pc_blk;      // cluster-block preconditioner: inverse blocks
+  mpsl::DBuf pc_idx;      // cluster-block preconditioner: index maps
 
   // launch shapes
   int m2l_chunks = 0;     // source chunks of the M2L grid (0: automatic)
@@ -189,6 +191,10 @@ struct mpsl_ctx {
   int s2l_chunks = 0;
   int m2s_chunks = 0;
 
+  // batches (captured HIP graphs) holding raw pointers to this context's
+  // tables and matvec work buffers; while > 0 nothing they read may move
+  int pinned = 0;
+
   // profiling of the M2L kernel
   bool prof = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -198,6 +204,8 @@ struct mpsl_ctx {
 namespace mpsl {
 int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes);
 void dev_free(DBuf &b);
+// MPSL_ESTATE (with a message) when a batch holds the context, else MPSL_OK.
+int check_unpinned(mpsl_ctx *ctx);
 int set_err(mpsl_ctx *ctx, int code, const std::string &msg);
 int disk_smatrix(double R, double k2, mpsl_c128 kp, int p, int pol, std::vector<zc> &S, std::string &err);
 int star_args(double a1, double a2, int a3, mpsl_c128 kp, int p, int n_bdry, int pol, int &nb, std::string &err);

@@ -987,6 +987,7 @@ extern "C" {
 
 int mpsl_set_far_field(mpsl_ctx *ctx, int method, double tol) {
   if (!ctx) return MPSL_EINVAL;
+  if (const int pe = mpsl::check_unpinned(ctx)) return pe;
   if (method != MPSL_FAR_AUTO && method != MPSL_FAR_DIRECT && method != MPSL_FAR_FMM)
     return mpsl::set_err(ctx, MPSL_EINVAL, "unknown far-field method");
   if (tol != 0.0 && !(tol >= 1e-13 && tol <= 1e-3))

@@ -69,6 +69,10 @@ int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const voi
 int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *h, void *w,
                     int64_t len);
 int launch_scale(mpsl_ctx *ctx, void *v, int64_t len, double s, const void *src);
+// Bytes of ctx->scal that launch_dotc_multi needs for k dot products.
+size_t dotc_scratch_bytes(int k);
+// Largest Krylov dimension of the GMRES solver (basis vectors kept at once).
+constexpr int kMaxKrylov = 20000;
 int launch_axpy_c(mpsl_ctx *ctx, void *y, const void *x, int64_t len, double a_re, double a_im);
 int launch_to_fp32(mpsl_ctx *ctx, const void *x64, void *x32, int64_t len);
 int launch_to_fp64(mpsl_ctx *ctx, const void *x32, void *x64, int64_t len);

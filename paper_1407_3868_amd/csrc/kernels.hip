@@ -1548,8 +1548,12 @@ int launch_fold_parts(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs,
   return MPSL_OK;
 }
 
+size_t dotc_scratch_bytes(int k) { return static_cast<size_t>(std::max(k, 1)) * kDotBlocks * sizeof(double2); }
+
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *w, int64_t len,
                       void *h_out) {
+  if (ctx->scal.bytes < dotc_scratch_bytes(k))
+    return set_err(ctx, MPSL_EINVAL, "reduction scratch too small for " + std::to_string(k) + " dot products");
   auto *scr = static_cast<double2 *>(ctx->scal.p);
   hipLaunchKernelGGL(k_dotc_part, dim3(kDotBlocks, k), dim3(kRed), 0, ctx->stream,
                      static_cast<const double2 *>(V), ld_v, static_cast<const double2 *>(w), len, scr);

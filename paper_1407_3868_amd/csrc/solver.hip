@@ -38,11 +38,16 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   if (o_.inner_tol <= 0.0) o_.inner_tol = 1e-5;
   len_ = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
   m_ = (o.restart > 0 && o.restart < o.maxiter) ? o.restart : o.maxiter;
-  m_ = std::min(m_, 1000);  // Arnoldi dot products are reduced in a 64K-entry scratch
+  if (m_ > kMaxKrylov)
+    return set_err(ctx, MPSL_EINVAL, "Krylov dimension (restart, or maxiter without restart) above " +
+                                         std::to_string(kMaxKrylov));
   const size_t c = sizeof(double2);
+  // the Arnoldi dot products reduce m + 1 rows of partial sums at once
+  int rc = dev_alloc(ctx, ctx->scal, dotc_scratch_bytes(m_ + 2));
+  if (rc) return rc;
   const size_t bytes = (static_cast<size_t>(m_ + 1) + 5) * len_ * c + 3 * static_cast<size_t>(m_ + 2) * c +
                        2 * len_ * sizeof(float2) + 8192;
-  int rc = dev_alloc(ctx, ctx->gm, bytes);
+  rc = dev_alloc(ctx, ctx->gm, bytes);
   if (rc) return rc;
   char *p = static_cast<char *>(ctx->gm.p);
   auto take = [&](size_t nb) {
