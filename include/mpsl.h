@@ -339,6 +339,53 @@ typedef struct {
   double inner_tol;   /* MPSL_FP32 only: inner GMRES tolerance (0: 1e-5)   */
 } mpsl_opts;
 
+/* ---- preconditioning of the solve ------------------------------------------
+ * Section 3.2 writes the system with the scattering matrices applied, which
+ * makes the diagonal block of each particle the identity; with
+ * MPSL_PRECOND_NONE (default) mpsl_solve runs GMRES on eq. (49) in that form.
+ * MPSL_PRECOND_CLUSTER extends the exact diagonal block from one particle to
+ * a cluster of nearby particles, for dense packings of high-contrast
+ * inclusions (where the Conclusions note that convergence degrades): the
+ * centres are cut by recursive coordinate bisection (a set of more than
+ * cluster_size particles is ordered by the coordinate of its longer extent,
+ * x on equal extents and particle index on equal coordinates, and cut after
+ * floor(n/2)) into clusters of at most cluster_size (0: 160) particles; per
+ * cluster c the free-space system of its own particles, K_c = I - S_c T_cc
+ * (Lemma 3.1 translations between them, their rotated scattering matrices),
+ * is assembled and inverted on the device in FP64, and GMRES solves
+ * (I - S (T + T_R)) M^{-1} u = S a with M = blockdiag_c K_c, returning
+ * beta = M^{-1} u.  This is right preconditioning: the solution and the
+ * residual reported are those of eq. (49).  MPSL_FP32 solves apply an FP32
+ * copy of the blocks (FP64 arithmetic).  The blocks are built at the first
+ * solve or apply after a change of particle, layers or geometry: device
+ * memory n_clusters m^2 16 bytes (and half that again for the FP32 copy),
+ * m = 64 ceil(largest cluster * P / 64), at most 16384 (MPSL_EINVAL above).
+ * A block whose inversion meets a zero pivot or a non-finite value is
+ * replaced by the identity (counted by mpsl_get_precond_info).
+ * MPSL_EINVAL for another kind or a negative size. */
+enum { MPSL_PRECOND_NONE = 0, MPSL_PRECOND_CLUSTER = 1 };
+int mpsl_set_preconditioner(mpsl_ctx *ctx, int kind, int cluster_size);
+
+/* Host, no device: cluster_of[j] (n entries) = cluster of particle j under
+ * the bisection rule above for centres xy (2n doubles), clusters numbered
+ * depth first (first half before second half); *n_clusters = their count.
+ * Either output may be NULL, not both.  MPSL_EINVAL for n <= 0, size < 1 or a
+ * non-finite coordinate. */
+int mpsl_compute_clusters(int64_t n, const double *xy, int cluster_size, int32_t *cluster_of, int *n_clusters);
+
+/* y = M^{-1} x for device vectors of N P complex128 (x, y distinct), with the
+ * blocks of precision prec (MPSL_FP32: the FP32 copy, FP64 arithmetic);
+ * builds the blocks when needed.  Asynchronous on the context stream after
+ * the build.  MPSL_ESTATE without MPSL_PRECOND_CLUSTER. */
+int mpsl_precond_apply_dev(mpsl_ctx *ctx, int prec, const void *x_dev, void *y_dev);
+
+/* Shape of the current blocks (zeros before they are built): clusters,
+ * particles of the largest, block dimension m, blocks replaced by the
+ * identity; and the seconds spent building blocks in this context so far.
+ * Any output may be NULL. */
+int mpsl_get_precond_info(const mpsl_ctx *ctx, int *n_clusters, int *max_cluster, int *block_dim, int *replaced,
+                          double *setup_seconds);
+
 typedef struct {
   int iterations;         /* matvecs of the working precision               */
   int fp64_matvecs;       /* FP64 matvecs (refinement residuals included)   */
@@ -348,6 +395,8 @@ typedef struct {
   const double *history;  /* residual history, context-owned, valid until
                              the next call on the context                  */
   int history_len;
+  double precond_seconds; /* part of seconds spent building preconditioner
+                             blocks (0 when they were already built)       */
 } mpsl_info;
 
 /* Solve eq. (49) for n_rhs sources src_xy[2*r], src_xy[2*r+1] (host).

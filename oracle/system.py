@@ -151,11 +151,16 @@ class Problem:
         Fm = np.exp(1j * lam[None, :] * x - g2[None, :] * (y + d))
         Cp = (Fp[:, None, :] * (c[:, None] * Zp).T[None, :, :]).reshape(N * P, -1)  # (NP, N_S)
         Cm = (Fm[:, None, :] * (c[:, None] * Zm).T[None, :, :]).reshape(N * P, -1)
-        TR = Cp @ sig[:, 1, :] + Cm @ sig[:, 2, :]
-        Sblk = np.zeros((N * P, N * P), dtype=np.complex128)
+        # T + T_R, then the block-diagonal S one block row at a time (the same
+        # products as S_blk @ (T + T_R) without forming S_blk)
+        K = T
+        K += Cp @ sig[:, 1, :]
+        K += Cm @ sig[:, 2, :]
         for l in range(N):
-            Sblk[l * P:(l + 1) * P, l * P:(l + 1) * P] = operators.rotated_smatrix(self.S_of(l), self.rot[l])
-        return np.eye(N * P) - Sblk @ (T + TR)
+            rows = slice(l * P, (l + 1) * P)
+            K[rows] = -(operators.rotated_smatrix(self.S_of(l), self.rot[l]) @ K[rows])
+        K[np.diag_indices(N * P)] += 1.0
+        return K
 
     def solve_lu(self, src):
         K = self.dense()

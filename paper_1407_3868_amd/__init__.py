@@ -18,6 +18,7 @@ FP32 = 1
 FAR_AUTO, FAR_DIRECT, FAR_FMM = 0, 1, 2
 TM, TE = 0, 1
 SOMM_DIRECT, SOMM_INTERP = 0, 1
+PRECOND_NONE, PRECOND_CLUSTER = 0, 1
 
 STATUS = {0: "MPSL_OK", -1: "MPSL_EINVAL", -2: "MPSL_ENOMEM", -3: "MPSL_EHIP", -4: "MPSL_ESTATE",
           -5: "MPSL_EGEOM", -6: "MPSL_ENOCONV", -7: "MPSL_EUNSUPPORTED", -8: "MPSL_EINSIDE",
@@ -96,6 +97,17 @@ def compute_contour_span(ks, b, t_max, h_max):
                                               n.value, lam.ctypes.data, w.ctypes.data, ctypes.byref(n)),
                 "contour span")
     return lam, w
+
+
+def compute_clusters(xy, cluster_size):
+    """Host: cluster of every particle under the bisection rule (mirrors mpsl_compute_clusters)."""
+    lib = _lib.load()
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    lab = np.zeros(xy.shape[0], np.int32)
+    nc = ctypes.c_int(0)
+    _host_check(lib.mpsl_compute_clusters(int(xy.shape[0]), xy.ctypes.data, int(cluster_size), lab.ctypes.data,
+                                          ctypes.byref(nc)), "clusters")
+    return lab, nc.value
 
 
 def span_contour_params(x_extent, tol=1e-10):
@@ -310,6 +322,22 @@ class Context:
     def sapply_dev(self, prec, x, alpha, y):
         return self._check(self.lib.mpsl_sapply_dev(self.h, int(prec), _ptr(x), _ptr(alpha), _ptr(y)))
 
+    # -- preconditioner -------------------------------------------------------
+    def set_preconditioner(self, kind, cluster_size=0):
+        """PRECOND_NONE or PRECOND_CLUSTER with clusters of at most cluster_size (0: 160)."""
+        return self._check(self.lib.mpsl_set_preconditioner(self.h, int(kind), int(cluster_size)))
+
+    def precond_apply_dev(self, prec, x, y):
+        return self._check(self.lib.mpsl_precond_apply_dev(self.h, int(prec), _ptr(x), _ptr(y)))
+
+    def precond_info(self):
+        nc, mx, m, rep = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        s = ctypes.c_double()
+        self._check(self.lib.mpsl_get_precond_info(self.h, ctypes.byref(nc), ctypes.byref(mx), ctypes.byref(m),
+                                                   ctypes.byref(rep), ctypes.byref(s)))
+        return dict(n_clusters=nc.value, max_cluster=mx.value, block_dim=m.value, replaced=rep.value,
+                    setup_seconds=s.value)
+
     # -- rhs, solve, field ----------------------------------------------------
     def rhs(self, src):
         n, p, _ = self.sizes()
@@ -330,7 +358,7 @@ class Context:
         hist = [info.history[i] for i in range(info.history_len)]
         meta = dict(status=rc, iterations=info.iterations, fp64_matvecs=info.fp64_matvecs,
                     refinements=info.refinements, rel_residual=info.rel_residual, seconds=info.seconds,
-                    history=hist)
+                    history=hist, precond_seconds=info.precond_seconds)
         return (out[0] if nr == 1 else out), meta
 
     def eval_field(self, src, beta, rcv):

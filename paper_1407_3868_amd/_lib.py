@@ -23,7 +23,8 @@ class Opts(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("fp64_matvecs", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
+                ("precond_seconds", ctypes.c_double)]
 
 
 P = ctypes.c_void_p
@@ -73,6 +74,10 @@ SIGNATURES = {
     "mpsl_reflect_dev": (I, [P, P, P, P]),
     "mpsl_s2l_dev": (I, [P, I, P, P]),
     "mpsl_sapply_dev": (I, [P, I, P, P, P]),
+    "mpsl_set_preconditioner": (I, [P, I, I]),
+    "mpsl_compute_clusters": (I, [L, P, I, P, ctypes.POINTER(I)]),
+    "mpsl_precond_apply_dev": (I, [P, I, P, P]),
+    "mpsl_get_precond_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), DP]),
     "mpsl_rhs": (I, [P, P, P]),
     "mpsl_solve": (I, [P, I, P, ctypes.POINTER(Opts), P, ctypes.POINTER(Info)]),
     "mpsl_eval_field": (I, [P, P, P, L, P, P]),

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmpsl.so")
-SOURCES = ["capi.hip", "kernels.hip", "solver.hip", "smatrix.hip", "batch.hip", "serve.hip", "fmm.hip", "layers.hip", "smatrix_dev.hip", "somm.hip"]
+SOURCES = ["capi.hip", "kernels.hip", "solver.hip", "smatrix.hip", "batch.hip", "serve.hip", "fmm.hip", "layers.hip", "smatrix_dev.hip", "somm.hip", "precond.hip"]
 ARCH = os.environ.get("MPSL_ARCH", "gfx950")
 
 FLAGS = [

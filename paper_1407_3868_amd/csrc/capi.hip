@@ -31,7 +31,7 @@ int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes) {
   // a captured batch reads the tables and matvec work buffers by address; only
   // the host-call staging and the solver's own buffers may move meanwhile
   if (ctx->pinned > 0 && &b != &ctx->xbuf && &b != &ctx->ybuf && &b != &ctx->gm && &b != &ctx->scal &&
-      &b != &ctx->pc_blk && &b != &ctx->pc_idx)
+      &b != &ctx->pc_blk && &b != &ctx->pc_blk32 && &b != &ctx->pc_idx && &b != &ctx->pc_part && &b != &ctx->pc_flag)
     return check_unpinned(ctx);
   if (b.p) {
     (void)hipFree(b.p);
@@ -143,7 +143,10 @@ void bessel_jy(int n, double x, double &j, double &y, double &jp, double &yp) {
   yp = (n == 0) ? -yn(1, x) : ym - n / x * y;
 }
 
-void invalidate(mpsl_ctx *ctx) { ctx->tables_ok = false; }
+void invalidate(mpsl_ctx *ctx) {
+  ctx->tables_ok = false;
+  ctx->pc_ok = ctx->pc_ok32 = false;
+}
 
 }  // namespace
 
@@ -577,7 +580,8 @@ void mpsl_destroy(mpsl_ctx *ctx) {
                   &ctx->ct.cq, &ctx->ct.W64, &ctx->ct.W32, &ctx->ct.U64, &ctx->gt.xy, &ctx->gt.rot64,
                   &ctx->gt.rot32, &ctx->gt.pair64, &ctx->gt.pair32, &ctx->gt.E64, &ctx->gt.E32, &ctx->gt.F64, &ctx->gt.F32, &ctx->part,
                   &ctx->m2s_part, &ctx->spec, &ctx->sigma, &ctx->Up64, &ctx->Up32, &ctx->xbuf,
-                  &ctx->ybuf, &ctx->gm, &ctx->scal};
+                  &ctx->ybuf, &ctx->gm, &ctx->scal, &ctx->pc_blk, &ctx->pc_blk32, &ctx->pc_idx, &ctx->pc_part,
+                  &ctx->pc_flag};
   for (DBuf *b : bufs) mpsl::dev_free(*b);
   mpsl::fmm_free(ctx);
   mpsl::somm_free(ctx);

@@ -178,8 +178,18 @@ struct mpsl_ctx {
   mpsl::DBuf bt;          // multi-RHS M2L: beta transposed to [n][P][r]
   mpsl::DBuf gm;          // GMRES workspace
   mpsl::DBuf scal;        // reductions
-  mpsl::DBuf pc_blk;      // cluster-block preconditioner: inverse blocks
-  mpsl::DBuf pc_idx;      // cluster-block preconditioner: index maps
+  // cluster-block right preconditioner of the solve (precond.hip)
+  int pc_kind = MPSL_PRECOND_NONE;
+  int pc_size = 160;      // largest cluster (particles)
+  bool pc_ok = false;     // FP64 blocks current for geometry and particle
+  bool pc_ok32 = false;   // FP32 copy current
+  int pc_nc = 0, pc_mp = 0, pc_m = 0, pc_replaced = 0;
+  double pc_setup_s = 0.0;
+  mpsl::DBuf pc_blk;      // double2 [nc][m][m]: inverse cluster blocks
+  mpsl::DBuf pc_blk32;    // float2 copy
+  mpsl::DBuf pc_idx;      // int32 [nc][mp] members, then [nc] counts
+  mpsl::DBuf pc_part;     // apply partial sums
+  mpsl::DBuf pc_flag;     // inversion failure flags
 
   // launch shapes
   int m2l_chunks = 0;     // source chunks of the M2L grid (0: automatic)
@@ -242,6 +252,12 @@ int make_contour_span(const std::vector<double> &ks, double b, double t_max, dou
 int make_contour(const std::vector<double> &ks, int n_nodes, double b, double t_max, std::vector<zc> &lam,
                  std::vector<zc> &w, std::string &err);
 int build_tables(mpsl_ctx *ctx);
+// Cluster-block preconditioner: build the inverse blocks (FP64, plus the FP32
+// copy for prec == MPSL_FP32) and apply y = M^{-1} x on FP64 device vectors.
+int precond_build(mpsl_ctx *ctx, int prec);
+int precond_apply(mpsl_ctx *ctx, int prec, const void *x, void *y);
+constexpr int kPcDefaultSize = 160;
+constexpr int kPcMaxDim = 16384;
 int ensure_work(mpsl_ctx *ctx);
 int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs);
 int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y);

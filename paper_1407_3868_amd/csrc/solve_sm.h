@@ -1,6 +1,7 @@
 // Resumable solver for eq. (49): restarted GMRES (Arnoldi by classical
 // Gram-Schmidt applied twice, FP64; Givens rotations on the host) inside an
-// FP64 residual loop.  In FP64 mode the inner matvecs are FP64 and the loop
+// FP64 residual loop, optionally right-preconditioned by the cluster blocks
+// (the Krylov operator is A M^{-1}; corrections are M^{-1} V y).  In FP64 mode the inner matvecs are FP64 and the loop
 // is plain restarted GMRES with a final true-residual check; in FP32 mode the
 // inner matvecs are complex64 (iterative refinement: x += d, r = b - A x in
 // FP64 after every inner solve).
@@ -34,6 +35,7 @@ class SolveSM {
   int fp64_matvecs() const { return fp64_mv_; }
   int refinements() const { return refin_; }
   double rel_residual() const { return rel_res_; }
+  double precond_seconds() const { return pc_s_; }
   const std::vector<double> &history() const { return hist_; }
 
  private:
@@ -58,6 +60,8 @@ class SolveSM {
   int j_ = 0;
   double bn_ = 0.0, rn_ = 0.0, inner_abs_ = 0.0, rel_res_ = 1.0;
   int inner_mv_ = 0, fp64_mv_ = 0, refin_ = 0;
+  bool pc_ = false;     // cluster-block right preconditioner active
+  double pc_s_ = 0.0;   // seconds spent building its blocks in init
   std::vector<double> hist_;
 };
 

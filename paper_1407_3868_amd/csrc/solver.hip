@@ -73,6 +73,13 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
     hh_ = nullptr;
     return set_err(ctx, MPSL_ENOMEM, "pinned host allocation failed");
   }
+  pc_ = ctx->pc_kind == MPSL_PRECOND_CLUSTER;
+  pc_s_ = 0.0;
+  if (pc_) {
+    const double before = ctx->pc_setup_s;
+    if ((rc = precond_build(ctx, o_.precision))) return rc;
+    pc_s_ = ctx->pc_setup_s - before;
+  }
   status_ = kRunning;
   inner_mv_ = fp64_mv_ = refin_ = 0;
   hist_.clear();
@@ -117,6 +124,10 @@ int SolveSM::launch() {
   if (phase_ == kInner) {
     double2 *vj = V_ + j_ * len_;
     double2 *vn = V_ + (j_ + 1) * len_;
+    if (pc_) {  // z = M^{-1} v_j, then A z
+      if ((rc = precond_apply(ctx, o_.precision, vj, w_))) return rc;
+      vj = w_;
+    }
     if (o_.precision == MPSL_FP64) {
       if ((rc = matvec(ctx, MPSL_FP64, vj, vn))) return rc;
     } else {
@@ -213,7 +224,12 @@ int SolveSM::finish_cycle() {
   MPSL_HIP_TRY(ctx, hipMemsetAsync(d_, 0, len_ * sizeof(double2), ctx->stream));
   int rc;
   if ((rc = launch_gemv_sub(ctx, V_, len_, j, h_, d_, len_))) return rc;  // d = V y
-  if ((rc = launch_axpy_c(ctx, xs_, d_, len_, 1.0, 0.0))) return rc;
+  if (pc_) {  // the correction is M^{-1} V y
+    if ((rc = precond_apply(ctx, o_.precision, d_, w_)) || (rc = launch_axpy_c(ctx, xs_, w_, len_, 1.0, 0.0)))
+      return rc;
+  } else if ((rc = launch_axpy_c(ctx, xs_, d_, len_, 1.0, 0.0))) {
+    return rc;
+  }
   ++refin_;
   phase_ = kResidual;
   return MPSL_OK;
@@ -277,6 +293,7 @@ int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *
       info->seconds = std::chrono::duration<double>(t1 - t0).count();
       info->history = ctx->hist.data();
       info->history_len = static_cast<int>(ctx->hist.size());
+      info->precond_seconds = sm.precond_seconds();
     }
     if (sm.status() != mpsl::SolveSM::kConverged) status = MPSL_ENOCONV;
   }

@@ -206,11 +206,17 @@ CONFIGS = {
 
 
 def make_workload(name: str, n_rhs: int = 1, src_seed: Optional[int] = None,
-                  n: Optional[int] = None) -> Workload:
-    """Build a named workload.  ``n`` overrides the particle count (same strip)."""
+                  n: Optional[int] = None, cut: Optional[int] = None) -> Workload:
+    """Build a named workload.  ``n`` overrides the particle count (same strip);
+    ``cut`` keeps only the ``cut`` particles of the full layout nearest to
+    x = 0 (smallest |x|, ties by index, original order): a window of the strip
+    at the recipe's density."""
     c = dict(CONFIGS[name])
     nn = int(n) if n is not None else c["n"]
     xy, rot = rejection_layout(nn, c["x_range"], c["y_range"], 0.75, c["seed"])
+    if cut is not None:
+        keep = np.sort(np.lexsort((np.arange(xy.shape[0]), np.abs(xy[:, 0])))[:int(cut)])
+        xy, rot = xy[keep], rot[keep]
     if n_rhs == 1 and src_seed is None:
         src = np.array([[0.0, 2.0]])
     else:

@@ -147,3 +147,32 @@ def test_layer_map_te_matches_oracle_node_solve(ks, th, c):
 def test_bad_polarization():
     with pytest.raises(mp.MpslError):
         mp.compute_disk_smatrix(0.25, 9.0, 15.0, 8, polarization=2)
+
+
+@pytest.mark.parametrize("name,n,size", [("c3", None, 160), ("c3", None, 40), ("c3", 777, 1), ("c5max", 3000, 97),
+                                         ("s150p12", None, 150), ("s150p12", None, 1000)])
+def test_clusters(name, n, size):
+    # recursive coordinate bisection: integer output, bit-exact
+    from oracle import precond as opc
+    from synth import make_workload
+    wl = make_workload(name, n=n)
+    lab, nc = mp.compute_clusters(wl.xy, size)
+    ref = opc.cluster_of(wl.xy, size)
+    assert nc == len(opc.clusters(wl.xy, size))
+    assert np.array_equal(lab, ref)
+
+
+def test_clusters_ties_and_grid():
+    from oracle import precond as opc
+    g = np.array([(x, y) for y in range(6) for x in range(6)], dtype=float)
+    for xy in (np.zeros((9, 2)), g, g[::-1].copy(), np.stack([np.arange(10.0), np.zeros(10)], 1)):
+        for size in (1, 2, 3, 4, 5, 100):
+            lab, nc = mp.compute_clusters(xy, size)
+            assert np.array_equal(lab, opc.cluster_of(xy, size))
+
+
+def test_clusters_reject_bad_input():
+    with pytest.raises(mp.MpslError):
+        mp.compute_clusters(np.zeros((3, 2)), 0)
+    with pytest.raises(mp.MpslError):
+        mp.compute_clusters(np.array([[0.0, np.nan]]), 2)
