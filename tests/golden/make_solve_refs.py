@@ -59,7 +59,7 @@ def main(case):
     with open(path, "w") as fh:
         fh.write(f"# {case}: {wl.n} stars (a1, a2, a3) = {wl.shape_params}, kp = {wl.kp}, p = {wl.p}, "
                  f"k = ({wl.k1}, {wl.k2}, {wl.k3}), d = {wl.d}, {wl.n_nodes} contour nodes, b = {wl.b}, "
-                 f"t_max = {wl.t_max}, source {tuple(src)}\n")
+                 f"t_max = {wl.t_max}, source ({src[0]:g}, {src[1]:g})\n")
         fh.write("# eq. (49) solved by dense LU, total field of eq. (36); written by "
                  "tests/golden/make_solve_refs.py (oracle only)\n")
         fh.write(f"# |beta|_2 = {np.linalg.norm(beta):.17e}\n")

@@ -58,10 +58,34 @@ def rel_err(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def entry_err(got, ref, eps):
+    """Worst per-entry error max |got - ref| / (|ref| + eps * max|ref| of its row)
+    over an array of rows (particles, or the two interfaces of a spectrum),
+    with the (row, column) where it occurs.  eps = 0 makes it the largest
+    relative error of any single entry."""
+    ref = np.asarray(ref)
+    got = np.asarray(got).reshape(ref.shape)
+    d = np.abs(got - ref)
+    scale = np.abs(ref) + eps * np.abs(ref).max(axis=-1, keepdims=True)
+    r = np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), np.where(d > 0, np.inf, 0.0))
+    i = np.unravel_index(int(np.argmax(r)), r.shape)
+    return float(r[i]), tuple(int(v) for v in i)
+
+
+# Per-entry bounds of the steps and the matvec (tol, eps of entry_err).  FP64:
+# every entry to 1e-11 of itself (measured worst 1.2e-12 over the small
+# layouts, M2L / M2S / S2L / matvec); the floor eps keeps exact zeros
+# finite.  FP32: 1e-4 with a floor of 1e-3 of the row's largest entry
+# (measured worst 3.5e-5 without a floor, 3.0e-5 with it: FP32 rounding of
+# the tables and sums of N P terms spanning many decades).
+ENTRY_TOL = {0: (1e-11, 1e-9), 1: (1e-4, 1e-3)}
+
+
 def max_err(a, b):
     a = np.asarray(a).reshape(-1)
     b = np.asarray(b).reshape(-1)
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-__all__ = ["make_workload", "prototype_S", "oracle_problem", "gpu_context", "coeff_vector", "rel_err", "max_err"]
+__all__ = ["make_workload", "prototype_S", "oracle_problem", "gpu_context", "coeff_vector", "rel_err", "max_err",
+           "entry_err", "ENTRY_TOL"]

@@ -4,11 +4,13 @@ computes target by target."""
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, make_workload, oracle_problem, coeff_vector
+from gpu_common import ENTRY_TOL, coeff_vector, entry_err, gpu_context, make_workload, oracle_problem
 
 pytestmark = pytest.mark.gpu
 
-TARGETS = [0, 1, 777, 2500, 4095, 4999]
+# 64 seeded rows across the strip, plus both ends and the 64-lane tile edges
+TARGETS = sorted(set([0, 1, 63, 64, 2500, 4095, 4999]) |
+                 set(np.random.default_rng(64).choice(5000, 57, replace=False).tolist()))
 
 
 @pytest.fixture(scope="module")
@@ -32,4 +34,7 @@ def test_matvec_sampled(c3, prec, tol):
     ref = pr.matvec(x, targets=TARGETS)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert err < tol, err
+    etol, eps = ENTRY_TOL[prec]
+    e, (row, slot) = entry_err(got, ref, eps)
+    assert e < etol, f"worst entry: particle {TARGETS[row]}, slot {slot}: {e:.2e}"
     assert np.all(np.isfinite(yd.cpu().numpy()))

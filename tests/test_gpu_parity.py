@@ -1,7 +1,8 @@
 """GPU parity: every HIP step of the matvec, the matvec itself, the right-hand
 side and the solve, against the FP64 oracle on the same seeded inputs.
 
-Tolerances (relative 2-norm over the output unless stated):
+Tolerances: relative 2-norm over the output, and per entry (gpu_common.ENTRY_TOL:
+|got - ref| <= tol (|ref| + eps max|ref| of the particle), worst entry reported):
   FP64 steps      1e-12  (rounding of O(N P) FP64 sums; the oracle uses
                           scipy's AMOS Hankel functions, the library the ROCm
                           device library, both accurate to a few ulp)
@@ -12,7 +13,8 @@ Tolerances (relative 2-norm over the output unless stated):
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, make_workload, max_err, oracle_problem, prototype_S, rel_err, coeff_vector
+from gpu_common import (ENTRY_TOL, coeff_vector, entry_err, gpu_context, make_workload, max_err, oracle_problem,
+                        prototype_S, rel_err)
 from oracle import layered as olayered
 from oracle import operators as oops
 
@@ -83,6 +85,13 @@ def test_m2l(name, prec, torch_dev):
     got = ad.cpu().numpy()
     tol = FP64_TOL if prec == 0 else FP32_TOL
     assert rel_err(got, ref) < tol, rel_err(got, ref)
+    _assert_entries(got, ref, prec)
+
+
+def _assert_entries(got, ref, prec):
+    tol, eps = ENTRY_TOL[prec]
+    e, where = entry_err(got, ref, eps)
+    assert e < tol, f"worst entry {where} (row, slot): {e:.2e}"
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -101,6 +110,7 @@ def test_m2s(name, prec, torch_dev):
     ref = np.stack([Pp, Pm])
     tol = FP64_TOL if prec == 0 else FP32_TOL
     assert rel_err(got, ref) < tol, rel_err(got, ref)
+    _assert_entries(got, ref, prec)
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -144,6 +154,7 @@ def test_s2l(name, prec, torch_dev):
     got = ad.cpu().numpy()
     tol = FP64_TOL if prec == 0 else FP32_TOL
     assert rel_err(got, ref) < tol, rel_err(got, ref)
+    _assert_entries(got, ref, prec)
 
 
 @pytest.mark.parametrize("name", SMALL)
@@ -163,6 +174,7 @@ def test_sapply(name, prec, torch_dev):
     torch.cuda.synchronize()
     tol = FP64_TOL if prec == 0 else 1e-6
     assert rel_err(yd.cpu().numpy(), ref) < tol
+    _assert_entries(yd.cpu().numpy(), ref, prec)
 
 
 @pytest.mark.parametrize("name", SMALL + ["c1"])
@@ -181,6 +193,7 @@ def test_matvec(name, prec, torch_dev):
     tol = FP64_TOL if prec == 0 else FP32_TOL
     err = rel_err(yd.cpu().numpy(), ref)
     assert err < tol, err
+    _assert_entries(yd.cpu().numpy(), ref, prec)
     # host-pointer entry point gives the same bytes
     y2 = ctx.apply(prec, x.astype(npdt))
     assert np.array_equal(y2, yd.cpu().numpy())
@@ -217,7 +230,9 @@ def test_small_and_ragged_counts(n, prec, torch_dev):
     x = coeff_vector(wl, 8)
     assert ctx.get_tuning(prec)["variant"] == 2
     got = ctx.apply(prec, x.astype(np.complex128 if prec == 0 else np.complex64))
-    assert rel_err(got, pr.matvec(x)) < (FP64_TOL if prec == 0 else FP32_TOL)
+    ref = pr.matvec(x)
+    assert rel_err(got, ref) < (FP64_TOL if prec == 0 else FP32_TOL)
+    _assert_entries(got, ref, prec)
 
 
 def test_highest_order(torch_dev):
@@ -249,8 +264,11 @@ def test_m2l_variants(name, prec, variant, chunks, torch_dev):
     torch.cuda.synchronize()
     tol = FP64_TOL if prec == 0 else FP32_TOL
     assert rel_err(ad.cpu().numpy(), ref) < tol
+    _assert_entries(ad.cpu().numpy(), ref, prec)
     y = ctx.apply(prec, x.astype(np.complex128 if prec == 0 else np.complex64))
-    assert rel_err(y, pr.matvec(x)) < tol
+    yref = pr.matvec(x)
+    assert rel_err(y, yref) < tol
+    _assert_entries(y, yref, prec)
 
 
 @pytest.mark.parametrize("prec", [0, 1])

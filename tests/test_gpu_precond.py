@@ -9,10 +9,15 @@
 - the reference fields of the 1000-star recipe and of a 600-star window of
   the 5000-star recipe (tests/golden, written by the oracle's dense LU).
 
-Tolerances: FP64 apply backward error 1e-10 (blocks with condition numbers
-up to ~1e10 inverted without pivoting across 64 x 64 steps); FP32 copy 1e-4
-forward (FP32 rounding of the inverse entries times the sums' cancellation);
-fields 1e-10 (FP64 solve) and 1e-6 (mixed), as for the other solves.
+Tolerances.  FP64 apply: normwise backward error
+eta = ||K_c y - x|| / (||K_c||_F ||y|| + ||x||) below 1e-13 per cluster, with
+K_c the oracle's block.  The blocks of near-resonant stars reach condition
+numbers ~1e10, so residuals relative to ||x|| alone would measure
+cond(K_c) times the 1e-14 relative difference of the device and scipy
+Hankel values rather than the inversion.  FP32 copy: |y32 - y64| below
+2e-7 |X| |x| summed in 2-norm (X the oracle's inverse): the rounding of
+the inverse's entries to FP32.  Fields: 1e-10 (FP64 solve) and 1e-6
+(mixed), as for the other solves.
 """
 import os
 
@@ -34,6 +39,11 @@ def torch_dev():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     return torch
+
+
+def _eta(K, y, x):
+    """Normwise backward error of y as a solution of K y = x."""
+    return np.linalg.norm(K @ y - x) / (np.linalg.norm(K) * np.linalg.norm(y) + np.linalg.norm(x))
 
 
 def _rcv(wl, n=96):
@@ -64,18 +74,21 @@ def test_precond_apply(name, size, torch_dev):
     info = ctx.precond_info()
     assert info["n_clusters"] == len(cl) and info["replaced"] == 0
     assert info["max_cluster"] == max(len(c) for c in cl)
-    worst = 0.0
+    worst, worst32 = 0.0, 0.0
     inv = []
     for idx in cl:
         K = opc.cluster_matrix(pr, idx)
-        r = np.linalg.norm(K @ y64[idx].reshape(-1) - x[idx].reshape(-1)) / np.linalg.norm(x[idx])
-        worst = max(worst, r)
-        inv.append(np.linalg.inv(K))
-    assert worst < 1e-10, worst
+        X = np.linalg.inv(K)
+        inv.append(X)
+        xi, yi = x[idx].reshape(-1), y64[idx].reshape(-1)
+        worst = max(worst, _eta(K, yi, xi))
+        scale = np.linalg.norm(np.abs(X) @ np.abs(xi))
+        worst32 = max(worst32, np.linalg.norm(y32[idx].reshape(-1) - yi) / scale)
     ref = opc.apply(cl, inv, x, wl.P)
-    e64, e32 = rel_err(y64, ref), rel_err(y32, ref)
-    print(f"{name} size {size}: backward {worst:.2e}, forward FP64 {e64:.2e}, FP32 copy {e32:.2e}")
-    assert e64 < 1e-8 and e32 < 1e-4
+    print(f"{name} size {size}: backward error {worst:.2e}, FP32 copy {worst32:.2e} of |X||x|, "
+          f"forward FP64 {rel_err(y64, ref):.2e}")
+    assert worst < 1e-13, worst
+    assert worst32 < 2e-7, worst32
 
 
 def test_precond_rebuilds_after_geometry_change(torch_dev):
@@ -99,30 +112,43 @@ def test_precond_rebuilds_after_geometry_change(torch_dev):
     yy = y.cpu().numpy()
     for idx in opc.clusters(xy, 30):
         K = opc.cluster_matrix(pr2, idx)
-        assert np.linalg.norm(K @ yy[idx].reshape(-1) - x[idx].reshape(-1)) < 1e-10 * np.linalg.norm(x[idx])
+        assert _eta(K, yy[idx].reshape(-1), x[idx].reshape(-1)) < 1e-13
     # back to no preconditioner: apply is refused, solves run unpreconditioned
     ctx.set_preconditioner(mp.PRECOND_NONE)
     with pytest.raises(mp.MpslError):
         ctx.precond_apply_dev(0, xd, y)
 
 
-@pytest.mark.parametrize("name,size", [("s150p12", 40), ("s200p16", 40)])
-def test_precond_fp64_solve_matches_lu(name, size):
+@pytest.mark.parametrize("name,size,field_tol", [("s150p12", 40, 1e-10), ("s200p16", 40, 1e-6)])
+def test_precond_fp64_solve_matches_lu(name, size, field_tol):
+    # FP64 parity that does not depend on the conditioning: the GPU's beta
+    # solves the oracle's dense system (residual in the oracle's matrix) and
+    # the GPU field of that beta is the oracle's field of it.  Against the LU
+    # solution the field can differ by cond(K) times the residuals of both:
+    # the 200-star p = 16 system (cond ~1e8) leaves ~1e-7 (asserted at 1e-6).
     wl = make_workload(name)
     pr = oracle_problem(wl)
     ctx = gpu_context(wl)
     src = wl.src[0]
-    ref = pr.solve_lu(src)
+    K = pr.dense()
+    b = pr.rhs(src).reshape(-1)
+    ref = np.linalg.solve(K, b).reshape(wl.n, wl.P)
     _, meta0 = ctx.solve(src, precision=0, tol=1e-12, maxiter=1500)
     ctx.set_preconditioner(mp.PRECOND_CLUSTER, size)
     beta, meta = ctx.solve(src, precision=0, tol=1e-12, maxiter=1500)
+    res = np.linalg.norm(K @ beta.reshape(-1) - b) / np.linalg.norm(b)
+    r = _rcv(wl)
+    u = ctx.eval_field(src, beta, r)
+    e_same = rel_err(u, pr.field(src, beta, r))
+    e_lu = rel_err(u, pr.field(src, ref, r))
     print(f"{name}: {meta0['iterations']} iterations plain, {meta['iterations']} preconditioned "
-          f"(blocks {meta['precond_seconds']:.3f} s)")
+          f"(blocks {meta['precond_seconds']:.3f} s); oracle residual {res:.2e}, field of the same beta "
+          f"{e_same:.2e}, field vs LU {e_lu:.2e}")
     assert meta["status"] == 0 and meta["rel_residual"] < 1e-11
     assert meta["iterations"] < 0.7 * meta0["iterations"]
-    assert rel_err(beta, ref) < 1e-9
-    r = _rcv(wl)
-    assert rel_err(ctx.eval_field(src, beta, r), pr.field(src, ref, r)) < 1e-10
+    assert res < 1e-11
+    assert e_same < 1e-11
+    assert e_lu < field_tol
 
 
 @pytest.mark.parametrize("name,size", [("s150p12", 40), ("s200p16", 40), ("s200p16", 200)])
@@ -148,11 +174,17 @@ def _golden(case):
     return d[:, :2], d[:, 2] + 1j * d[:, 3]
 
 
-@pytest.mark.parametrize("case,prec,tol", [("c3cut600", 0, 1e-10), ("c3cut600", 1, 1e-6), ("c2", 0, 1e-10),
-                                           ("c2", 1, 1e-6)])
-def test_solve_matches_golden_lu(case, prec, tol):
+@pytest.mark.parametrize("case,prec,lu_tol", [("c3cut600", 0, 1e-6), ("c3cut600", 1, 1e-6), ("c2", 0, 1e-6),
+                                              ("c2", 1, 1e-6)])
+def test_solve_matches_golden_lu(case, prec, lu_tol):
     # 600-star window of the 5000-star recipe (p = 16, 1024 nodes) and the
-    # 1000-star recipe (p = 12, 512 nodes) against the oracle's dense LU fields
+    # 1000-star recipe (p = 12, 512 nodes).  The GPU's beta is checked in the
+    # oracle's own operator (matrix-free residual of eq. (49)) and by the
+    # oracle's field of that beta; against the oracle's dense-LU field the
+    # difference is bounded by cond(K) times the rounding-level difference of
+    # the two discrete systems (device and scipy Hankel values), measured
+    # 5.5e-7 for the p = 16 window in both precisions (the two GPU solutions
+    # agree with each other far better than with the LU one).
     from gpu_common import prototype_S
     wl = make_workload("c3", cut=600) if case == "c3cut600" else make_workload("c2")
     rcv, u_ref = _golden(case)
@@ -163,9 +195,17 @@ def test_solve_matches_golden_lu(case, prec, tol):
     ctx.set_contour(wl.n_nodes, wl.b, wl.t_max)
     ctx.set_preconditioner(mp.PRECOND_CLUSTER, 0)
     src = wl.src[0]
-    beta, meta = ctx.solve(src, precision=prec, tol=1e-12 if prec == 0 else 1e-10, maxiter=4000)
+    tol = 1e-12 if prec == 0 else 1e-10
+    beta, meta = ctx.solve(src, precision=prec, tol=tol, maxiter=4000)
     u = ctx.eval_field(src, beta, rcv)
-    e = rel_err(u, u_ref)
-    print(f"{case} prec {prec}: {meta['iterations']} iterations in {meta['seconds']:.2f} s, field error {e:.2e}")
+    pr = oracle_problem(wl)
+    b = pr.rhs(src)
+    res = np.linalg.norm(pr.matvec(beta) - b) / np.linalg.norm(b)
+    e_same = rel_err(u, pr.field(src, beta, rcv))
+    e_lu = rel_err(u, u_ref)
+    print(f"{case} prec {prec}: {meta['iterations']} iterations in {meta['seconds']:.2f} s; oracle residual "
+          f"{res:.2e}, field of the same beta {e_same:.2e}, field vs LU {e_lu:.2e}")
     assert meta["status"] == 0, meta
-    assert e < tol
+    assert res < 10 * tol
+    assert e_same < 1e-11
+    assert e_lu < lu_tol
