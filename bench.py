@@ -93,8 +93,42 @@ def _matvec_rate(ctx, torch, prec, x_np, steps, warmup):
     return (t1 - t0), m2l_ms, cnt, finite
 
 
+def _oracle_m2l_part(args):
+    """One worker of the all-core oracle timing: the oracle's M2L for some targets."""
+    xy, k2, p, x, targets = args
+    from threadpoolctl import threadpool_limits
+
+    from oracle import operators as oo
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oo.m2l_apply(xy, k2, p, x, targets=targets)
+        return time.perf_counter() - t0
+
+
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
 def _cpu_baseline(wl, S, x, n_targets=24):
-    """The FP64 oracle's matvec, timed on a bounded sample of the workload."""
+    """The FP64 oracle's matvec, timed on a bounded sample of the workload: on
+    one host thread, and on every core available to the process (the sampled
+    targets' M2L spread over one worker process per core, the BLAS parts
+    threaded over all cores)."""
+    import concurrent.futures
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -102,10 +136,11 @@ def _cpu_baseline(wl, S, x, n_targets=24):
     from oracle import operators as oo
     from oracle import system as osys
 
+    model, cores = _host_cpu()
+    lam, w = oc.contour(wl.n_nodes, wl.b, wl.t_max, [wl.k1, wl.k2, wl.k3])
+    pr = osys.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, S, wl.xy, wl.rot, lam, w)
+    tg = list(np.linspace(0, wl.n - 1, n_targets).astype(int))
     with threadpool_limits(limits=1):
-        lam, w = oc.contour(wl.n_nodes, wl.b, wl.t_max, [wl.k1, wl.k2, wl.k3])
-        pr = osys.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, S, wl.xy, wl.rot, lam, w)
-        tg = list(np.linspace(0, wl.n - 1, n_targets).astype(int))
         t0 = time.perf_counter()
         oo.m2l_apply(wl.xy, wl.k2, wl.p, x, targets=tg)
         t1 = time.perf_counter()
@@ -115,12 +150,29 @@ def _cpu_baseline(wl, S, x, n_targets=24):
         t3 = time.perf_counter()
         pr.apply_S(a[tg], targets=tg)
         t4 = time.perf_counter()
-    per_matvec = (t1 - t0) * wl.n / n_targets + (t2 - t1) + (t3 - t2) + (t4 - t3) * wl.n / n_targets
-    return {"value": 1.0 / per_matvec, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 numpy/scipy oracle on one host thread: all-pairs M2L and S-apply for "
-                       f"{n_targets} of {wl.n} targets (scaled by {wl.n}/{n_targets}), M2S, 4x4 node "
-                       f"solves and S2L in full; {t4 - t0:.1f} s measured, "
-                       f"{per_matvec:.1f} s per full matvec")}
+    one = (t1 - t0) * wl.n / n_targets + (t2 - t1) + (t3 - t2) + (t4 - t3) * wl.n / n_targets
+    # all cores: n_targets per worker, one worker per core
+    tall = list(np.linspace(0, wl.n - 1, n_targets * cores).astype(int))
+    parts = [(wl.xy, wl.k2, wl.p, x, tall[i::cores]) for i in range(cores)]
+    with concurrent.futures.ProcessPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(_oracle_m2l_part, parts[:cores]))       # start-up of the workers, untimed
+        a0 = time.perf_counter()
+        list(ex.map(_oracle_m2l_part, parts))
+        a1 = time.perf_counter()
+    with threadpool_limits(limits=cores):
+        a2 = time.perf_counter()
+        sig = pr.sigma(beta=x)
+        a = oo.s2l(sig[:, 1], sig[:, 2], wl.xy, lam, w, wl.k2, wl.d, wl.p)
+        a3 = time.perf_counter()
+    allc = (a1 - a0) * wl.n / len(tall) + (a3 - a2) + (t4 - t3) * wl.n / n_targets / cores
+    return {"value": 1.0 / allc, "unit": "matvecs/s", "cores": cores, "kind": "oracle", "cpu_model": model,
+            "one_thread": {"value": 1.0 / one, "seconds_per_matvec": one},
+            "seconds_per_matvec": allc,
+            "sample": (f"FP64 numpy/scipy oracle on {model}: all-pairs M2L for {len(tall)} of {wl.n} targets "
+                       f"in {cores} worker processes (one per core, scaled by {wl.n}/{len(tall)}), M2S, 4x4 node "
+                       f"solves and S2L in full with {cores} BLAS threads, S-apply scaled from one thread; "
+                       f"{allc:.1f} s per full matvec on all cores, {one:.1f} s on one thread "
+                       f"({n_targets} targets)")}
 
 
 def _batch_workload(args, torch, mp):
@@ -329,6 +381,58 @@ def _fmm_workload(args, torch, mp):
     return out
 
 
+def _solve_leg(args, mp, ctx, wl, flops):
+    """Solves of eq. (49) at the benchmark configuration to tol 1e-6, with the
+    cluster-block right preconditioner (built once per geometry, timed as
+    setup), for seeded point sources: p50 / p99 per precision, and the field
+    of the mixed-precision solution against the FP64 one at 4096 seeded
+    receivers in all three layers."""
+    import numpy as np
+
+    from synth import receivers
+
+    rng = np.random.default_rng(1003)
+    srcs = [np.array([0.0, 2.0])] + [np.array([rng.uniform(-200.0, 200.0), rng.uniform(1.0, 3.0)])
+                                     for _ in range(args.solve_sources - 1)]
+    ctx.set_preconditioner(mp.PRECOND_CLUSTER, args.cluster)
+    res = {"tol": wl.tol, "preconditioner": {"kind": "cluster blocks", "cluster_size": args.cluster}}
+    betas = {}
+    for name, prec in (("mixed", 1), ("fp64", 0)):
+        secs, its, conv, metas = [], [], 0, []
+        for i, src in enumerate(srcs):
+            beta, meta = ctx.solve(src, precision=prec, tol=wl.tol, maxiter=args.solve_maxiter, inner_tol=1e-5)
+            secs.append(meta["seconds"] - meta["precond_seconds"])
+            its.append(meta["iterations"])
+            conv += meta["status"] == 0
+            metas.append(meta)
+            if i == 0:
+                betas[name] = beta
+            print(f"# solve {name} source {i}: {meta['iterations']} its, {secs[-1]:.2f} s, "
+                  f"res {meta['rel_residual']:.2e}", file=sys.stderr, flush=True)
+        ms = np.array(secs) * 1e3
+        ms_it = float(np.sum(ms) / max(1, np.sum(its)))
+        peak = PEAK_FP32 if prec == 1 else PEAK_FP64
+        res[name] = {"sources": len(srcs), "converged": int(conv), "p50_ms": float(np.percentile(ms, 50)),
+                     "p99_ms": float(np.percentile(ms, 99)), "mean_ms": float(ms.mean()),
+                     "iterations": its, "refinements": [m["refinements"] for m in metas],
+                     "rel_residual_max": float(max(m["rel_residual"] for m in metas)),
+                     "ms_per_iteration": ms_it,
+                     # ideal time of the iteration's M2L at the peak / measured time per iteration
+                     "iteration_roofline_frac": flops / peak * 1e3 / ms_it}
+    res["preconditioner"].update(ctx.precond_info())
+    xs = wl.xy[:, 0]
+    rcv = receivers(4096, (xs.min() - 2.0, xs.max() + 2.0), (-wl.d - 2.0, 3.0), wl.xy, 1002, particle_excl=0.35,
+                    source=srcs[0], source_excl=0.05)
+    u32 = ctx.eval_field(srcs[0], betas["mixed"], rcv)
+    u64 = ctx.eval_field(srcs[0], betas["fp64"], rcv)
+    res["field_4096_receivers"] = {
+        "mixed_vs_fp64_rel_l2": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64)),
+        "mixed_vs_fp64_max_rel": float(np.max(np.abs(u32 - u64)) / np.max(np.abs(u64))),
+        "note": "both solves to relative residual 1e-6; the difference bounds how far the mixed-precision "
+                "solution is from the FP64 one, not from the continuous problem"}
+    return res
+
+
 def _span_leg(args, torch, mp, wl, x, y_count):
     """The same 5000-particle matvec on span-rule contours (panels no longer
     than h = 12/X and 6/X for the strip's extent X, b = 2/X, t_max = 24), which
@@ -383,7 +487,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-solve", action="store_true", help="skip the solve timings")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--solve-maxiter", type=int, default=1500)
+    ap.add_argument("--solve-maxiter", type=int, default=4000)
+    ap.add_argument("--solve-sources", type=int, default=10, help="seeded point sources per precision")
+    ap.add_argument("--cluster", type=int, default=160, help="largest cluster of the block preconditioner")
+    ap.add_argument("--no-batch", action="store_true", help="skip the short many-RHS / many-config leg")
     ap.add_argument("--no-autotune", action="store_true", help="use the default M2L launch shape")
     ap.add_argument("--no-fmm", action="store_true", help="skip the FMM far-field comparison")
     ap.add_argument("--no-span", action="store_true", help="skip the span-rule contour legs")
@@ -525,28 +632,10 @@ def main():
         out["fmm_far_field"] = fm
 
     if not args.no_solve:
-        solves = {}
-        for name, prec in (("mixed", 1), ("fp64", 0)):
-            beta, meta = ctx.solve(wl.src[0], precision=prec, tol=wl.tol, maxiter=args.solve_maxiter,
-                                   inner_tol=1e-4)
-            its = max(1, meta["iterations"])
-            ms_it = meta["seconds"] * 1e3 / its
-            peak = PEAK_FP32 if prec == 1 else PEAK_FP64
-            solves[name] = {"seconds": meta["seconds"], "iterations": meta["iterations"],
-                            "fp64_matvecs": meta["fp64_matvecs"], "refinements": meta["refinements"],
-                            "rel_residual": meta["rel_residual"], "converged": meta["status"] == 0,
-                            "tol": wl.tol, "ms_per_iteration": ms_it,
-                            # ideal time of the iteration's M2L at the vector peak / measured time
-                            "iteration_roofline_frac": flops / peak * 1e3 / ms_it}
-            print(f"# solve {name}: {meta['iterations']} its, {meta['seconds']:.2f} s, "
-                  f"res {meta['rel_residual']:.2e}", file=sys.stderr, flush=True)
-        out["solve"] = solves
-        if solves["mixed"]["converged"] and solves["fp64"]["converged"]:
-            out["mixed_vs_fp64_solve_speedup"] = solves["fp64"]["seconds"] / solves["mixed"]["seconds"]
-        elif solves["mixed"]["iterations"] == solves["fp64"]["iterations"]:
-            # both stopped at the iteration limit: the same work in both precisions
-            out["mixed_vs_fp64_solve_speedup_equal_iterations"] = (solves["fp64"]["seconds"] /
-                                                                   solves["mixed"]["seconds"])
+        out["solve"] = _solve_leg(args, mp, ctx, wl, flops)
+        sv = out["solve"]
+        if sv["mixed"]["converged"] == sv["mixed"]["sources"] and sv["fp64"]["converged"] == sv["fp64"]["sources"]:
+            out["mixed_vs_fp64_solve_speedup"] = sv["fp64"]["p50_ms"] / sv["mixed"]["p50_ms"]
 
     if not args.no_span:
         yc = torch.zeros_like(xd)
@@ -558,6 +647,11 @@ def main():
         out["span_contour"] = _span_leg(args, torch, mp, wl, x, y_count)
         print(f"# span legs: {json.dumps(out['span_contour'])}", file=sys.stderr, flush=True)
 
+    if not args.no_batch:
+        short = argparse.Namespace(**vars(args))
+        short.steps, short.warmup = 5, 1
+        out["batch"] = _batch_workload(short, torch, mp)
+        print(f"# batch: {json.dumps(out['batch'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(wl, S, x)
     print(json.dumps(out), flush=True)

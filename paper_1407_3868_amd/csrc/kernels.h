@@ -69,6 +69,9 @@ int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const voi
 int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *h, void *w,
                     int64_t len);
 int launch_scale(mpsl_ctx *ctx, void *v, int64_t len, double s, const void *src);
+// h[i] -= q[i] (q^H h) for i < k (one block): the projection onto span(W)
+// in V coordinates used when a GMRES cycle recycles the first cycle's space.
+int launch_proj_fix(mpsl_ctx *ctx, void *h, const void *q, int k);
 // Bytes of ctx->scal that launch_dotc_multi needs for k dot products.
 size_t dotc_scratch_bytes(int k);
 // Largest Krylov dimension of the GMRES solver (basis vectors kept at once).

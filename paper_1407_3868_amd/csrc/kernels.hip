@@ -1081,6 +1081,31 @@ __global__ void k_gemv_sub(const double2 *__restrict__ V, int64_t ld_v, int k,
   w[i] = st(acc);
 }
 
+__global__ __launch_bounds__(kRed) void k_proj_fix(double2 *__restrict__ h, const double2 *__restrict__ q, int k) {
+  __shared__ double sr[kRed], si[kRed];
+  double re = 0.0, im = 0.0;
+  for (int i = threadIdx.x; i < k; i += kRed) {  // q^H h
+    re += q[i].x * h[i].x + q[i].y * h[i].y;
+    im += q[i].x * h[i].y - q[i].y * h[i].x;
+  }
+  sr[threadIdx.x] = re;
+  si[threadIdx.x] = im;
+  __syncthreads();
+  for (int o = kRed / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      si[threadIdx.x] += si[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double ar = sr[0], ai = si[0];
+  for (int i = threadIdx.x; i < k; i += kRed) {
+    const double2 qi = q[i];
+    h[i].x -= qi.x * ar - qi.y * ai;
+    h[i].y -= qi.x * ai + qi.y * ar;
+  }
+}
+
 __global__ void k_scale(double2 *__restrict__ v, const double2 *__restrict__ src, int64_t len, double s) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= len) return;
@@ -1544,6 +1569,13 @@ int launch_fold_parts(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs,
   else
     hipLaunchKernelGGL(k_fold_parts<float>, grid, dim3(256), 0, ctx->stream, static_cast<float2 *>(part), chunks,
                        len, pstride);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_proj_fix(mpsl_ctx *ctx, void *h, const void *q, int k) {
+  hipLaunchKernelGGL(k_proj_fix, dim3(1), dim3(kRed), 0, ctx->stream, static_cast<double2 *>(h),
+                     static_cast<const double2 *>(q), k);
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }

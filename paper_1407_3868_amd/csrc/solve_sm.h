@@ -1,7 +1,20 @@
 // Resumable solver for eq. (49): restarted GMRES (Arnoldi by classical
 // Gram-Schmidt applied twice, FP64; Givens rotations on the host) inside an
 // FP64 residual loop, optionally right-preconditioned by the cluster blocks
-// (the Krylov operator is A M^{-1}; corrections are M^{-1} V y).  In FP64 mode the inner matvecs are FP64 and the loop
+// (the Krylov operator is A M^{-1}; corrections are M^{-1} V y).
+//
+// Cycles after the first recycle the first cycle's Krylov space (augmented
+// GMRES in the GCRO form).  The first cycle leaves A M^{-1} V_k = V_{k+1} H_k
+// with H_k = Q [R; 0] (Q the product of its Givens rotations), so
+// W = V_{k+1} Q[:, :k] is an orthonormal basis of A U for U = M^{-1} V_k R^{-1}.
+// A later cycle starts from r - W W^H r, orthogonalises every new vector
+// against W as well as its own basis, and its correction is
+// M^{-1} (V_k R^{-1} (W^H r - E z) + V' z), E the W-coefficients of the new
+// vectors, z its least-squares solution.  In V_{k+1} coordinates the
+// projector onto W is s -> s - q (q^H s), q the last column of Q, so both
+// bases are swept in one pass.  With FP32 matvecs the later (refinement)
+// cycles then keep the convergence the first cycle built up instead of
+// starting their Krylov space from scratch.  In FP64 mode the inner matvecs are FP64 and the loop
 // is plain restarted GMRES with a final true-residual check; in FP32 mode the
 // inner matvecs are complex64 (iterative refinement: x += d, r = b - A x in
 // FP64 after every inner solve).
@@ -22,6 +35,8 @@ int rhs_device(mpsl_ctx *ctx, const double *src, void *dev);
 
 class SolveSM {
  public:
+  // smallest room (basis vectors) left for a later cycle to recycle the first
+  static constexpr int kMinCycle = 16;
   enum Status { kRunning = 0, kConverged = 1, kExhausted = 2 };
 
   ~SolveSM();
@@ -41,6 +56,9 @@ class SolveSM {
  private:
   int begin_inner();
   int finish_cycle();
+  void keep_first_cycle();  // record W of the first cycle for the later ones
+  // (Omega s)[:k0] for a V_{k+1}-coordinate vector s (Omega = Q^H)
+  std::vector<zc> w_coords(const std::vector<zc> &s) const;
 
   enum Phase { kInner, kResidual };
   mpsl_ctx *ctx_ = nullptr;
@@ -62,6 +80,13 @@ class SolveSM {
   int inner_mv_ = 0, fp64_mv_ = 0, refin_ = 0;
   bool pc_ = false;     // cluster-block right preconditioner active
   double pc_s_ = 0.0;   // seconds spent building its blocks in init
+  // recycled first-cycle space (k0_ = 0: none); base_ = first vector of the
+  // current cycle's basis in V_
+  int k0_ = 0, base_ = 0, cycles_ = 0;
+  std::vector<zc> R0_, cs0_, sn0_;  // R (k0 x k0, row-major) and rotations of the first cycle
+  std::vector<zc> yC_;              // W^H r of the current cycle
+  std::vector<zc> Cs_;              // V_{k+1} coefficients of the new vectors, [j][k0 + 1]
+  double2 *q_ = nullptr;            // device: last column of Q (k0 + 1)
   std::vector<double> hist_;
 };
 

@@ -45,7 +45,7 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   // the Arnoldi dot products reduce m + 1 rows of partial sums at once
   int rc = dev_alloc(ctx, ctx->scal, dotc_scratch_bytes(m_ + 2));
   if (rc) return rc;
-  const size_t bytes = (static_cast<size_t>(m_ + 1) + 5) * len_ * c + 3 * static_cast<size_t>(m_ + 2) * c +
+  const size_t bytes = (static_cast<size_t>(m_ + 1) + 5) * len_ * c + 4 * static_cast<size_t>(m_ + 2) * c +
                        2 * len_ * sizeof(float2) + 8192;
   rc = dev_alloc(ctx, ctx->gm, bytes);
   if (rc) return rc;
@@ -64,6 +64,7 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   h_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
   h2_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
   nrm_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
+  q_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
   x32_ = reinterpret_cast<float2 *>(take(len_ * sizeof(float2)));
   y32_ = reinterpret_cast<float2 *>(take(len_ * sizeof(float2)));
   if (hh_) (void)hipHostFree(hh_);
@@ -82,6 +83,9 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   }
   status_ = kRunning;
   inner_mv_ = fp64_mv_ = refin_ = 0;
+  k0_ = base_ = cycles_ = 0;
+  R0_.clear();
+  Cs_.clear();
   hist_.clear();
   MPSL_HIP_TRY(ctx, hipMemcpyAsync(b_, b_dev, len_ * c, hipMemcpyDeviceToDevice, ctx->stream));
   MPSL_HIP_TRY(ctx, hipMemsetAsync(xs_, 0, len_ * c, ctx->stream));
@@ -102,18 +106,62 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   return begin_inner();
 }
 
+std::vector<zc> SolveSM::w_coords(const std::vector<zc> &s) const {
+  std::vector<zc> t(s);
+  for (int i = 0; i < k0_; ++i) {  // Omega = G_{k-1} ... G_0
+    const zc a = t[i], b = t[i + 1];
+    t[i] = std::conj(cs0_[i]) * a + std::conj(sn0_[i]) * b;
+    t[i + 1] = -sn0_[i] * a + cs0_[i] * b;
+  }
+  t.resize(k0_);
+  return t;
+}
+
+void SolveSM::keep_first_cycle() {
+  const int k = j_, m = m_;
+  k0_ = k;
+  R0_.assign(static_cast<size_t>(k) * k, zc(0.0, 0.0));
+  for (int a = 0; a < k; ++a)
+    for (int b = a; b < k; ++b) R0_[static_cast<size_t>(a) * k + b] = H_[static_cast<size_t>(a) * m + b];
+  cs0_.assign(cs_.begin(), cs_.begin() + k);
+  sn0_.assign(sn_.begin(), sn_.begin() + k);
+}
+
 int SolveSM::begin_inner() {
+  mpsl_ctx *ctx = ctx_;
+  const size_t c = sizeof(double2);
   inner_abs_ = (o_.precision == MPSL_FP64) ? o_.tol * bn_ : std::max(o_.inner_tol * rn_, 0.5 * o_.tol * bn_);
-  int rc = launch_scale(ctx_, V_, len_, 1.0 / rn_, r_);
-  if (rc) return rc;
+  int rc;
+  double rn = rn_;
+  base_ = k0_ > 0 ? k0_ + 1 : 0;
+  yC_.assign(k0_, zc(0.0, 0.0));
+  Cs_.clear();
+  if (k0_ > 0) {  // r <- (I - W W^H) r (twice), yC = W^H r
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((rc = launch_dotc_multi(ctx, V_, len_, k0_ + 1, r_, len_, h_)) ||
+          (rc = launch_proj_fix(ctx, h_, q_, k0_ + 1)) || (rc = launch_gemv_sub(ctx, V_, len_, k0_ + 1, h_, r_, len_)))
+        return rc;
+      MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_, h_, (k0_ + 1) * c, hipMemcpyDeviceToHost, ctx->stream));
+      MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+      std::vector<zc> sv(k0_ + 1);
+      for (int i = 0; i <= k0_; ++i) sv[i] = zc(hh_[i].x, hh_[i].y);
+      const std::vector<zc> f = w_coords(sv);
+      for (int i = 0; i < k0_; ++i) yC_[i] += f[i];
+    }
+    if ((rc = launch_dotc_multi(ctx, r_, 0, 1, r_, len_, nrm_))) return rc;
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + 2 * (m_ + 2), nrm_, c, hipMemcpyDeviceToHost, ctx->stream));
+    MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    rn = std::sqrt(std::max(hh_[2 * (m_ + 2)].x, 0.0));
+  }
   H_.assign(static_cast<size_t>(m_ + 1) * m_, zc(0.0, 0.0));
   cs_.assign(m_, zc(0.0, 0.0));
   sn_.assign(m_, zc(0.0, 0.0));
   gv_.assign(m_ + 1, zc(0.0, 0.0));
-  gv_[0] = rn_;
+  gv_[0] = rn;
   j_ = 0;
   phase_ = kInner;
-  return MPSL_OK;
+  if (!(rn > 0.0)) return finish_cycle();  // the recycled space already holds the correction
+  return launch_scale(ctx, V_ + base_ * len_, len_, 1.0 / rn, r_);
 }
 
 int SolveSM::launch() {
@@ -122,8 +170,8 @@ int SolveSM::launch() {
   const size_t c = sizeof(double2);
   int rc;
   if (phase_ == kInner) {
-    double2 *vj = V_ + j_ * len_;
-    double2 *vn = V_ + (j_ + 1) * len_;
+    double2 *vj = V_ + (base_ + j_) * len_;
+    double2 *vn = V_ + (base_ + j_ + 1) * len_;
     if (pc_) {  // z = M^{-1} v_j, then A z
       if ((rc = precond_apply(ctx, o_.precision, vj, w_))) return rc;
       vj = w_;
@@ -135,15 +183,17 @@ int SolveSM::launch() {
           (rc = launch_to_fp64(ctx, y32_, vn, len_)))
         return rc;
     }
-    // two passes of classical Gram-Schmidt, then the norm
-    if ((rc = launch_dotc_multi(ctx, V_, len_, j_ + 1, vn, len_, h_)) ||
-        (rc = launch_gemv_sub(ctx, V_, len_, j_ + 1, h_, vn, len_)) ||
-        (rc = launch_dotc_multi(ctx, V_, len_, j_ + 1, vn, len_, h2_)) ||
-        (rc = launch_gemv_sub(ctx, V_, len_, j_ + 1, h2_, vn, len_)) ||
-        (rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_)))
-      return rc;
-    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_, h_, (j_ + 1) * c, hipMemcpyDeviceToHost, ctx->stream));
-    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + (m_ + 2), h2_, (j_ + 1) * c, hipMemcpyDeviceToHost, ctx->stream));
+    // two passes of classical Gram-Schmidt over [V_{k0+1} | this cycle's
+    // basis] (the recycled part projected onto W only), then the norm
+    const int nb = base_ + j_ + 1;
+    for (double2 *h : {h_, h2_}) {
+      if ((rc = launch_dotc_multi(ctx, V_, len_, nb, vn, len_, h))) return rc;
+      if (k0_ > 0 && (rc = launch_proj_fix(ctx, h, q_, k0_ + 1))) return rc;
+      if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h, vn, len_))) return rc;
+    }
+    if ((rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_))) return rc;
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_, h_, nb * c, hipMemcpyDeviceToHost, ctx->stream));
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + (m_ + 2), h2_, nb * c, hipMemcpyDeviceToHost, ctx->stream));
   } else {
     if ((rc = matvec(ctx, MPSL_FP64, xs_, w_)) || (rc = launch_scale(ctx, r_, len_, 1.0, b_)) ||
         (rc = launch_axpy_c(ctx, r_, w_, len_, -1.0, 0.0)) ||
@@ -163,12 +213,15 @@ int SolveSM::complete() {
   if (phase_ == kInner) {
     ++inner_mv_;
     if (o_.precision == MPSL_FP64) ++fp64_mv_;
-    const int j = j_, m = m_;
+    const int j = j_, m = m_, b0 = base_;
     if (!std::isfinite(nn)) return set_err(ctx, MPSL_ENUMERIC, "non-finite Arnoldi norm");
     for (int i = 0; i <= j; ++i)
-      H_[i * m + j] = zc(hh_[i].x + hh_[m + 2 + i].x, hh_[i].y + hh_[m + 2 + i].y);
+      H_[i * m + j] = zc(hh_[b0 + i].x + hh_[m + 2 + b0 + i].x, hh_[b0 + i].y + hh_[m + 2 + b0 + i].y);
+    for (int i = 0; b0 > 0 && i <= k0_; ++i)  // coefficients on V_{k0+1} (projected onto W)
+      Cs_.push_back(zc(hh_[i].x + hh_[m + 2 + i].x, hh_[i].y + hh_[m + 2 + i].y));
     H_[(j + 1) * m + j] = nn;
-    if (nn > 0.0 && (rc = launch_scale(ctx, V_ + (j + 1) * len_, len_, 1.0 / nn, V_ + (j + 1) * len_))) return rc;
+    double2 *vn = V_ + (b0 + j + 1) * len_;
+    if (nn > 0.0 && (rc = launch_scale(ctx, vn, len_, 1.0 / nn, vn))) return rc;
     for (int i = 0; i < j; ++i) {  // previous rotations, then a new one
       const zc a = H_[i * m + j], b = H_[(i + 1) * m + j];
       H_[i * m + j] = std::conj(cs_[i]) * a + std::conj(sn_[i]) * b;
@@ -190,7 +243,7 @@ int SolveSM::complete() {
     const double res = std::abs(gv_[j + 1]);
     hist_.push_back(res / bn_);
     j_ = j + 1;
-    if (res < inner_abs_ || j_ == m_ || nn == 0.0 || inner_mv_ >= o_.maxiter) return finish_cycle();
+    if (res < inner_abs_ || j_ == m_ - base_ || nn == 0.0 || inner_mv_ >= o_.maxiter) return finish_cycle();
     return MPSL_OK;
   }
   // residual phase
@@ -218,18 +271,49 @@ int SolveSM::finish_cycle() {
     for (int k = i + 1; k < j; ++k) s -= H_[i * m + k] * y[k];
     y[i] = s / H_[i * m + i];
   }
+  // coefficients of the correction over V_[0 .. base_ + j): with a recycled
+  // first cycle, V_k R^{-1} (yC - E z) on its k0 vectors (E z = (Omega sum Cs_i y_i)[:k0])
+  const int nb = base_ + j;
+  std::vector<zc> coef(nb, zc(0.0, 0.0));
+  if (base_ > 0) {
+    const int k = k0_;
+    std::vector<zc> e(k + 1, zc(0.0, 0.0));
+    for (int i = 0; i < j; ++i)
+      for (int t = 0; t <= k; ++t) e[t] += Cs_[static_cast<size_t>(i) * (k + 1) + t] * y[i];
+    const std::vector<zc> f = w_coords(e);
+    for (int a = k - 1; a >= 0; --a) {
+      zc s = yC_[a] - f[a];
+      for (int bb = a + 1; bb < k; ++bb) s -= R0_[static_cast<size_t>(a) * k + bb] * coef[bb];
+      coef[a] = s / R0_[static_cast<size_t>(a) * k + a];
+    }
+  }
+  for (int i = 0; i < j; ++i) coef[base_ + i] = y[i];
   double2 *hy = hh_ + 2 * (m_ + 2) + 1;  // pinned, separate from the D2H staging
-  for (int i = 0; i < j; ++i) hy[i] = make_double2(-y[i].real(), -y[i].imag());
-  MPSL_HIP_TRY(ctx, hipMemcpyAsync(h_, hy, j * sizeof(double2), hipMemcpyHostToDevice, ctx->stream));
+  for (int i = 0; i < nb; ++i) hy[i] = make_double2(-coef[i].real(), -coef[i].imag());
+  MPSL_HIP_TRY(ctx, hipMemcpyAsync(h_, hy, nb * sizeof(double2), hipMemcpyHostToDevice, ctx->stream));
   MPSL_HIP_TRY(ctx, hipMemsetAsync(d_, 0, len_ * sizeof(double2), ctx->stream));
   int rc;
-  if ((rc = launch_gemv_sub(ctx, V_, len_, j, h_, d_, len_))) return rc;  // d = V y
+  if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h_, d_, len_))) return rc;  // d = V coef
   if (pc_) {  // the correction is M^{-1} V y
     if ((rc = precond_apply(ctx, o_.precision, d_, w_)) || (rc = launch_axpy_c(ctx, xs_, w_, len_, 1.0, 0.0)))
       return rc;
   } else if ((rc = launch_axpy_c(ctx, xs_, d_, len_, 1.0, 0.0))) {
     return rc;
   }
+  // the first cycle's space is kept for the later ones while the basis has room
+  if (cycles_ == 0 && j >= 1 && m_ - (j + 1) >= kMinCycle && inner_mv_ < o_.maxiter) {
+    keep_first_cycle();
+    std::vector<zc> qv(k0_ + 1, zc(0.0, 0.0));  // q = Omega^H e_k
+    qv[k0_] = 1.0;
+    for (int i = k0_ - 1; i >= 0; --i) {
+      const zc a = qv[i], b = qv[i + 1];
+      qv[i] = cs0_[i] * a - std::conj(sn0_[i]) * b;
+      qv[i + 1] = sn0_[i] * a + std::conj(cs0_[i]) * b;
+    }
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(q_, qv.data(), (k0_ + 1) * sizeof(double2), hipMemcpyHostToDevice, ctx->stream));
+    MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  ++cycles_;
   ++refin_;
   phase_ = kResidual;
   return MPSL_OK;
