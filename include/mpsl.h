@@ -293,6 +293,20 @@ void mpsl_batch_destroy(mpsl_batch *batch);
  * beta_dev, alpha_dev: N*P complex in precision prec; alpha is overwritten. */
 int mpsl_m2l_dev(mpsl_ctx *ctx, int prec, const void *beta_dev, void *alpha_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the M2L of
+ * mpsl_m2l_dev, with the same arguments and result, that allocates nothing.
+ * Its partial expansions live in a fixed 64 MiB device array of the library
+ * (one per device, held until the process ends), so N P times 16 bytes
+ * (FP64) or 8 bytes (FP32) must fit in 64 MiB (MPSL_EINVAL otherwise); the
+ * number of source chunks is the default one capped by that room.  The
+ * context's tables must already exist (MPSL_ESTATE until a call such as
+ * mpsl_m2l_dev or mpsl_apply_dev has built them) and the far field must be
+ * direct (MPSL_EUNSUPPORTED with the FMM active).  All calls on one device
+ * share the array: calls that overlap in time on one device (other streams,
+ * other host threads or contexts) race and must be serialised by the caller. */
+int mpsl_m2l_dev_noalloc(mpsl_ctx *ctx, int prec, const void *beta_dev, void *alpha_dev);
+
 /* Row b1, multipole-to-Sommerfeld (Theorem 5.1, factor as derived from the
  * Sommerfeld form (3) of H_0): P+/P- spectra of all multipoles on y = 0 and
  * y = -d, reduced over particles:

@@ -307,6 +307,10 @@ class Context:
     def m2l_dev(self, prec, beta, alpha):
         return self._check(self.lib.mpsl_m2l_dev(self.h, int(prec), _ptr(beta), _ptr(alpha)))
 
+    def m2l_dev_noalloc(self, prec, beta, alpha):
+        """mpsl_m2l_dev without device allocation (fixed 64 MiB library scratch)."""
+        return self._check(self.lib.mpsl_m2l_dev_noalloc(self.h, int(prec), _ptr(beta), _ptr(alpha)))
+
     def m2s_dev(self, prec, beta, spec):
         return self._check(self.lib.mpsl_m2s_dev(self.h, int(prec), _ptr(beta), _ptr(spec)))
 

@@ -70,6 +70,7 @@ SIGNATURES = {
     "mpsl_batch_launch": (I, [P, P]),
     "mpsl_batch_destroy": (None, [P]),
     "mpsl_m2l_dev": (I, [P, I, P, P]),
+    "mpsl_m2l_dev_noalloc": (I, [P, I, P, P]),
     "mpsl_m2s_dev": (I, [P, I, P, P]),
     "mpsl_reflect_dev": (I, [P, P, P, P]),
     "mpsl_s2l_dev": (I, [P, I, P, P]),

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <set>
 
@@ -532,6 +533,40 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y) { return matvec(ctx,
 
 }  // namespace mpsl
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free M2L (mpsl_m2l_dev_noalloc): the
+// partial local expansions of its source chunks.  Each device holds its own
+// copy for the life of the process; host code uses only the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in there).
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;  // 64 MiB
+static __device__ __align__(256) double2 scratch[kScratchBytes / sizeof(double2)];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+// Look the array up once per device, with that device current.
+int scratch_setup(int device) {
+  if (device < 0 || device >= kScratchDevices) return MPSL_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return MPSL_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return MPSL_EHIP;
+  }
+  g_scratch_ptr[device] = p;
+  return MPSL_OK;
+}
+
+void *scratch_ptr(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 // ===========================================================================
 extern "C" {
 
@@ -563,6 +598,7 @@ int mpsl_create(mpsl_ctx **out, int device) {
   }
   if (device < 0 || device >= cnt) return MPSL_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return MPSL_EHIP;
+  if (const int rc = scratch_setup(device)) return rc;
   mpsl_ctx *ctx = new (std::nothrow) mpsl_ctx();
   if (!ctx) return MPSL_ENOMEM;
   ctx->device = device;
@@ -981,6 +1017,34 @@ int mpsl_m2l_dev(mpsl_ctx *ctx, int prec, const void *beta, void *alpha) {
     return rc;
   }
   return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, ca, alpha);
+}
+
+int mpsl_m2l_dev_noalloc(mpsl_ctx *ctx, int prec, const void *beta, void *alpha) {
+  if (!ctx || !beta || !alpha || (prec != MPSL_FP64 && prec != MPSL_FP32)) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if (!ctx->has_layers || !ctx->has_particle || !ctx->has_geom)
+    return mpsl::set_err(ctx, MPSL_ESTATE, "layers, particle and geometry first");
+  const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
+  const size_t slot = static_cast<size_t>(ctx->n) * (2 * ctx->p + 1) * esz;
+  if (slot > kScratchBytes)
+    return mpsl::set_err(ctx, MPSL_EINVAL,
+                         "N P = " + std::to_string(ctx->n * (2 * ctx->p + 1)) + " needs " + std::to_string(slot) +
+                             " bytes per partial expansion, above the " + std::to_string(kScratchBytes) +
+                             "-byte scratch of the allocation-free M2L");
+  if (!ctx->tables_ok || !ctx->gt.pairs_ok)
+    return mpsl::set_err(ctx, MPSL_ESTATE, "tables not built: call mpsl_m2l_dev or mpsl_apply_dev once first");
+  if (ctx->fmm.active)
+    return mpsl::set_err(ctx, MPSL_EUNSUPPORTED, "the allocation-free M2L is the direct all-pairs form (FMM active)");
+  void *scr = scratch_ptr(ctx->device);
+  if (!scr) return mpsl::set_err(ctx, MPSL_ESTATE, "device scratch not set up");
+  // as many source chunks as the default launch shape asks for, while their
+  // partial slots fit; every slot is written in full by the M2L (empty
+  // chunks write zeros), so nothing needs clearing
+  const int ca = static_cast<int>(std::max<size_t>(
+      1, std::min<size_t>(static_cast<size_t>(mpsl::chunks_m2l(ctx, prec)), kScratchBytes / slot)));
+  int rc;
+  if ((rc = mpsl::launch_m2l(ctx, prec, beta, scr, ca))) return rc;
+  return mpsl::launch_sum_parts(ctx, prec, scr, ca, alpha);
 }
 
 int mpsl_m2s_dev(mpsl_ctx *ctx, int prec, const void *beta, void *spec) {
