@@ -370,9 +370,10 @@ typedef struct {
  * (I - S (T + T_R)) M^{-1} u = S a with M = blockdiag_c K_c, returning
  * beta = M^{-1} u.  This is right preconditioning: the solution and the
  * residual reported are those of eq. (49).  MPSL_FP32 solves apply an FP32
- * copy of the blocks (FP64 arithmetic).  The blocks are built at the first
- * solve or apply after a change of particle, layers or geometry: device
- * memory n_clusters m^2 16 bytes (and half that again for the FP32 copy),
+ * copy of the blocks (FP64 arithmetic) and release the FP64 blocks once the
+ * copy is made (an FP64 solve afterwards builds them again).  The blocks are
+ * built at the first solve or apply after a change of particle, layers or
+ * geometry: device memory n_clusters m^2 16 bytes (FP64) or 8 bytes (FP32),
  * m = 64 ceil(largest cluster * P / 64), at most 16384 (MPSL_EINVAL above).
  * A block whose inversion meets a zero pivot or a non-finite value is
  * replaced by the identity (counted by mpsl_get_precond_info).
@@ -485,7 +486,22 @@ int mpsl_profile_read(mpsl_ctx *ctx, double *m2l_ms_avg, int *count);
 
 enum { MPSL_PARTICLE_DISK = 0, MPSL_PARTICLE_STAR = 1, MPSL_PARTICLE_MATRIX = 2 };
 
-/* One self-contained solve request (the library copies every array). */
+/* Contour rule of a request: MPSL_CONTOUR_COUNT as mpsl_set_contour
+ * (n_nodes, b, t_max); MPSL_CONTOUR_SPAN as mpsl_set_contour_span
+ * (b, t_max, h_max). */
+enum { MPSL_CONTOUR_COUNT = 0, MPSL_CONTOUR_SPAN = 1 };
+
+/* Host, no device: the span-rule parameters the comment of
+ * mpsl_set_contour_span recommends for a layout of lateral extent x_extent
+ * (particles and sources; values below 1 count as 1):
+ * b = min(0.2, 2 / X), h_max = 6 / X for tol <= 1e-8 (about 1e-11 on the
+ * layered interaction of two particles X apart), else 12 / X (about 1e-6).
+ * MPSL_EINVAL for non-finite or non-positive arguments. */
+int mpsl_span_contour_params(double x_extent, double tol, double *b, double *h_max);
+
+/* One self-contained solve request (the library copies every array).  A
+ * zero-filled tail (contour .. cluster_size) selects the count-rule contour,
+ * direct Sommerfeld sums and no cluster preconditioner. */
 typedef struct {
   mpsl_c128 k1, k2, k3;    /* layer wavenumbers (see mpsl_set_layers)          */
   double d;                /* middle-layer thickness                           */
@@ -503,6 +519,11 @@ typedef struct {
   double b, t_max;         /* contour offset and truncation                    */
   double src[2];           /* point source in layer 1                          */
   mpsl_opts opts;          /* precision, tol, maxiter, restart, inner_tol      */
+  int contour;             /* MPSL_CONTOUR_COUNT or MPSL_CONTOUR_SPAN          */
+  double h_max;            /* MPSL_CONTOUR_SPAN: longest panel                 */
+  int sommerfeld;          /* MPSL_SOMM_DIRECT or MPSL_SOMM_INTERP             */
+  int precond;             /* MPSL_PRECOND_NONE or MPSL_PRECOND_CLUSTER        */
+  int cluster_size;        /* MPSL_PRECOND_CLUSTER: largest cluster (0: 160)   */
 } mpsl_request;
 
 typedef struct {
@@ -517,6 +538,8 @@ typedef struct {
                                  queued, admitted (memory reserved), prepared,
                                  finished                                      */
   size_t hbm_bytes;           /* device memory reserved for the request        */
+  const char *error;          /* message of a failed request ("" otherwise),
+                                 owned by the server until mpsl_server_release */
 } mpsl_result;
 
 typedef struct mpsl_server mpsl_server;

@@ -111,10 +111,13 @@ def compute_clusters(xy, cluster_size):
 
 
 def span_contour_params(x_extent, tol=1e-10):
-    """(b, h_max) of the span rule for a layout of lateral extent x_extent:
-    b = min(0.2, 2 / X), h_max = 6 / X for tol <= 1e-8, else 12 / X."""
-    X = max(float(x_extent), 1.0)
-    return min(0.2, 2.0 / X), (6.0 if tol <= 1e-8 else 12.0) / X
+    """(b, h_max) of the span rule for a layout of lateral extent x_extent
+    (mirrors mpsl_span_contour_params)."""
+    lib = _lib.load()
+    b, h = ctypes.c_double(), ctypes.c_double()
+    _host_check(lib.mpsl_span_contour_params(float(x_extent), float(tol), ctypes.byref(b), ctypes.byref(h)),
+                "span contour parameters")
+    return b.value, h.value
 
 
 def compute_layer_map(ks, thickness, particle_layer, lam, polarization=TM):
@@ -425,8 +428,10 @@ class Server:
         self._keep = {}
 
     def submit(self, k, d, particle, shape, kp, p, xy, rot, n_nodes, b, t_max, src, precision=FP64, tol=1e-10,
-               maxiter=500, restart=0, inner_tol=0.0, S=None, r_enclose=0.0, n_bdry=0):
-        """Queue one request; returns its ticket (arrays are copied by the library)."""
+               maxiter=500, restart=0, inner_tol=0.0, S=None, r_enclose=0.0, n_bdry=0, contour=0, h_max=0.0,
+               sommerfeld=SOMM_DIRECT, precond=PRECOND_NONE, cluster_size=0):
+        """Queue one request; returns its ticket (arrays are copied by the library).
+        contour 0 = count rule (n_nodes, b, t_max), 1 = span rule (b, t_max, h_max)."""
         xy = np.ascontiguousarray(xy, dtype=np.float64)
         rot = None if rot is None else np.ascontiguousarray(rot, dtype=np.float64)
         Sa = None if S is None else _carr(S)
@@ -447,6 +452,8 @@ class Server:
         r.n_nodes, r.b, r.t_max = int(n_nodes), float(b), float(t_max)
         r.src[0], r.src[1] = float(src[0]), float(src[1])
         r.opts = _lib.Opts(int(precision), float(tol), int(maxiter), int(restart), float(inner_tol))
+        r.contour, r.h_max, r.sommerfeld = int(contour), float(h_max), int(sommerfeld)
+        r.precond, r.cluster_size = int(precond), int(cluster_size)
         t = ctypes.c_uint64()
         rc = self.lib.mpsl_server_submit(self.h, ctypes.byref(r), ctypes.byref(t))
         if rc != 0:
@@ -457,7 +464,8 @@ class Server:
     def _result(res):
         out = dict(status=res.status, iterations=res.iterations, fp64_matvecs=res.fp64_matvecs,
                    refinements=res.refinements, rel_residual=res.rel_residual, t_submit=res.t_submit,
-                   t_admit=res.t_admit, t_start=res.t_start, t_finish=res.t_finish, hbm_bytes=res.hbm_bytes)
+                   t_admit=res.t_admit, t_start=res.t_start, t_finish=res.t_finish, hbm_bytes=res.hbm_bytes,
+                   error=(res.error or b"").decode(errors="replace"))
         if res.beta:
             P = 2 * res.p + 1
             arr = np.ctypeslib.as_array(ctypes.cast(res.beta, ctypes.POINTER(ctypes.c_double)),

@@ -57,6 +57,7 @@ SIGNATURES = {
     "mpsl_compute_contour": (I, [c128, c128, c128, I, D, D, P, P]),
     "mpsl_set_contour_span": (I, [P, D, D, D]),
     "mpsl_set_sommerfeld_method": (I, [P, I]),
+    "mpsl_span_contour_params": (I, [D, D, DP, DP]),
     "mpsl_compute_contour_span": (I, [I, P, D, D, D, I, P, P, P]),
     "mpsl_set_contour_nodes": (I, [P, I, P, P]),
     "mpsl_get_contour": (I, [P, I, P, P]),
@@ -136,7 +137,8 @@ class Request(ctypes.Structure):
                 ("S", ctypes.c_void_p), ("r_enclose", ctypes.c_double), ("n", ctypes.c_int64),
                 ("xy", ctypes.c_void_p), ("rot", ctypes.c_void_p), ("n_nodes", ctypes.c_int),
                 ("b", ctypes.c_double), ("t_max", ctypes.c_double), ("src", ctypes.c_double * 2),
-                ("opts", Opts)]
+                ("opts", Opts), ("contour", ctypes.c_int), ("h_max", ctypes.c_double), ("sommerfeld", ctypes.c_int),
+                ("precond", ctypes.c_int), ("cluster_size", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -144,7 +146,7 @@ class Result(ctypes.Structure):
                 ("beta", ctypes.POINTER(c128)), ("iterations", ctypes.c_int), ("fp64_matvecs", ctypes.c_int),
                 ("refinements", ctypes.c_int), ("rel_residual", ctypes.c_double), ("t_submit", ctypes.c_double),
                 ("t_admit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_finish", ctypes.c_double),
-                ("hbm_bytes", ctypes.c_size_t)]
+                ("hbm_bytes", ctypes.c_size_t), ("error", ctypes.c_char_p)]
 
 
 SIGNATURES.update({

@@ -907,6 +907,14 @@ int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max) {
   return MPSL_OK;
 }
 
+int mpsl_span_contour_params(double x_extent, double tol, double *b, double *h_max) {
+  if (!b || !h_max || !std::isfinite(x_extent) || !(tol > 0.0) || !std::isfinite(tol)) return MPSL_EINVAL;
+  const double X = std::max(x_extent, 1.0);
+  *b = std::min(0.2, 2.0 / X);
+  *h_max = (tol <= 1e-8 ? 6.0 : 12.0) / X;
+  return MPSL_OK;
+}
+
 int mpsl_set_sommerfeld_method(mpsl_ctx *ctx, int method) {
   if (!ctx) return MPSL_EINVAL;
   if (const int pe = mpsl::check_unpinned(ctx)) return pe;

@@ -256,6 +256,8 @@ int build_tables(mpsl_ctx *ctx);
 // copy for prec == MPSL_FP32) and apply y = M^{-1} x on FP64 device vectors.
 int precond_build(mpsl_ctx *ctx, int prec);
 int precond_apply(mpsl_ctx *ctx, int prec, const void *x, void *y);
+// Clusters of the bisection rule for n centres: count and largest size.
+int cluster_shape(int64_t n, const double *xy, int size, int *nc, int *mp);
 constexpr int kPcDefaultSize = 160;
 constexpr int kPcMaxDim = 16384;
 int ensure_work(mpsl_ctx *ctx);

@@ -507,12 +507,12 @@ __global__ void k_pc_apply_sum(const double2 *__restrict__ part, const int32_t *
 // Build the FP64 blocks (and the FP32 copy when prec is MPSL_FP32).
 int precond_build(mpsl_ctx *ctx, int prec) {
   if (ctx->pc_kind != MPSL_PRECOND_CLUSTER) return MPSL_OK;
+  if (prec == MPSL_FP32 ? ctx->pc_ok32 : ctx->pc_ok) return MPSL_OK;
   int rc = build_tables(ctx);
   if (rc) return rc;
   const auto t0 = std::chrono::steady_clock::now();
   const int P = 2 * ctx->p + 1;
   if (!ctx->pc_ok) {
-    ctx->pc_ok32 = false;
     std::vector<int64_t> idx;
     std::vector<std::pair<size_t, size_t>> ranges;
     make_clusters(ctx->n, ctx->xy.data(), ctx->pc_size, idx, ranges);
@@ -586,12 +586,17 @@ int precond_build(mpsl_ctx *ctx, int prec) {
     ctx->pc_replaced = replaced;
     ctx->pc_ok = true;
   }
-  if (prec == MPSL_FP32 && !ctx->pc_ok32) {
+  if (prec == MPSL_FP32) {
+    // the mixed-precision solve applies only the FP32 copy: the FP64 blocks
+    // are released (an FP64 solve on this context rebuilds them)
     const size_t len = static_cast<size_t>(ctx->pc_nc) * ctx->pc_m * ctx->pc_m;
     if ((rc = dev_alloc(ctx, ctx->pc_blk32, len * sizeof(float2)))) return rc;
     hipLaunchKernelGGL(k_pc_to32, dim3(4096), dim3(256), 0, ctx->stream, static_cast<const double2 *>(ctx->pc_blk.p),
                        static_cast<float2 *>(ctx->pc_blk32.p), static_cast<int64_t>(len));
     PC_CHECK(ctx);
+    MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    dev_free(ctx->pc_blk);
+    ctx->pc_ok = false;
     ctx->pc_ok32 = true;
   }
   MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -599,10 +604,22 @@ int precond_build(mpsl_ctx *ctx, int prec) {
   return MPSL_OK;
 }
 
+int cluster_shape(int64_t n, const double *xy, int size, int *nc, int *mp) {
+  if (n <= 0 || !xy || size < 1) return MPSL_EINVAL;
+  std::vector<int64_t> idx;
+  std::vector<std::pair<size_t, size_t>> ranges;
+  make_clusters(n, xy, size, idx, ranges);
+  int big = 0;
+  for (auto &r : ranges) big = std::max(big, static_cast<int>(r.second - r.first));
+  *nc = static_cast<int>(ranges.size());
+  *mp = big;
+  return MPSL_OK;
+}
+
 // y = M^{-1} x on FP64 vectors (device, N P entries), with the blocks of
 // precision prec.  x and y must not overlap.
 int precond_apply(mpsl_ctx *ctx, int prec, const void *x, void *y) {
-  if (!ctx->pc_ok || (prec == MPSL_FP32 && !ctx->pc_ok32))
+  if (prec == MPSL_FP32 ? !ctx->pc_ok32 : !ctx->pc_ok)
     return set_err(ctx, MPSL_ESTATE, "preconditioner blocks not built");
   const int P = 2 * ctx->p + 1;
   const int nc = ctx->pc_nc, mp = ctx->pc_mp, m = ctx->pc_m;
@@ -674,7 +691,7 @@ int mpsl_precond_apply_dev(mpsl_ctx *ctx, int prec, const void *x_dev, void *y_d
 int mpsl_get_precond_info(const mpsl_ctx *ctx, int *n_clusters, int *max_cluster, int *block_dim, int *replaced,
                           double *setup_seconds) {
   if (!ctx) return MPSL_EINVAL;
-  const bool ok = ctx->pc_kind == MPSL_PRECOND_CLUSTER && ctx->pc_ok;
+  const bool ok = ctx->pc_kind == MPSL_PRECOND_CLUSTER && (ctx->pc_ok || ctx->pc_ok32);
   if (n_clusters) *n_clusters = ok ? ctx->pc_nc : 0;
   if (max_cluster) *max_cluster = ok ? ctx->pc_mp : 0;
   if (block_dim) *block_dim = ok ? ctx->pc_m : 0;

@@ -45,22 +45,41 @@ struct Job {
   double rel_res = 0.0;
 };
 
+// Contour node count of a request (host rule of the library).
+size_t request_nodes(const mpsl_request &r) {
+  if (r.contour != MPSL_CONTOUR_SPAN) return static_cast<size_t>(r.n_nodes);
+  const double re[3] = {r.k1.re, r.k2.re, r.k3.re};
+  int ns = 0;
+  if (mpsl_compute_contour_span(3, re, r.b, r.t_max, r.h_max, 0, nullptr, nullptr, &ns) != MPSL_OK) return 0;
+  return static_cast<size_t>(ns);
+}
+
 size_t estimate_bytes(const mpsl_request &r) {
   const size_t n = static_cast<size_t>(r.n), P = 2 * static_cast<size_t>(r.p) + 1;
-  const size_t ns = static_cast<size_t>(r.n_nodes);
+  const size_t ns = request_nodes(r);
   const int maxit = r.opts.maxiter > 0 ? r.opts.maxiter : 500;
-  const size_t m = static_cast<size_t>(std::min(1000, (r.opts.restart > 0 && r.opts.restart < maxit) ? r.opts.restart
-                                                                                                       : maxit));
+  const size_t m = static_cast<size_t>((r.opts.restart > 0 && r.opts.restart < maxit) ? r.opts.restart : maxit);
   const size_t tb = (n + 127) / 128;
   const size_t ca = std::min(n, (2560 + tb - 1) / tb), cb = std::max<size_t>(1, std::min(ns / 8, (1024 + tb - 1) / tb));
   // far field: all-pairs tables, or the FMM (default above 8000 particles)
   // with its neighbour lists, per-particle shift rows and box expansions
   size_t b = n > 8000 ? 32768 * n + (64 << 20) : 96 * n * n;
-  b += 2 * 2 * n * ns * 24;                    // plane-wave factors E, F, both precisions
+  if (r.sommerfeld == MPSL_SOMM_INTERP)
+    b += ns * 24 * 8 + 2 * ns * 16 + n * 64 * P;  // interpolation weights, node maps, tile sums
+  else
+    b += 2 * 2 * n * ns * 24;                  // plane-wave factors E, F, both precisions
   b += n * P * 24 + ns * P * 128;              // rotation phases, per-node tables
   b += (2 * ca + cb) * n * P * 16;             // partial local expansions (tuning headroom)
   b += (m + 6) * n * P * 16 + 2 * n * P * 8;   // Krylov basis and solver vectors
-  b += 4 * n * P * 16 + (64 << 10) * 16;       // staging and reduction scratch
+  b += 4 * n * P * 16 + (m + 2) * 64 * 16;     // staging and reduction scratch
+  if (r.precond == MPSL_PRECOND_CLUSTER && r.xy) {  // inverse cluster blocks (FP64 while built)
+    const int size = r.cluster_size > 0 ? r.cluster_size : mpsl::kPcDefaultSize;
+    int nc = 0, mp = 0;
+    if (mpsl::cluster_shape(r.n, r.xy, size, &nc, &mp) == MPSL_OK) {
+      const size_t mb = (static_cast<size_t>(mp) * P + 63) / 64 * 64;
+      b += static_cast<size_t>(nc) * mb * mb * (r.opts.precision == MPSL_FP32 ? 24 : 16);
+    }
+  }
   return b;
 }
 
@@ -103,8 +122,13 @@ int setup_job(mpsl_server *s, Job &j) {
   else
     rc = mpsl_set_scattering_matrix(j.ctx, r.p, r.r_enclose, j.S.data());
   if (rc) return rc;
-  if ((rc = mpsl_set_geometry(j.ctx, r.n, j.xy.data(), j.rot.empty() ? nullptr : j.rot.data())) ||
-      (rc = mpsl_set_contour(j.ctx, r.n_nodes, r.b, r.t_max)))
+  if ((rc = mpsl_set_sommerfeld_method(j.ctx, r.sommerfeld)) ||
+      (rc = mpsl_set_geometry(j.ctx, r.n, j.xy.data(), j.rot.empty() ? nullptr : j.rot.data())))
+    return rc;
+  rc = r.contour == MPSL_CONTOUR_SPAN ? mpsl_set_contour_span(j.ctx, r.b, r.t_max, r.h_max)
+                                      : mpsl_set_contour(j.ctx, r.n_nodes, r.b, r.t_max);
+  if (rc) return rc;
+  if (r.precond == MPSL_PRECOND_CLUSTER && (rc = mpsl_set_preconditioner(j.ctx, r.precond, r.cluster_size)))
     return rc;
   if ((rc = mpsl::build_tables(j.ctx))) return rc;
   const int64_t len = r.n * static_cast<int64_t>(2 * r.p + 1);
@@ -273,7 +297,12 @@ int mpsl_server_create(mpsl_server **out, int device, size_t hbm_budget, int max
 }
 
 int mpsl_server_submit(mpsl_server *s, const mpsl_request *r, uint64_t *ticket) {
-  if (!s || !r || !ticket || !r->xy || r->n <= 0 || r->p < mpsl::kMinP || r->p > mpsl::kMaxP || r->n_nodes <= 0)
+  if (!s || !r || !ticket || !r->xy || r->n <= 0 || r->p < mpsl::kMinP || r->p > mpsl::kMaxP)
+    return MPSL_EINVAL;
+  if ((r->contour != MPSL_CONTOUR_COUNT && r->contour != MPSL_CONTOUR_SPAN) ||
+      (r->contour == MPSL_CONTOUR_COUNT && r->n_nodes <= 0) || (r->contour == MPSL_CONTOUR_SPAN && !(r->h_max > 0.0)) ||
+      (r->sommerfeld != MPSL_SOMM_DIRECT && r->sommerfeld != MPSL_SOMM_INTERP) ||
+      (r->precond != MPSL_PRECOND_NONE && r->precond != MPSL_PRECOND_CLUSTER) || r->cluster_size < 0)
     return MPSL_EINVAL;
   if (r->particle == MPSL_PARTICLE_MATRIX && !r->S) return MPSL_EINVAL;
   auto j = std::make_shared<Job>();
@@ -303,6 +332,7 @@ int mpsl_server_submit(mpsl_server *s, const mpsl_request *r, uint64_t *ticket) 
 
 static void fill_result(const Job &j, mpsl_result *res) {
   res->status = j.status;
+  res->error = j.err.c_str();
   res->n = j.req.n;
   res->p = j.req.p;
   res->beta = j.beta.empty() ? nullptr : j.beta.data();

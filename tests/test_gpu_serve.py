@@ -90,3 +90,43 @@ def test_admission_respects_budget_and_errors_are_reported():
     out = _wait(srv, srv.submit(**bad))
     assert out["status"] == -5 and "beta" not in out
     srv.close()
+
+
+def test_span_contour_and_preconditioner_requests():
+    """Requests on a span-rule contour with the interpolated Sommerfeld sums
+    and the cluster preconditioner: bitwise the library's own solve with the
+    same settings, alone and in a mix with plain requests, and the oracle's
+    LU solution of the same discrete system (star layout, both precisions)."""
+    import paper_1407_3868_amd as mp
+    wl = make_workload("s150p12")
+    X = float(wl.xy[:, 0].max() - wl.xy[:, 0].min())
+    b, h = mp.span_contour_params(X, 1e-10)
+    assert (b, h) == (min(0.2, 2.0 / X), 6.0 / X)
+    extra = dict(contour=1, n_nodes=0, b=b, t_max=24.0, h_max=h, sommerfeld=mp.SOMM_INTERP,
+                 precond=mp.PRECOND_CLUSTER, cluster_size=40)
+    reqs = [dict(_req(wl, tol=1e-11, maxiter=1500), **extra), dict(_req(wl, precision=1, tol=1e-9), **extra),
+            _req(make_workload("c1"))]
+    srv = mp.Server(0, hbm_budget=64 << 30, max_active=1)
+    alone = [_wait(srv, srv.submit(**r)) for r in reqs]
+    srv.close()
+    srv = mp.Server(0, hbm_budget=64 << 30, max_active=8)
+    mix = [_wait(srv, t) for t in [srv.submit(**r) for r in reqs]]
+    srv.close()
+    for a, m in zip(alone, mix):
+        assert a["status"] == 0 and m["status"] == 0, (a["error"], m["error"])
+        assert np.array_equal(a["beta"], m["beta"])
+    ctx = mp.Context(0)
+    ctx.set_sommerfeld_method(mp.SOMM_INTERP)
+    ctx.set_layers(wl.k1, wl.k2, wl.k3, wl.d)
+    ctx.set_scattering_matrix(wl.p, wl.r_enclose, prototype_S(wl))
+    ctx.set_geometry(wl.xy, wl.rot)
+    ctx.set_contour_span(b, 24.0, h)
+    ctx.set_preconditioner(mp.PRECOND_CLUSTER, 40)
+    beta, meta = ctx.solve(wl.src[0], precision=0, tol=1e-11, maxiter=1500)
+    assert np.array_equal(beta, mix[0]["beta"])
+    from oracle import system as osys
+    lam, w = ctx.get_contour()
+    pr = osys.Problem(wl.k1, wl.k2, wl.k3, wl.d, wl.p, prototype_S(wl), wl.xy, wl.rot, lam, w)
+    ref = pr.solve_lu(wl.src[0])
+    assert rel_err(mix[0]["beta"], ref) < 1e-8
+    assert rel_err(mix[1]["beta"], ref) < 1e-6
