@@ -498,7 +498,22 @@ __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__rest
 // epilogue (a reduction over the 16 lanes that hold one node's orders).  One
 // wave per 16 nodes; lane i supplies A[i % 16][i / 16] = E of node q0 + i % 16
 // for particle m0 + i / 16 (16 consecutive nodes: coalesced) and
-// B[i / 16][i % 16] = beta of that particle and order.
+// B[i / 16][i % 16] = beta of that particle and order.  Complex products take
+// three real MFMAs (Gauss: P1 = sum Ar Br, P2 = sum Ai Bi, P3 = sum (Ar + Ai)
+// (Br + Bi); re = P1 - P2, im = P3 - P1 - P2).
+//
+// Orders on the matrix cores and on the vector units: full 16-order tiles go
+// to the MFMAs; a remainder of one or two orders (p = 16: 33 = 2 x 16 + 1,
+// p = 8: 17 = 16 + 1) is accumulated on the vector units instead of a tile of
+// which it would fill at most 2/16; a longer remainder gets a padded tile.
+template <int P> struct OrderSplit {
+  static constexpr int NF = P / 16;
+  static constexpr int REM = P - 16 * NF;
+  static constexpr bool VALU_REM = REM > 0 && REM <= 2;
+  static constexpr int NT = VALU_REM ? NF : (P + 15) / 16;  // MFMA tiles
+  static constexpr int NV = VALU_REM ? REM : 0;             // vector-unit orders, slots 16 NT ..
+};
+
 constexpr int kM2sWaves = 4;
 template <typename T, int p>
 __global__ __launch_bounds__(64 * kM2sWaves) void k_m2s_mfma(const cv_t<T> *__restrict__ E,
@@ -507,7 +522,8 @@ __global__ __launch_bounds__(64 * kM2sWaves) void k_m2s_mfma(const cv_t<T> *__re
                                                              cv_t<T> *__restrict__ part, int n, int ns,
                                                              int chunk_len, int chunks) {
   constexpr int P = 2 * p + 1;
-  constexpr int NT = (P + 15) / 16;  // order tiles
+  constexpr int NT = OrderSplit<P>::NT, NV = OrderSplit<P>::NV;
+  typedef typename mfma4<T>::v4 v4;
   const int c = blockIdx.y;
   const int s = blockIdx.z & 1;   // side
   const int r = blockIdx.z >> 1;  // right-hand side
@@ -521,39 +537,53 @@ __global__ __launch_bounds__(64 * kM2sWaves) void k_m2s_mfma(const cv_t<T> *__re
   const int qic = min(qi, ns - 1);
   const int kr = lane >> 4;
   const cv_t<T> *Es = E + static_cast<int64_t>(s) * n * ns;
-  typename mfma4<T>::v4 are[NT], aim[NT];
+  v4 P1[NT], P2[NT], P3[NT];
+  cx<T> vr[NV > 0 ? NV : 1];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    are[t] = typename mfma4<T>::v4{0, 0, 0, 0};
-    aim[t] = typename mfma4<T>::v4{0, 0, 0, 0};
-  }
+  for (int t = 0; t < NT; ++t) P1[t] = P2[t] = P3[t] = v4{0, 0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < (NV > 0 ? NV : 1); ++v) vr[v] = mk<T>(0, 0);
   if (m0 < m1) {
     // operands of particle group mb (loads clamped into range, zeros selected
     // past the chunk), the next group fetched while the current one multiplies
-    auto fetch = [&](int mb, cv_t<T> &a, cv_t<T> (&b)[NT]) {
-      const int mc = min(mb + kr, m1 - 1);
-      a = Es[static_cast<int64_t>(mc) * ns + qic];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = beta[static_cast<int64_t>(mc) * P + min(t * 16 + (lane & 15), P - 1)];
+    struct Ops {
+      cv_t<T> a, b[NT], bv[NV > 0 ? NV : 1];
     };
-    cv_t<T> an, bn[NT];
-    fetch(m0, an, bn);
-    for (int mb = m0; mb < m1; mb += 4) {
-      const cv_t<T> ac = an;
-      cv_t<T> bc[NT];
+    auto fetch = [&](int mb, Ops &o) {
+      const int mc = min(mb + kr, m1 - 1);
+      o.a = Es[static_cast<int64_t>(mc) * ns + qic];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) bc[t] = bn[t];
-      if (mb + 4 < m1) fetch(mb + 4, an, bn);
+      for (int t = 0; t < NT; ++t) o.b[t] = beta[static_cast<int64_t>(mc) * P + min(t * 16 + (lane & 15), P - 1)];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) o.bv[v] = beta[static_cast<int64_t>(mc) * P + 16 * NT + v];
+    };
+    Ops nx;
+    fetch(m0, nx);
+    for (int mb = m0; mb < m1; mb += 4) {
+      const Ops cu = nx;
+      if (mb + 4 < m1) fetch(mb + 4, nx);
       const bool mv = mb + kr < m1;
-      const T zr = mv ? ac.x : T(0), zi = mv ? ac.y : T(0);
+      const T zr = mv ? cu.a.x : T(0), zi = mv ? cu.a.y : T(0), zs = zr + zi;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        are[t] = mfma4<T>::mac(zr, bc[t].x, are[t]);
-        are[t] = mfma4<T>::mac(-zi, bc[t].y, are[t]);
-        aim[t] = mfma4<T>::mac(zr, bc[t].y, aim[t]);
-        aim[t] = mfma4<T>::mac(zi, bc[t].x, aim[t]);
+        const bool cv = t * 16 + (lane & 15) < P;  // padded tile (long remainders only)
+        const T br = cv ? cu.b[t].x : T(0), bi = cv ? cu.b[t].y : T(0);
+        P1[t] = mfma4<T>::mac(zr, br, P1[t]);
+        P2[t] = mfma4<T>::mac(zi, bi, P2[t]);
+        P3[t] = mfma4<T>::mac(zs, br + bi, P3[t]);
       }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) cmac(vr[v], mk<T>(zr, zi), ld<T>(cu.bv[v]));
     }
+  }
+  // vector-unit orders: sum over the four particles of each node (lane
+  // groups); lane i then holds node q0 + i % 16
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    vr[v].re += __shfl_xor(vr[v].re, 16);
+    vr[v].im += __shfl_xor(vr[v].im, 16);
+    vr[v].re += __shfl_xor(vr[v].re, 32);
+    vr[v].im += __shfl_xor(vr[v].im, 32);
   }
   // epilogue: contract each node's orders with W, reduce over the 16 lanes
   // holding that node's columns, one lane per node stores
@@ -561,18 +591,25 @@ __global__ __launch_bounds__(64 * kM2sWaves) void k_m2s_mfma(const cv_t<T> *__re
   cv_t<T> *o = part + ((2 * static_cast<int64_t>(r) + s) * chunks + c) * ns;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int q = q0 + mfma4<T>::row(lane, j);
+    const int row = mfma4<T>::row(lane, j);
+    const int q = q0 + row;
     const int qc = min(q, ns - 1);
     cx<T> acc = mk<T>(0, 0);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int col = t * 16 + (lane & 15);
-      if (col < P) cmac(acc, mk<T>(are[t][j], aim[t][j]), ld<T>(Ws[static_cast<int64_t>(qc) * P + col]));
+      const T p1 = P1[t][j], p2 = P2[t][j], p3 = P3[t][j];
+      if (col < P) cmac(acc, mk<T>(p1 - p2, p3 - p1 - p2), ld<T>(Ws[static_cast<int64_t>(qc) * P + col]));
     }
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) {
       acc.re += __shfl_xor(acc.re, off, 16);
       acc.im += __shfl_xor(acc.im, off, 16);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {  // node q's remainder orders live in lane `row`
+      const cx<T> g = mk<T>(__shfl(vr[v].re, row), __shfl(vr[v].im, row));
+      cmac(acc, g, ld<T>(Ws[static_cast<int64_t>(qc) * P + 16 * NT + v]));
     }
     if ((lane & 15) == 0 && q < ns) o[q] = st(acc);
   }
@@ -584,8 +621,9 @@ __global__ __launch_bounds__(64 * kM2sWaves) void k_m2s_mfma(const cv_t<T> *__re
 // (M = particle, N = order, K = node).  One wave per 16 particles and all
 // order tiles; lane i supplies A[i % 16][i / 16] = F of particle l0 + i % 16 at
 // node q0 + i / 16 (16 consecutive particles per node: coalesced) and
-// B[i / 16][i % 16] = the S2L coefficient of that node and order; the complex
-// product runs as four real chains per tile.
+// B[i / 16][i % 16] = the S2L coefficient of that node and order; complex
+// products take three real MFMAs (Gauss), and a remainder of one or two
+// orders runs on the vector units (OrderSplit).
 constexpr int kS2lWaves = 4;
 template <typename T, int p>
 __global__ __launch_bounds__(64 * kS2lWaves) void k_s2l_mfma(const cv_t<T> *__restrict__ F,
@@ -593,7 +631,8 @@ __global__ __launch_bounds__(64 * kS2lWaves) void k_s2l_mfma(const cv_t<T> *__re
                                                              cv_t<T> *__restrict__ part, int n, int ns,
                                                              int chunk_len, int64_t pstride) {
   constexpr int P = 2 * p + 1;
-  constexpr int NT = (P + 15) / 16;  // order tiles
+  constexpr int NT = OrderSplit<P>::NT, NV = OrderSplit<P>::NV;
+  typedef typename mfma4<T>::v4 v4;
   Up += 2 * static_cast<int64_t>(ns) * P * blockIdx.z;  // right-hand side
   part += blockIdx.z * pstride;
   const int c = blockIdx.y;
@@ -605,56 +644,55 @@ __global__ __launch_bounds__(64 * kS2lWaves) void k_s2l_mfma(const cv_t<T> *__re
   const int li = l0 + (lane & 15);
   const bool lv = li < n;
   const int kr = lane >> 4;
-  typename mfma4<T>::v4 are[NT], aim[NT];
+  v4 P1[NT], P2[NT], P3[NT];
+  cx<T> vr[NV > 0 ? NV : 1];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    are[t] = typename mfma4<T>::v4{0, 0, 0, 0};
-    aim[t] = typename mfma4<T>::v4{0, 0, 0, 0};
-  }
-  if (q0 >= q1) goto store;  // empty chunk
-  {
+  for (int t = 0; t < NT; ++t) P1[t] = P2[t] = P3[t] = v4{0, 0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < (NV > 0 ? NV : 1); ++v) vr[v] = mk<T>(0, 0);
+  if (q0 < q1) {
     // operands of node group qb (loads clamped into range, zeros selected
     // outside it), the next group fetched while the current one multiplies
     const int lic = lv ? li : n - 1;
-    auto fetch = [&](int side, int qb, cv_t<T> &a, cv_t<T> (&b)[NT]) {
+    struct Ops {
+      cv_t<T> a, b[NT], bv[NV > 0 ? NV : 1];
+    };
+    auto fetch = [&](int side, int qb, Ops &o) {
       const int q = qb + kr;
       const int qc = min(q, q1 - 1);
-      a = F[(side * static_cast<int64_t>(ns) + qc) * n + lic];
+      o.a = F[(side * static_cast<int64_t>(ns) + qc) * n + lic];
+      const cv_t<T> *u = Up + (side * static_cast<int64_t>(ns) + qc) * P;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int col = min(t * 16 + (lane & 15), P - 1);
-        b[t] = Up[(side * static_cast<int64_t>(ns) + qc) * P + col];
-      }
+      for (int t = 0; t < NT; ++t) o.b[t] = u[min(t * 16 + (lane & 15), P - 1)];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) o.bv[v] = u[16 * NT + v];
     };
-    cv_t<T> an, bn[NT];
-    fetch(0, q0, an, bn);
+    Ops nx;
+    fetch(0, q0, nx);
     for (int side = 0, qb = q0; side < 2;) {
-      const cv_t<T> ac = an;
-      cv_t<T> bc[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) bc[t] = bn[t];
+      const Ops cu = nx;
       const bool qv = qb + kr < q1;
       int ns_side = side, ns_qb = qb + 4;
       if (ns_qb >= q1) {
         ns_side = side + 1;
         ns_qb = q0;
       }
-      if (ns_side < 2) fetch(ns_side, ns_qb, an, bn);
-      const T zr = (qv && lv) ? ac.x : T(0), zi = (qv && lv) ? ac.y : T(0);
+      if (ns_side < 2) fetch(ns_side, ns_qb, nx);
+      const T zr = (qv && lv) ? cu.a.x : T(0), zi = (qv && lv) ? cu.a.y : T(0), zs = zr + zi;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const bool cv = qv && (t * 16 + (lane & 15)) < P;
-        const T br = cv ? bc[t].x : T(0), bi = cv ? bc[t].y : T(0);
-        are[t] = mfma4<T>::mac(zr, br, are[t]);
-        are[t] = mfma4<T>::mac(-zi, bi, are[t]);
-        aim[t] = mfma4<T>::mac(zr, bi, aim[t]);
-        aim[t] = mfma4<T>::mac(zi, br, aim[t]);
+        const T br = cv ? cu.b[t].x : T(0), bi = cv ? cu.b[t].y : T(0);
+        P1[t] = mfma4<T>::mac(zr, br, P1[t]);
+        P2[t] = mfma4<T>::mac(zi, bi, P2[t]);
+        P3[t] = mfma4<T>::mac(zs, br + bi, P3[t]);
       }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) cmac(vr[v], mk<T>(zr, zi), ld<T>(cu.bv[v]));
       side = ns_side;
       qb = ns_qb;
     }
   }
-store:
   cv_t<T> *o = part + static_cast<int64_t>(c) * n * P;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -662,8 +700,18 @@ store:
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int l = l0 + mfma4<T>::row(lane, j);
-      if (l < n && col < P) o[static_cast<int64_t>(l) * P + col] = st(mk<T>(are[t][j], aim[t][j]));
+      const T p1 = P1[t][j], p2 = P2[t][j], p3 = P3[t][j];
+      if (l < n && col < P) o[static_cast<int64_t>(l) * P + col] = st(mk<T>(p1 - p2, p3 - p1 - p2));
     }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {  // sum over the four node lanes of each particle
+    cx<T> z = vr[v];
+    z.re += __shfl_xor(z.re, 16);
+    z.im += __shfl_xor(z.im, 16);
+    z.re += __shfl_xor(z.re, 32);
+    z.im += __shfl_xor(z.im, 32);
+    if (lane < 16 && lv) o[static_cast<int64_t>(li) * P + 16 * NT + v] = st(z);
   }
 }
 
