@@ -412,6 +412,9 @@ typedef struct {
   int history_len;
   double precond_seconds; /* part of seconds spent building preconditioner
                              blocks (0 when they were already built)       */
+  int reorthogonalizations; /* Arnoldi steps that needed a second classical
+                             Gram-Schmidt pass (the first removed more than
+                             half of the new vector's squared norm)        */
 } mpsl_info;
 
 /* Solve eq. (49) for n_rhs sources src_xy[2*r], src_xy[2*r+1] (host).

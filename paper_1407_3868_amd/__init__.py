@@ -365,7 +365,8 @@ class Context:
         hist = [info.history[i] for i in range(info.history_len)]
         meta = dict(status=rc, iterations=info.iterations, fp64_matvecs=info.fp64_matvecs,
                     refinements=info.refinements, rel_residual=info.rel_residual, seconds=info.seconds,
-                    history=hist, precond_seconds=info.precond_seconds)
+                    history=hist, precond_seconds=info.precond_seconds,
+                    reorthogonalizations=info.reorthogonalizations)
         return (out[0] if nr == 1 else out), meta
 
     def eval_field(self, src, beta, rcv):

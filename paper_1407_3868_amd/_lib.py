@@ -24,7 +24,7 @@ class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("fp64_matvecs", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
-                ("precond_seconds", ctypes.c_double)]
+                ("precond_seconds", ctypes.c_double), ("reorthogonalizations", ctypes.c_int)]
 
 
 P = ctypes.c_void_p

@@ -1080,7 +1080,8 @@ constexpr int kRed = 256;
 
 __global__ __launch_bounds__(kRed) void k_dotc_part(const double2 *__restrict__ V, int64_t ld_v,
                                                     const double2 *__restrict__ w, int64_t len,
-                                                    double2 *__restrict__ part) {
+                                                    double2 *__restrict__ part, const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;  // the pass is not needed (k_dotc_final writes zeros)
   const int j = blockIdx.y;
   const int b = blockIdx.x;
   const double2 *v = V + j * ld_v;
@@ -1105,9 +1106,14 @@ __global__ __launch_bounds__(kRed) void k_dotc_part(const double2 *__restrict__ 
   if (threadIdx.x == 0) part[j * gridDim.x + b] = make_double2(sr[0], si[0]);
 }
 
-__global__ void k_dotc_final(const double2 *__restrict__ part, int k, int nb, double2 *__restrict__ h) {
+__global__ void k_dotc_final(const double2 *__restrict__ part, int k, int nb, double2 *__restrict__ h,
+                             const int32_t *__restrict__ skip) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k) return;
+  if (skip && *skip) {
+    h[j] = make_double2(0.0, 0.0);
+    return;
+  }
   double re = 0.0, im = 0.0;
   for (int b = 0; b < nb; ++b) {
     re += part[j * nb + b].x;
@@ -1117,9 +1123,10 @@ __global__ void k_dotc_final(const double2 *__restrict__ part, int k, int nb, do
 }
 
 __global__ void k_gemv_sub(const double2 *__restrict__ V, int64_t ld_v, int k,
-                           const double2 *__restrict__ h, double2 *__restrict__ w, int64_t len) {
+                           const double2 *__restrict__ h, double2 *__restrict__ w, int64_t len,
+                           const int32_t *__restrict__ skip) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= len) return;
+  if (i >= len || (skip && *skip)) return;
   cx<double> acc = ld<double>(w[i]);
   for (int j = 0; j < k; ++j) {
     const cx<double> v = ld<double>(V[j * ld_v + i]);
@@ -1127,6 +1134,13 @@ __global__ void k_gemv_sub(const double2 *__restrict__ V, int64_t ld_v, int k,
     acc = acc - v * hj;
   }
   w[i] = st(acc);
+}
+
+// Second Gram-Schmidt pass only when the first cancelled much of the vector
+// (Daniel, Gragg, Kaufman and Stewart): skip = ||w after||^2 >= eta2 ||w before||^2.
+__global__ void k_reorth_flag(const double2 *__restrict__ before, const double2 *__restrict__ after, double eta2,
+                              int32_t *__restrict__ skip) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) skip[0] = after->x >= eta2 * before->x ? 1 : 0;
 }
 
 __global__ __launch_bounds__(kRed) void k_proj_fix(double2 *__restrict__ h, const double2 *__restrict__ q, int k) {
@@ -1631,22 +1645,30 @@ int launch_proj_fix(mpsl_ctx *ctx, void *h, const void *q, int k) {
 size_t dotc_scratch_bytes(int k) { return static_cast<size_t>(std::max(k, 1)) * kDotBlocks * sizeof(double2); }
 
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *w, int64_t len,
-                      void *h_out) {
+                      void *h_out, const int32_t *skip) {
   if (ctx->scal.bytes < dotc_scratch_bytes(k))
     return set_err(ctx, MPSL_EINVAL, "reduction scratch too small for " + std::to_string(k) + " dot products");
   auto *scr = static_cast<double2 *>(ctx->scal.p);
   hipLaunchKernelGGL(k_dotc_part, dim3(kDotBlocks, k), dim3(kRed), 0, ctx->stream,
-                     static_cast<const double2 *>(V), ld_v, static_cast<const double2 *>(w), len, scr);
+                     static_cast<const double2 *>(V), ld_v, static_cast<const double2 *>(w), len, scr, skip);
   LAUNCH_CHECK(ctx);
   hipLaunchKernelGGL(k_dotc_final, dim3(cdiv(k, 256)), dim3(256), 0, ctx->stream, scr, k, kDotBlocks,
-                     static_cast<double2 *>(h_out));
+                     static_cast<double2 *>(h_out), skip);
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }
 
-int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *h, void *w, int64_t len) {
+int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *h, void *w, int64_t len,
+                    const int32_t *skip) {
   hipLaunchKernelGGL(k_gemv_sub, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<const double2 *>(V),
-                     ld_v, k, static_cast<const double2 *>(h), static_cast<double2 *>(w), len);
+                     ld_v, k, static_cast<const double2 *>(h), static_cast<double2 *>(w), len, skip);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_reorth_flag(mpsl_ctx *ctx, const void *before, const void *after, double eta2, int32_t *skip) {
+  hipLaunchKernelGGL(k_reorth_flag, dim3(1), dim3(64), 0, ctx->stream, static_cast<const double2 *>(before),
+                     static_cast<const double2 *>(after), eta2, skip);
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }

@@ -1,5 +1,6 @@
 // Resumable solver for eq. (49): restarted GMRES (Arnoldi by classical
-// Gram-Schmidt applied twice, FP64; Givens rotations on the host) inside an
+// Gram-Schmidt, FP64, a second pass where the first cancelled much of the
+// vector; Givens rotations on the host) inside an
 // FP64 residual loop, optionally right-preconditioned by the cluster blocks
 // (the Krylov operator is A M^{-1}; corrections are M^{-1} V y).
 //
@@ -51,6 +52,7 @@ class SolveSM {
   int refinements() const { return refin_; }
   double rel_residual() const { return rel_res_; }
   double precond_seconds() const { return pc_s_; }
+  int reorthogonalizations() const { return reorth_; }
   const std::vector<double> &history() const { return hist_; }
 
  private:
@@ -72,7 +74,7 @@ class SolveSM {
   double2 *h_ = nullptr, *h2_ = nullptr, *nrm_ = nullptr;
   float2 *x32_ = nullptr, *y32_ = nullptr;
   // pinned host staging
-  double2 *hh_ = nullptr;  // 2 (m + 2) + 1 entries: h, h2, norm
+  double2 *hh_ = nullptr;  // pinned: h, h2 (m + 2 each), norm, y (m + 1), second-pass flag
   // host Hessenberg state
   std::vector<zc> H_, cs_, sn_, gv_;
   int j_ = 0;
@@ -87,6 +89,8 @@ class SolveSM {
   std::vector<zc> yC_;              // W^H r of the current cycle
   std::vector<zc> Cs_;              // V_{k+1} coefficients of the new vectors, [j][k0 + 1]
   double2 *q_ = nullptr;            // device: last column of Q (k0 + 1)
+  int32_t *skip_ = nullptr;         // device: second Gram-Schmidt pass not needed
+  int reorth_ = 0;                  // iterations that needed the second pass
   std::vector<double> hist_;
 };
 

@@ -65,12 +65,13 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   h2_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
   nrm_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
   q_ = reinterpret_cast<double2 *>(take((m_ + 2) * c));
+  skip_ = reinterpret_cast<int32_t *>(take(256));
   x32_ = reinterpret_cast<float2 *>(take(len_ * sizeof(float2)));
   y32_ = reinterpret_cast<float2 *>(take(len_ * sizeof(float2)));
   if (hh_) (void)hipHostFree(hh_);
   hh_ = nullptr;
-  // pinned staging: h (m+2), h2 (m+2), norm (1), y (m+1)
-  if (hipHostMalloc(reinterpret_cast<void **>(&hh_), (3 * static_cast<size_t>(m_ + 2) + 1) * c) != hipSuccess) {
+  // pinned staging: h (m+2), h2 (m+2), norm (1), y (m+1), second-pass flag (1)
+  if (hipHostMalloc(reinterpret_cast<void **>(&hh_), (3 * static_cast<size_t>(m_ + 2) + 2) * c) != hipSuccess) {
     hh_ = nullptr;
     return set_err(ctx, MPSL_ENOMEM, "pinned host allocation failed");
   }
@@ -83,7 +84,7 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   }
   status_ = kRunning;
   inner_mv_ = fp64_mv_ = refin_ = 0;
-  k0_ = base_ = cycles_ = 0;
+  k0_ = base_ = cycles_ = reorth_ = 0;
   R0_.clear();
   Cs_.clear();
   hist_.clear();
@@ -183,15 +184,25 @@ int SolveSM::launch() {
           (rc = launch_to_fp64(ctx, y32_, vn, len_)))
         return rc;
     }
-    // two passes of classical Gram-Schmidt over [V_{k0+1} | this cycle's
-    // basis] (the recycled part projected onto W only), then the norm
+    // classical Gram-Schmidt over [V_{k0+1} | this cycle's basis] (the
+    // recycled part projected onto W only), repeated once when the first pass
+    // removed more than 1 - 1/2 of ||w||^2 (decided on the device: the second
+    // pass's kernels read the flag); then the norm.  The first pass's dots
+    // include w itself (it follows the basis in V_), giving ||w||^2.
     const int nb = base_ + j_ + 1;
-    for (double2 *h : {h_, h2_}) {
-      if ((rc = launch_dotc_multi(ctx, V_, len_, nb, vn, len_, h))) return rc;
-      if (k0_ > 0 && (rc = launch_proj_fix(ctx, h, q_, k0_ + 1))) return rc;
-      if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h, vn, len_))) return rc;
-    }
-    if ((rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_))) return rc;
+    if ((rc = launch_dotc_multi(ctx, V_, len_, nb + 1, vn, len_, h_))) return rc;
+    if (k0_ > 0 && (rc = launch_proj_fix(ctx, h_, q_, k0_ + 1))) return rc;
+    if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h_, vn, len_)) ||
+        (rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_)) ||
+        (rc = launch_reorth_flag(ctx, h_ + nb, nrm_, 0.5, skip_)))
+      return rc;
+    if ((rc = launch_dotc_multi(ctx, V_, len_, nb, vn, len_, h2_, skip_))) return rc;
+    if (k0_ > 0 && (rc = launch_proj_fix(ctx, h2_, q_, k0_ + 1))) return rc;
+    if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h2_, vn, len_, skip_)) ||
+        (rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_)))
+      return rc;
+    MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + 3 * (m_ + 2) + 1, skip_, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     ctx->stream));
     MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_, h_, nb * c, hipMemcpyDeviceToHost, ctx->stream));
     MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + (m_ + 2), h2_, nb * c, hipMemcpyDeviceToHost, ctx->stream));
   } else {
@@ -215,6 +226,7 @@ int SolveSM::complete() {
     if (o_.precision == MPSL_FP64) ++fp64_mv_;
     const int j = j_, m = m_, b0 = base_;
     if (!std::isfinite(nn)) return set_err(ctx, MPSL_ENUMERIC, "non-finite Arnoldi norm");
+    if (*reinterpret_cast<const int32_t *>(hh_ + 3 * (m_ + 2) + 1) == 0) ++reorth_;
     for (int i = 0; i <= j; ++i)
       H_[i * m + j] = zc(hh_[b0 + i].x + hh_[m + 2 + b0 + i].x, hh_[b0 + i].y + hh_[m + 2 + b0 + i].y);
     for (int i = 0; b0 > 0 && i <= k0_; ++i)  // coefficients on V_{k0+1} (projected onto W)
@@ -378,6 +390,7 @@ int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *
       info->history = ctx->hist.data();
       info->history_len = static_cast<int>(ctx->hist.size());
       info->precond_seconds = sm.precond_seconds();
+      info->reorthogonalizations = sm.reorthogonalizations();
     }
     if (sm.status() != mpsl::SolveSM::kConverged) status = MPSL_ENOCONV;
   }
