@@ -63,13 +63,17 @@ int launch_fold_parts(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs 
 int launch_sapply(mpsl_ctx *ctx, int prec, const void *x, const void *alpha, void *y, int nrhs = 1,
                   int64_t astride = 0);
 
-// GMRES helpers (FP64 complex vectors of length len).  skip (device, may be
-// null): when *skip != 0 the dot products come out zero and the update does
-// nothing (a second Gram-Schmidt pass found unnecessary on the device).
+// GMRES helpers (FP64 complex vectors of length len; the k vectors of V in
+// FP64, or FP32 when v_prec is MPSL_FP32, with FP64 products and sums).  skip
+// (device, may be null): when *skip != 0 the dot products come out zero and
+// the update does nothing (a second Gram-Schmidt pass found unnecessary on the
+// device).
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *w, int64_t len,
-                      void *h_out, const int32_t *skip = nullptr);
+                      void *h_out, const int32_t *skip = nullptr, int v_prec = MPSL_FP64);
 int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld, int k, const void *h, void *w,
-                    int64_t len, const int32_t *skip = nullptr);
+                    int64_t len, const int32_t *skip = nullptr, int v_prec = MPSL_FP64);
+// v32 = s src, rounded to complex64.
+int launch_scale_to_fp32(mpsl_ctx *ctx, void *v32, int64_t len, double s, const void *src);
 // skip = ||after||^2 >= eta2 ||before||^2 (both the real part of a dot product).
 int launch_reorth_flag(mpsl_ctx *ctx, const void *before, const void *after, double eta2, int32_t *skip);
 int launch_scale(mpsl_ctx *ctx, void *v, int64_t len, double s, const void *src);

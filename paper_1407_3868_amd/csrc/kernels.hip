@@ -1078,32 +1078,64 @@ __global__ void k_rhs_transpose(const float2 *__restrict__ x, float2 *__restrict
 constexpr int kDotBlocks = 64;
 constexpr int kRed = 256;
 
-__global__ __launch_bounds__(kRed) void k_dotc_part(const double2 *__restrict__ V, int64_t ld_v,
+// V holds the basis in FP64 (double2) or, for the mixed-precision solve, FP32
+// (float2); products and sums are FP64 either way.  Each block takes one
+// slice of w and kDotVecs basis vectors, so every w element is loaded once
+// for kDotVecs products (w would otherwise be re-read from L2 once per
+// vector: at a basis of several hundred vectors that traffic exceeded V's).
+// Sums: per thread, then across the wave by xor shuffles, then the four
+// waves in order (deterministic).
+constexpr int kDotVecs = 8;
+template <typename TV>
+__global__ __launch_bounds__(kRed) void k_dotc_part(const TV *__restrict__ V, int64_t ld_v, int k,
                                                     const double2 *__restrict__ w, int64_t len,
                                                     double2 *__restrict__ part, const int32_t *__restrict__ skip) {
   if (skip && *skip) return;  // the pass is not needed (k_dotc_final writes zeros)
-  const int j = blockIdx.y;
+  const int j0 = blockIdx.y * kDotVecs;
+  const int nv = min(kDotVecs, k - j0);
   const int b = blockIdx.x;
-  const double2 *v = V + j * ld_v;
-  double re = 0.0, im = 0.0;
+  double re[kDotVecs], im[kDotVecs];
+#pragma unroll
+  for (int u = 0; u < kDotVecs; ++u) re[u] = im[u] = 0.0;
   for (int64_t i = b * static_cast<int64_t>(kRed) + threadIdx.x; i < len;
        i += static_cast<int64_t>(kRed) * gridDim.x) {
-    const double2 a = v[i], c = w[i];
-    re += a.x * c.x + a.y * c.y;
-    im += a.x * c.y - a.y * c.x;
-  }
-  __shared__ double sr[kRed], si[kRed];
-  sr[threadIdx.x] = re;
-  si[threadIdx.x] = im;
-  __syncthreads();
-  for (int o = kRed / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      sr[threadIdx.x] += sr[threadIdx.x + o];
-      si[threadIdx.x] += si[threadIdx.x + o];
+    const double2 c = w[i];
+#pragma unroll
+    for (int u = 0; u < kDotVecs; ++u) {
+      if (u < nv) {
+        const TV a = V[(j0 + u) * ld_v + i];
+        const double ax = a.x, ay = a.y;
+        re[u] += ax * c.x + ay * c.y;
+        im[u] += ax * c.y - ay * c.x;
+      }
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0) part[j * gridDim.x + b] = make_double2(sr[0], si[0]);
+  __shared__ double sr[kRed / 64][kDotVecs], si[kRed / 64][kDotVecs];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < kDotVecs; ++u) {
+    double r = re[u], m = im[u];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      r += __shfl_xor(r, o);
+      m += __shfl_xor(m, o);
+    }
+    if (lane == 0) {
+      sr[wv][u] = r;
+      si[wv][u] = m;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    const int u = threadIdx.x;
+    double r = 0.0, m = 0.0;
+#pragma unroll
+    for (int v = 0; v < kRed / 64; ++v) {
+      r += sr[v][u];
+      m += si[v][u];
+    }
+    part[(j0 + u) * gridDim.x + b] = make_double2(r, m);
+  }
 }
 
 __global__ void k_dotc_final(const double2 *__restrict__ part, int k, int nb, double2 *__restrict__ h,
@@ -1122,16 +1154,24 @@ __global__ void k_dotc_final(const double2 *__restrict__ part, int k, int nb, do
   h[j] = make_double2(re, im);
 }
 
-__global__ void k_gemv_sub(const double2 *__restrict__ V, int64_t ld_v, int k,
+template <typename TV>
+__global__ void k_gemv_sub(const TV *__restrict__ V, int64_t ld_v, int k,
                            const double2 *__restrict__ h, double2 *__restrict__ w, int64_t len,
                            const int32_t *__restrict__ skip) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= len || (skip && *skip)) return;
   cx<double> acc = ld<double>(w[i]);
-  for (int j = 0; j < k; ++j) {
-    const cx<double> v = ld<double>(V[j * ld_v + i]);
-    const cx<double> hj = ld<double>(h[j]);
-    acc = acc - v * hj;
+  int j = 0;
+  for (; j + 8 <= k; j += 8) {  // eight loads in flight per lane
+    TV a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = V[(j + u) * ld_v + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = acc - mk<double>(a[u].x, a[u].y) * ld<double>(h[j + u]);
+  }
+  for (; j < k; ++j) {
+    const TV a = V[j * ld_v + i];
+    acc = acc - mk<double>(a.x, a.y) * ld<double>(h[j]);
   }
   w[i] = st(acc);
 }
@@ -1166,6 +1206,13 @@ __global__ __launch_bounds__(kRed) void k_proj_fix(double2 *__restrict__ h, cons
     h[i].x -= qi.x * ar - qi.y * ai;
     h[i].y -= qi.x * ai + qi.y * ar;
   }
+}
+
+__global__ void k_scale_to32(float2 *__restrict__ v, const double2 *__restrict__ src, int64_t len, double s) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= len) return;
+  const double2 a = src[i];
+  v[i] = make_float2(static_cast<float>(s * a.x), static_cast<float>(s * a.y));
 }
 
 __global__ void k_scale(double2 *__restrict__ v, const double2 *__restrict__ src, int64_t len, double s) {
@@ -1645,12 +1692,17 @@ int launch_proj_fix(mpsl_ctx *ctx, void *h, const void *q, int k) {
 size_t dotc_scratch_bytes(int k) { return static_cast<size_t>(std::max(k, 1)) * kDotBlocks * sizeof(double2); }
 
 int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *w, int64_t len,
-                      void *h_out, const int32_t *skip) {
+                      void *h_out, const int32_t *skip, int v_prec) {
   if (ctx->scal.bytes < dotc_scratch_bytes(k))
     return set_err(ctx, MPSL_EINVAL, "reduction scratch too small for " + std::to_string(k) + " dot products");
   auto *scr = static_cast<double2 *>(ctx->scal.p);
-  hipLaunchKernelGGL(k_dotc_part, dim3(kDotBlocks, k), dim3(kRed), 0, ctx->stream,
-                     static_cast<const double2 *>(V), ld_v, static_cast<const double2 *>(w), len, scr, skip);
+  const dim3 grid(kDotBlocks, cdiv(k, kDotVecs));
+  if (v_prec == MPSL_FP32)
+    hipLaunchKernelGGL(k_dotc_part<float2>, grid, dim3(kRed), 0, ctx->stream, static_cast<const float2 *>(V), ld_v,
+                       k, static_cast<const double2 *>(w), len, scr, skip);
+  else
+    hipLaunchKernelGGL(k_dotc_part<double2>, grid, dim3(kRed), 0, ctx->stream, static_cast<const double2 *>(V), ld_v,
+                       k, static_cast<const double2 *>(w), len, scr, skip);
   LAUNCH_CHECK(ctx);
   hipLaunchKernelGGL(k_dotc_final, dim3(cdiv(k, 256)), dim3(256), 0, ctx->stream, scr, k, kDotBlocks,
                      static_cast<double2 *>(h_out), skip);
@@ -1659,9 +1711,22 @@ int launch_dotc_multi(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const v
 }
 
 int launch_gemv_sub(mpsl_ctx *ctx, const void *V, int64_t ld_v, int k, const void *h, void *w, int64_t len,
-                    const int32_t *skip) {
-  hipLaunchKernelGGL(k_gemv_sub, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<const double2 *>(V),
-                     ld_v, k, static_cast<const double2 *>(h), static_cast<double2 *>(w), len, skip);
+                    const int32_t *skip, int v_prec) {
+  if (v_prec == MPSL_FP32)
+    hipLaunchKernelGGL(k_gemv_sub<float2>, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream,
+                       static_cast<const float2 *>(V), ld_v, k, static_cast<const double2 *>(h),
+                       static_cast<double2 *>(w), len, skip);
+  else
+    hipLaunchKernelGGL(k_gemv_sub<double2>, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream,
+                       static_cast<const double2 *>(V), ld_v, k, static_cast<const double2 *>(h),
+                       static_cast<double2 *>(w), len, skip);
+  LAUNCH_CHECK(ctx);
+  return MPSL_OK;
+}
+
+int launch_scale_to_fp32(mpsl_ctx *ctx, void *v32, int64_t len, double s, const void *src) {
+  hipLaunchKernelGGL(k_scale_to32, dim3(cdiv(len, 256)), dim3(256), 0, ctx->stream, static_cast<float2 *>(v32),
+                     static_cast<const double2 *>(src), len, s);
   LAUNCH_CHECK(ctx);
   return MPSL_OK;
 }

@@ -70,7 +70,8 @@ size_t estimate_bytes(const mpsl_request &r) {
     b += 2 * 2 * n * ns * 24;                  // plane-wave factors E, F, both precisions
   b += n * P * 24 + ns * P * 128;              // rotation phases, per-node tables
   b += (2 * ca + cb) * n * P * 16;             // partial local expansions (tuning headroom)
-  b += (m + 6) * n * P * 16 + 2 * n * P * 8;   // Krylov basis and solver vectors
+  // Krylov basis (FP32 in the mixed-precision solve) and solver vectors
+  b += (m + 1) * n * P * (r.opts.precision == MPSL_FP32 ? 8 : 16) + 6 * n * P * 16 + 2 * n * P * 8;
   b += 4 * n * P * 16 + (m + 2) * 64 * 16;     // staging and reduction scratch
   if (r.precond == MPSL_PRECOND_CLUSTER && r.xy) {  // inverse cluster blocks (FP64 while built)
     const int size = r.cluster_size > 0 ? r.cluster_size : mpsl::kPcDefaultSize;

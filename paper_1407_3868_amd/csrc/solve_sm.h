@@ -56,6 +56,11 @@ class SolveSM {
   const std::vector<double> &history() const { return hist_; }
 
  private:
+  void *vslot(int j) const {
+    return static_cast<char *>(V_) + static_cast<size_t>(j) * len_ * (vp_ == MPSL_FP32 ? sizeof(float2) : sizeof(double2));
+  }
+  // V_'s slot j = s src (src FP64)
+  int store_basis(int j, double s, const double2 *src);
   int begin_inner();
   int finish_cycle();
   void keep_first_cycle();  // record W of the first cycle for the later ones
@@ -69,8 +74,13 @@ class SolveSM {
   int m_ = 0;
   int phase_ = kInner;
   int status_ = kRunning;
-  // device (inside ctx->gm)
-  double2 *V_ = nullptr, *w_ = nullptr, *r_ = nullptr, *xs_ = nullptr, *b_ = nullptr, *d_ = nullptr;
+  // device (inside ctx->gm).  The basis V_ is FP64, or FP32 in the mixed
+  // solve (vp_): its inner solve only reaches inner_tol, and the refinement
+  // recomputes the residual in FP64.  u_ holds the new Arnoldi vector in FP64
+  // while it is orthogonalised (in FP64 mode it is V_'s next slot itself).
+  void *V_ = nullptr;
+  int vp_ = MPSL_FP64;
+  double2 *u_ = nullptr, *w_ = nullptr, *r_ = nullptr, *xs_ = nullptr, *b_ = nullptr, *d_ = nullptr;
   double2 *h_ = nullptr, *h2_ = nullptr, *nrm_ = nullptr;
   float2 *x32_ = nullptr, *y32_ = nullptr;
   // pinned host staging

@@ -45,7 +45,9 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
   // the Arnoldi dot products reduce m + 1 rows of partial sums at once
   int rc = dev_alloc(ctx, ctx->scal, dotc_scratch_bytes(m_ + 2));
   if (rc) return rc;
-  const size_t bytes = (static_cast<size_t>(m_ + 1) + 5) * len_ * c + 4 * static_cast<size_t>(m_ + 2) * c +
+  vp_ = o_.precision == MPSL_FP32 ? MPSL_FP32 : MPSL_FP64;
+  const size_t vb = vp_ == MPSL_FP32 ? sizeof(float2) : sizeof(double2);
+  const size_t bytes = static_cast<size_t>(m_ + 1) * len_ * vb + 6 * len_ * c + 4 * static_cast<size_t>(m_ + 2) * c +
                        2 * len_ * sizeof(float2) + 8192;
   rc = dev_alloc(ctx, ctx->gm, bytes);
   if (rc) return rc;
@@ -55,7 +57,8 @@ int SolveSM::init(mpsl_ctx *ctx, const mpsl_opts &o, const void *b_dev) {
     p += (nb + 255) / 256 * 256;
     return q;
   };
-  V_ = reinterpret_cast<double2 *>(take((m_ + 1) * len_ * c));
+  V_ = take((m_ + 1) * len_ * vb);
+  u_ = reinterpret_cast<double2 *>(take(len_ * c));
   w_ = reinterpret_cast<double2 *>(take(len_ * c));
   r_ = reinterpret_cast<double2 *>(take(len_ * c));
   xs_ = reinterpret_cast<double2 *>(take(len_ * c));
@@ -139,8 +142,9 @@ int SolveSM::begin_inner() {
   Cs_.clear();
   if (k0_ > 0) {  // r <- (I - W W^H) r (twice), yC = W^H r
     for (int pass = 0; pass < 2; ++pass) {
-      if ((rc = launch_dotc_multi(ctx, V_, len_, k0_ + 1, r_, len_, h_)) ||
-          (rc = launch_proj_fix(ctx, h_, q_, k0_ + 1)) || (rc = launch_gemv_sub(ctx, V_, len_, k0_ + 1, h_, r_, len_)))
+      if ((rc = launch_dotc_multi(ctx, V_, len_, k0_ + 1, r_, len_, h_, nullptr, vp_)) ||
+          (rc = launch_proj_fix(ctx, h_, q_, k0_ + 1)) ||
+          (rc = launch_gemv_sub(ctx, V_, len_, k0_ + 1, h_, r_, len_, nullptr, vp_)))
         return rc;
       MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_, h_, (k0_ + 1) * c, hipMemcpyDeviceToHost, ctx->stream));
       MPSL_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -162,7 +166,12 @@ int SolveSM::begin_inner() {
   j_ = 0;
   phase_ = kInner;
   if (!(rn > 0.0)) return finish_cycle();  // the recycled space already holds the correction
-  return launch_scale(ctx, V_ + base_ * len_, len_, 1.0 / rn, r_);
+  return store_basis(base_, 1.0 / rn, r_);
+}
+
+int SolveSM::store_basis(int j, double s, const double2 *src) {
+  if (vp_ == MPSL_FP32) return launch_scale_to_fp32(ctx_, vslot(j), len_, s, src);
+  return launch_scale(ctx_, vslot(j), len_, s, src);
 }
 
 int SolveSM::launch() {
@@ -171,34 +180,44 @@ int SolveSM::launch() {
   const size_t c = sizeof(double2);
   int rc;
   if (phase_ == kInner) {
-    double2 *vj = V_ + (base_ + j_) * len_;
-    double2 *vn = V_ + (base_ + j_ + 1) * len_;
-    if (pc_) {  // z = M^{-1} v_j, then A z
-      if ((rc = precond_apply(ctx, o_.precision, vj, w_))) return rc;
-      vj = w_;
-    }
+    const int nb = base_ + j_ + 1;
+    const void *vj = vslot(base_ + j_);
+    // the new vector w = A M^{-1} v_j (FP64)
+    double2 *vn = vp_ == MPSL_FP32 ? u_ : static_cast<double2 *>(vslot(nb));
     if (o_.precision == MPSL_FP64) {
+      if (pc_) {
+        if ((rc = precond_apply(ctx, MPSL_FP64, vj, w_))) return rc;
+        vj = w_;
+      }
       if ((rc = matvec(ctx, MPSL_FP64, vj, vn))) return rc;
     } else {
-      if ((rc = launch_to_fp32(ctx, vj, x32_, len_)) || (rc = matvec(ctx, MPSL_FP32, x32_, y32_)) ||
-          (rc = launch_to_fp64(ctx, y32_, vn, len_)))
+      if (pc_ && ((rc = launch_to_fp64(ctx, vj, w_, len_)) || (rc = precond_apply(ctx, MPSL_FP32, w_, d_)) ||
+                  (rc = launch_to_fp32(ctx, d_, x32_, len_))))
+        return rc;
+      if ((rc = matvec(ctx, MPSL_FP32, pc_ ? x32_ : vj, y32_)) || (rc = launch_to_fp64(ctx, y32_, vn, len_)))
         return rc;
     }
     // classical Gram-Schmidt over [V_{k0+1} | this cycle's basis] (the
     // recycled part projected onto W only), repeated once when the first pass
     // removed more than 1 - 1/2 of ||w||^2 (decided on the device: the second
-    // pass's kernels read the flag); then the norm.  The first pass's dots
-    // include w itself (it follows the basis in V_), giving ||w||^2.
-    const int nb = base_ + j_ + 1;
-    if ((rc = launch_dotc_multi(ctx, V_, len_, nb + 1, vn, len_, h_))) return rc;
+    // pass's kernels read the flag); then the norm.  With an FP64 basis the
+    // first pass's dots include w itself (it follows the basis in V_), giving
+    // ||w||^2; with an FP32 basis w is apart and has its own dot product.
+    if (vp_ == MPSL_FP32) {
+      if ((rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, h_ + nb)) ||
+          (rc = launch_dotc_multi(ctx, V_, len_, nb, vn, len_, h_, nullptr, vp_)))
+        return rc;
+    } else if ((rc = launch_dotc_multi(ctx, V_, len_, nb + 1, vn, len_, h_))) {
+      return rc;
+    }
     if (k0_ > 0 && (rc = launch_proj_fix(ctx, h_, q_, k0_ + 1))) return rc;
-    if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h_, vn, len_)) ||
+    if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h_, vn, len_, nullptr, vp_)) ||
         (rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_)) ||
         (rc = launch_reorth_flag(ctx, h_ + nb, nrm_, 0.5, skip_)))
       return rc;
-    if ((rc = launch_dotc_multi(ctx, V_, len_, nb, vn, len_, h2_, skip_))) return rc;
+    if ((rc = launch_dotc_multi(ctx, V_, len_, nb, vn, len_, h2_, skip_, vp_))) return rc;
     if (k0_ > 0 && (rc = launch_proj_fix(ctx, h2_, q_, k0_ + 1))) return rc;
-    if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h2_, vn, len_, skip_)) ||
+    if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h2_, vn, len_, skip_, vp_)) ||
         (rc = launch_dotc_multi(ctx, vn, 0, 1, vn, len_, nrm_)))
       return rc;
     MPSL_HIP_TRY(ctx, hipMemcpyAsync(hh_ + 3 * (m_ + 2) + 1, skip_, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -232,8 +251,9 @@ int SolveSM::complete() {
     for (int i = 0; b0 > 0 && i <= k0_; ++i)  // coefficients on V_{k0+1} (projected onto W)
       Cs_.push_back(zc(hh_[i].x + hh_[m + 2 + i].x, hh_[i].y + hh_[m + 2 + i].y));
     H_[(j + 1) * m + j] = nn;
-    double2 *vn = V_ + (b0 + j + 1) * len_;
-    if (nn > 0.0 && (rc = launch_scale(ctx, vn, len_, 1.0 / nn, vn))) return rc;
+    if (nn > 0.0 &&
+        (rc = store_basis(b0 + j + 1, 1.0 / nn, vp_ == MPSL_FP32 ? u_ : static_cast<const double2 *>(vslot(b0 + j + 1)))))
+      return rc;
     for (int i = 0; i < j; ++i) {  // previous rotations, then a new one
       const zc a = H_[i * m + j], b = H_[(i + 1) * m + j];
       H_[i * m + j] = std::conj(cs_[i]) * a + std::conj(sn_[i]) * b;
@@ -305,7 +325,7 @@ int SolveSM::finish_cycle() {
   MPSL_HIP_TRY(ctx, hipMemcpyAsync(h_, hy, nb * sizeof(double2), hipMemcpyHostToDevice, ctx->stream));
   MPSL_HIP_TRY(ctx, hipMemsetAsync(d_, 0, len_ * sizeof(double2), ctx->stream));
   int rc;
-  if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h_, d_, len_))) return rc;  // d = V coef
+  if ((rc = launch_gemv_sub(ctx, V_, len_, nb, h_, d_, len_, nullptr, vp_))) return rc;  // d = V coef
   if (pc_) {  // the correction is M^{-1} V y
     if ((rc = precond_apply(ctx, o_.precision, d_, w_)) || (rc = launch_axpy_c(ctx, xs_, w_, len_, 1.0, 0.0)))
       return rc;
