@@ -618,14 +618,19 @@ __global__ __launch_bounds__(64 * kM2sWaves) void k_m2s_mfma(const cv_t<T> *__re
 // ---------------------------------------------------------------------------
 // Row b3 on the matrix cores: S2L as a GEMM over the nodes of both interfaces,
 //   part[c][l][n] = sum_{side, q in chunk c} F[side][q][l] Up[side][q][n]
-// (M = particle, N = order, K = node).  One wave per 16 particles and all
-// order tiles; lane i supplies A[i % 16][i / 16] = F of particle l0 + i % 16 at
-// node q0 + i / 16 (16 consecutive particles per node: coalesced) and
-// B[i / 16][i % 16] = the S2L coefficient of that node and order; complex
-// products take three real MFMAs (Gauss), and a remainder of one or two
-// orders runs on the vector units (OrderSplit).
+// (M = particle, N = order, K = node).  One wave per 16 MT particles (MT
+// tiles of 16) and all order tiles; lane i supplies A[i % 16][i / 16] = F of
+// particle l0 + 16 t + i % 16 at node q0 + i / 16 (16 consecutive particles
+// per node: coalesced) and B[i / 16][i % 16] = the S2L coefficient of that
+// node and order, loaded once for the MT particle tiles; complex products
+// take three real MFMAs (Gauss), and a remainder of one or two orders runs on
+// the vector units (OrderSplit).
 constexpr int kS2lWaves = 4;
-template <typename T, int p>
+// particle tiles per wave: two in FP32 (the coefficient loads shared by
+// both); one in FP64, where a second tile's accumulators would leave one
+// wave per SIMD
+template <typename T> constexpr int s2l_tiles() { return sizeof(T) == 4 ? 2 : 1; }
+template <typename T, int p, int MT>
 __global__ __launch_bounds__(64 * kS2lWaves) void k_s2l_mfma(const cv_t<T> *__restrict__ F,
                                                              const cv_t<T> *__restrict__ Up,
                                                              cv_t<T> *__restrict__ part, int n, int ns,
@@ -639,28 +644,37 @@ __global__ __launch_bounds__(64 * kS2lWaves) void k_s2l_mfma(const cv_t<T> *__re
   const int q0 = c * chunk_len;
   const int q1 = min(ns, q0 + chunk_len);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int l0 = (blockIdx.x * kS2lWaves + w) * 16;
+  const int l0 = (blockIdx.x * kS2lWaves + w) * 16 * MT;
   if (l0 >= n) return;  // the whole wave lies past the last particle (no barriers below)
-  const int li = l0 + (lane & 15);
-  const bool lv = li < n;
   const int kr = lane >> 4;
-  v4 P1[NT], P2[NT], P3[NT];
-  cx<T> vr[NV > 0 ? NV : 1];
+  int li[MT];
+  bool lv[MT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) P1[t] = P2[t] = P3[t] = v4{0, 0, 0, 0};
+  for (int m = 0; m < MT; ++m) {
+    li[m] = l0 + 16 * m + (lane & 15);
+    lv[m] = li[m] < n;
+  }
+  v4 P1[MT][NT], P2[MT][NT], P3[MT][NT];
+  cx<T> vr[MT][NV > 0 ? NV : 1];
 #pragma unroll
-  for (int v = 0; v < (NV > 0 ? NV : 1); ++v) vr[v] = mk<T>(0, 0);
+  for (int m = 0; m < MT; ++m) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) P1[m][t] = P2[m][t] = P3[m][t] = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int v = 0; v < (NV > 0 ? NV : 1); ++v) vr[m][v] = mk<T>(0, 0);
+  }
   if (q0 < q1) {
     // operands of node group qb (loads clamped into range, zeros selected
     // outside it), the next group fetched while the current one multiplies
-    const int lic = lv ? li : n - 1;
     struct Ops {
-      cv_t<T> a, b[NT], bv[NV > 0 ? NV : 1];
+      cv_t<T> a[MT], b[NT], bv[NV > 0 ? NV : 1];
     };
     auto fetch = [&](int side, int qb, Ops &o) {
       const int q = qb + kr;
       const int qc = min(q, q1 - 1);
-      o.a = F[(side * static_cast<int64_t>(ns) + qc) * n + lic];
+      const cv_t<T> *f = F + (side * static_cast<int64_t>(ns) + qc) * n;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) o.a[m] = f[lv[m] ? li[m] : n - 1];
       const cv_t<T> *u = Up + (side * static_cast<int64_t>(ns) + qc) * P;
 #pragma unroll
       for (int t = 0; t < NT; ++t) o.b[t] = u[min(t * 16 + (lane & 15), P - 1)];
@@ -678,40 +692,52 @@ __global__ __launch_bounds__(64 * kS2lWaves) void k_s2l_mfma(const cv_t<T> *__re
         ns_qb = q0;
       }
       if (ns_side < 2) fetch(ns_side, ns_qb, nx);
-      const T zr = (qv && lv) ? cu.a.x : T(0), zi = (qv && lv) ? cu.a.y : T(0), zs = zr + zi;
+      T br[NT], bi[NT], bs[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const bool cv = qv && (t * 16 + (lane & 15)) < P;
-        const T br = cv ? cu.b[t].x : T(0), bi = cv ? cu.b[t].y : T(0);
-        P1[t] = mfma4<T>::mac(zr, br, P1[t]);
-        P2[t] = mfma4<T>::mac(zi, bi, P2[t]);
-        P3[t] = mfma4<T>::mac(zs, br + bi, P3[t]);
+        br[t] = cv ? cu.b[t].x : T(0);
+        bi[t] = cv ? cu.b[t].y : T(0);
+        bs[t] = br[t] + bi[t];
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) cmac(vr[v], mk<T>(zr, zi), ld<T>(cu.bv[v]));
+      for (int m = 0; m < MT; ++m) {
+        const T zr = (qv && lv[m]) ? cu.a[m].x : T(0), zi = (qv && lv[m]) ? cu.a[m].y : T(0), zs = zr + zi;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          P1[m][t] = mfma4<T>::mac(zr, br[t], P1[m][t]);
+          P2[m][t] = mfma4<T>::mac(zi, bi[t], P2[m][t]);
+          P3[m][t] = mfma4<T>::mac(zs, bs[t], P3[m][t]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cmac(vr[m][v], mk<T>(zr, zi), ld<T>(cu.bv[v]));
+      }
       side = ns_side;
       qb = ns_qb;
     }
   }
   cv_t<T> *o = part + static_cast<int64_t>(c) * n * P;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int col = t * 16 + (lane & 15);
+  for (int m = 0; m < MT; ++m) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int l = l0 + mfma4<T>::row(lane, j);
-      const T p1 = P1[t][j], p2 = P2[t][j], p3 = P3[t][j];
-      if (l < n && col < P) o[static_cast<int64_t>(l) * P + col] = st(mk<T>(p1 - p2, p3 - p1 - p2));
+    for (int t = 0; t < NT; ++t) {
+      const int col = t * 16 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int l = l0 + 16 * m + mfma4<T>::row(lane, j);
+        const T p1 = P1[m][t][j], p2 = P2[m][t][j], p3 = P3[m][t][j];
+        if (l < n && col < P) o[static_cast<int64_t>(l) * P + col] = st(mk<T>(p1 - p2, p3 - p1 - p2));
+      }
     }
-  }
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {  // sum over the four node lanes of each particle
-    cx<T> z = vr[v];
-    z.re += __shfl_xor(z.re, 16);
-    z.im += __shfl_xor(z.im, 16);
-    z.re += __shfl_xor(z.re, 32);
-    z.im += __shfl_xor(z.im, 32);
-    if (lane < 16 && lv) o[static_cast<int64_t>(li) * P + 16 * NT + v] = st(z);
+    for (int v = 0; v < NV; ++v) {  // sum over the four node lanes of each particle
+      cx<T> z = vr[m][v];
+      z.re += __shfl_xor(z.re, 16);
+      z.im += __shfl_xor(z.im, 16);
+      z.re += __shfl_xor(z.re, 32);
+      z.im += __shfl_xor(z.im, 32);
+      if (lane < 16 && lv[m]) o[static_cast<int64_t>(li[m]) * P + 16 * NT + v] = st(z);
+    }
   }
 }
 
@@ -1603,14 +1629,15 @@ template <typename T>
 static int launch_s2l_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstride) {
   const int n = static_cast<int>(ctx->n);
   const int chunk_len = cdiv(ctx->ns, chunks);
-  const dim3 grid(cdiv(n, 16 * kS2lWaves), chunks, nrhs);
+  constexpr int MT = s2l_tiles<T>();
+  const dim3 grid(cdiv(n, 16 * MT * kS2lWaves), chunks, nrhs);
   const bool f64 = std::is_same<T, double>::value;
   const auto *F = static_cast<const cv_t<T> *>(f64 ? ctx->gt.F64.p : ctx->gt.F32.p);
   const auto *Up = static_cast<const cv_t<T> *>(f64 ? ctx->Up64.p : ctx->Up32.p);
   auto *o = static_cast<cv_t<T> *>(part);
   switch (ctx->p) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_s2l_mfma<T, PP>), grid, dim3(64 * kS2lWaves), 0, ctx->stream, F, Up, o, n, ctx->ns, chunk_len, pstride); break;
+  case PP: hipLaunchKernelGGL((k_s2l_mfma<T, PP, MT>), grid, dim3(64 * kS2lWaves), 0, ctx->stream, F, Up, o, n, ctx->ns, chunk_len, pstride); break;
     MPSL_P_CASES(X)
 #undef X
     default: return set_err(ctx, MPSL_EUNSUPPORTED, "expansion order outside 1..20");
