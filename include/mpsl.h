@@ -230,6 +230,14 @@ int mpsl_set_contour_span(mpsl_ctx *ctx, double b, double t_max, double h_max);
 enum { MPSL_SOMM_DIRECT = 0, MPSL_SOMM_INTERP = 1 };
 int mpsl_set_sommerfeld_method(mpsl_ctx *ctx, int method);
 
+/* Shape of the MPSL_SOMM_INTERP plan of the current problem (after a first
+ * apply or solve; MPSL_ESTATE before): active = 1 when the interpolated
+ * transforms are in use, particle tiles, lambda-intervals, coarse nodes
+ * (24 per interval plus one per direct node) and direct contour nodes.
+ * Any output pointer may be NULL. */
+int mpsl_get_somm_info(const mpsl_ctx *ctx, int *active, int *tiles, int *intervals, int *coarse_nodes,
+                       int *direct_nodes);
+
 /* Host, no device: the span rule's nodes and weights for the real parts
  * re_k[0 .. n_k) of the layer wavenumbers.  *n_nodes receives the count;
  * with lam and w NULL nothing else is written, otherwise both must hold

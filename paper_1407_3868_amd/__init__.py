@@ -395,6 +395,12 @@ class Context:
         """Direct all-pairs or FMM far field (FAR_AUTO / FAR_DIRECT / FAR_FMM)."""
         return self._check(self.lib.mpsl_set_far_field(self.h, int(method), float(tol)))
 
+    def somm_info(self):
+        v = [ctypes.c_int() for _ in range(5)]
+        self._check(self.lib.mpsl_get_somm_info(self.h, *[ctypes.byref(x) for x in v]))
+        return dict(active=bool(v[0].value), tiles=v[1].value, intervals=v[2].value, coarse_nodes=v[3].value,
+                    direct_nodes=v[4].value)
+
     def fmm_info(self, prec=FP64):
         a, lv, pl, pt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         side, work, pairs = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()

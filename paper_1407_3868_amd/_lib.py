@@ -89,6 +89,8 @@ SIGNATURES = {
     "mpsl_profile": (I, [P, I]),
     "mpsl_profile_read": (I, [P, DP, ctypes.POINTER(I)]),
     "mpsl_set_far_field": (I, [P, I, ctypes.c_double]),
+    "mpsl_get_somm_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                               ctypes.POINTER(I)]),
     "mpsl_get_fmm_info": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), DP, ctypes.POINTER(I),
                               ctypes.POINTER(I), ctypes.POINTER(L), DP]),
 }

@@ -737,3 +737,16 @@ int somm_build(mpsl_ctx *ctx) {
 }
 
 }  // namespace mpsl
+
+extern "C" int mpsl_get_somm_info(const mpsl_ctx *ctx, int *active, int *tiles, int *intervals, int *coarse_nodes,
+                                  int *direct_nodes) {
+  if (!ctx) return MPSL_EINVAL;
+  if (!ctx->tables_ok) return MPSL_ESTATE;
+  const mpsl::SommPlan &pl = ctx->somm;
+  if (active) *active = pl.active ? 1 : 0;
+  if (tiles) *tiles = pl.active ? pl.nT : 0;
+  if (intervals) *intervals = pl.active ? pl.nint : 0;
+  if (coarse_nodes) *coarse_nodes = pl.active ? pl.nc : 0;
+  if (direct_nodes) *direct_nodes = pl.active ? pl.ndir : 0;
+  return MPSL_OK;
+}
