@@ -272,17 +272,23 @@ def _batch_workload(args, torch, mp):
     return out
 
 
-def _serve_workload(args, torch, mp):
-    """A Poisson stream of design-loop requests through the continuous-batching server."""
+def _serve_requests(mp, nreq, prec, n_max=20000):
+    """The design-loop request stream: N log-uniform in [200, n_max], p in
+    {8, 12, 16}, star or disk, k2 ~ U[6, 12], d ~ U[8, 60], strip of height
+    d - 2 and width N / (0.3 (d - 2)), source at (0, 2); span-rule contours
+    resolving the strip's width (h = 12 / X for the mixed solves' 1e-6, 6 / X
+    for FP64's 1e-10) with the interpolated Sommerfeld transforms, except
+    where that rule would pass 2^19 nodes (count rule, 1024 nodes, reported);
+    the cluster-block preconditioner; tol 1e-6 (mixed) / 1e-10 (FP64)."""
     import numpy as np
 
     from synth import rejection_layout
 
     rng = np.random.default_rng(6)
-    nreq = args.requests
-
-    def make(i):
-        n = int(round(np.exp(rng.uniform(np.log(200), np.log(20000)))))
+    tol = 1e-6 if prec == 1 else 1e-10
+    reqs = []
+    for i in range(nreq):
+        n = int(round(np.exp(rng.uniform(np.log(200), np.log(n_max)))))
         p = int(rng.choice([8, 12, 16]))
         star = bool(rng.integers(0, 2))
         k2 = float(rng.uniform(6.0, 12.0))
@@ -290,18 +296,40 @@ def _serve_workload(args, torch, mp):
         h = d - 2.0
         width = n / (0.3 * h)
         xy, rot = rejection_layout(n, (-width / 2, width / 2), (-d + 1.0, -1.0), 0.75, 1000 + i)
-        return dict(k=(6.0, k2, 12.0), d=d, particle=1 if star else 0,
-                    shape=(0.25, 0.05, 5) if star else (0.25,), kp=15.0, p=p, xy=xy, rot=rot, n_nodes=1024,
-                    b=min(0.2, 2.0 / width), t_max=32.0, src=(0.0, 2.0), tol=1e-8, maxiter=400, n_bdry=128)
+        b, hmax = mp.span_contour_params(width, tol)
+        ns = len(mp.compute_contour_span((6.0, k2, 12.0), b, 24.0, hmax)[0]) if width < 40000 else 1 << 30
+        r = dict(k=(6.0, k2, 12.0), d=d, particle=1 if star else 0, shape=(0.25, 0.05, 5) if star else (0.25,),
+                 kp=15.0, p=p, xy=xy, rot=rot, src=(0.0, 2.0), tol=tol, maxiter=3000, n_bdry=128, precision=prec,
+                 precond=mp.PRECOND_CLUSTER, inner_tol=1e-5)
+        if ns <= (1 << 19):
+            r.update(contour=1, n_nodes=0, b=b, t_max=24.0, h_max=hmax, sommerfeld=mp.SOMM_INTERP)
+        else:
+            r.update(contour=0, n_nodes=1024, b=min(0.2, 2.0 / width), t_max=32.0)
+        reqs.append((r, ns))
+    return reqs
 
-    reqs = [make(i) for i in range(nreq)]
-    out = {"workload": (f"{nreq} requests: N log-uniform [200, 20000] (FMM far field above 8000), "
-                        "p in {8, 12, 16}, star or disk, k2 ~ U[6, 12], d ~ U[8, 60], 1024 nodes, tol 1e-8, "
-                        "at most 400 iterations; Poisson arrivals at 0.8 / (mean isolated service time)")}
-    for name, prec in (("fp64", 0), ("mixed", 1)):
+
+def _serve_workload(args, torch, mp, n_max=20000):
+    """A Poisson stream of design-loop requests through the continuous-batching server."""
+    import numpy as np
+
+    nreq = args.requests
+    far = " (FMM far field above 8000)" if n_max > 8000 else ""
+    out = {"workload": (f"{nreq} requests: N log-uniform [200, {n_max}]{far}, p in {{8, 12, 16}}, "
+                        "star or disk, k2 ~ U[6, 12], d ~ U[8, 60], span-rule contours (interpolated transforms) "
+                        "resolving each strip, cluster-block preconditioner, tol 1e-6 mixed / 1e-10 FP64; "
+                        "Poisson arrivals at 0.8 / (mean isolated service time)")}
+    modes = [(name, prec) for name, prec in (("mixed", 1), ("fp64", 0)) if name in args.serve_modes.split(",")]
+    for name, prec in modes:
+        reqs = _serve_requests(mp, nreq, prec, n_max)
         # isolated service time on a calibration sample
         srv = mp.Server(0, hbm_budget=200 << 30, max_active=1)
-        cal = [srv.wait(srv.submit(**dict(r, precision=prec))) for r in reqs[:6]]
+        cal = []
+        for i, (r, ns) in enumerate(reqs[:args.serve_calibration]):
+            cal.append(srv.wait(srv.submit(**r)))
+            print(f"# serve {name} calibration {i}: N {r['xy'].shape[0]}, p {r['p']}, {ns} nodes, "
+                  f"{cal[-1]['iterations']} its, {cal[-1]['t_finish'] - cal[-1]['t_submit']:.2f} s, "
+                  f"status {cal[-1]['status']}", file=sys.stderr, flush=True)
         srv.close()
         mean_service = float(np.mean([c["t_finish"] - c["t_submit"] for c in cal]))
         qps = 0.8 / mean_service
@@ -309,20 +337,30 @@ def _serve_workload(args, torch, mp):
         srv = mp.Server(0, hbm_budget=200 << 30, max_active=16)
         t0 = time.perf_counter()
         tickets = []
-        for r, g in zip(reqs, gaps):
+        for (r, _), g in zip(reqs, gaps):
             time.sleep(float(g))
-            tickets.append(srv.submit(**dict(r, precision=prec)))
-        res = [srv.wait(t) for t in tickets]
+            tickets.append(srv.submit(**r))
+        res = []
+        for i, t in enumerate(tickets):
+            res.append(srv.wait(t))
+            print(f"# serve {name} request {i}: {res[-1]['iterations']} its, "
+                  f"{res[-1]['t_finish'] - res[-1]['t_submit']:.2f} s, status {res[-1]['status']}",
+                  file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
         srv.close()
         lat = np.array([r["t_finish"] - r["t_submit"] for r in res]) * 1e3
-        conv = sum(1 for r in res if r["status"] == 0)
+        ok = np.array([r["status"] == 0 for r in res])
+        resolved = sum(1 for r, _ in reqs if r["contour"] == 1)
         out[name] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                      "mean_ms": float(lat.mean()), "throughput_req_s": nreq / wall, "qps_offered": qps,
-                     "mean_isolated_service_ms": mean_service * 1e3, "converged": conv, "requests": nreq,
-                     "iterations_mean": float(np.mean([r["iterations"] for r in res]))}
-        print(f"# serve {name}: p50 {out[name]['p50_ms']:.1f} ms, p99 {out[name]['p99_ms']:.1f} ms",
-              file=sys.stderr, flush=True)
+                     "mean_isolated_service_ms": mean_service * 1e3, "converged": int(ok.sum()), "requests": nreq,
+                     "p50_ms_converged": float(np.percentile(lat[ok], 50)) if ok.any() else None,
+                     "p99_ms_converged": float(np.percentile(lat[ok], 99)) if ok.any() else None,
+                     "span_rule_requests": resolved, "max_nodes": int(max(ns for _, ns in reqs)),
+                     "iterations_mean": float(np.mean([r["iterations"] for r in res])),
+                     "statuses": sorted(set(int(r["status"]) for r in res))}
+        print(f"# serve {name}: p50 {out[name]['p50_ms']:.1f} ms, p99 {out[name]['p99_ms']:.1f} ms, "
+              f"{int(ok.sum())}/{nreq} converged", file=sys.stderr, flush=True)
     return out
 
 
@@ -428,8 +466,19 @@ def _solve_leg(args, mp, ctx, wl, flops):
     res["field_4096_receivers"] = {
         "mixed_vs_fp64_rel_l2": float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64)),
         "mixed_vs_fp64_max_rel": float(np.max(np.abs(u32 - u64)) / np.max(np.abs(u64))),
-        "note": "both solves to relative residual 1e-6; the difference bounds how far the mixed-precision "
-                "solution is from the FP64 one, not from the continuous problem"}
+        "note": "both solves to relative residual 1e-6; the difference is that tolerance amplified by the "
+                "conditioning, not the error of the FP32 arithmetic"}
+    # the mixed-precision field error itself: mixed to 1e-8 against an FP64 reference to 1e-10
+    bt, mt = ctx.solve(srcs[0], precision=1, tol=1e-8, maxiter=args.solve_maxiter, inner_tol=1e-5)
+    br, mr = ctx.solve(srcs[0], precision=0, tol=1e-10, maxiter=args.solve_maxiter)
+    ut, ur = ctx.eval_field(srcs[0], bt, rcv), ctx.eval_field(srcs[0], br, rcv)
+    res["field_4096_receivers"]["tight"] = {
+        "mixed_tol": 1e-8, "fp64_tol": 1e-10, "mixed_iterations": mt["iterations"],
+        "fp64_iterations": mr["iterations"], "converged": bool(mt["status"] == 0 and mr["status"] == 0),
+        "mixed_seconds": mt["seconds"], "fp64_seconds": mr["seconds"],
+        "mixed_vs_fp64_rel_l2": float(np.linalg.norm(ut - ur) / np.linalg.norm(ur)),
+        "mixed_vs_fp64_max_rel": float(np.max(np.abs(ut - ur)) / np.max(np.abs(ur)))}
+    print(f"# tight pair: {json.dumps(res['field_4096_receivers']['tight'])}", file=sys.stderr, flush=True)
     return res
 
 
@@ -459,6 +508,8 @@ def _span_leg(args, torch, mp, wl, x, y_count):
         ctx.apply_dev(0, xd, yd)
         torch.cuda.synchronize()
         leg = {"h_max": hf / X, "n_nodes": ns, "sommerfeld": "interp" if method == mp.SOMM_INTERP else "direct"}
+        if method == mp.SOMM_INTERP:
+            leg["somm_plan"] = ctx.somm_info()
         for name, prec in (("fp32", 1), ("fp64", 0)):
             dt, m2l_ms, _, fin = _matvec_rate(ctx, torch, prec, x, args.steps, args.warmup)
             leg[name] = {"matvecs_per_s": args.steps / dt, "ms_per_matvec": dt / args.steps * 1e3,
@@ -498,6 +549,10 @@ def main():
                     help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching; "
                          "serve: Poisson request stream through the server; fmm: 20000 particles, FMM vs direct")
     ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
+    ap.add_argument("--serve-calibration", type=int, default=6, help="serve: requests timed alone for the QPS")
+    ap.add_argument("--serve-modes", default="mixed,fp64", help="serve: precisions to run (mixed, fp64)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the short serving leg")
+    ap.add_argument("--no-fmm20k", action="store_true", help="skip the short 20000-particle FMM leg")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -652,6 +707,18 @@ def main():
         short.steps, short.warmup = 5, 1
         out["batch"] = _batch_workload(short, torch, mp)
         print(f"# batch: {json.dumps(out['batch'])}", file=sys.stderr, flush=True)
+    if not args.no_fmm20k:
+        short = argparse.Namespace(**vars(args))
+        short.steps = 10
+        out["fmm_20000"] = _fmm_workload(short, torch, mp)
+        print(f"# fmm 20000: {json.dumps(out['fmm_20000'])}", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        # a short request stream of the serving mix with N up to 2000 (the
+        # full mix: --workload serve)
+        short = argparse.Namespace(**vars(args))
+        short.requests, short.serve_calibration, short.serve_modes = 8, 4, "mixed,fp64"
+        out["serve_short"] = _serve_workload(short, torch, mp, n_max=2000)
+        print(f"# serve (short): {json.dumps(out['serve_short'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(wl, S, x)
     print(json.dumps(out), flush=True)
