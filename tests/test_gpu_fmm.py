@@ -6,7 +6,9 @@ and a mixed-precision solve through the FMM reaches 1e-6 in the field.
 The error is measured as the matvec sees it: the local expansions pass
 through the particles' rotated scattering matrices before they enter
 y = x - S (T + T_R) x, so the check is on S (alpha_fmm - alpha_ref)
-relative to S alpha_ref, with beta in the range of S (coeff_vector)."""
+relative to S alpha_ref, with beta in the range of S (coeff_vector).  The
+raw local expansions are held to the same bounds (measured FP64 6.8e-12 at
+200 stars and 5.3e-14 at 1000; FP32 1.4e-6 and 7.7e-7)."""
 import numpy as np
 import pytest
 
@@ -61,8 +63,10 @@ def test_fmm_m2l_matches_direct(name, rows, prec):
     rows = list(range(wl.n)) if rows is None else rows
     ref = m2l_apply(wl.xy, wl.k2, wl.p, x, targets=rows)
     err = _weighted_err(wl, got[rows], ref, rows)
-    print("weighted err", err, "raw err", rel_err(got[rows], ref), flush=True)
+    raw = rel_err(got[rows], ref)
+    print("weighted err", err, "raw err", raw, flush=True)
     assert err < FP_TOL[prec], err
+    assert raw < FP_TOL[prec], raw
     assert np.all(np.isfinite(got))
 
 
@@ -135,8 +139,10 @@ def test_fmm_auto_at_20000_sampled(big, prec):
     rows = [0, 4999, 10000, 19999]
     ref = m2l_apply(wl.xy, wl.k2, wl.p, x, targets=rows)
     err = _weighted_err(wl, got[rows], ref, rows)
-    print("weighted err", err, flush=True)
+    raw = rel_err(got[rows], ref)
+    print("weighted err", err, "raw err", raw, flush=True)
     assert err < FP_TOL[prec], err
+    assert raw < FP_TOL[prec], raw
     assert np.all(np.isfinite(got))
 
 
