@@ -175,6 +175,92 @@ def _cpu_baseline(wl, S, x, n_targets=24):
                        f"({n_targets} targets)")}
 
 
+def _cpu_baseline_full(args):
+    """The rest of the oracle timing plan, on the host alone (no GPU): the
+    dense assembly of eq. (49) and its LU solve for the 16-disk (C1) and the
+    1000-star (C2) recipes with BLAS threads on every core, and the oracle's
+    matrix-free matvec for two right-hand sides and two of the perturbed
+    configurations of the 2000-star batching recipe (C4).  The 5000-star
+    dense system (436 GB) is out of reach; its matrix-free matvec is the
+    default run's cpu_baseline."""
+    import concurrent.futures
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import contour as oc
+    from oracle import mie as omie
+    from oracle import star as ostar
+    from oracle import system as osys
+    from synth import make_workload, perturbed_layout, rejection_layout
+
+    model, cores = _host_cpu()
+    out = {"kind": "oracle", "cpu_model": model, "cores": cores}
+
+    def problem(wl, S, xy=None, rot=None, d=None, b=None):
+        lam, w = oc.contour(wl.n_nodes, wl.b if b is None else b, wl.t_max, [wl.k1, wl.k2, wl.k3])
+        return osys.Problem(wl.k1, wl.k2, wl.k3, wl.d if d is None else d, wl.p, S,
+                            wl.xy if xy is None else xy, wl.rot if rot is None else rot, lam, w)
+
+    def smatrix(wl):
+        if wl.shape == "disk":
+            return np.diag(omie.disk_smatrix(wl.shape_params[0], wl.k2, wl.kp, wl.p))
+        a1, a2, a3 = wl.shape_params
+        return ostar.star_smatrix(a1, a2, a3, wl.k2, wl.kp, wl.p, nb=256)
+
+    for name in ("c1", "c2"):
+        wl = make_workload(name)
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            S = smatrix(wl)
+            t1 = time.perf_counter()
+            pr = problem(wl, S)
+            K = pr.dense()
+            t2 = time.perf_counter()
+            print(f"# cpu {name}: assembled {wl.n * wl.P} unknowns in {t2 - t1:.1f} s", file=sys.stderr, flush=True)
+            b = pr.rhs(wl.src[0]).reshape(-1)
+            beta = np.linalg.solve(K, b)
+            t3 = time.perf_counter()
+        res = float(np.linalg.norm(K @ beta - b) / np.linalg.norm(b))
+        del K
+        out[name] = {"particles": wl.n, "unknowns": wl.n * wl.P, "scattering_matrix_s": t1 - t0,
+                     "assembly_s": t2 - t1, "lu_solve_s": t3 - t2, "relative_residual": res}
+        print(f"# cpu {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+
+    wl = make_workload("c4", n_rhs=2, src_seed=4)
+    with threadpool_limits(limits=cores):
+        S = smatrix(wl)
+    rng = np.random.default_rng(5)
+    ns = np.round(np.exp(rng.uniform(np.log(500), np.log(4000), 32))).astype(int)
+    cases = [("rhs 0", wl.xy, wl.rot, wl.d, wl.b, wl.src[0]), ("rhs 1", wl.xy, wl.rot, wl.d, wl.b, wl.src[1])]
+    for i in range(2):
+        width = ns[i] / (0.3 * 18.0)
+        xy, rot = rejection_layout(int(ns[i]), (-width / 2, width / 2), (-19.0, -1.0), 0.75, 100 + i)
+        xy, rot = perturbed_layout(xy, rot, 0.05, 200 + i, 0.75, y_range=(-19.6, -0.4))
+        cases.append((f"config {i} (N = {ns[i]})", xy, rot, 20.0, min(0.2, 2.0 / width), (0.0, 2.0)))
+    c4 = []
+    with concurrent.futures.ProcessPoolExecutor(max_workers=cores) as ex:
+        for label, xy, rot, d, b, src in cases:
+            pr = problem(wl, S, xy, rot, d, b)
+            x = pr.rhs(src)
+            n = xy.shape[0]
+            tg = list(range(n))
+            parts = [(xy, wl.k2, wl.p, x, tg[i::cores]) for i in range(cores)]
+            a0 = time.perf_counter()
+            list(ex.map(_oracle_m2l_part, parts))
+            a1 = time.perf_counter()
+            with threadpool_limits(limits=cores):
+                pr.apply_S(pr.layer_local(beta=x))   # M2S, node solves, S2L and the S apply
+                a2 = time.perf_counter()
+            c4.append({"case": label, "particles": int(n), "m2l_s": a1 - a0, "layered_s": a2 - a1,
+                       "matvec_s": a2 - a0})
+            print(f"# cpu c4 {label}: {json.dumps(c4[-1])}", file=sys.stderr, flush=True)
+    out["c4_matvecs"] = c4
+    out["c3_note"] = ("5000 stars: dense LU needs 436 GB; the matrix-free matvec is the default run's "
+                      "cpu_baseline, and a 1450-iteration GMRES at that rate is the matvec time times 1450")
+    return out
+
+
 def _batch_workload(args, torch, mp):
     """64 sources over one 2000-star p = 12 geometry, and 32 perturbed configurations."""
     import numpy as np
@@ -337,15 +423,26 @@ def _serve_workload(args, torch, mp, n_max=20000):
         srv = mp.Server(0, hbm_budget=200 << 30, max_active=16)
         t0 = time.perf_counter()
         tickets = []
-        for (r, _), g in zip(reqs, gaps):
+        for i, ((r, ns), g) in enumerate(zip(reqs, gaps)):
             time.sleep(float(g))
             tickets.append(srv.submit(**r))
-        res = []
-        for i, t in enumerate(tickets):
-            res.append(srv.wait(t))
-            print(f"# serve {name} request {i}: {res[-1]['iterations']} its, "
-                  f"{res[-1]['t_finish'] - res[-1]['t_submit']:.2f} s, status {res[-1]['status']}",
-                  file=sys.stderr, flush=True)
+            print(f"# serve {name} submitted {i} at {time.perf_counter() - t0:.1f} s: N {r['xy'].shape[0]}, "
+                  f"p {r['p']}, {ns} nodes", file=sys.stderr, flush=True)
+        res = [None] * len(tickets)
+        pending = list(range(len(tickets)))
+        while pending:  # in order of completion
+            left = []
+            for i in pending:
+                r = srv.wait(tickets[i], timeout=0.0)
+                if r is None:
+                    left.append(i)
+                    continue
+                res[i] = r
+                print(f"# serve {name} request {i}: {r['iterations']} its, "
+                      f"{r['t_finish'] - r['t_submit']:.2f} s, status {r['status']}", file=sys.stderr, flush=True)
+            pending = left
+            if pending:
+                time.sleep(0.05)
         wall = time.perf_counter() - t0
         srv.close()
         lat = np.array([r["t_finish"] - r["t_submit"] for r in res]) * 1e3
@@ -545,9 +642,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="use the default M2L launch shape")
     ap.add_argument("--no-fmm", action="store_true", help="skip the FMM far-field comparison")
     ap.add_argument("--no-span", action="store_true", help="skip the span-rule contour legs")
-    ap.add_argument("--workload", choices=["c3", "batch", "serve", "fmm"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "batch", "serve", "fmm", "cpu"], default="c3",
                     help="c3: the 5000-particle matvec (default); batch: multi-RHS and multi-config batching; "
-                         "serve: Poisson request stream through the server; fmm: 20000 particles, FMM vs direct")
+                         "serve: Poisson request stream through the server; fmm: 20000 particles, FMM vs direct; "
+                         "cpu: the oracle's dense assembly and LU (16 disks, 1000 stars) and matvecs of the "
+                         "2000-star batching recipe on the host (no GPU)")
     ap.add_argument("--requests", type=int, default=40, help="serve: number of requests")
     ap.add_argument("--serve-calibration", type=int, default=6, help="serve: requests timed alone for the QPS")
     ap.add_argument("--serve-modes", default="mixed,fp64", help="serve: precisions to run (mixed, fp64)")
@@ -559,6 +658,10 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.workload == "cpu":
+        print(json.dumps({"cpu_baseline_full": _cpu_baseline_full(args)}), flush=True)
+        return
 
     import numpy as np
     import torch
