@@ -1403,8 +1403,12 @@ int chunks_s2l(const mpsl_ctx *ctx, int nrhs) {
 
 int chunks_m2s(const mpsl_ctx *ctx, int nrhs) {
   if (ctx->m2s_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2s_chunks, ctx->n));
+  // about 2048 node-group x chunk tasks, but at least 80 particles per chunk:
+  // shorter chunks spend more on the epilogue and on summing the partials
+  // than they gain in parallelism (1024 nodes, 5000 particles: 256 -> 63
+  // chunks, M2S and partial sum 75 -> about 45 us in FP32)
   const int qb = cdiv(ctx->ns, kThreads) * 2 * nrhs;
-  const int c = cdiv(2048, qb);
+  const int64_t c = std::min<int64_t>(cdiv(2048, qb), cdiv(ctx->n, 80));
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
 }
 
