@@ -43,6 +43,22 @@ __device__ inline cx<double> cexp64(double a, double b) {
   return {e * c, e * s};
 }
 template <typename T> __device__ inline cx<T> cvt(cx<double> v) { return {static_cast<T>(v.re), static_cast<T>(v.im)}; }
+
+// e^{a + i b} in the matvec precision.  FP64: as cexp64.  FP32: the phase
+// (up to |lambda| times the strip width) is reduced modulo 2 pi in FP64 with
+// a two-term 2 pi, then the exponential and the sine and cosine are evaluated
+// in FP32 (the result is rounded to FP32 anyway; relative error ~2e-7).
+template <typename T> __device__ inline cx<T> cexpT(double a, double b);
+template <> __device__ inline cx<double> cexpT<double>(double a, double b) { return cexp64(a, b); }
+template <> __device__ inline cx<float> cexpT<float>(double a, double b) {
+  constexpr double kTwoPiHi = 6.283185307179586, kTwoPiLo = 2.4492935982947064e-16;
+  const double k = rint(b * 0.15915494309189535);
+  const float r = static_cast<float>(fma(-k, kTwoPiHi, b) - k * kTwoPiLo);
+  float sn, cs;
+  sincosf(r, &sn, &cs);
+  const float e = expf(static_cast<float>(a));
+  return {e * cs, e * sn};
+}
 template <typename T> __device__ inline cx<double> up(cx<T> v) { return {static_cast<double>(v.re), static_cast<double>(v.im)}; }
 
 
@@ -72,7 +88,7 @@ __global__ __launch_bounds__(256) void k_si_tileG(const cv_t<T> *__restrict__ be
     const int m = perm[k];
     const double dx = xy[m].x - xT, dy = xy[m].y - yT;
     // e^{-i lam dx + sg g2 dy}
-    const cx<T> e = cvt<T>(cexp64(li * dx + sg * gr * dy, -lr * dx + sg * gi * dy));
+    const cx<T> e = cexpT<T>(li * dx + sg * gr * dy, -lr * dx + sg * gi * dy);
     const cv_t<T> *b = beta + static_cast<int64_t>(m) * P;
     cx<T> bw = mk<T>(0, 0);
 #pragma unroll
@@ -166,7 +182,7 @@ __global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine_dir(
     for (int t = j; t < nT; t += kSiFineSplit) {
       const double xT = txy[t].x, yT = txy[t].y;
       const double yy = s == 0 ? yT : -(d + yT);
-      acc = acc + cexp64(li * xT + gr * yy, -lr * xT + gi * yy) * up<T>(ld<T>(Gs[static_cast<int64_t>(t) * nc]));
+      acc = acc + up<T>(cexpT<T>(li * xT + gr * yy, -lr * xT + gi * yy)) * up<T>(ld<T>(Gs[static_cast<int64_t>(t) * nc]));
     }
   }
   red[j][ql] = st(acc);
@@ -212,9 +228,9 @@ __global__ __launch_bounds__(256) void k_si_coarseB_dir(const double2 *__restric
   const double xT = txy[t].x, yT = txy[t].y;
   const double yy = s == 0 ? yT : -(yT + d);
   const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
-  const cx<double> v = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]) *
-                       cexp64(-li * xT + gr * yy, lr * xT + gi * yy);
-  B[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c] = st(cvt<T>(v));
+  const cx<T> v = cvt<T>(ld<double>(cq[q]) * ld<double>(sigma[s * ns + q])) *
+                  cexpT<T>(-li * xT + gr * yy, lr * xT + gi * yy);
+  B[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c] = st(v);
 }
 
 
@@ -275,7 +291,7 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_alpha_mfma(
       // e^{i lam_c dx + sg g2_c dy} B[T][c]
       const double sg = s == 0 ? 1.0 : -1.0;
       const double lr = lamc[c].x, li = lamc[c].y, gr = gc[c].x, gi = gc[c].y;
-      a = cvt<T>(cexp64(-li * dx + sg * gr * dy, lr * dx + sg * gi * dy)) *
+      a = cexpT<T>(-li * dx + sg * gr * dy, lr * dx + sg * gi * dy) *
           ld<T>(B[((static_cast<int64_t>(rr) * 2 + s) * nT + t) * nc + c]);
     }
     const T as = a.re + a.im;
@@ -414,7 +430,7 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_coarseB_mfma(
     if (kv && tv) {
       const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
       const cx<double> u = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]);
-      v = cvt<T>(u * cexp64(-li * xT + gr * yy, lr * xT + gi * yy));
+      v = cvt<T>(u) * cexpT<T>(-li * xT + gr * yy, lr * xT + gi * yy);
     }
     const double *L = Lw + static_cast<int64_t>(q) * kSommNc;
 #pragma unroll
