@@ -36,31 +36,72 @@ constexpr double kTileW = 8.0, kTileH = 4.0, kIntervalL = 1.0, kDirect = 0.3;
 #define SOMM_P_CASES(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20)
 
-__device__ inline cx<double> cexp64(double a, double b) {
-  double s, c;
-  sincos(b, &s, &c);
-  const double e = exp(a);
-  return {e * c, e * s};
+// sin and cos of r, |r| <= pi / 4, by their Taylor series (terms up to r^9
+// and r^10 in FP32, r^17 and r^18 in FP64: the first term left out is below
+// 2e-10 and 1e-19 there).
+__device__ inline void sincos_quarter(float r, float &s, float &c) {
+  const float r2 = r * r;
+  s = r * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
+  c = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320 + r2 * (-1.0f / 3628800)))));
 }
-template <typename T> __device__ inline cx<T> cvt(cx<double> v) { return {static_cast<T>(v.re), static_cast<T>(v.im)}; }
+__device__ inline void sincos_quarter(double r, double &s, double &c) {
+  const double r2 = r * r;
+  double ps = 1.0 / 355687428096000.0, pc = 1.0 / 6402373705728000.0;  // 1/17!, 1/18!
+  ps = 1.0 / 1307674368000.0 - r2 * ps;   // 1/15!
+  ps = 1.0 / 6227020800.0 - r2 * ps;      // 1/13!
+  ps = 1.0 / 39916800.0 - r2 * ps;        // 1/11!
+  ps = 1.0 / 362880.0 - r2 * ps;          // 1/9!
+  ps = 1.0 / 5040.0 - r2 * ps;
+  ps = 1.0 / 120.0 - r2 * ps;
+  ps = 1.0 / 6.0 - r2 * ps;
+  s = r * (1.0 - r2 * ps);
+  pc = 1.0 / 20922789888000.0 - r2 * pc;  // 1/16!
+  pc = 1.0 / 87178291200.0 - r2 * pc;     // 1/14!
+  pc = 1.0 / 479001600.0 - r2 * pc;       // 1/12!
+  pc = 1.0 / 3628800.0 - r2 * pc;         // 1/10!
+  pc = 1.0 / 40320.0 - r2 * pc;
+  pc = 1.0 / 720.0 - r2 * pc;
+  pc = 1.0 / 24.0 - r2 * pc;
+  pc = 0.5 - r2 * pc;
+  c = 1.0 - r2 * pc;
+}
 
-// e^{a + i b} in the matvec precision.  FP64: as cexp64.  FP32: the phase
-// (up to |lambda| times the strip width) is reduced modulo 2 pi in FP64 with
-// a two-term 2 pi, then the exponential and the sine and cosine are evaluated
-// in FP32 (the result is rounded to FP32 anyway; relative error ~2e-7).
-template <typename T> __device__ inline cx<T> cexpT(double a, double b);
-template <> __device__ inline cx<double> cexpT<double>(double a, double b) { return cexp64(a, b); }
-template <> __device__ inline cx<float> cexpT<float>(double a, double b) {
-  constexpr double kTwoPiHi = 6.283185307179586, kTwoPiLo = 2.4492935982947064e-16;
-  const double k = rint(b * 0.15915494309189535);
-  const float r = static_cast<float>(fma(-k, kTwoPiHi, b) - k * kTwoPiLo);
-  float sn, cs;
-  sincosf(r, &sn, &cs);
-  const float e = expf(static_cast<float>(a));
+// e^{a + i b} in the matvec precision.  The phase b (up to |lambda| times the
+// strip width) is reduced in FP64 to r = b - k pi/2, |r| <= pi/4, with a
+// two-term pi/2 (Cody and Waite); sin and cos of r come from the series
+// above in T and are rotated by k quarter turns; exp(a) in T.  In FP32 the
+// relative error is ~2e-7 (the result is rounded to FP32 anyway); in FP64 a
+// few units in the last place.  No large-argument path: every lane runs the
+// same instructions.
+template <typename T> __device__ inline cx<T> cexpT(double a, double b) {
+  constexpr double kHalfPiHi = 1.5707963267948966, kHalfPiLo = 6.123233995736766e-17;
+  const double k = rint(b * 0.6366197723675814);
+  const double r = fma(-k, kHalfPiLo, fma(-k, kHalfPiHi, b));
+  T sr, cr;
+  sincos_quarter(static_cast<T>(r), sr, cr);
+  const int qd = static_cast<int>(static_cast<long long>(k) & 3);
+  const T sn = qd == 0 ? sr : qd == 1 ? cr : qd == 2 ? -sr : -cr;
+  const T cs = qd == 0 ? cr : qd == 1 ? -sr : qd == 2 ? -cr : sr;
+  const T e = exp(static_cast<T>(a));
   return {e * cs, e * sn};
 }
+__device__ inline cx<double> cexp64(double a, double b) { return cexpT<double>(a, b); }
+template <typename T> __device__ inline cx<T> cvt(cx<double> v) { return {static_cast<T>(v.re), static_cast<T>(v.im)}; }
 template <typename T> __device__ inline cx<double> up(cx<T> v) { return {static_cast<double>(v.re), static_cast<double>(v.im)}; }
 
+
+// 16x16x4 MFMA of the precision T and the row a result register holds.
+template <typename T> struct si_mfma;
+template <> struct si_mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
+template <> struct si_mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
+};
 
 // M2S, step 1 (FP32): one lane per (tile, coarse node), blockIdx.z = 2 rhs + side.
 // (The matrix-core form below is slower in FP32 at ~10 particles per tile.)
@@ -98,68 +139,88 @@ __global__ __launch_bounds__(256) void k_si_tileG(const cv_t<T> *__restrict__ be
   G[((static_cast<int64_t>(r) * 2 + s) * nT + t) * nc + c] = st(acc);
 }
 
-// M2S, step 2, interval nodes: one block per (interval, run of kSiFineNodes
-// of its nodes) from the table fblk; kSiFineSplit lanes per node, each
-// summing a quarter of the tile list, combined through LDS in a fixed order.
-// The interval's coarse values G[T][c0 .. c0 + kSommNc) and weights come
-// through wave-uniform loads; spectra in FP64 as the direct path.
-constexpr int kSiFineSplit = 4;
-constexpr int kSiFineNodes = 64;  // nodes per block (block: kSiFineNodes * kSiFineSplit lanes)
+// M2S, step 2, interval nodes, on the matrix cores: per interval
+//   H[T][q] = sum_k G[T][c0 + k] L[q][k]      (M = tile, N = node, K = 24)
+//   spec[q] = sum_T e^{-i lam_q x_T + g2_q yy_T} H[T][q]
+// One wave per 16 nodes of a block's run of kSiFineNodes (from fblk), all
+// tiles in steps of 16: lane i supplies A[i % 16][i / 16] = G of tile
+// tb + i % 16 (complex, two real MFMAs) and B[i / 16][i % 16] = L of node
+// i % 16 (loaded once).  The result rows a lane holds are four tiles of its
+// node column; along a column their factors change by e^{-g2 h} per tile
+// height in the direction in which they shrink (down on side 0, up on side
+// 1; no FP32 overflow), and the four tiles are walked in that order with an
+// exponential where a column starts.  Each lane sums per step in the matvec
+// precision and across steps in FP64; the four row groups are added at the end.
+constexpr int kSiFineSplit = 4;   // waves per block
+constexpr int kSiFineNodes = 64;  // nodes per block (16 per wave)
 template <typename T>
-__global__ __launch_bounds__(kSiFineNodes *kSiFineSplit) void k_si_fine(
+__global__ __launch_bounds__(64 * kSiFineSplit) void k_si_fine(
     const cv_t<T> *__restrict__ G, const double2 *__restrict__ lam, const double2 *__restrict__ g2,
     const double2 *__restrict__ txy, const int *__restrict__ ivl, const int *__restrict__ fperm,
     const int *__restrict__ fblk, const double *__restrict__ Lw, int ns, int nT, int nc, double d,
     double tile_h, double2 *__restrict__ spec) {
-  static_assert(kSiFineNodes == 64, "one wave per tile share");
-  __shared__ double2 red[kSiFineSplit][kSiFineNodes];
-  // the tile share is the wave index: wave-uniform, so the tile loop's loads are scalar
-  const int j = __builtin_amdgcn_readfirstlane(threadIdx.x / kSiFineNodes), ql = threadIdx.x - j * kSiFineNodes;
-  const int iv = fblk[2 * blockIdx.x], off = fblk[2 * blockIdx.x + 1];
+  static_assert(kSiFineNodes == 16 * kSiFineSplit, "16 nodes per wave");
+  typedef typename si_mfma<T>::v4 v4;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  // XCD-aware order: blocks are dealt to the 8 XCDs round-robin, so block b
+  // takes run x q + min(x, rem) + b / 8 (x = b % 8) and each XCD works
+  // through consecutive runs of the same intervals
+  const int nb = gridDim.x, xq = nb / 8, xr = nb % 8, x = blockIdx.x % 8;
+  const int fb = x * xq + min(x, xr) + blockIdx.x / 8;
+  const int iv = fblk[2 * fb], off = fblk[2 * fb + 1] + 16 * w;
   const int f0 = ivl[4 * iv], nf = ivl[4 * iv + 1], c0 = ivl[4 * iv + 2];
-  const bool act = off + ql < nf;
-  const int q = fperm[f0 + (act ? off + ql : 0)];
-  const int s = blockIdx.y & 1, r = blockIdx.y >> 1;
+  if (off >= nf) return;  // the whole wave lies past the interval's nodes (no barriers below)
+  const int s = blockIdx.y & 1, rr = blockIdx.y >> 1;
+  const bool qv = off + r < nf;
+  const int q = fperm[f0 + (qv ? off + r : off)];
+  T bl[6];  // B operand of the six K steps: L[q][4 ks + g]
+#pragma unroll
+  for (int ks = 0; ks < 6; ++ks) bl[ks] = qv ? static_cast<T>(Lw[static_cast<int64_t>(q) * kSommNc + 4 * ks + g]) : T(0);
   const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
-  T wq[kSommNc];
+  const cx<T> Fd = cexpT<T>(-gr * tile_h, -gi * tile_h);
+  const double ih = 1.0 / tile_h;
+  const int jbeg = s == 0 ? 3 : 0, jstep = s == 0 ? -1 : 1;
+  const cv_t<T> *Gs = G + ((static_cast<int64_t>(rr) * 2 + s) * nT) * nc + c0;
+  cx<double> acc = mk(0.0, 0.0);
+  for (int tb = 0; tb < nT; tb += 16) {
+    const int ta = tb + r;
+    const bool av = ta < nT;
+    const cv_t<T> *Ga = Gs + static_cast<int64_t>(av ? ta : 0) * nc + g;
+    v4 hr = v4{0, 0, 0, 0}, hi = v4{0, 0, 0, 0};
 #pragma unroll
-  for (int k = 0; k < kSommNc; ++k) wq[k] = static_cast<T>(Lw[static_cast<int64_t>(q) * kSommNc + k]);
-  const cv_t<T> *Gs = G + ((static_cast<int64_t>(r) * 2 + s) * nT) * nc + c0;
-  // e^{-i lam x_T + g2 y_T} (side 0), e^{-i lam x_T - g2 (d + y_T)} (side 1).  Wave j
-  // walks a contiguous range of the tile list, which is column by column (x, then y):
-  // along a column the factor changes by Fy^k for a step of k tile heights, so the
-  // exponential is evaluated only where a column starts or a gap is long.
-  const double sg = s == 0 ? 1.0 : -1.0;
-  const cx<double> Fy = cexp64(sg * gr * tile_h, sg * gi * tile_h);
-  const int ta = static_cast<int>((static_cast<int64_t>(nT) * j) / kSiFineSplit);
-  const int tb = static_cast<int>((static_cast<int64_t>(nT) * (j + 1)) / kSiFineSplit);
-  cx<double> acc = mk(0.0, 0.0), E = mk(0.0, 0.0);
-  double xp = 0.0, yp = 0.0;
-  for (int t = ta; t < tb; ++t) {
-    const double xT = txy[t].x, yT = txy[t].y;
-    const int k = t > ta && xT == xp ? static_cast<int>(lrint((yT - yp) / tile_h)) : 0;
-    if (k >= 1 && k <= 4) {
-      for (int u = 0; u < k; ++u) E = E * Fy;
-    } else {
-      const double yy = s == 0 ? yT : -(d + yT);
-      E = cexp64(li * xT + gr * yy, -lr * xT + gi * yy);
+    for (int ks = 0; ks < 6; ++ks) {
+      const cx<T> a = av ? ld<T>(Ga[4 * ks]) : mk<T>(0, 0);
+      hr = si_mfma<T>::mac(a.re, bl[ks], hr);
+      hi = si_mfma<T>::mac(a.im, bl[ks], hi);
     }
-    xp = xT;
-    yp = yT;
-    const cv_t<T> *Gt = Gs + static_cast<int64_t>(t) * nc;
-    cx<T> h = mk<T>(0, 0);
+    cx<T> E = mk<T>(0, 0), blk = mk<T>(0, 0);
+    double xp = 0.0, yp = 0.0;
 #pragma unroll
-    for (int k = 0; k < kSommNc; ++k) h = h + wq[k] * ld<T>(Gt[k]);
-    acc = acc + E * up<T>(h);
+    for (int u = 0; u < 4; ++u) {
+      const int j = jbeg + jstep * u;
+      const int t = tb + si_mfma<T>::row(lane, j);
+      if (t < nT) {
+        const double xT = txy[t].x, yT = txy[t].y;
+        const int k = u > 0 && xT == xp ? static_cast<int>(lrint(fabs(yT - yp) * ih)) : 0;
+        if (k >= 1 && k <= 4) {
+          for (int v = 0; v < k; ++v) E = E * Fd;
+        } else {
+          const double yy = s == 0 ? yT : -(d + yT);
+          E = cexpT<T>(li * xT + gr * yy, -lr * xT + gi * yy);
+        }
+        xp = xT;
+        yp = yT;
+        cmac(blk, E, mk<T>(hr[j], hi[j]));
+      }
+    }
+    acc = acc + up<T>(blk);
   }
-  red[j][ql] = st(acc);
-  __syncthreads();
-  if (j == 0 && act) {
-    cx<double> sum = ld<double>(red[0][ql]);
-#pragma unroll
-    for (int u = 1; u < kSiFineSplit; ++u) sum = sum + ld<double>(red[u][ql]);
-    spec[(static_cast<int64_t>(r) * 2 + s) * ns + q] = st(sum);
-  }
+  acc.re += __shfl_xor(acc.re, 16);
+  acc.im += __shfl_xor(acc.im, 16);
+  acc.re += __shfl_xor(acc.re, 32);
+  acc.im += __shfl_xor(acc.im, 32);
+  if (g == 0 && qv) spec[(static_cast<int64_t>(rr) * 2 + s) * ns + q] = st(acc);
 }
 
 // M2S, step 2, direct nodes (their own coarse node, weight 1): one lane per
@@ -246,17 +307,6 @@ inline int cdv(int64_t a, int64_t b) { return static_cast<int>((a + b - 1) / b);
 // block; blockIdx.y takes a chunk of the (side, coarse node) pairs and writes
 // its own partial slot.
 constexpr int kSiAlphaWaves = 4;
-template <typename T> struct si_mfma;
-template <> struct si_mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
-};
-template <> struct si_mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
-};
 
 template <typename T, int p>
 __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_alpha_mfma(
