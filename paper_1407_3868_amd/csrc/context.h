@@ -86,6 +86,8 @@ struct SommPlan {
   DBuf dir;         // int32[ndir][2]: contour node and coarse node of each direct node
   DBuf G;           // work [nrhs][2][nT][nc] in the matvec precision
   DBuf fblk;        // M2S interval-node blocks: (interval, first node)
+  DBuf trow;        // int32[nT]: tiles in row-major order (by y, then x)
+  DBuf Fx;          // double2[ns]: e^{i lam_q w}, the factor between horizontally adjacent tiles
   DBuf Bp;          // S2L node-chunk partials [chunk][nrhs][2][nT][24 nint] in the matvec precision
   const void *sigma = nullptr;  // S2L densities recorded by the coefficient step
 };

@@ -439,69 +439,102 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_tileG_mfma(
 // S2L, step 1 for the Chebyshev intervals on the matrix cores:
 // B[T][k] = sum_q V_T(q) L[q][k] with V_T(q) = c_q sigma(q) e^{i lam_q x_T + sg g2_q y_T}
 // is a GEMM with M = tile, N = interpolation column k (24, two 16-column
-// tiles), K = the interval's fine nodes.  Lane i forms V for (tile i % 16,
-// node i / 16 of the step) — one FP64 exponential per (tile, node) — as the A
-// operand and loads L[q][k] for (node i / 16, column i % 16) as B; complex A
-// times real B in two real MFMAs.  grid: (interval, blocks of 16 * kSiAlphaWaves
-// tiles, chunk of the interval's nodes + nchunk * (2 rhs + side)); chunk cz
-// writes its own partial slot Bp[cz][rhs, side][t][k], k over the intervals'
-// coarse nodes (which come first in the coarse-node order), summed in order by
+// tiles), K = the interval's fine nodes.  A wave takes 16 RB tiles in
+// row-major order (trow) as RB row blocks: lane i owns tiles
+// trow[tw + RB (i % 16) + b], b < RB, consecutive in that order and usually
+// horizontal neighbours, and forms their V for node i / 16 of the step as the
+// A operand of row block b: one exponential for the first, then one complex
+// multiply by e^{i lam w} (modulus ~1, table Fx) per tile (an exponential
+// again where a row of tiles ends).  L[q][k] for (node i / 16, column i % 16)
+// is the B operand, shared by the row blocks; complex A times real B in two
+// real MFMAs.  grid: (interval, blocks of 16 RB * kSiAlphaWaves tiles, chunk
+// of the interval's nodes + nchunk * (2 rhs + side)); chunk cz writes its own
+// partial slot Bp[cz][rhs, side][t][k], k over the intervals' coarse nodes
+// (which come first in the coarse-node order), summed in order by
 // k_si_coarseB_sum.
+template <typename T> constexpr int coarse_rb() { return sizeof(T) == 4 ? 4 : 2; }
 template <typename T>
 __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_coarseB_mfma(
     const double2 *__restrict__ sigma, const double2 *__restrict__ cq, const double2 *__restrict__ lam,
-    const double2 *__restrict__ g2, const double2 *__restrict__ txy, const int *__restrict__ ivl,
-    const int *__restrict__ fperm, const double *__restrict__ Lw, int ns, int nT, int nci, int nchunk,
-    double d, cv_t<T> *__restrict__ Bp) {
+    const double2 *__restrict__ g2, const double2 *__restrict__ Fx, const double2 *__restrict__ txy,
+    const int *__restrict__ trow, const int *__restrict__ ivl, const int *__restrict__ fperm,
+    const double *__restrict__ Lw, int ns, int nT, int nci, int nchunk, double d, double tile_w,
+    cv_t<T> *__restrict__ Bp) {
+  constexpr int RB = coarse_rb<T>();
   typedef typename si_mfma<T>::v4 v4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const int iv = blockIdx.x;
-  const int tw = (blockIdx.y * kSiAlphaWaves + w) * 16;  // first tile of this wave
+  const int tw = (blockIdx.y * kSiAlphaWaves + w) * 16 * RB;  // first row-major slot of this wave
   const int cz = blockIdx.z % nchunk, rs = blockIdx.z / nchunk;
   const int s = rs & 1, rr = rs >> 1;
   const int f0 = ivl[4 * iv], nf = ivl[4 * iv + 1], c0 = ivl[4 * iv + 2];
   const int i0 = static_cast<int>((static_cast<int64_t>(nf) * cz) / nchunk);
   const int i1 = static_cast<int>((static_cast<int64_t>(nf) * (cz + 1)) / nchunk);
   sigma += static_cast<int64_t>(rr) * 2 * ns;
-  const int ta = tw + r;  // this lane's tile (A row)
-  const bool tv = ta < nT;
-  const double2 tc = txy[tv ? ta : 0];
-  const double xT = tc.x;
-  const double yy = s == 0 ? tc.y : -(tc.y + d);
-  v4 acc[2][2];
+  // this lane's tiles, their centres, and the steps between them (0: new exponential)
+  int tb[RB], kst[RB];
+  double xb[RB], yb[RB];
+  const double iw = 1.0 / tile_w;
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt) acc[nt][0] = acc[nt][1] = v4{0, 0, 0, 0};
+  for (int b = 0; b < RB; ++b) {
+    const int o = tw + RB * r + b;
+    tb[b] = o < nT ? trow[o] : -1;
+    const double2 tc = txy[tb[b] >= 0 ? tb[b] : 0];
+    xb[b] = tc.x;
+    yb[b] = s == 0 ? tc.y : -(tc.y + d);
+    const int k = b > 0 && yb[b] == yb[b - 1] ? static_cast<int>(lrint((xb[b] - xb[b - 1]) * iw)) : 0;
+    kst[b] = k >= 1 && k <= 4 ? k : 0;
+  }
+  v4 acc[RB][2][2];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) acc[b][nt][0] = acc[b][nt][1] = v4{0, 0, 0, 0};
   for (int i = i0; i < i1; i += 4) {
     const int ii = i + g;  // this lane's node (K index)
     const bool kv = ii < i1;
     const int q = fperm[f0 + (kv ? ii : i0)];
-    cx<T> v = mk<T>(0, 0);
-    if (kv && tv) {
-      const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
-      const cx<double> u = ld<double>(cq[q]) * ld<double>(sigma[s * ns + q]);
-      v = cvt<T>(u) * cexpT<T>(-li * xT + gr * yy, lr * xT + gi * yy);
-    }
+    const double lr = lam[q].x, li = lam[q].y, gr = g2[q].x, gi = g2[q].y;
+    const cx<T> u = kv ? cvt<T>(ld<double>(cq[q]) * ld<double>(sigma[s * ns + q])) : mk<T>(0, 0);
+    const cx<T> fx = cvt<T>(ld<double>(Fx[q]));
     const double *L = Lw + static_cast<int64_t>(q) * kSommNc;
+    T lq[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) {
       const int k = nt * 16 + r;
-      const T lq = (kv && k < kSommNc) ? static_cast<T>(L[k]) : T(0);
-      acc[nt][0] = si_mfma<T>::mac(v.re, lq, acc[nt][0]);
-      acc[nt][1] = si_mfma<T>::mac(v.im, lq, acc[nt][1]);
+      lq[nt] = (kv && k < kSommNc) ? static_cast<T>(L[k]) : T(0);
+    }
+    cx<T> E = mk<T>(0, 0);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      if (kst[b] > 0) {
+        for (int v = 0; v < kst[b]; ++v) E = E * fx;
+      } else {
+        E = cexpT<T>(-li * xb[b] + gr * yb[b], lr * xb[b] + gi * yb[b]);
+      }
+      const cx<T> v = tb[b] >= 0 ? u * E : mk<T>(0, 0);
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        acc[b][nt][0] = si_mfma<T>::mac(v.re, lq[nt], acc[b][nt][0]);
+        acc[b][nt][1] = si_mfma<T>::mac(v.im, lq[nt], acc[b][nt][1]);
+      }
     }
   }
-  // result register j of lane i: tile tw + row(i, j), column nt * 16 + i % 16
+  // result register j of lane i in row block b: tile trow[tw + RB row(i, j) + b], column nt * 16 + i % 16
   cv_t<T> *o = Bp + (static_cast<int64_t>(cz) * (gridDim.z / nchunk) + rs) * nT * static_cast<int64_t>(nci) + c0;
 #pragma unroll
-  for (int nt = 0; nt < 2; ++nt) {
-    const int k = nt * 16 + r;
+  for (int b = 0; b < RB; ++b)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int t = tw + si_mfma<T>::row(lane, j);
-      if (t < nT && k < kSommNc) o[static_cast<int64_t>(t) * nci + k] = st(mk<T>(acc[nt][0][j], acc[nt][1][j]));
+    for (int nt = 0; nt < 2; ++nt) {
+      const int k = nt * 16 + r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int os = tw + RB * si_mfma<T>::row(lane, j) + b;
+        if (os < nT && k < kSommNc)
+          o[static_cast<int64_t>(trow[os]) * nci + k] = st(mk<T>(acc[b][nt][0][j], acc[b][nt][1][j]));
+      }
     }
-  }
 }
 
 template <typename T>
@@ -575,15 +608,16 @@ int s2l_interp_t(mpsl_ctx *ctx, void *part, int chunks, int nrhs, int64_t pstrid
   const auto *txy = static_cast<const double2 *>(pl.txy.p);
   if (pl.nint > 0) {
     // node chunks so that the launch has about 2048 blocks
-    const int nci = kSommNc * pl.nint, tb = cdv(pl.nT, 16 * kSiAlphaWaves);
+    const int nci = kSommNc * pl.nint, tb = cdv(pl.nT, 16 * coarse_rb<T>() * kSiAlphaWaves);
     const int nchunk = std::max(1, std::min(16, cdv(2048, static_cast<int64_t>(pl.nint) * tb * 2 * nrhs)));
     const int64_t rows = 2ll * nrhs * pl.nT;
     if ((rc = dev_alloc(ctx, pl.Bp, static_cast<size_t>(nchunk) * rows * nci * sizeof(cv_t<T>)))) return rc;
     auto *Bp = static_cast<cv_t<T> *>(pl.Bp.p);
-    hipLaunchKernelGGL(k_si_coarseB_mfma<T>, dim3(pl.nint, cdv(pl.nT, 16 * kSiAlphaWaves), nchunk * 2 * nrhs),
-                       dim3(64 * kSiAlphaWaves), 0, ctx->stream, sig, cq, lam, g2, txy,
-                       static_cast<const int *>(pl.ivl.p), static_cast<const int *>(pl.fperm.p),
-                       static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT, nci, nchunk, ctx->d, Bp);
+    hipLaunchKernelGGL(k_si_coarseB_mfma<T>, dim3(pl.nint, tb, nchunk * 2 * nrhs), dim3(64 * kSiAlphaWaves), 0,
+                       ctx->stream, sig, cq, lam, g2, static_cast<const double2 *>(pl.Fx.p), txy,
+                       static_cast<const int *>(pl.trow.p), static_cast<const int *>(pl.ivl.p),
+                       static_cast<const int *>(pl.fperm.p), static_cast<const double *>(pl.Lw.p), ctx->ns, pl.nT,
+                       nci, nchunk, ctx->d, pl.tile_w, Bp);
     hipLaunchKernelGGL(k_si_coarseB_sum<T>, dim3(cdv(rows * nci, 256)), dim3(256), 0, ctx->stream, Bp, nchunk, rows,
                        pl.nT, pl.nc, nci, B);
   }
@@ -626,7 +660,8 @@ int launch_s2l_interp(mpsl_ctx *ctx, int prec, void *part, int chunks, int nrhs,
 void somm_free(mpsl_ctx *ctx) {
   SommPlan &pl = ctx->somm;
   DBuf *b[] = {&pl.perm, &pl.tstart, &pl.txy, &pl.ptile, &pl.lamc, &pl.gc, &pl.Wc64, &pl.Wc32, &pl.Zc64,
-               &pl.Zc32, &pl.Lw, &pl.ivl, &pl.fperm, &pl.dir, &pl.G, &pl.Bp, &pl.fblk};
+               &pl.Zc32, &pl.Lw, &pl.ivl, &pl.fperm, &pl.dir, &pl.G, &pl.Bp, &pl.fblk,
+               &pl.trow, &pl.Fx};
   for (DBuf *x : b) dev_free(*x);
   pl.active = false;
   pl.sigma = nullptr;
@@ -663,6 +698,14 @@ int somm_build(mpsl_ctx *ctx) {
     txy.push_back(make_double2(x0 + (kv.first.first + 0.5) * kTileW, y0 + (kv.first.second + 0.5) * kTileH));
   }
   pl.nT = id;
+  // row-major tile order: along it, neighbours are usually horizontally adjacent
+  std::vector<int> trow;
+  {
+    std::vector<std::pair<std::pair<int64_t, int64_t>, int>> byrow;
+    for (const auto &kv : tiles) byrow.push_back({{kv.first.second, kv.first.first}, kv.second});
+    std::sort(byrow.begin(), byrow.end());
+    for (const auto &e : byrow) trow.push_back(e.second);
+  }
   std::vector<int> ptile(n), tstart(pl.nT + 1, 0), perm(n);
   for (int64_t m = 0; m < n; ++m) {
     ptile[m] = tiles[key[m]];
@@ -796,8 +839,18 @@ int somm_build(mpsl_ctx *ctx) {
       (rc = upload(pl.ivl, ivl.data(), ivl.size() * sizeof(int))) ||
       (rc = upload(pl.fperm, fperm.data(), fperm.size() * sizeof(int))) ||
       (rc = upload(pl.dir, dir.data(), dir.size() * sizeof(int))) ||
-      (rc = upload(pl.fblk, fblk.data(), fblk.size() * sizeof(int))))
+      (rc = upload(pl.fblk, fblk.data(), fblk.size() * sizeof(int))) ||
+      (rc = upload(pl.trow, trow.data(), trow.size() * sizeof(int))))
     return rc;
+
+  {  // e^{i lam_q w} per contour node
+    std::vector<double2> fx(ns);
+    for (int q = 0; q < ns; ++q) {
+      const zc v = std::exp(zc(0.0, 1.0) * ctx->lam[q] * kTileW);
+      fx[q] = make_double2(v.real(), v.imag());
+    }
+    if ((rc = upload(pl.Fx, fx.data(), fx.size() * sizeof(double2)))) return rc;
+  }
   pl.active = true;
   return MPSL_OK;
 }
