@@ -351,13 +351,16 @@ int mpsl_rhs(mpsl_ctx *ctx, const double *src_xy, mpsl_c128 *rhs);
 
 typedef struct {
   int precision;      /* MPSL_FP64: FP64 GMRES; MPSL_FP32: FP32 matvecs inside
-                         FP64 iterative refinement (Arnoldi always FP64)      */
+                         FP64 iterative refinement; the inner Krylov basis
+                         is stored in complex64 (orthogonalisation sums in
+                         FP64), the residual and solution in FP64           */
   double tol;         /* relative residual target ||r|| / ||b||             */
   int maxiter;        /* total matvec budget of the Krylov solver           */
   int restart;        /* Krylov dimension before restart (0: maxiter, i.e.
                          unrestarted).  At most 20000 (MPSL_EINVAL above);
-                         the basis holds (dimension + 1) N P complex128 in
-                         device memory (MPSL_ENOMEM when it does not fit)   */
+                         the basis holds (dimension + 1) N P complex128
+                         (complex64 with MPSL_FP32) in device memory
+                         (MPSL_ENOMEM when it does not fit)                 */
   double inner_tol;   /* MPSL_FP32 only: inner GMRES tolerance (0: 1e-5)   */
 } mpsl_opts;
 
