@@ -458,7 +458,7 @@ int ensure_work(mpsl_ctx *ctx) {
   const int P = 2 * ctx->p + 1;
   const size_t len = static_cast<size_t>(ctx->n) * P;
   const int ca = std::max(chunks_m2l(ctx, MPSL_FP64), chunks_m2l(ctx, MPSL_FP32));
-  const int cb = chunks_s2l(ctx), cc = chunks_m2s(ctx);
+  const int cb = std::max(chunks_s2l(ctx, 1, MPSL_FP64), chunks_s2l(ctx, 1, MPSL_FP32)), cc = chunks_m2s(ctx);
   int rc;
   if ((rc = dev_alloc(ctx, ctx->part, (ca + cb) * len * sizeof(double2))) ||
       (rc = dev_alloc(ctx, ctx->m2s_part, 2ull * cc * ctx->ns * sizeof(double2))) ||
@@ -485,7 +485,7 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
   const bool mrhs = !fmm && prec == MPSL_FP32 && nrhs >= kMrhsMin;
   const int ca = fmm ? fmm_slots(ctx)
                      : (mrhs ? chunks_m2l_mrhs(ctx, nrhs) : std::max(1, chunks_m2l(ctx, prec) / nrhs));
-  const int cb = chunks_s2l(ctx, nrhs);
+  const int cb = chunks_s2l(ctx, nrhs, prec);
   const int cc = chunks_m2s(ctx, nrhs);
   const int P = 2 * ctx->p + 1;
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
@@ -602,6 +602,10 @@ int mpsl_create(mpsl_ctx **out, int device) {
   mpsl_ctx *ctx = new (std::nothrow) mpsl_ctx();
   if (!ctx) return MPSL_ENOMEM;
   ctx->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    ctx->n_cu = cus;
+  (void)hipGetLastError();
   *out = ctx;
   return MPSL_OK;
 }
@@ -1076,7 +1080,7 @@ int mpsl_s2l_dev(mpsl_ctx *ctx, int prec, const void *sigma, void *alpha) {
   MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
   int rc = mpsl::build_tables(ctx);
   if (rc) return rc;
-  const int cb = mpsl::chunks_s2l(ctx);
+  const int cb = mpsl::chunks_s2l(ctx, 1, prec);
   if ((rc = mpsl::launch_s2l_coef(ctx, sigma))) return rc;
   if ((rc = mpsl::launch_s2l(ctx, prec, ctx->part.p, cb))) return rc;
   return mpsl::launch_sum_parts(ctx, prec, ctx->part.p, cb, alpha);

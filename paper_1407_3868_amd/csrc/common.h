@@ -46,6 +46,23 @@ template <typename T> __host__ __device__ inline void cmac(cx<T> &acc, cx<T> a, 
   acc.im = fma(a.im, b.re, acc.im);
 }
 
+// One 16x16x4 matrix-core multiply-accumulate in precision T, D = A B + C.
+// Operand layout (both precisions): lane i supplies A[i % 16][i / 16] and
+// B[i / 16][i % 16]; result register j of lane i is D[row(i, j)][i % 16],
+// row = 4 (i / 16) + j for f32 and i / 16 + 4 j for f64 (measured on gfx950
+// with one-hot operands).
+template <typename T> struct mfma4;
+template <> struct mfma4<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
+template <> struct mfma4<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
+};
+
 }  // namespace mpsl
 
 #define MPSL_HIP_TRY(ctx, call)                                                              \

@@ -124,6 +124,7 @@ struct FmmPlan {
 
 struct mpsl_ctx {
   int device = 0;
+  int n_cu = 256;          // compute units of the device (launch-shape rules)
   hipStream_t stream = nullptr;
   std::string err;
 

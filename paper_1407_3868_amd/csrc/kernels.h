@@ -98,9 +98,13 @@ int launch_field(mpsl_ctx *ctx, const void *beta, const void *gl, const void *am
 
 // Source chunks of the M2L grid for precision prec (tuned, set, or automatic).
 int chunks_m2l(const mpsl_ctx *ctx, int prec);
+// Sources per chunk of the matrix-core M2L for a grid of `chunks` chunks
+// (whole groups of four sources).
+int m2l_mfma_chunk_len(int n, int chunks);
 // Partial buffers written by one M2L launch.
 inline int m2l_slots(const mpsl_ctx *ctx, int prec) { return chunks_m2l(ctx, prec); }
-int chunks_s2l(const mpsl_ctx *ctx, int nrhs = 1);
+// Node chunks of the S2L grid for precision prec (its particle tiles differ).
+int chunks_s2l(const mpsl_ctx *ctx, int nrhs, int prec);
 int chunks_m2s(const mpsl_ctx *ctx, int nrhs = 1);
 
 // Sommerfeld transforms by tile-local interpolation (somm.hip): M2S spectra

@@ -8,6 +8,7 @@
 //   W (M2S order sums)  [2][ns][P]
 //   Up (S2L coeffs)     [2][ns][P]
 //   spec, sigma         [2][ns]                FP64
+#include <atomic>
 #include <cmath>
 
 #include "kernels.h"
@@ -387,22 +388,8 @@ __global__ void k_fold_parts(cv_t<T> *__restrict__ part, int chunks, int64_t len
 // 16 MT x KP) by B with 16x16x4 MFMA, the complex product as four real
 // chains (re += Sr Br - Si Bi, im += Sr Bi + Si Br); the result goes back
 // through LDS for coalesced stores.
-//   MFMA 16x16x4 operand layout (both precisions): lane i supplies
-//   A[i % 16][i / 16] and B[i / 16][i % 16].  Result register j of lane i is
-//   D[4 (i / 16) + j][i % 16] for f32 and D[i / 16 + 4 j][i % 16] for f64
-//   (measured on gfx950 with one-hot operands).
+//   (MFMA operand layout: mfma4 in common.h.)
 constexpr int kSapplyThreads = 256;
-template <typename T> struct mfma4;
-template <> struct mfma4<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
-};
-template <> struct mfma4<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
-};
 
 template <typename T, int p>
 __global__ __launch_bounds__(kSapplyThreads) void k_sapply(const cv_t<T> *__restrict__ x,
@@ -1385,20 +1372,81 @@ int chunks_m2l(const mpsl_ctx *ctx, int prec) {
   if (ctx->m2l_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2l_chunks, ctx->n));
   // about 2560 blocks of 128 lanes, or 10240 of 4 waves on the matrix cores
   const int v = m2l_variant(ctx, prec);
-  const int c = v >= kM2LMfma ? cdiv(10240, cdiv(ctx->n, 64 * (v == kM2LMfmaWide ? 2 : 1)))
-                              : cdiv(2560, cdiv(ctx->n, kThreads));
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
+  int c = v >= kM2LMfma ? cdiv(10240, cdiv(ctx->n, 64 * (v == kM2LMfmaWide ? 2 : 1)))
+                        : cdiv(2560, cdiv(ctx->n, kThreads));
+  c = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
+  // matrix cores: chunks of whole groups of four sources (m2l_mfma_chunk_len),
+  // counted so that none is empty
+  if (v >= kM2LMfma) c = cdiv(ctx->n, m2l_mfma_chunk_len(static_cast<int>(ctx->n), c));
+  return c;
 }
 
-int chunks_s2l(const mpsl_ctx *ctx, int nrhs) {
+// Chunk count for a launch of bpc blocks per chunk whose blocks all carry the
+// same work.  With `slots` blocks resident at once on the whole chip
+// (compute units x blocks per unit), B blocks run in ceil(B / slots) waves,
+// and each block holds 1/c of the work, so the launch takes about
+// ceil(bpc c / slots) / c; of the counts in [lo, hi] the smallest within 3 %
+// of the best is taken (fewer partial slots to sum).  At 5000 particles and
+// 26816 nodes the FP32 S2L's 26 chunks made 1040 blocks for 1024 slots, a
+// second wave of 16 blocks (0.82 ms; 50 chunks, 2000 blocks: about 0.63 ms).
+static int balanced_chunks(int64_t bpc, int64_t slots, int lo, int hi) {
+  lo = std::max(1, lo);
+  hi = std::max(lo, hi);
+  slots = std::max<int64_t>(1, slots);
+  auto cost = [&](int c) { return static_cast<double>((bpc * c + slots - 1) / slots) / c; };
+  double best = 1e300;
+  for (int c = lo; c <= hi; ++c) best = std::min(best, cost(c));
+  for (int c = lo; c <= hi; ++c)
+    if (cost(c) <= 1.03 * best) return c;
+  return lo;
+}
+
+// Blocks of the matrix-core S2L kernel resident per compute unit (occupancy
+// query, cached per precision and order; 1 if the query fails).
+template <typename T>
+static int s2l_resident(int p) {
+  static std::atomic<int> cache[kMaxP + 1];
+  if (p < kMinP || p > kMaxP) return 1;
+  int r = cache[p].load(std::memory_order_relaxed);
+  if (r > 0) return r;
+  constexpr int MT = s2l_tiles<T>();
+  const void *fn = nullptr;
+  switch (p) {
+#define X(PP) \
+  case PP: fn = reinterpret_cast<const void *>(&k_s2l_mfma<T, PP, MT>); break;
+    MPSL_P_CASES(X)
+#undef X
+  }
+  int nb = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * kS2lWaves, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  cache[p].store(nb, std::memory_order_relaxed);
+  return nb;
+}
+
+int chunks_s2l(const mpsl_ctx *ctx, int nrhs, int prec) {
   if (ctx->somm.active) {  // the interpolated S2L: chunks of coarse nodes, one slot each
     const int tb = cdiv(ctx->n, 128) * nrhs;
     return std::max(1, std::min(64, std::min(cdiv(1024, tb), 2 * ctx->somm.nc)));
   }
   if (ctx->s2l_chunks > 0) return std::min(ctx->s2l_chunks, ctx->ns);
+  // about 1024 blocks of 128 lanes' worth of particles, at least 8 nodes per
+  // chunk; on long contours raised by up to 2x to fill the last wave of
+  // blocks (fewer chunks would enlarge the coefficient rows that the resident
+  // blocks read at once: at 26816 nodes 19 FP64 chunks ran slower than 26,
+  // 29 faster).  Short contours keep it: each chunk adds a partial slot of n P
+  // entries to write and sum, about what the better fill gains at 1024 nodes.
   const int tb = cdiv(ctx->n, kThreads) * nrhs;
-  const int c = cdiv(1024, tb);
-  return std::max(1, std::min(c, ctx->ns / 8 > 0 ? ctx->ns / 8 : 1));
+  const int cmax = std::max(1, ctx->ns / 8);
+  const int c0 = std::min(cdiv(1024, tb), cmax);
+  if (ctx->ns < 4096) return std::max(1, c0);
+  const bool f64 = prec == MPSL_FP64;
+  const int64_t bpc =
+      static_cast<int64_t>(cdiv(ctx->n, 16 * kS2lWaves * (f64 ? s2l_tiles<double>() : s2l_tiles<float>()))) * nrhs;
+  const int64_t slots = static_cast<int64_t>(ctx->n_cu) * (f64 ? s2l_resident<double>(ctx->p) : s2l_resident<float>(ctx->p));
+  return balanced_chunks(bpc, slots, std::max(1, c0), std::min(2 * c0, cmax));
 }
 
 int chunks_m2s(const mpsl_ctx *ctx, int nrhs) {
@@ -1440,6 +1488,13 @@ int launch_pair_tables(mpsl_ctx *ctx) {
   return MPSL_OK;
 }
 
+// Sources per chunk of the matrix-core M2L: each MFMA step takes a group of
+// four sources, so a chunk length that is not a multiple of 4 leaves a part
+// of one group's matrix work on zeros in every chunk (39 sources: 2.5 %
+// of the launch at 5000 particles); trailing chunks may come out empty and
+// then write zero partials.
+int m2l_mfma_chunk_len(int n, int chunks) { return (cdiv(n, chunks) + 3) / 4 * 4; }
+
 template <typename T>
 static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks, int variant, int nrhs,
                         int64_t pstride) {
@@ -1456,14 +1511,15 @@ static int launch_m2l_t(mpsl_ctx *ctx, const void *beta, void *part, int chunks,
     const int nt = variant == kM2LMfma ? 1 : 2;
     const dim3 g(cdiv(n, 16 * nt * kM2lMfmaWaves), chunks, nrhs);
     const dim3 blk(64 * kM2lMfmaWaves);
+    const int cl = m2l_mfma_chunk_len(n, chunks);
     switch (ctx->p) {
 #define X(PP)                                                                                               \
   case PP:                                                                                                  \
     if constexpr (PP <= kM2LMfmaMaxP) {                                                                     \
       if (nt == 1)                                                                                          \
-        hipLaunchKernelGGL((k_m2l_mfma<T, PP, 1>), g, blk, 0, ctx->stream, pairs, b, o, n, chunk_len, bs, pstride); \
+        hipLaunchKernelGGL((k_m2l_mfma<T, PP, 1>), g, blk, 0, ctx->stream, pairs, b, o, n, cl, bs, pstride); \
       else                                                                                                  \
-        hipLaunchKernelGGL((k_m2l_mfma<T, PP, 2>), g, blk, 0, ctx->stream, pairs, b, o, n, chunk_len, bs, pstride); \
+        hipLaunchKernelGGL((k_m2l_mfma<T, PP, 2>), g, blk, 0, ctx->stream, pairs, b, o, n, cl, bs, pstride); \
     }                                                                                                       \
     break;
       MPSL_P_CASES(X)

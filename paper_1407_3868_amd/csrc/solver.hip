@@ -15,7 +15,7 @@ namespace mpsl {
 int rhs_device(mpsl_ctx *ctx, const double *src, void *dev) {
   int rc = build_tables(ctx);
   if (rc) return rc;
-  const int cb = chunks_s2l(ctx);
+  const int cb = chunks_s2l(ctx, 1, MPSL_FP64);
   if ((rc = launch_reflect(ctx, nullptr, src, ctx->sigma.p))) return rc;
   if ((rc = launch_s2l_coef(ctx, ctx->sigma.p))) return rc;
   if ((rc = launch_s2l(ctx, MPSL_FP64, ctx->part.p, cb))) return rc;

@@ -90,18 +90,6 @@ template <typename T> __device__ inline cx<T> cvt(cx<double> v) { return {static
 template <typename T> __device__ inline cx<double> up(cx<T> v) { return {static_cast<double>(v.re), static_cast<double>(v.im)}; }
 
 
-// 16x16x4 MFMA of the precision T and the row a result register holds.
-template <typename T> struct si_mfma;
-template <> struct si_mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mac(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int lane, int j) { return 4 * (lane >> 4) + j; }
-};
-template <> struct si_mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 mac(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  static __device__ inline int row(int lane, int j) { return (lane >> 4) + 4 * j; }
-};
 
 // M2S, step 1 (FP32): one lane per (tile, coarse node), blockIdx.z = 2 rhs + side.
 // (The matrix-core form below is slower in FP32 at ~10 particles per tile.)
@@ -160,7 +148,7 @@ __global__ __launch_bounds__(64 * kSiFineSplit) void k_si_fine(
     const int *__restrict__ fblk, const double *__restrict__ Lw, int ns, int nT, int nc, double d,
     double tile_h, double2 *__restrict__ spec) {
   static_assert(kSiFineNodes == 16 * kSiFineSplit, "16 nodes per wave");
-  typedef typename si_mfma<T>::v4 v4;
+  typedef typename mfma4<T>::v4 v4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   // XCD-aware order: blocks are dealt to the 8 XCDs round-robin, so block b
@@ -191,15 +179,15 @@ __global__ __launch_bounds__(64 * kSiFineSplit) void k_si_fine(
 #pragma unroll
     for (int ks = 0; ks < 6; ++ks) {
       const cx<T> a = av ? ld<T>(Ga[4 * ks]) : mk<T>(0, 0);
-      hr = si_mfma<T>::mac(a.re, bl[ks], hr);
-      hi = si_mfma<T>::mac(a.im, bl[ks], hi);
+      hr = mfma4<T>::mac(a.re, bl[ks], hr);
+      hi = mfma4<T>::mac(a.im, bl[ks], hi);
     }
     cx<T> E = mk<T>(0, 0), blk = mk<T>(0, 0);
     double xp = 0.0, yp = 0.0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int j = jbeg + jstep * u;
-      const int t = tb + si_mfma<T>::row(lane, j);
+      const int t = tb + mfma4<T>::row(lane, j);
       if (t < nT) {
         const double xT = txy[t].x, yT = txy[t].y;
         const int k = u > 0 && xT == xp ? static_cast<int>(lrint(fabs(yT - yp) * ih)) : 0;
@@ -316,7 +304,7 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_alpha_mfma(
     int64_t pstride) {
   constexpr int P = 2 * p + 1;
   constexpr int NTN = (P + 15) / 16;
-  typedef typename si_mfma<T>::v4 v4;
+  typedef typename mfma4<T>::v4 v4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const int ch = blockIdx.y, rr = blockIdx.z;
@@ -350,9 +338,9 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_alpha_mfma(
     for (int nt = 0; nt < NTN; ++nt) {
       const int o = nt * 16 + r;  // this lane's order (B column)
       const cx<T> zz = (kv && o < P) ? ld<T>(z[o]) : mk<T>(0, 0);
-      acc[nt][0] = si_mfma<T>::mac(a.re, zz.re, acc[nt][0]);
-      acc[nt][1] = si_mfma<T>::mac(a.im, zz.im, acc[nt][1]);
-      acc[nt][2] = si_mfma<T>::mac(as, zz.re + zz.im, acc[nt][2]);
+      acc[nt][0] = mfma4<T>::mac(a.re, zz.re, acc[nt][0]);
+      acc[nt][1] = mfma4<T>::mac(a.im, zz.im, acc[nt][1]);
+      acc[nt][2] = mfma4<T>::mac(as, zz.re + zz.im, acc[nt][2]);
     }
   }
   // result register j of lane i: particle lw + row(i, j), order nt * 16 + i % 16
@@ -362,7 +350,7 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_alpha_mfma(
     const int o = nt * 16 + r;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int pl = lw + si_mfma<T>::row(lane, j);
+      const int pl = lw + mfma4<T>::row(lane, j);
       if (pl < n && o < P) {
         const T p1 = acc[nt][0][j], p2 = acc[nt][1][j], p3 = acc[nt][2][j];
         out[static_cast<int64_t>(pl) * P + o] = st(mk<T>(p1 - p2, p3 - p1 - p2));
@@ -386,7 +374,7 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_tileG_mfma(
     cv_t<T> *__restrict__ G) {
   constexpr int P = 2 * p + 1;
   constexpr int KP = (P + 3) / 4 * 4;
-  typedef typename si_mfma<T>::v4 v4;
+  typedef typename mfma4<T>::v4 v4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const int t = blockIdx.y;
@@ -410,15 +398,15 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_tileG_mfma(
       const int j = kk + g;  // order (K index) of this lane
       const cx<T> a = (ma >= 0 && j < P) ? ld<T>(b[j]) : mk<T>(0, 0);
       const cx<T> z = (cv && j < P) ? ld<T>(W[j]) : mk<T>(0, 0);
-      d0 = si_mfma<T>::mac(a.re, z.re, d0);
-      d1 = si_mfma<T>::mac(a.im, z.im, d1);
-      d2 = si_mfma<T>::mac(a.re + a.im, z.re + z.im, d2);
+      d0 = mfma4<T>::mac(a.re, z.re, d0);
+      d1 = mfma4<T>::mac(a.im, z.im, d1);
+      d2 = mfma4<T>::mac(a.re + a.im, z.re + z.im, d2);
     }
     if (cv) {
       const double lr = lamc[c].x, li = lamc[c].y, gr = gc[c].x, gi = gc[c].y;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int k = mb + si_mfma<T>::row(lane, q);  // particle of result register q
+        const int k = mb + mfma4<T>::row(lane, q);  // particle of result register q
         if (k < m1) {
           const int m = perm[k];
           const double dx = xy[m].x - xT, dy = xy[m].y - yT;
@@ -461,7 +449,7 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_coarseB_mfma(
     const double *__restrict__ Lw, int ns, int nT, int nci, int nchunk, double d, double tile_w,
     cv_t<T> *__restrict__ Bp) {
   constexpr int RB = coarse_rb<T>();
-  typedef typename si_mfma<T>::v4 v4;
+  typedef typename mfma4<T>::v4 v4;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const int iv = blockIdx.x;
@@ -516,8 +504,8 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_coarseB_mfma(
       const cx<T> v = tb[b] >= 0 ? u * E : mk<T>(0, 0);
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) {
-        acc[b][nt][0] = si_mfma<T>::mac(v.re, lq[nt], acc[b][nt][0]);
-        acc[b][nt][1] = si_mfma<T>::mac(v.im, lq[nt], acc[b][nt][1]);
+        acc[b][nt][0] = mfma4<T>::mac(v.re, lq[nt], acc[b][nt][0]);
+        acc[b][nt][1] = mfma4<T>::mac(v.im, lq[nt], acc[b][nt][1]);
       }
     }
   }
@@ -530,7 +518,7 @@ __global__ __launch_bounds__(64 * kSiAlphaWaves) void k_si_coarseB_mfma(
       const int k = nt * 16 + r;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int os = tw + RB * si_mfma<T>::row(lane, j) + b;
+        const int os = tw + RB * mfma4<T>::row(lane, j) + b;
         if (os < nT && k < kSommNc)
           o[static_cast<int64_t>(trow[os]) * nci + k] = st(mk<T>(acc[b][nt][0][j], acc[b][nt][1][j]));
       }

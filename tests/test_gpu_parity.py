@@ -294,7 +294,10 @@ def test_m2l_matrix_cores_multi_rhs_and_empty_chunks(prec, torch_dev):
     masked)."""
     torch = torch_dev
     wl, pr, ctx = _setup("s150p12")
-    ctx.set_tuning(prec, 2, 149)   # chunk length 2: the last chunk is empty
+    # 149 chunks of 150 sources: the chunk length rounds up to one group of
+    # four, so 38 chunks hold sources and the other 111 are empty (49 chunks
+    # per right-hand side in the three-source batch: 38 full, 11 empty)
+    ctx.set_tuning(prec, 2, 149)
     X = np.stack([coeff_vector(wl, 20 + r) for r in range(3)])
     npdt = np.complex128 if prec == 0 else np.complex64
     xd = torch.from_numpy(X.astype(npdt)).cuda()
