@@ -54,10 +54,10 @@ struct FmmLevel {
 // One launch of the translation kernel: groups of boxes, each writing one
 // expansion per box as a sum of Toeplitz products over the group's terms.
 struct FmmStage {
-  int tasks = 0;                       // groups launched (one block per output tile)
+  int tasks = 0;                       // groups launched (one block per output window)
   int pout = 0;                        // output expansion length
-  int tps = 0, G = 0, l8 = 0;          // lanes per box, boxes per group, table tile / 8
-  int tiles = 1;                       // output tiles of kRB * tps slots
+  int G = 0;                           // boxes per group
+  int tiles = 1;                       // output windows of the translation block
   int tj = 64;                         // input tile length
   int64_t task_off = 0;                // first group in FmmPlan::groups
   int nchunk = 1;                      // partial-local chunks summed after the launch

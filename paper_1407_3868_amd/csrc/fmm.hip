@@ -25,14 +25,9 @@ namespace mpsl {
 
 namespace {
 
-constexpr int kRB = 8;                // consecutive outputs per lane
-constexpr int kToepMaxThreads = 256;  // translation kernel block
-constexpr size_t kLdsBudget = 64 * 1024;
-constexpr int kMaxBoxOrder = 600;     // largest box order (LDS of one term in FP64)
+constexpr int kMaxBoxOrder = 600;     // largest box order
 constexpr int kAutoThreshold = 8000;  // MPSL_FAR_AUTO: FMM above this many particles
 
-constexpr int kMaxTileJ = 256;         // longest input tile of the translation kernel
-constexpr int kMaxGroup = 32;          // boxes per group
 constexpr int kTargetBlocks = 2048;    // blocks a translation launch aims for (8 per CU)
 constexpr int kMaxChunks = 64;         // term chunks of one stage
 
@@ -308,94 +303,194 @@ __global__ void k_fmm_l2p(const cv_t<T> *__restrict__ lin, const int *__restrict
   }
 }
 
-// Translation of a group of boxes (one block per group task).  The G boxes
-// of a group share every table row of the task's terms (boxes of one
-// parity class see the same offsets and the same child position), so each
-// term's table is staged once per input tile in LDS while every subset of
-// tps lanes stages its own box's input tile and keeps kRB consecutive
-// outputs per lane in registers across all terms, with the Toeplitz window
-// in registers (one LDS read of the table and one broadcast read of the
-// input per kRB complex MACs).  The table tile is stored permuted, logical
-// index x at (x mod 8) * l8 + x / 8, so that lanes whose windows lie 8
-// entries apart read consecutive words.  A box whose input is absent in a
-// term (ins < 0) skips it.
-template <typename T>
-__global__ __launch_bounds__(kToepMaxThreads) void k_fmm_group(const FmmGroup *__restrict__ groups,
-                                                                const FmmGTerm *__restrict__ terms,
-                                                                const int64_t *__restrict__ ins,
-                                                                const int64_t *__restrict__ outs,
-                                                                const cv_t<T> *__restrict__ xin,
-                                                                const cv_t<T> *__restrict__ tabs,
-                                                                cv_t<T> *__restrict__ xout, int pout, int tps, int G,
-                                                                int l8, int tj) {
-  extern __shared__ __align__(16) unsigned char grp_smem[];
-  cx<T> *Hp = reinterpret_cast<cx<T> *>(grp_smem);
-  const int hl = 8 * l8;
-  const int sub = threadIdx.x / tps, lt = threadIdx.x - sub * tps;
-  cx<T> *Ms = Hp + hl + sub * tj;
+// Translation of a group of boxes on the matrix cores (one block per group
+// task and window of output slots).  The boxes of a group (one parity class)
+// share every table row of the task's terms.  For one term (a table row T
+// shared by the group's boxes) the group's outputs form a GEMM
+//   Y[j'][b] += sum_j T[j - j' + P_out - 1] X_b[j]
+// with M = output slot, K = input slot, N = box of the group (16 NB boxes).
+// Each wave owns 16 consecutive output slots and all box columns; the block
+// (kFmmMfmaWaves waves) a window of 16 kFmmMfmaWaves slots (blockIdx.y).  Per
+// term and input tile of tj slots the block stages the group's inputs
+// X[j][b] and the window of T its slots reach in LDS (real and imaginary
+// parts apart); lane i supplies A[i % 16][i / 16] = T of its output slot and
+// input slot and B[i / 16][i % 16] = X of that input slot and box.  Complex
+// products take three real MFMAs (Gauss): P1 = sum Ar Br, P2 = sum Ai Bi,
+// P3 = sum (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2.  Absent
+// inputs (ins < 0) and input slots past the term's length are staged as
+// zeros.  The input rows are 16 mod 64 words apart (NB = 1) or 48 (NB = 2),
+// so that the four rows one B read touches lie in different LDS banks.
+constexpr int kFmmMfmaWaves = 4;
+constexpr int kFmmMfmaRows = 16 * kFmmMfmaWaves;  // output slots per block
+constexpr int kFmmGroup = 16;                     // boxes per group (16 NB)
+constexpr int kFmmTileMax = 128;                  // longest input tile (registers of the prefetch)
+constexpr size_t kFmmLds = 40 * 1024;             // LDS of one translation block
+
+// LDS bytes of the matrix-core translation block for input tiles of tj slots
+// (element size esz): the term cache, inputs [tj][16 or 48] and the table
+// window [tj + rows], real and imaginary parts apart.
+constexpr int kFmmTermCache = 32;                 // terms of one block, at most
+__host__ __device__ constexpr size_t fmm_term_cache_bytes(int nc) {
+  return static_cast<size_t>(kFmmTermCache) * (nc * sizeof(int64_t) + sizeof(int64_t) + sizeof(int));
+}
+inline size_t fmm_mfma_lds(int tj, size_t esz) {
+  const int sx = kFmmGroup == 16 ? 16 : 48;
+  return fmm_term_cache_bytes(kFmmGroup) +
+         (2 * static_cast<size_t>(tj) * sx + 2 * static_cast<size_t>(tj + kFmmMfmaRows)) * esz;
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(64 * kFmmMfmaWaves) void k_fmm_group_mfma(const FmmGroup *__restrict__ groups,
+                                                                       const FmmGTerm *__restrict__ terms,
+                                                                       const int64_t *__restrict__ ins,
+                                                                       const int64_t *__restrict__ outs,
+                                                                       const cv_t<T> *__restrict__ xin,
+                                                                       const cv_t<T> *__restrict__ tabs,
+                                                                       cv_t<T> *__restrict__ xout, int pout, int tj) {
+  constexpr int NC = 16 * NB;               // box columns of a group
+  constexpr int SX = NB == 1 ? 16 : 48;     // LDS row stride of the staged inputs
+  constexpr int RB = kFmmMfmaRows;
+  constexpr int NT = 64 * kFmmMfmaWaves;
+  static_assert(NT % NC == 0, "each thread stages one box column");
+  typedef typename mfma4<T>::v4 v4;
+  extern __shared__ __align__(16) unsigned char fgm_smem[];
+  // the block's terms (at most kFmmTermCache): per-box input offsets, table
+  // offset and input length, read from LDS by every tile's prefetch
+  int64_t *Cin = reinterpret_cast<int64_t *>(fgm_smem);  // [kFmmTermCache][NC]
+  int64_t *Ctab = Cin + kFmmTermCache * NC;                // [kFmmTermCache]
+  int *Cpin = reinterpret_cast<int *>(Ctab + kFmmTermCache);
+  T *Xr = reinterpret_cast<T *>(fgm_smem + fmm_term_cache_bytes(NC));  // [tj][SX]
+  T *Xi = Xr + tj * SX;
+  T *Hr = Xi + tj * SX;                     // [tj + RB]
+  T *Hi = Hr + tj + RB;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
   const FmmGroup gr = groups[blockIdx.x];
-  const bool box_ok = sub < gr.nbox;
-  const int ngroups = cdiv(pout, kRB);
-  // output tile of this block: slots [o0, o0 + TO)
-  const int TO = kRB * tps, o0 = blockIdx.y * TO;
-  {
-    const int g = blockIdx.y * tps + lt;
-    const bool act = box_ok && g < ngroups;
-    const int jb = (g < ngroups ? g : blockIdx.y * tps) * kRB;
-    cx<T> acc[kRB];
+  const int nterm = gr.t1 - gr.t0;          // <= kFmmTermCache (host-checked)
+  for (int e = threadIdx.x; e < nterm * NC; e += 64 * kFmmMfmaWaves) {
+    const FmmGTerm tm = terms[gr.t0 + e / NC];
+    Cin[e] = ins[tm.ins + e % NC];
+  }
+  for (int e = threadIdx.x; e < nterm; e += 64 * kFmmMfmaWaves) {
+    const FmmGTerm tm = terms[gr.t0 + e];
+    Ctab[e] = tm.tab;
+    Cpin[e] = tm.pin;
+  }
+  __syncthreads();
+  const int ob = blockIdx.y * RB;           // first output slot of the block
+  const int sb = threadIdx.x % NC;          // box column this thread stages
+  const int sj = threadIdx.x / NC;          // first input row it stages
+  constexpr int RS = NT / NC;               // input rows staged per pass
+  constexpr int RPT = kFmmTileMax / RS;     // staged input rows per thread, at most
+  constexpr int WPT = (kFmmTileMax + RB + NT - 1) / NT;  // staged window entries per thread, at most
+  static_assert(RPT <= 32 && WPT <= 32, "bit masks of the staged entries");
+  v4 P1[NB], P2[NB], P3[NB];
 #pragma unroll
-    for (int r = 0; r < kRB; ++r) acc[r] = mk<T>(0, 0);
-    // The table tile of input tile j0 holds rows k = j0 + pout - o0 - TO + x'
-    // at local x' (so that x' = j - j' + o0 + TO - 1 - j0); the window of
-    // slot r starts at local a - r.
-    const int a = o0 + TO - 1 - jb;
-    for (int t = gr.t0; t < gr.t1; ++t) {
-      const FmmGTerm tm = terms[t];
-      const int64_t in = box_ok ? ins[tm.ins + sub] : -1;
-      const int tl = tm.pin + pout - 1;
-      for (int j0 = 0; j0 < tm.pin; j0 += tj) {
-        __syncthreads();
-        const int kb = j0 + pout - o0 - TO;  // table row of local index 0
-        for (int xl = threadIdx.x; xl < hl; xl += blockDim.x) {
-          const int k = kb + xl;
-          Hp[(xl & 7) * l8 + (xl >> 3)] = (k >= 0 && k < tl) ? ld<T>(tabs[tm.tab + k]) : mk<T>(0, 0);
+  for (int nb = 0; nb < NB; ++nb) P1[nb] = P2[nb] = P3[nb] = v4{0, 0, 0, 0};
+  // operands of the next (term, input tile), fetched into registers while
+  // the matrix cores work on the current one.  Loads are clamped into range
+  // and issued unconditionally; which of them count is kept as bit masks and
+  // applied when the values go to LDS, so that nothing waits for the loads
+  // before then.
+  cx<T> xs[RPT], hs[WPT];
+  uint32_t xok = 0, hok = 0;
+  auto fetch = [&](int t, int j0) {
+    const int tc = t - gr.t0;
+    const int tpin = Cpin[tc];
+    const int64_t ttab = Ctab[tc];
+    const int tl = tpin + pout - 1;
+    const int64_t in = sb < gr.nbox ? Cin[tc * NC + sb] : -1;
+    // window entry x holds table row kb + x, kb = j0 - ob - (RB - 1) + P_out - 1
+    const int kb = j0 - ob - (RB - 1) + pout - 1;
+    hok = 0;
+#pragma unroll
+    for (int r = 0; r < WPT; ++r) {
+      const int x = threadIdx.x + r * NT, k = kb + x;
+      hs[r] = ld<T>(tabs[ttab + min(max(k, 0), tl - 1)]);
+      hok |= static_cast<uint32_t>(x < tj + RB && k >= 0 && k < tl) << r;
+    }
+    const int64_t ib = in >= 0 ? in : 0;
+    xok = 0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int j = sj + r * RS;
+      xs[r] = ld<T>(xin[ib + min(j0 + j, tpin - 1)]);
+      xok |= static_cast<uint32_t>(j < tj && in >= 0 && j0 + j < tpin) << r;
+    }
+  };
+  if (gr.t0 < gr.t1) fetch(gr.t0, 0);
+  for (int t = gr.t0, j0 = 0; t < gr.t1;) {
+    const int pin = Cpin[t - gr.t0];
+    __syncthreads();  // the previous tile consumed
+#pragma unroll
+    for (int r = 0; r < WPT; ++r) {
+      const int x = threadIdx.x + r * NT;
+      if (x < tj + RB) {
+        const bool ok = (hok >> r) & 1;
+        Hr[x] = ok ? hs[r].re : T(0);
+        Hi[x] = ok ? hs[r].im : T(0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int j = sj + r * RS;
+      if (j < tj) {
+        const bool ok = (xok >> r) & 1;
+        Xr[j * SX + sb] = ok ? xs[r].re : T(0);
+        Xi[j * SX + sb] = ok ? xs[r].im : T(0);
+      }
+    }
+    __syncthreads();
+    int tn = t, jn = j0 + tj;
+    if (jn >= pin) {
+      ++tn;
+      jn = 0;
+    }
+    if (tn < gr.t1) fetch(tn, jn);
+    // k steps of 4 input slots in groups of KU (tj is a multiple of 4 KU, and
+    // the staged rows past the term's input are zeros)
+    constexpr int KU = 4;
+    const int kgroups = (min(tj, pin - j0) + 4 * KU - 1) / (4 * KU);
+    // output slot ob + 16 w + i and input slot j0 + jl meet at window entry
+    // jl - 16 w - i + RB - 1
+    const int xo = RB - 1 - 16 * w - i;
+    for (int kg = 0; kg < kgroups; ++kg) {
+      T ar[KU], ai[KU], br[KU][NB], bi[KU][NB];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int jl = 4 * (KU * kg + u) + kq;
+        ar[u] = Hr[jl + xo];
+        ai[u] = Hi[jl + xo];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          br[u][nb] = Xr[jl * SX + 16 * nb + i];
+          bi[u][nb] = Xi[jl * SX + 16 * nb + i];
         }
-        for (int i = lt; i < tj; i += tps)
-          Ms[i] = (in >= 0 && j0 + i < tm.pin) ? ld<T>(xin[in + j0 + i]) : mk<T>(0, 0);
-        __syncthreads();
-        if (act && in >= 0) {
-          cx<T> w[kRB];
+      }
 #pragma unroll
-          for (int r = 0; r < kRB; ++r) {
-            const int x = a - r;
-            w[r] = Hp[(x & 7) * l8 + (x >> 3)];
-          }
-          int addr[8];
+      for (int u = 0; u < KU; ++u) {
+        const T as = ar[u] + ai[u];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int x = a + u + 1;
-            addr[u] = (x & 7) * l8 + (x >> 3);
-          }
-          const int steps = cdiv(min(tj, tm.pin - j0), 8);
-          for (int s8 = 0; s8 < steps; ++s8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              const cx<T> m = Ms[8 * s8 + u];
-#pragma unroll
-              for (int r = 0; r < kRB; ++r) cmac(acc[r], w[r], m);
-#pragma unroll
-              for (int r = kRB - 1; r > 0; --r) w[r] = w[r - 1];
-              w[0] = Hp[addr[u] + s8];
-            }
-          }
+        for (int nb = 0; nb < NB; ++nb) {
+          P1[nb] = mfma4<T>::mac(ar[u], br[u][nb], P1[nb]);
+          P2[nb] = mfma4<T>::mac(ai[u], bi[u][nb], P2[nb]);
+          P3[nb] = mfma4<T>::mac(as, br[u][nb] + bi[u][nb], P3[nb]);
         }
       }
     }
-    if (act) {
-      const int64_t o = outs[gr.outs + sub];
+    t = tn;
+    j0 = jn;
+  }
 #pragma unroll
-      for (int r = 0; r < kRB; ++r)
-        if (jb + r < pout) xout[o + jb + r] = st(acc[r]);
+  for (int nb = 0; nb < NB; ++nb) {
+    const int b = 16 * nb + i;
+    if (b >= gr.nbox) continue;
+    const int64_t o = outs[gr.outs + b];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int slot = ob + 16 * w + mfma4<T>::row(lane, j);
+      const T p1 = P1[nb][j], p2 = P2[nb][j], p3 = P3[nb][j];
+      if (slot < pout) xout[o + slot] = st(mk<T>(p1 - p2, p3 - p1 - p2));
     }
   }
 }
@@ -489,33 +584,26 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
   std::vector<int> Pl(top + 1);
   for (int l = 0; l <= top; ++l) Pl[l] = 2 * f.lv[l].p[pi] + 1;
 
-  // launch shape of every stage: lanes per box (tps <= 64, kRB outputs
-  // each), output tiles, boxes per group and term chunks (partial
-  // expansions summed afterwards in a fixed order), chosen so that every
-  // launch has enough blocks to fill the chip
+  // launch shape of every stage (matrix-core translation kernel): output
+  // windows of kFmmMfmaRows slots, groups of kFmmGroup boxes, term chunks
+  // (partial expansions summed afterwards in a fixed order) so that every
+  // launch has enough blocks to fill the chip, and input tiles that split the
+  // longest input evenly within the LDS budget
+  const size_t esz = pi == 0 ? sizeof(double) : sizeof(float);
   auto plan = [&](int pout, int pin_max, const std::vector<int64_t> &cls, int nterms) {
     FmmStage s;
-    const int ng = cdiv(pout, kRB);
     s.pout = pout;
-    s.tps = std::min(64, ng);
-    s.tiles = cdiv(ng, s.tps);
-    s.G = std::max(1, std::min(kMaxGroup, kToepMaxThreads / s.tps));
-    auto blocks = [&](int G) {
-      int64_t b = 0;
-      for (auto c : cls) b += cdiv(c, G);
-      return b * s.tiles;
-    };
-    // fewer boxes per group only while a block keeps two full waves
-    while (s.G > 1 && (s.G / 2) * s.tps >= 128 && blocks(s.G) < kTargetBlocks) s.G /= 2;
-    s.nchunk = std::min({kMaxChunks, std::max(1, nterms),
-                         std::max(1, cdiv(kTargetBlocks, std::max<int64_t>(1, blocks(s.G))))});
-    // input tile: the whole input when it fits, at most kMaxTileJ, within the LDS budget
-    s.tj = std::min(kMaxTileJ, cdiv(pin_max, 8) * 8);
-    auto lds = [&](int tj) {
-      return (8.0 * cdiv(kRB * s.tps + tj + 8, 8) + static_cast<double>(s.G) * tj) * 16.0;  // FP64 bytes
-    };
-    while (s.tj > 64 && lds(s.tj) > static_cast<double>(kLdsBudget)) s.tj = cdiv(s.tj / 2, 8) * 8;
-    s.l8 = cdiv(kRB * s.tps + s.tj + 8, 8);
+    s.tiles = cdiv(pout, kFmmMfmaRows);
+    s.G = kFmmGroup;
+    int64_t blocks = 0;
+    for (auto c : cls) blocks += cdiv(c, s.G);
+    blocks *= s.tiles;
+    s.nchunk = std::min({kMaxChunks, std::max(1, nterms), std::max(1, cdiv(kTargetBlocks, std::max<int64_t>(1, blocks)))});
+    s.nchunk = std::max(s.nchunk, cdiv(std::max(1, nterms), kFmmTermCache));  // chunks fit the term cache
+    int cap = kFmmTileMax;
+    while (cap > 16 && fmm_mfma_lds(cap, esz) > kFmmLds) cap -= 16;
+    const int ntile = cdiv(std::max(1, pin_max), cap);
+    s.tj = cdiv(cdiv(std::max(1, pin_max), ntile), 16) * 16;  // whole groups of four k steps
     return s;
   };
   std::vector<FmmStage> shp_up(top + 1), shp_dn(top + 1);
@@ -527,7 +615,11 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
         ++cls[l < top ? ((b % g.nx[l]) & 1) + 2 * ((b / g.nx[l]) & 1) : 0];
         ++nonempty;
       }
-    shp_dn[l] = plan(Pl[l], l < top ? std::max(Pl[l], Pl[l + 1]) : Pl[l], cls, l < top ? 28 : static_cast<int>(nonempty));
+    // terms of one group: 27 interaction offsets of a parity class and the
+    // parent's L2L below the top; at the top every offset of the level's
+    // box grid outside the 3 x 3 neighbourhood may occur
+    const int top_terms = std::max(1, (2 * g.nx[l] - 1) * (2 * g.ny[l] - 1) - 9);
+    shp_dn[l] = plan(Pl[l], l < top ? std::max(Pl[l], Pl[l + 1]) : Pl[l], cls, l < top ? 28 : top_terms);
     if (l > 0) shp_up[l] = plan(Pl[l], Pl[l - 1], {nonempty}, 4);
   }
 
@@ -733,6 +825,7 @@ bool build_precision(mpsl_ctx *ctx, const Grid &g, int top, int pi, std::vector<
       for (int64_t gi = 0; gi < st.tasks; ++gi) {
         const FmmGroup &gr = groups[st.task_off + gi];
         if (gr.nbox < 1 || gr.nbox > st.G || gr.t0 > gr.t1 || gr.t1 > static_cast<int>(terms.size()) ||
+            gr.t1 - gr.t0 > kFmmTermCache ||
             gr.outs + gr.nbox > static_cast<int64_t>(outs.size())) {
           why = "group outside its lists";
           return false;
@@ -929,14 +1022,14 @@ template <typename T>
 int launch_stage(mpsl_ctx *ctx, int pi, const FmmStage &st) {
   if (st.tasks == 0) return MPSL_OK;
   FmmPlan &f = ctx->fmm;
-  const size_t lds = (8 * static_cast<size_t>(st.l8) + static_cast<size_t>(st.G) * st.tj) * sizeof(cx<T>);
-  if (lds > kLdsBudget) return set_err(ctx, MPSL_EUNSUPPORTED, "FMM translation exceeds the LDS budget");
-  hipLaunchKernelGGL(k_fmm_group<T>, dim3(st.tasks, st.tiles), dim3(st.G * st.tps), lds, ctx->stream,
-                     static_cast<const FmmGroup *>(f.groups[pi].p) + st.task_off,
+  const size_t lds = fmm_mfma_lds(st.tj, sizeof(T));
+  if (st.G != kFmmGroup || st.tj < 16 || st.tj % 16 || st.tj > kFmmTileMax || lds > kFmmLds)
+    return set_err(ctx, MPSL_EUNSUPPORTED, "FMM translation shape outside the kernel's limits");
+  hipLaunchKernelGGL((k_fmm_group_mfma<T, kFmmGroup / 16>), dim3(st.tasks, st.tiles), dim3(64 * kFmmMfmaWaves), lds,
+                     ctx->stream, static_cast<const FmmGroup *>(f.groups[pi].p) + st.task_off,
                      static_cast<const FmmGTerm *>(f.terms[pi].p), static_cast<const int64_t *>(f.ins[pi].p),
                      static_cast<const int64_t *>(f.outs[pi].p), static_cast<const cv_t<T> *>(f.xb.p),
-                     static_cast<const cv_t<T> *>(f.tab[pi].p), static_cast<cv_t<T> *>(f.xb.p), st.pout, st.tps,
-                     st.G, st.l8, st.tj);
+                     static_cast<const cv_t<T> *>(f.tab[pi].p), static_cast<cv_t<T> *>(f.xb.p), st.pout, st.tj);
   MPSL_HIP_TRY(ctx, hipGetLastError());
   if (st.nchunk > 1) {
     hipLaunchKernelGGL(k_fmm_chunk_sum<T>, dim3(cdiv(st.sum_len, 256)), dim3(256), 0, ctx->stream,
