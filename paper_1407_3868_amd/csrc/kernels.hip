@@ -817,7 +817,9 @@ __global__ __launch_bounds__(64 * kM2lMfmaWaves) void k_m2l_mfma(const cv_t<T> *
       sa[2][s][v + OFS] = b.re + b.im;
     }
     __syncthreads();
-    for (int g0 = 0; g0 < sb; g0 += 4) {
+    // a wave whose targets all lie past the last particle (the grid's tail)
+    // stages its share of the batch and meets the barriers, but multiplies nothing
+    for (int g0 = 0; g0 < sb && lt0 < n; g0 += 4) {
       const int s = g0 + g;  // this lane's source within the batch
       cx<T> hp[NT], hc[NT], t[NT], tq[NT];
       T tz[NT];
