@@ -941,7 +941,7 @@ __global__ __launch_bounds__(64 * kM2lMfmaWaves) void k_m2l_mfma(const cv_t<T> *
 // Toeplitz translation T^{ml}[n'][nu] = h_{nu-n'} is built once and applied to
 // the coefficients of 64 right-hand sides as a GEMM  alpha_l[n'][r] +=
 // sum_nu T[n'][nu] beta_m[nu][r]  with 16x16x4 MFMA (M = n', K = nu, N = r),
-// the complex product as four real chains.  One wave per target, kMrhsWaves
+// complex products in three real MFMAs (Gauss).  One wave per target, kMrhsWaves
 // targets per block, grid.y source chunks, grid.z groups of 64 right-hand
 // sides.  Lanes 0..7 of each wave run the Hankel recurrences of 8 sources
 // at a time (from the pair table, as in k_m2l) into zero-padded LDS rows;
@@ -974,11 +974,12 @@ __global__ __launch_bounds__(64 * kMrhsWaves) void k_m2l_mrhs(const float2 *__re
   const int m0 = c * chunk_len;
   const int m1 = min(n, m0 + chunk_len);
   typedef float v4 __attribute__((ext_vector_type(4)));
-  v4 are[MT][NT], aim[MT][NT];
+  // Gauss: P1 = sum Ar Br, P2 = sum Ai Bi, P3 = sum (Ar + Ai)(Br + Bi)
+  v4 P1[MT][NT], P2[MT][NT], P3[MT][NT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int ct = 0; ct < NT; ++ct) are[mt][ct] = aim[mt][ct] = v4{0, 0, 0, 0};
+    for (int ct = 0; ct < NT; ++ct) P1[mt][ct] = P2[mt][ct] = P3[mt][ct] = v4{0, 0, 0, 0};
   const int col = lane & 15, kq = lane >> 4;
   // B of source m: rows k (zero rows k >= P in bt), 64 right-hand sides
   float2 pre[BL];
@@ -1036,22 +1037,23 @@ __global__ __launch_bounds__(64 * kMrhsWaves) void k_m2l_mrhs(const float2 *__re
 #pragma unroll
       for (int k0 = 0; k0 < KP; k0 += 4) {
         const int k = k0 + kq;
-        float br[NT], bi[NT];
+        float br[NT], bi[NT], bs[NT];
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
           const float2 bv = Bs[buf][k][ct * 16 + col];
           br[ct] = bv.x;
           bi[ct] = bv.y;
+          bs[ct] = bv.x + bv.y;
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
           const float2 a = hrow[k - (mt * 16 + col) + OFF];
+          const float as = a.x + a.y;
 #pragma unroll
           for (int ct = 0; ct < NT; ++ct) {
-            are[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, br[ct], are[mt][ct], 0, 0, 0);
-            are[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, bi[ct], are[mt][ct], 0, 0, 0);
-            aim[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bi[ct], aim[mt][ct], 0, 0, 0);
-            aim[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, br[ct], aim[mt][ct], 0, 0, 0);
+            P1[mt][ct] = mfma4<float>::mac(a.x, br[ct], P1[mt][ct]);
+            P2[mt][ct] = mfma4<float>::mac(a.y, bi[ct], P2[mt][ct]);
+            P3[mt][ct] = mfma4<float>::mac(as, bs[ct], P3[mt][ct]);
           }
         }
       }
@@ -1069,8 +1071,9 @@ __global__ __launch_bounds__(64 * kMrhsWaves) void k_m2l_mrhs(const float2 *__re
       for (int j = 0; j < 4; ++j) {
         const int row = mt * 16 + 4 * kq + j;
         const int r = r0 + ct * 16 + col;
+        const float p1 = P1[mt][ct][j], p2 = P2[mt][ct][j], p3 = P3[mt][ct][j];
         if (row < P && r < nrhs)
-          part[r * pstride + c * len + static_cast<int64_t>(l) * P + row] = make_float2(are[mt][ct][j], aim[mt][ct][j]);
+          part[r * pstride + c * len + static_cast<int64_t>(l) * P + row] = make_float2(p1 - p2, p3 - p1 - p2);
       }
 }
 
