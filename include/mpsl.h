@@ -82,9 +82,17 @@ const char *mpsl_status_string(int status);
 const char *mpsl_last_error(const mpsl_ctx *ctx);
 
 /* Create a context on HIP device `device`.  Owns all device memory and one
- * stream (the null stream of the device unless mpsl_set_stream is called). */
-int mpsl_create(mpsl_ctx **out, int device);
+ * stream (the null stream of the device unless mpsl_set_stream is called).
+ * hbm_budget: device bytes the context may hold at once (tables, work buffers,
+ * Krylov basis, preconditioner blocks); a call whose allocation would exceed
+ * it fails with MPSL_ENOMEM (that buffer is not allocated; the context stays
+ * valid).  0 = no limit beyond the device's memory. */
+int mpsl_create(mpsl_ctx **out, int device, size_t hbm_budget);
 void mpsl_destroy(mpsl_ctx *ctx);
+
+/* Device bytes the context holds now and its budget (0: none); either output
+ * pointer may be NULL. */
+int mpsl_get_memory(const mpsl_ctx *ctx, size_t *bytes_in_use, size_t *hbm_budget);
 
 /* Run all later device work on `stream` (a hipStream_t, e.g. torch's current
  * stream); NULL selects the device's null stream. */
@@ -436,11 +444,14 @@ int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *
                mpsl_c128 *beta_out, mpsl_info *info);
 
 /* Total field (eq. (36)) at n_rcv receivers rcv_xy (host, 2 doubles each) for
- * the source src_xy and coefficients beta (host, N*P mpsl_c128):
+ * n_rhs sources src_xy[2*r], src_xy[2*r+1] and their coefficients beta (host,
+ * n_rhs*N*P mpsl_c128, [rhs][particle][n+p], as mpsl_solve writes them):
  * layer 1: G + u_1^s; layer 2: u_2^t + u_2^b + sum of multipoles; layer 3: u_3^s.
- * Receivers inside an enclosing disk get NaN and the call returns
- * MPSL_EINSIDE after filling all other values.  u_out: host, n_rcv. */
-int mpsl_eval_field(mpsl_ctx *ctx, const double *src_xy, const mpsl_c128 *beta,
+ * u_out: host, n_rhs*n_rcv ([rhs][receiver]).  Every source must lie above the
+ * top interface (MPSL_EINVAL otherwise, nothing written).  Receivers inside an
+ * enclosing disk get NaN and the call returns MPSL_EINSIDE after filling all
+ * other values. */
+int mpsl_eval_field(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_c128 *beta,
                     int64_t n_rcv, const double *rcv_xy, mpsl_c128 *u_out);
 
 /* Launch-shape tuning of the M2L kernel (row a1), per precision.  Variants:

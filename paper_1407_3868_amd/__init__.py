@@ -173,12 +173,13 @@ class Batch:
 
 
 class Context:
-    """One mpsl context on a HIP device (mirrors mpsl_create/mpsl_destroy)."""
+    """One mpsl context on a HIP device (mirrors mpsl_create/mpsl_destroy);
+    hbm_budget: device bytes it may hold (0: no limit)."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, hbm_budget=0):
         self.lib = _lib.load()
         h = ctypes.c_void_p()
-        rc = self.lib.mpsl_create(ctypes.byref(h), int(device))
+        rc = self.lib.mpsl_create(ctypes.byref(h), int(device), int(hbm_budget))
         if rc != 0:
             raise MpslError(rc, "mpsl_create failed (no HIP device?)")
         self.h = h
@@ -188,6 +189,12 @@ class Context:
         if getattr(self, "h", None):
             self.lib.mpsl_destroy(self.h)
             self.h = None
+
+    def memory(self):
+        """(device bytes in use, HBM budget) of the context (mpsl_get_memory)."""
+        u, b = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.lib.mpsl_get_memory(self.h, ctypes.byref(u), ctypes.byref(b)))
+        return u.value, b.value
 
     def __del__(self):
         try:
@@ -370,13 +377,16 @@ class Context:
         return (out[0] if nr == 1 else out), meta
 
     def eval_field(self, src, beta, rcv):
+        """Total field at receivers rcv [R, 2] for one source (src [2], beta [N, P]:
+        returns [R]) or several (src [n_rhs, 2], beta [n_rhs, N, P]: returns [n_rhs, R])."""
         s = np.ascontiguousarray(src, dtype=np.float64)
+        nrhs = 1 if s.ndim == 1 else s.shape[0]
         b = _carr(beta)
         r = np.ascontiguousarray(rcv, dtype=np.float64)
-        u = np.empty(r.shape[0], np.complex128)
-        self._check(self.lib.mpsl_eval_field(self.h, s.ctypes.data, b.ctypes.data, int(r.shape[0]),
+        u = np.empty((nrhs, r.shape[0]), np.complex128)
+        self._check(self.lib.mpsl_eval_field(self.h, int(nrhs), s.ctypes.data, b.ctypes.data, int(r.shape[0]),
                                              r.ctypes.data, u.ctypes.data), allow=(-8,))
-        return u
+        return u[0] if s.ndim == 1 else u
 
     def autotune(self, prec):
         return self._check(self.lib.mpsl_autotune(self.h, int(prec)))

@@ -37,8 +37,9 @@ DP = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "mpsl_status_string": (ctypes.c_char_p, [I]),
     "mpsl_last_error": (ctypes.c_char_p, [P]),
-    "mpsl_create": (I, [ctypes.POINTER(P), I]),
+    "mpsl_create": (I, [ctypes.POINTER(P), I, ctypes.c_size_t]),
     "mpsl_destroy": (None, [P]),
+    "mpsl_get_memory": (I, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "mpsl_set_stream": (I, [P, P]),
     "mpsl_set_layers": (I, [P, c128, c128, c128, D]),
     "mpsl_set_layer_stack": (I, [P, I, P, P, I]),
@@ -82,7 +83,7 @@ SIGNATURES = {
     "mpsl_get_precond_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I), DP]),
     "mpsl_rhs": (I, [P, P, P]),
     "mpsl_solve": (I, [P, I, P, ctypes.POINTER(Opts), P, ctypes.POINTER(Info)]),
-    "mpsl_eval_field": (I, [P, P, P, L, P, P]),
+    "mpsl_eval_field": (I, [P, I, P, P, L, P, P]),
     "mpsl_autotune": (I, [P, I]),
     "mpsl_set_tuning": (I, [P, I, I, I]),
     "mpsl_get_tuning": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(I), DP]),

@@ -34,25 +34,31 @@ int dev_alloc(mpsl_ctx *ctx, DBuf &b, size_t bytes) {
   if (ctx->pinned > 0 && &b != &ctx->xbuf && &b != &ctx->ybuf && &b != &ctx->gm && &b != &ctx->scal &&
       &b != &ctx->pc_blk && &b != &ctx->pc_blk32 && &b != &ctx->pc_idx && &b != &ctx->pc_part && &b != &ctx->pc_flag)
     return check_unpinned(ctx);
-  if (b.p) {
-    (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-  }
+  dev_free(b);
   if (bytes == 0) return MPSL_OK;
+  if (ctx->hbm_budget > 0 && ctx->hbm_used + bytes > ctx->hbm_budget)
+    return set_err(ctx, MPSL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes would exceed the " +
+                                         "context's HBM budget (" + std::to_string(ctx->hbm_used) + " of " +
+                                         std::to_string(ctx->hbm_budget) + " bytes in use)");
   if (hipMalloc(&b.p, bytes) != hipSuccess) {
     b.p = nullptr;
     (void)hipGetLastError();
     return set_err(ctx, MPSL_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
   b.bytes = bytes;
+  b.used = &ctx->hbm_used;
+  ctx->hbm_used += bytes;
   return MPSL_OK;
 }
 
 void dev_free(DBuf &b) {
-  if (b.p) (void)hipFree(b.p);
+  if (b.p) {
+    (void)hipFree(b.p);
+    if (b.used) *b.used -= b.bytes;
+  }
   b.p = nullptr;
   b.bytes = 0;
+  b.used = nullptr;
 }
 
 namespace {
@@ -588,7 +594,7 @@ const char *mpsl_status_string(int s) {
 
 const char *mpsl_last_error(const mpsl_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-int mpsl_create(mpsl_ctx **out, int device) {
+int mpsl_create(mpsl_ctx **out, int device, size_t hbm_budget) {
   if (!out) return MPSL_EINVAL;
   *out = nullptr;
   int cnt = 0;
@@ -602,11 +608,19 @@ int mpsl_create(mpsl_ctx **out, int device) {
   mpsl_ctx *ctx = new (std::nothrow) mpsl_ctx();
   if (!ctx) return MPSL_ENOMEM;
   ctx->device = device;
+  ctx->hbm_budget = hbm_budget;
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     ctx->n_cu = cus;
   (void)hipGetLastError();
   *out = ctx;
+  return MPSL_OK;
+}
+
+int mpsl_get_memory(const mpsl_ctx *ctx, size_t *bytes_in_use, size_t *hbm_budget) {
+  if (!ctx) return MPSL_EINVAL;
+  if (bytes_in_use) *bytes_in_use = ctx->hbm_used;
+  if (hbm_budget) *hbm_budget = ctx->hbm_budget;
   return MPSL_OK;
 }
 

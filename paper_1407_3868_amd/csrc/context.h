@@ -16,6 +16,7 @@ using zc = std::complex<double>;
 struct DBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  size_t *used = nullptr;  // the owning context's count of device bytes in use
 };
 
 // Device tables derived from the contour alone (FP64 master + FP32 copy).
@@ -125,6 +126,8 @@ struct FmmPlan {
 struct mpsl_ctx {
   int device = 0;
   int n_cu = 256;          // compute units of the device (launch-shape rules)
+  size_t hbm_budget = 0;   // device bytes the context may hold (0: no limit)
+  size_t hbm_used = 0;     // device bytes it holds now
   hipStream_t stream = nullptr;
   std::string err;
 

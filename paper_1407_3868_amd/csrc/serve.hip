@@ -112,7 +112,7 @@ namespace {
 int setup_job(mpsl_server *s, Job &j) {
   const mpsl_request &r = j.req;
   if (hipSetDevice(s->device) != hipSuccess) return MPSL_EHIP;
-  int rc = mpsl_create(&j.ctx, s->device);
+  int rc = mpsl_create(&j.ctx, s->device, 0);  // admission already charged the estimate
   if (rc) return rc;
   if (hipStreamCreateWithFlags(&j.stream, hipStreamNonBlocking) != hipSuccess) return MPSL_EHIP;
   if ((rc = mpsl_set_stream(j.ctx, j.stream)) || (rc = mpsl_set_layers(j.ctx, r.k1, r.k2, r.k3, r.d))) return rc;

@@ -417,14 +417,12 @@ int mpsl_solve(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_opts *
   return status;
 }
 
-int mpsl_eval_field(mpsl_ctx *ctx, const double *src, const mpsl_c128 *beta, int64_t n_rcv, const double *rcv,
-                    mpsl_c128 *u_out) {
-  if (!ctx || !src || !beta || !rcv || !u_out || n_rcv <= 0) return MPSL_EINVAL;
-  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  int rc = mpsl::build_tables(ctx);
-  if (rc) return rc;
-  if (!(src[1] > ctx->yint[0]))
-    return mpsl::set_err(ctx, MPSL_EINVAL, "the source must lie in the top half-space (above the top interface)");
+namespace {
+
+// Total field of one source and its coefficients at n_rcv receivers.
+int eval_field_one(mpsl_ctx *ctx, const double *src, const mpsl_c128 *beta, int64_t n_rcv, const double *rcv,
+                   mpsl_c128 *u_out) {
+  int rc = MPSL_OK;
   const int ns = ctx->ns;
   const int64_t len = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
   if ((rc = mpsl::dev_alloc(ctx, ctx->xbuf, len * sizeof(double2)))) return rc;
@@ -472,6 +470,30 @@ int mpsl_eval_field(mpsl_ctx *ctx, const double *src, const mpsl_c128 *beta, int
   for (int64_t i = 0; i < n_rcv; ++i)
     if (std::isnan(u_out[i].re)) return mpsl::set_err(ctx, MPSL_EINSIDE, "receiver inside an enclosing disk");
   return MPSL_OK;
+}
+
+}  // namespace
+
+int mpsl_eval_field(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_c128 *beta, int64_t n_rcv,
+                    const double *rcv_xy, mpsl_c128 *u_out) {
+  if (!ctx || n_rhs < 1 || !src_xy || !beta || !rcv_xy || !u_out || n_rcv <= 0) return MPSL_EINVAL;
+  MPSL_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  int rc = mpsl::build_tables(ctx);
+  if (rc) return rc;
+  for (int r = 0; r < n_rhs; ++r)
+    if (!(src_xy[2 * r + 1] > ctx->yint[0]))
+      return mpsl::set_err(ctx, MPSL_EINVAL, "every source must lie in the top half-space (above the top interface)");
+  const int64_t len = ctx->n * static_cast<int64_t>(2 * ctx->p + 1);
+  bool inside = false;
+  for (int r = 0; r < n_rhs; ++r) {
+    rc = eval_field_one(ctx, src_xy + 2 * r, beta + r * len, n_rcv, rcv_xy, u_out + r * n_rcv);
+    if (rc == MPSL_EINSIDE) {
+      inside = true;
+    } else if (rc) {
+      return rc;
+    }
+  }
+  return inside ? mpsl::set_err(ctx, MPSL_EINSIDE, "receiver inside an enclosing disk") : MPSL_OK;
 }
 
 }  // extern "C"

@@ -54,5 +54,5 @@ def test_create_without_device_fails_cleanly(lib):
     if torch.cuda.is_available():
         pytest.skip("a device is present")
     h = ctypes.c_void_p()
-    rc = lib.mpsl_create(ctypes.byref(h), 0)
+    rc = lib.mpsl_create(ctypes.byref(h), 0, 0)
     assert rc != 0 and not h.value
