@@ -454,7 +454,10 @@ __global__ __launch_bounds__(64 * kFmmMfmaWaves) void k_fmm_group_mfma(const Fmm
     // output slot ob + 16 w + i and input slot j0 + jl meet at window entry
     // jl - 16 w - i + RB - 1
     const int xo = RB - 1 - 16 * w - i;
-    for (int kg = 0; kg < kgroups; ++kg) {
+    // a wave whose 16 output slots all lie past P_out (the last window of a
+    // stage) stages its share and meets the barriers but multiplies nothing
+    const int kgw = ob + 16 * w < pout ? kgroups : 0;
+    for (int kg = 0; kg < kgw; ++kg) {
       T ar[KU], ai[KU], br[KU][NB], bi[KU][NB];
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
