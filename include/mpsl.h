@@ -462,10 +462,11 @@ int mpsl_eval_field(mpsl_ctx *ctx, int n_rhs, const double *src_xy, const mpsl_c
  * with the source coefficients in shifted form, 16 or 32 targets per wave),
  * for p <= 16 only (a stored 2 or 3 runs as 0 at larger p, and the autotuner
  * skips them there).
- * mpsl_autotune times the variants at 1/2, 1 and 2 times the default number
- * of source chunks on the current problem (pseudo-random input, HIP events on
- * the context stream, each launch with the summation of its partial slots)
- * and keeps the fastest (a later candidate must be more than 1 % faster); mpsl_set_tuning forces a choice
+ * mpsl_autotune times the variants at 1, 1/2 and 2 times the default number
+ * of source chunks, in that order, on the current problem (pseudo-random
+ * input, HIP events on the context stream, each launch with the summation of
+ * its partial slots) and keeps the fastest (a later candidate must be more
+ * than 1 % faster, so near-ties keep the default); mpsl_set_tuning forces a choice
  * (chunks 0 = default).  Tuning is kept until changed; it never changes
  * results beyond floating-point summation order. */
 int mpsl_autotune(mpsl_ctx *ctx, int prec);

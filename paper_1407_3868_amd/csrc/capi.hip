@@ -1170,7 +1170,10 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
   const size_t len = static_cast<size_t>(ctx->n) * P;
   if ((rc = mpsl::dev_alloc(ctx, ctx->xbuf, len * esz))) return rc;
   if ((rc = mpsl::launch_fill_hash(ctx, prec, ctx->xbuf.p, static_cast<int64_t>(len), 12345u))) return rc;
-  const int cands[3] = {std::max(1, base / 2), base, static_cast<int>(std::min<int64_t>(2LL * base, ctx->n))};
+  // the default count first: the others must beat it by more than 1 % (at 5000
+  // particles half the default ties with it once the smaller partial sum is
+  // counted, while its own launch fills the last wave of blocks worse)
+  const int cands[3] = {base, std::max(1, base / 2), static_cast<int>(std::min<int64_t>(2LL * base, ctx->n))};
   hipEvent_t e0, e1;
   MPSL_HIP_TRY(ctx, hipEventCreate(&e0));
   MPSL_HIP_TRY(ctx, hipEventCreate(&e1));
@@ -1187,7 +1190,7 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
       };
       if ((rc = run())) break;  // warm-up
       if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = MPSL_EHIP; break; }
-      const int reps = 3;
+      const int reps = 5;
       for (int r = 0; r < reps && !rc; ++r) rc = run();
       if (rc) break;
       float ms = 0.f;
@@ -1198,7 +1201,7 @@ int mpsl_autotune(mpsl_ctx *ctx, int prec) {
       }
       const double avg = ms / reps;
       // a later candidate must win by more than 1 %: near-ties keep the earlier
-      // (fewer chunks, less partial-sum traffic) and the choice stays stable
+      // one and the choice stays stable run to run
       if (avg < 0.99 * best) {
         best = avg;
         bv = variant;
