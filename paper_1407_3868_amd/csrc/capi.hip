@@ -464,7 +464,8 @@ int ensure_work(mpsl_ctx *ctx) {
   const int P = 2 * ctx->p + 1;
   const size_t len = static_cast<size_t>(ctx->n) * P;
   const int ca = std::max(chunks_m2l(ctx, MPSL_FP64), chunks_m2l(ctx, MPSL_FP32));
-  const int cb = std::max(chunks_s2l(ctx, 1, MPSL_FP64), chunks_s2l(ctx, 1, MPSL_FP32)), cc = chunks_m2s(ctx);
+  const int cb = std::max(chunks_s2l(ctx, 1, MPSL_FP64), chunks_s2l(ctx, 1, MPSL_FP32));
+  const int cc = std::max(chunks_m2s(ctx, 1, MPSL_FP64), chunks_m2s(ctx, 1, MPSL_FP32));
   int rc;
   if ((rc = dev_alloc(ctx, ctx->part, (ca + cb) * len * sizeof(double2))) ||
       (rc = dev_alloc(ctx, ctx->m2s_part, 2ull * cc * ctx->ns * sizeof(double2))) ||
@@ -492,7 +493,7 @@ int matvec(mpsl_ctx *ctx, int prec, const void *x, void *y, int nrhs) {
   const int ca = fmm ? fmm_slots(ctx)
                      : (mrhs ? chunks_m2l_mrhs(ctx, nrhs) : std::max(1, chunks_m2l(ctx, prec) / nrhs));
   const int cb = chunks_s2l(ctx, nrhs, prec);
-  const int cc = chunks_m2s(ctx, nrhs);
+  const int cc = chunks_m2s(ctx, nrhs, prec);
   const int P = 2 * ctx->p + 1;
   const size_t esz = prec == MPSL_FP64 ? sizeof(double2) : sizeof(float2);
   const int64_t len = ctx->n * static_cast<int64_t>(P);

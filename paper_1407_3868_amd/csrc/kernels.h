@@ -105,7 +105,8 @@ int m2l_mfma_chunk_len(int n, int chunks);
 inline int m2l_slots(const mpsl_ctx *ctx, int prec) { return chunks_m2l(ctx, prec); }
 // Node chunks of the S2L grid for precision prec (its particle tiles differ).
 int chunks_s2l(const mpsl_ctx *ctx, int nrhs, int prec);
-int chunks_m2s(const mpsl_ctx *ctx, int nrhs = 1);
+// Particle chunks of the M2S grid for precision prec.
+int chunks_m2s(const mpsl_ctx *ctx, int nrhs, int prec);
 
 // Sommerfeld transforms by tile-local interpolation (somm.hip): M2S spectra
 // into spec ([nrhs][2][ns], FP64) and S2L local expansions into one part slot

@@ -1454,15 +1454,48 @@ int chunks_s2l(const mpsl_ctx *ctx, int nrhs, int prec) {
   return balanced_chunks(bpc, slots, std::max(1, c0), std::min(2 * c0, cmax));
 }
 
-int chunks_m2s(const mpsl_ctx *ctx, int nrhs) {
+// Blocks of the matrix-core M2S kernel resident per compute unit (occupancy
+// query, cached per precision and order; 1 if the query fails).
+template <typename T>
+static int m2s_resident(int p) {
+  static std::atomic<int> cache[kMaxP + 1];
+  if (p < kMinP || p > kMaxP) return 1;
+  int r = cache[p].load(std::memory_order_relaxed);
+  if (r > 0) return r;
+  const void *fn = nullptr;
+  switch (p) {
+#define X(PP) \
+  case PP: fn = reinterpret_cast<const void *>(&k_m2s_mfma<T, PP>); break;
+    MPSL_P_CASES(X)
+#undef X
+  }
+  int nb = 0;
+  if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64 * kM2sWaves, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  cache[p].store(nb, std::memory_order_relaxed);
+  return nb;
+}
+
+int chunks_m2s(const mpsl_ctx *ctx, int nrhs, int prec) {
   if (ctx->m2s_chunks > 0) return static_cast<int>(std::min<int64_t>(ctx->m2s_chunks, ctx->n));
   // about 2048 node-group x chunk tasks, but at least 80 particles per chunk:
   // shorter chunks spend more on the epilogue and on summing the partials
   // than they gain in parallelism (1024 nodes, 5000 particles: 256 -> 63
   // chunks, M2S and partial sum 75 -> about 45 us in FP32)
   const int qb = cdiv(ctx->ns, kThreads) * 2 * nrhs;
-  const int64_t c = std::min<int64_t>(cdiv(2048, qb), cdiv(ctx->n, 80));
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(c, ctx->n)));
+  const int c0 = static_cast<int>(std::max<int64_t>(
+      1, std::min<int64_t>(std::min<int64_t>(cdiv(2048, qb), cdiv(ctx->n, 80)), ctx->n)));
+  // short contours: lowered by up to half to the count whose blocks fill
+  // whole waves of the resident slots (1024 nodes, 5000 particles: 63 chunks
+  // made 2016 blocks for 1792 FP32 slots; 55 make 1760).  Long contours run
+  // many waves already and keep it (3 to 20 chunks within 0.5 % at 26816 nodes).
+  if (ctx->ns >= 4096) return c0;
+  const bool f64 = prec == MPSL_FP64;
+  const int64_t bpc = static_cast<int64_t>(cdiv(ctx->ns, 16 * kM2sWaves)) * 2 * nrhs;
+  const int64_t slots = static_cast<int64_t>(ctx->n_cu) * (f64 ? m2s_resident<double>(ctx->p) : m2s_resident<float>(ctx->p));
+  return balanced_chunks(bpc, slots, std::max(1, c0 / 2), c0);
 }
 
 #define LAUNCH_CHECK(ctx)                                                          \
@@ -1636,7 +1669,7 @@ int launch_fmm_near(mpsl_ctx *ctx, int prec, const void *beta, void *out) {
 template <typename T>
 static int launch_m2s_t(mpsl_ctx *ctx, const void *beta, void *spec, int nrhs) {
   const int n = static_cast<int>(ctx->n);
-  const int chunks = chunks_m2s(ctx, nrhs);
+  const int chunks = chunks_m2s(ctx, nrhs, std::is_same<T, double>::value ? MPSL_FP64 : MPSL_FP32);
   const int chunk_len = cdiv(n, chunks);
   const dim3 grid(cdiv(ctx->ns, 16 * kM2sWaves), chunks, 2 * nrhs);
   const bool f64 = std::is_same<T, double>::value;
