@@ -319,20 +319,26 @@ __global__ void k_fmm_l2p(const cv_t<T> *__restrict__ lin, const int *__restrict
 // P3 = sum (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2.  Absent
 // inputs (ins < 0) and input slots past the term's length are staged as
 // zeros.  The input rows are 16 mod 64 words apart (NB = 1) or 48 (NB = 2),
-// so that the four rows one B read touches lie in different LDS banks.
+// so that the four rows one B read touches lie in different LDS banks.  The
+// block's term list is cached in LDS at the start, and the next tile's
+// operands are loaded into registers while the current tile's MFMAs run.
 constexpr int kFmmMfmaWaves = 4;
 constexpr int kFmmMfmaRows = 16 * kFmmMfmaWaves;  // output slots per block
 constexpr int kFmmGroup = 16;                     // boxes per group (16 NB)
 constexpr int kFmmTileMax = 128;                  // longest input tile (registers of the prefetch)
 constexpr size_t kFmmLds = 40 * 1024;             // LDS of one translation block
 
-// LDS bytes of the matrix-core translation block for input tiles of tj slots
-// (element size esz): the term cache, inputs [tj][16 or 48] and the table
-// window [tj + rows], real and imaginary parts apart.
 constexpr int kFmmTermCache = 32;                 // terms of one block, at most
+
+// LDS bytes of a block's term list (per term: nc input offsets, the table
+// offset and the input length).
 __host__ __device__ constexpr size_t fmm_term_cache_bytes(int nc) {
   return static_cast<size_t>(kFmmTermCache) * (nc * sizeof(int64_t) + sizeof(int64_t) + sizeof(int));
 }
+
+// LDS bytes of the matrix-core translation block for input tiles of tj slots
+// (element size esz): the term list, inputs [tj][16 or 48] and the table
+// window [tj + rows], real and imaginary parts apart.
 inline size_t fmm_mfma_lds(int tj, size_t esz) {
   const int sx = kFmmGroup == 16 ? 16 : 48;
   return fmm_term_cache_bytes(kFmmGroup) +
